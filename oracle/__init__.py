@@ -1,0 +1,231 @@
+"""FP64 CPU oracle (ctypes wrapper around oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+benchmark's CPU-baseline leg.  The GPU library never imports or links it.
+
+Every function takes geometry in mm and images in 1/mm, as numpy float64.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SRC_PATH = os.path.join(_HERE, "oracle.c")
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (FP64, OpenMP).  Returns the library path."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.run(["gcc", "-O2", "-fopenmp", "-fno-fast-math", "-ffp-contract=off", "-std=c11",
+                        "-Wall", "-shared", "-fPIC", "-o", tmp, SRC_PATH, "-lm"], check=True)
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class _Geom(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("pad0", ctypes.c_int32), ("pixel_mm", ctypes.c_double),
+                ("n_views", ctypes.c_int32), ("n_channels", ctypes.c_int32),
+                ("sad_mm", ctypes.c_double), ("sdd_mm", ctypes.c_double),
+                ("fan_half_angle_rad", ctypes.c_double), ("start_angle_rad", ctypes.c_double)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("lambda0", ctypes.c_double), ("lambda_inc", ctypes.c_double),
+                ("lambda_dec", ctypes.c_double), ("lambda_min", ctypes.c_double),
+                ("mu0_per_mm", ctypes.c_double), ("tv_eps_per_mm", ctypes.c_double)]
+
+
+class _State(ctypes.Structure):
+    _fields_ = [("n_done", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("lambda_", ctypes.c_double), ("f_prev", ctypes.c_double)]
+
+
+DEFAULT_PARAMS = dict(lambda0=0.01, lambda_inc=1e-4, lambda_dec=2e-4, lambda_min=1e-4,
+                      mu0_per_mm=0.005, tv_eps_per_mm=1e-5)
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build(force=False)
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        d, i32, i64 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64
+        L.oracle_project.argtypes = [P(_Geom), P(d), P(d), P(i32), i32]
+        L.oracle_backproject.argtypes = [P(_Geom), P(d), P(d), P(i32), i32]
+        L.oracle_count_pairs.argtypes = [P(_Geom), P(i32), i32, P(i64)]
+        L.oracle_ray_major.argtypes = [P(_Geom), P(i32)]
+        L.oracle_tv.argtypes = [i32, d, P(d), P(d), P(d)]
+        L.oracle_loglik.argtypes = [i64, P(d), P(d)]
+        L.oracle_loglik.restype = d
+        L.oracle_lambda_next.argtypes = [P(_Params), i32, d, d, d]
+        L.oracle_lambda_next.restype = d
+        L.oracle_initial_image.argtypes = [P(_Geom), d, P(d)]
+        L.oracle_os_iterate.argtypes = [P(_Geom), i32, d, P(_Params), P(d), d, P(d), i32, P(_State),
+                                        P(d), P(d)]
+        L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [i32]
+        _lib = L
+    return _lib
+
+
+def _g(geom) -> _Geom:
+    n, px, nv, nc, sad, sdd, fan, start = geom.as_tuple()
+    return _Geom(n, 0, px, nv, nc, sad, sdd, fan, start)
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with status {rc}")
+
+
+def _views(views):
+    if views is None:
+        return None, 0
+    v = np.ascontiguousarray(views, dtype=np.int32)
+    return v, len(v)
+
+
+def subset_views(n_views: int, subsets: int, s: int) -> np.ndarray:
+    """Views of subset s: every M-th view starting at s (equal-interval thinning)."""
+    return np.arange(s, n_views, subsets, dtype=np.int32)
+
+
+def project(geom, img, views=None) -> np.ndarray:
+    """Joseph line integrals of img (1/mm) for the listed views (default all): [n_sel][n_ch]."""
+    img = np.ascontiguousarray(img, dtype=np.float64).reshape(geom.n, geom.n)
+    v, nv = _views(views)
+    nsel = geom.n_views if v is None else nv
+    out = np.zeros((nsel, geom.n_channels), np.float64)
+    _check(lib().oracle_project(ctypes.byref(_g(geom)), _dp(img), _dp(out), None if v is None else _ip(v), nv),
+           "project")
+    return out
+
+
+def backproject(geom, sino, views=None) -> np.ndarray:
+    """Exact transpose of project (weights in mm): [N][N]."""
+    v, nv = _views(views)
+    nsel = geom.n_views if v is None else nv
+    sino = np.ascontiguousarray(sino, dtype=np.float64).reshape(nsel, geom.n_channels)
+    out = np.zeros((geom.n, geom.n), np.float64)
+    _check(lib().oracle_backproject(ctypes.byref(_g(geom)), _dp(sino), _dp(out),
+                                    None if v is None else _ip(v), nv), "backproject")
+    return out
+
+
+def count_pairs(geom, views=None) -> int:
+    """Number of (ray, in-image pixel) interpolation pairs over the listed views."""
+    v, nv = _views(views)
+    out = ctypes.c_int64(0)
+    _check(lib().oracle_count_pairs(ctypes.byref(_g(geom)), None if v is None else _ip(v), nv,
+                                    ctypes.byref(out)), "count_pairs")
+    return int(out.value)
+
+
+def ray_major(geom) -> np.ndarray:
+    """0 = x-major, 1 = y-major, [n_views][n_ch]."""
+    out = np.zeros((geom.n_views, geom.n_channels), np.int32)
+    _check(lib().oracle_ray_major(ctypes.byref(_g(geom)), _ip(out)), "ray_major")
+    return out
+
+
+def tv(img, eps: float):
+    """(TV value, g_R = -dTV/dmu) of an N x N image."""
+    img = np.ascontiguousarray(img, dtype=np.float64)
+    n = img.shape[0]
+    val = ctypes.c_double(0)
+    grad = np.zeros_like(img)
+    _check(lib().oracle_tv(n, eps, _dp(img), ctypes.byref(val), _dp(grad)), "tv")
+    return float(val.value), grad
+
+
+def loglik(ell, ytilde) -> float:
+    ell = np.ascontiguousarray(ell, dtype=np.float64).ravel()
+    yt = np.ascontiguousarray(ytilde, dtype=np.float64).ravel()
+    return float(lib().oracle_loglik(ell.size, _dp(ell), _dp(yt)))
+
+
+def lambda_next(first: bool, lam_prev: float, f_n: float, f_prev: float, params=None) -> float:
+    p = _Params(**(params or DEFAULT_PARAMS))
+    return float(lib().oracle_lambda_next(ctypes.byref(p), int(first), lam_prev, f_n, f_prev))
+
+
+def initial_image(geom, mu0_per_mm: float = 0.005) -> np.ndarray:
+    out = np.zeros((geom.n, geom.n), np.float64)
+    _check(lib().oracle_initial_image(ctypes.byref(_g(geom)), mu0_per_mm, _dp(out)), "initial_image")
+    return out
+
+
+class State:
+    """Resumable iteration state (sub-iterations done, lambda, previous f, flags)."""
+
+    def __init__(self):
+        self._s = _State(0, 0, 0.0, 0.0)
+
+    @property
+    def n_done(self):
+        return self._s.n_done
+
+    @property
+    def lam(self):
+        return self._s.lambda_
+
+    @property
+    def f_prev(self):
+        return self._s.f_prev
+
+    @property
+    def flags(self):
+        return self._s.flags
+
+
+def os_iterate(geom, subsets: int, beta: float, counts, i0: float, img=None, n_iter: int = 1,
+               state: State | None = None, lambda_schedule=None, params=None, want_trace=True,
+               allow_numeric=False):
+    """Ordered-subset TV gradient iteration (Eq. 3 with Eqs. 4-5).  Returns (img, trace[n_iter][2])."""
+    p = dict(DEFAULT_PARAMS)
+    if params:
+        p.update(params)
+    cp = _Params(**p)
+    counts = np.ascontiguousarray(counts, dtype=np.float64).reshape(geom.n_views, geom.n_channels)
+    if img is None:
+        img = initial_image(geom, p["mu0_per_mm"])
+    img = np.array(img, dtype=np.float64, order="C").reshape(geom.n, geom.n)
+    trace = np.zeros((n_iter, 2), np.float64) if want_trace else None
+    sched = None
+    if lambda_schedule is not None:
+        sched = np.ascontiguousarray(lambda_schedule, dtype=np.float64)
+        assert sched.size >= n_iter
+    rc = lib().oracle_os_iterate(ctypes.byref(_g(geom)), subsets, beta, ctypes.byref(cp), _dp(counts), i0,
+                                 _dp(img), n_iter, ctypes.byref(state._s) if state else None,
+                                 _dp(trace) if trace is not None else None,
+                                 _dp(sched) if sched is not None else None)
+    if rc == 3 and allow_numeric:
+        return img, trace
+    _check(rc, "os_iterate")
+    return img, trace
+
+
+def set_threads(n: int):
+    lib().oracle_set_num_threads(n)
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
