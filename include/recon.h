@@ -1,0 +1,198 @@
+/*
+ * recon.h — C ABI of the MI355X (gfx950) ordered-subset TV reconstruction library.
+ *
+ * Method: Ozaki et al., "Fast Statistical Iterative Reconstruction for MVCT in
+ * TomoTherapy" (arXiv:1903.10088).  The library maximises the posterior of
+ * section 2 (Eqs. 1-2: Poisson transmission likelihood plus a total-variation
+ * prior, image constrained positive) by the gradient iteration of Eq. 3 with
+ * the adaptive convergence parameter of Eqs. 4-5 (section 3.C.2), over
+ * equal-interval view subsets with the prior weight scaled by the thinning
+ * factor (section 3.D).  Every step runs in hand-written HIP kernels on the GPU.
+ *
+ * Conventions shared by all entry points
+ *  - Units: lengths in mm, attenuation in 1/mm.  The step rule works in the
+ *    paper's cm / (1/cm) internally; that conversion is hidden.
+ *  - Image: float32, n*n, row-major, element [j][i] at j*n + i, pixel centre
+ *    x = (i - (n-1)/2) * pixel_mm, y = (j - (n-1)/2) * pixel_mm.  The
+ *    reconstruction disc is x^2 + y^2 <= (n * pixel_mm / 2)^2; outside it the
+ *    iterate is held at zero.
+ *  - Fan beam: view v has its source at SAD * (cos b, sin b),
+ *    b = start_angle + 2 pi v / n_views (counter-clockwise); channel k lies on
+ *    an arc centred on the source at fan angle g = (k - (n_channels-1)/2) * dg,
+ *    dg = 2 * gamma_max / n_channels, gamma_max = fan_half_angle_rad or, when
+ *    that is 0, asin(R / SAD) with R = n * pixel_mm / 2; the ray leaves the
+ *    source towards angle b + pi + g.
+ *  - Sinogram: float32 [view][channel], row-major.  "subset s" (0 <= s < M)
+ *    means the views v with v mod M == s in increasing order; subset -1 means
+ *    all views in natural order.
+ *  - Device pointers: every float / double pointer marked d_ is device memory
+ *    owned by the caller, contiguous, and must stay valid until the work
+ *    queued on `stream` has finished.  `stream` is a hipStream_t (NULL = the
+ *    null stream).  Calls are asynchronous unless stated otherwise.
+ *  - Errors: every call returns a recon_status; nothing is thrown across the
+ *    ABI.  recon_last_error() returns a message for the last failure on the
+ *    calling thread.  A handle is not thread-safe; distinct handles may be used
+ *    from distinct threads and streams.
+ */
+#ifndef RECON_H
+#define RECON_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RECON_OK = 0,
+    RECON_INVALID_ARG = 1, /* null pointer, bad size, unsupported geometry or parameter */
+    RECON_DEVICE = 2,      /* a HIP runtime call failed */
+    RECON_NUMERIC = 3,     /* a non-finite squared difference was met during an iteration */
+    RECON_OOM = 4          /* device or host allocation failed */
+} recon_status;
+
+/* Fan-beam geometry.  Requirements: n >= 2, pixel_mm > 0, n_views >= 1,
+ * 1 <= n_channels <= 65535, sad_mm > sqrt(2) * n * pixel_mm / 2 (the whole
+ * pixel grid lies on the detector side of the source), full fan angle below
+ * 90 degrees.  sdd_mm is carried for completeness: on an arc detector centred
+ * on the source it does not change any line integral. */
+typedef struct {
+    int32_t n;
+    int32_t reserved0;
+    double pixel_mm;
+    int32_t n_views;
+    int32_t n_channels;
+    double sad_mm;
+    double sdd_mm;
+    double fan_half_angle_rad;
+    double start_angle_rad;
+} recon_geometry;
+
+/* Step rule and prior parameters (section 3.C).  Defaults (recon_default_params):
+ * lambda0 0.01, lambda_inc 1e-4 (Eq. 4), lambda_dec 2e-4 (Eq. 5), lambda_min 1e-4
+ * (floor; not in the paper), mu0_per_mm 0.005 (0.05/cm, section 3.C.2),
+ * tv_eps_per_mm 1e-5 (smoothing of the TV norm; not in the paper). */
+typedef struct {
+    double lambda0;
+    double lambda_inc;
+    double lambda_dec;
+    double lambda_min;
+    double mu0_per_mm;
+    double tv_eps_per_mm;
+} recon_params;
+
+/* Resumable iteration state (host memory).  A zero-filled struct with
+ * n_done = 0 starts a fresh run. */
+typedef struct {
+    int32_t n_done;  /* sub-iterations completed so far */
+    int32_t flags;   /* bit 0: a non-finite squared difference was met */
+    double lambda;   /* convergence parameter of the last sub-iteration */
+    double f_prev;   /* squared difference of the last sub-iteration */
+} recon_state;
+
+typedef struct recon_handle recon_handle;
+
+void recon_default_params(recon_params* out);
+const char* recon_status_string(recon_status s);
+const char* recon_last_error(void);
+
+/* Creates a handle for one geometry, M = `subsets` equal-interval subsets
+ * (section 3.D, 1 <= M <= n_views) and TV weight `beta` >= 0 (the alpha of
+ * Eq. 2; the update uses beta / M, section 3.D).  params NULL selects the
+ * defaults.  Builds the ray tables on the host in double precision, uploads
+ * them to the current HIP device and allocates the handle's workspace.  Blocks
+ * until the upload has finished.  *out receives the handle. */
+recon_status recon_create(const recon_geometry* geom, int32_t subsets, double beta,
+                          const recon_params* params, recon_handle** out);
+
+/* Frees the handle, its device tables, workspace and cached graphs.
+ * Synchronises the device first.  NULL is accepted. */
+recon_status recon_destroy(recon_handle* h);
+
+/* Joseph forward projection (section 4.C "reprojection"): d_sino = A d_img for
+ * the views of `subset` (-1 = all), in the order defined above.  d_img is
+ * [n][n] in 1/mm, d_sino is [n_sel][n_channels] line integrals
+ * (dimensionless).  A ray with |cos| >= |sin| of its direction is sampled once
+ * per image column, else once per row; each sample linearly interpolates the
+ * two nearest pixels across the sampling line and is weighted by the path
+ * length per column (row), pixel_mm / |cos| (|sin|); pixels outside the image
+ * are zero. */
+recon_status recon_project(recon_handle* h, const float* d_img, float* d_sino, int32_t subset, void* stream);
+
+/* Matched backprojection: d_img = A^T d_sino (overwrites d_img), the exact
+ * transpose of recon_project for the same subset, computed per pixel with
+ * no atomics (deterministic).  The likelihood gradient of section 2 is
+ * A^T (exp(-A mu) - y / I0). */
+recon_status recon_backproject(recon_handle* h, const float* d_sino, float* d_img, int32_t subset, void* stream);
+
+/* Gradient of the TV prior: d_grad = -dTV/dmu for
+ * TV(mu) = sum_r sqrt(dx_r^2 + dy_r^2 + eps^2), forward differences
+ * dx = mu[j][i+1] - mu[j][i], dy = mu[j+1][i] - mu[j][i], zero past the last
+ * column / row, eps = tv_eps_per_mm.  Dimensionless, [n][n]. */
+recon_status recon_tv_grad(recon_handle* h, const float* d_img, float* d_grad, void* stream);
+
+/* Runs n_iter ordered-subset sub-iterations (one sub-iteration = one
+ * "iteration" of the paper: one subset s = n mod M):
+ *   f_n      = mean over the subset's rays of (l_i - p_i)^2, l = A_s mu^(n),
+ *              p = ln(I0 / max(y, 1))                     (section 3.C.2)
+ *   lambda_n = lambda_0 at n = 0, else lambda_{n-1} + lambda_inc if
+ *              f_n < f_{n-1}, else lambda_{n-1} - lambda_dec; floor lambda_min
+ *                                                          (Eqs. 4-5)
+ *   mu^(n+1) = mask * max(0, mu^(n) + lambda_n [A_s^T (exp(-l) - y/I0)
+ *              + (beta/M) (-dTV/dmu)])   in cm and 1/cm    (Eq. 3)
+ * d_counts: [n_views][n_channels] transmission counts y (natural view order);
+ * i0: blank-scan counts (> 0).  d_img: in = mu^(n_done) in 1/mm (pass the
+ * homogeneous start from recon_initial_image for a fresh run), out = the
+ * final iterate.  state: NULL = fresh run (nothing returned), else read and
+ * updated (blocks until the run has finished).  d_trace: NULL or device
+ * double [n_iter][2] receiving (f_n, lambda_n).  d_lambda_schedule: NULL or
+ * device double [n_iter] replacing the step rule (a replay hook for parity
+ * checks; f is still computed).  Sub-iterations are replayed from cached
+ * HIP graphs, one per subset epoch.  Returns RECON_NUMERIC when state is
+ * given and a non-finite squared difference was met. */
+recon_status recon_os_iterate(recon_handle* h, const float* d_counts, float i0, float* d_img, int32_t n_iter,
+                              recon_state* state, double* d_trace, const double* d_lambda_schedule,
+                              void* stream);
+
+/* Writes the homogeneous start image (section 3.C.2): mu0_per_mm inside the
+ * reconstruction disc, 0 outside. */
+recon_status recon_initial_image(recon_handle* h, float* d_img, void* stream);
+
+/* Geometry queries (host, synchronous). */
+recon_status recon_subset_size(recon_handle* h, int32_t subset, int32_t* n_views_out);
+
+/* Per-kernel launch shapes (threads per ray segment split for the projector,
+ * pixel tile for the backprojector) are chosen by the library; this pins them
+ * for tuning and tests.  fp_segments in {1, 2, 4, 8, 16}; 0 keeps the current
+ * value.  Cached graphs are dropped. */
+recon_status recon_set_launch(recon_handle* h, int32_t fp_segments, int32_t reserved);
+
+
+/* Number of (ray, in-image pixel) interpolation pairs of `subset` (-1 = all
+ * views): the pixel reads of the projector and the sinogram reads of the
+ * backprojector, from the handle's own ray tables.  Host, synchronous. */
+recon_status recon_count_pairs(recon_handle* h, int32_t subset, int64_t* pairs);
+
+/* Measurement helper: runs n_iter (1..4096) sub-iterations of recon_os_iterate
+ * from d_img with direct launches (no graph, fresh step rule), records HIP
+ * events around every kernel on `stream`, and writes the mean duration in ms
+ * of the projector, the step-rule and the fused backprojection + update
+ * kernels to ms_out[0..2].  d_img is advanced as by recon_os_iterate.  Blocks
+ * until done. */
+recon_status recon_time_kernels(recon_handle* h, const float* d_counts, float i0, float* d_img, int32_t n_iter,
+                                double* ms_out, void* stream);
+
+/* Host-only self-check of the ray tables (no GPU needed): for every
+ * view_stride-th view and every pixel, counts the (pixel, ray) pairs with a
+ * nonzero interpolation weight that the backprojector's candidate window would
+ * miss (*missed, must be 0), the candidates it enumerates (*candidates) and
+ * the nonzero pairs (*pairs); also counts projector samples outside a ray's
+ * stored sample range into *missed. */
+recon_status recon_check_tables(const recon_geometry* geom, int32_t subsets, int32_t view_stride, int64_t* missed,
+                                int64_t* candidates, int64_t* pairs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RECON_H */

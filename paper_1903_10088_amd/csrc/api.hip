@@ -1,0 +1,632 @@
+// C ABI of the reconstruction library: handle creation (ray tables built on the
+// host in double precision), the single-operator entry points, and the
+// ordered-subset driver that replays each subset epoch from a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gather.h"
+#include "internal.h"
+#include "recon.h"
+
+using namespace recon;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+recon_status fail(recon_status s, const std::string& msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                                    \
+    do {                                                                                                 \
+        hipError_t _e = (expr);                                                                          \
+        if (_e != hipSuccess)                                                                            \
+            return fail(_e == hipErrorOutOfMemory ? RECON_OOM : RECON_DEVICE,                            \
+                        std::string(#expr) + ": " + hipGetErrorString(_e));                              \
+    } while (0)
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct Tables {
+    std::vector<ViewRec> views;
+    std::vector<RayGeo> rg;
+    std::vector<RayMeta> rm;
+    std::vector<int> perm, start, count;
+    Geo geo;
+};
+
+recon_status check_geometry(const recon_geometry* g, int M)
+{
+    if (!g) return fail(RECON_INVALID_ARG, "geometry is NULL");
+    if (g->n < 2 || g->n > 16384) return fail(RECON_INVALID_ARG, "n must be in [2, 16384]");
+    if (!(g->pixel_mm > 0)) return fail(RECON_INVALID_ARG, "pixel_mm must be > 0");
+    if (g->n_views < 1) return fail(RECON_INVALID_ARG, "n_views must be >= 1");
+    if (g->n_channels < 1 || g->n_channels > 65535) return fail(RECON_INVALID_ARG, "n_channels out of range");
+    if ((long)g->n_views * g->n_channels > (1L << 30)) return fail(RECON_INVALID_ARG, "too many rays");
+    const double half = 0.5 * g->n * g->pixel_mm;
+    if (!(g->sad_mm > std::sqrt(2.0) * half))
+        return fail(RECON_INVALID_ARG, "sad_mm must exceed the half-diagonal of the pixel grid");
+    const double gmax = g->fan_half_angle_rad > 0 ? g->fan_half_angle_rad : std::asin(half / g->sad_mm);
+    if (!(gmax < kPi / 4)) return fail(RECON_INVALID_ARG, "full fan angle must be below 90 degrees");
+    if (M < 1 || M > g->n_views) return fail(RECON_INVALID_ARG, "subsets must be in [1, n_views]");
+    return RECON_OK;
+}
+
+// Ray tables in subset order, computed in double precision and stored in float.
+recon_status build_tables(const recon_geometry* g, int M, Tables& T)
+{
+    const int N = g->n, nv = g->n_views, nch = g->n_channels;
+    const double dpx = g->pixel_mm;
+    const double c = 0.5 * (N - 1);
+    const double half = 0.5 * N * dpx;
+    const double gmax = g->fan_half_angle_rad > 0 ? g->fan_half_angle_rad : std::asin(half / g->sad_mm);
+    const double dg = 2.0 * gmax / nch;
+
+    T.perm.clear();
+    T.start.assign(M, 0);
+    T.count.assign(M, 0);
+    for (int s = 0; s < M; ++s) {
+        T.start[s] = (int)T.perm.size();
+        for (int v = s; v < nv; v += M) T.perm.push_back(v);
+        T.count[s] = (int)T.perm.size() - T.start[s];
+    }
+    T.views.assign(nv, ViewRec{});
+    T.rg.assign((size_t)nv * nch, RayGeo{});
+    T.rm.assign((size_t)nv * nch, RayMeta{});
+    std::vector<int> major(nch);
+    std::vector<double> a_tab((size_t)nv * nch), s_tab((size_t)nv * nch);
+    for (int q = 0; q < nv; ++q) {
+        const int v = T.perm[q];
+        const double beta = g->start_angle_rad + 2.0 * kPi * (double)v / (double)nv;
+        const double sx = g->sad_mm * std::cos(beta) / dpx, sy = g->sad_mm * std::sin(beta) / dpx;
+        for (int k = 0; k < nch; ++k) {
+            const double gam = ((double)k - 0.5 * (double)(nch - 1)) * dg;
+            const double dx = std::cos(beta + kPi + gam), dy = std::sin(beta + kPi + gam);
+            const int mj = std::fabs(dx) >= std::fabs(dy) ? 0 : 1;
+            major[k] = mj;
+            double slope, a, scale;
+            if (mj == 0) {  // crossing row u at column t: u = sy + (t - c - sx) * dy/dx + c
+                slope = dy / dx;
+                a = sy + (-c - sx) * slope + c;
+                scale = dpx / std::fabs(dx);
+            } else {        // crossing column u at row t
+                slope = dx / dy;
+                a = sx + (-c - sy) * slope + c;
+                scale = dpx / std::fabs(dy);
+            }
+            // sample lines t in [0, N-1] where -1 < u(t) < N (some in-image pixel has weight),
+            // widened by one line on each side
+            long lo = 1, hi = 0;
+            if (std::fabs(slope) < 1e-300) {
+                if (a > -1.0 && a < N) { lo = 0; hi = N - 1; }
+            } else {
+                double ta = (-1.0 - a) / slope, tb = ((double)N - a) / slope;
+                double tmin = std::max(std::min(ta, tb), -4.0), tmax = std::min(std::max(ta, tb), (double)N + 4);
+                lo = std::max(0L, (long)std::floor(tmin) - 1);
+                hi = std::min((long)N - 1, (long)std::ceil(tmax) + 1);
+            }
+            if (lo > hi) { lo = 1; hi = 0; }
+            const size_t r = (size_t)q * nch + k;
+            a_tab[r] = a;
+            s_tab[r] = slope;
+            T.rm[r] = RayMeta{(float)scale, (uint32_t)lo | ((uint32_t)hi << 15) | ((uint32_t)mj << 30)};
+        }
+        int flips = 0, k_split = nch;
+        for (int k = 1; k < nch; ++k)
+            if (major[k] != major[k - 1]) {
+                if (flips == 0) k_split = k;
+                ++flips;
+            }
+        if (flips > 1) return fail(RECON_INVALID_ARG, "a view's rays change major axis more than once");
+        ViewRec& V = T.views[q];
+        V.sx = (float)sx;
+        V.sy = (float)sy;
+        V.cb = (float)std::cos(beta);
+        V.sb = (float)std::sin(beta);
+        V.ray0 = q * nch;
+        V.k_split = k_split;
+        V.first_major = major[0];
+        V.nat_view = v;
+    }
+    // Split u(t) = a + t slope into (a_int + t s_hi) + (a_frac + t s_lo): with
+    // |a| + N < 2^B, s_hi a multiple of 2^-q and q = 23 - B, every lattice value
+    // a_int + t s_hi (t < N) and its difference with an integer is an exact
+    // float32, and t s_hi itself is exact because t < 2^B and s_hi has at most
+    // q + 1 significant bits.
+    double max_u = 0.0;
+    for (size_t r = 0; r < a_tab.size(); ++r) max_u = std::max(max_u, std::fabs(a_tab[r]) + N);
+    const int B = (int)std::ceil(std::log2(max_u + 2.0));
+    const int qbits = 23 - B;
+    if (qbits < 4) return fail(RECON_INVALID_ARG, "geometry too large for the float32 ray tables");
+    const double quantum = std::ldexp(1.0, -qbits);
+    for (size_t r = 0; r < a_tab.size(); ++r) {
+        const double a_int = std::floor(a_tab[r]);
+        const double s_hi = std::nearbyint(s_tab[r] / quantum) * quantum;
+        T.rg[r] = RayGeo{(float)a_int, (float)(a_tab[r] - a_int), (float)s_hi, (float)(s_tab[r] - s_hi)};
+    }
+    Geo& G = T.geo;
+    G.n = N;
+    G.P = N + 2 * PAD;
+    G.nv = nv;
+    G.nch = nch;
+    G.c = (float)c;
+    G.dg_inv = (float)(1.0 / dg);
+    G.kc = (float)(0.5 * (nch - 1));
+    // the candidate window is linear in the pixel offset; its curvature error is
+    // at most 1 / (2 r^2 dgamma) channels at source distance r (pixels)
+    const double rmin = (g->sad_mm - std::sqrt(2.0) * half) / dpx;
+    G.margin = (float)(0.05 + 1.0 / (rmin * rmin * dg));
+    const double max_sin = std::min(1.0, std::sqrt(2.0) * half / g->sad_mm);
+    const double max_tan = max_sin / std::sqrt(std::max(1e-12, 1.0 - max_sin * max_sin));
+    G.use_poly = max_tan <= 0.5 ? 1 : 0;
+    return RECON_OK;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+void drop_graphs(recon_handle* h)
+{
+    for (auto& gexec : h->graph)
+        if (gexec) {
+            (void)hipGraphExecDestroy(gexec);
+            gexec = nullptr;
+        }
+}
+
+StepRule rule_of(const recon_handle* h)
+{
+    return StepRule{h->p.lambda0, h->p.lambda_inc, h->p.lambda_dec, h->p.lambda_min};
+}
+
+UpdateConst update_const(const recon_handle* h)
+{
+    UpdateConst uc;
+    // The step of Eq. 3 is taken in cm and 1/cm: mu_cm = 10 mu_mm and the
+    // likelihood gradient per cm is a tenth of the per-mm one, so in mm units
+    // mu' = mu + lambda (g_L,mm / 100 + (beta / M) g_R / 10).
+    uc.c_l = 0.01f;
+    uc.c_r = (float)(h->beta / (10.0 * h->M));
+    uc.eps = (float)h->p.tv_eps_per_mm;
+    uc.pad = 0.0f;
+    return uc;
+}
+
+// One sub-iteration on subset s reading image buffer `in`, writing 1 - in.
+hipError_t enqueue_subiter(recon_handle* h, int s, int in, hipStream_t st)
+{
+    const Geo& G = h->geo;
+    const int q0 = h->subset_start[s], nq = h->subset_count[s];
+    const int ray0 = q0 * G.nch, nrays = nq * G.nch;
+    hipError_t e = launch_fp_os(G, h->fp_segments, h->d_img[in], h->d_imgT[in], h->d_raygeo, h->d_raymeta, ray0,
+                                nrays, h->d_yt, h->d_p, h->d_w, h->d_e, st);
+    if (e != hipSuccess) return e;
+    e = launch_lambda(h->d_e, ray0, nrays, h->d_state, rule_of(h), st);
+    if (e != hipSuccess) return e;
+    return launch_bp_update(G, h->d_views, h->d_raygeo, h->d_w, q0, nq, h->d_img[in], h->d_img[1 - in],
+                            h->d_imgT[1 - in], h->d_state, update_const(h), st);
+}
+
+// Graph of one full epoch (subsets 0..M-1) starting from buffer `parity`.
+recon_status get_graph(recon_handle* h, int parity, hipGraphExec_t* out)
+{
+    if (h->graph[parity]) {
+        *out = h->graph[parity];
+        return RECON_OK;
+    }
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    int in = parity;
+    for (int s = 0; s < h->M && err == hipSuccess; ++s) {
+        err = enqueue_subiter(h, s, in, h->cap_stream);
+        in = 1 - in;
+    }
+    hipError_t end = hipStreamEndCapture(h->cap_stream, &graph);
+    if (err != hipSuccess || end != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(RECON_DEVICE, std::string("graph capture failed: ") +
+                                      hipGetErrorString(err != hipSuccess ? err : end));
+    }
+    hipGraphExec_t exec = nullptr;
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(RECON_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
+    h->graph[parity] = exec;
+    *out = exec;
+    return RECON_OK;
+}
+
+void free_handle(recon_handle* h)
+{
+    if (!h) return;
+    drop_graphs(h);
+    void* ptrs[] = {h->d_views, h->d_raygeo, h->d_raymeta, h->d_img[0], h->d_img[1], h->d_imgT[0], h->d_imgT[1],
+                    h->d_yt,    h->d_p,      h->d_w,       h->d_e,      h->d_state};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (h->h_state) (void)hipHostFree(h->h_state);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    delete h;
+}
+
+}  // namespace
+
+extern "C" {
+
+void recon_default_params(recon_params* out)
+{
+    if (!out) return;
+    out->lambda0 = 0.01;
+    out->lambda_inc = 1e-4;
+    out->lambda_dec = 2e-4;
+    out->lambda_min = 1e-4;
+    out->mu0_per_mm = 0.005;
+    out->tv_eps_per_mm = 1e-5;
+}
+
+const char* recon_status_string(recon_status s)
+{
+    switch (s) {
+    case RECON_OK: return "ok";
+    case RECON_INVALID_ARG: return "invalid argument";
+    case RECON_DEVICE: return "device error";
+    case RECON_NUMERIC: return "non-finite value";
+    case RECON_OOM: return "out of memory";
+    }
+    return "unknown status";
+}
+
+const char* recon_last_error(void) { return g_last_error.c_str(); }
+
+recon_status recon_create(const recon_geometry* geom, int32_t subsets, double beta, const recon_params* params,
+                          recon_handle** out)
+{
+    if (!out) return fail(RECON_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    recon_status st = check_geometry(geom, subsets);
+    if (st != RECON_OK) return st;
+    if (!(beta >= 0) || !std::isfinite(beta)) return fail(RECON_INVALID_ARG, "beta must be finite and >= 0");
+    recon_params p;
+    recon_default_params(&p);
+    if (params) p = *params;
+    if (!(p.tv_eps_per_mm > 0) || !(p.lambda_min >= 0) || !(p.lambda0 > 0))
+        return fail(RECON_INVALID_ARG, "bad step-rule or TV parameters");
+
+    Tables T;
+    st = build_tables(geom, subsets, T);
+    if (st != RECON_OK) return st;
+
+    recon_handle* h = new (std::nothrow) recon_handle();
+    if (!h) return fail(RECON_OOM, "host allocation failed");
+    h->g = *geom;
+    h->p = p;
+    h->M = subsets;
+    h->beta = beta;
+    h->geo = T.geo;
+    h->perm = T.perm;
+    h->subset_start = T.start;
+    h->subset_count = T.count;
+    h->max_subset_views = *std::max_element(T.count.begin(), T.count.end());
+    h->fp_segments = geom->n >= 256 ? 8 : 4;
+    h->h_raygeo = T.rg;
+    h->h_raymeta = T.rm;
+
+    auto bail = [&](recon_status s) {
+        free_handle(h);
+        return s;
+    };
+#define H_TRY(expr)                                                                                       \
+    do {                                                                                                  \
+        hipError_t _e = (expr);                                                                           \
+        if (_e != hipSuccess)                                                                             \
+            return bail(fail(_e == hipErrorOutOfMemory ? RECON_OOM : RECON_DEVICE,                        \
+                             std::string(#expr) + ": " + hipGetErrorString(_e)));                         \
+    } while (0)
+
+    H_TRY(hipGetDevice(&h->device));
+    const size_t nrays = (size_t)geom->n_views * geom->n_channels;
+    const size_t pimg = (size_t)geom->n * h->geo.P * sizeof(float);
+    H_TRY(hipMalloc(&h->d_views, T.views.size() * sizeof(ViewRec)));
+    H_TRY(hipMalloc(&h->d_raygeo, nrays * sizeof(RayGeo)));
+    H_TRY(hipMalloc(&h->d_raymeta, nrays * sizeof(RayMeta)));
+    for (int b = 0; b < 2; ++b) {
+        H_TRY(hipMalloc(&h->d_img[b], pimg));
+        H_TRY(hipMalloc(&h->d_imgT[b], pimg));
+        H_TRY(hipMemset(h->d_img[b], 0, pimg));
+        H_TRY(hipMemset(h->d_imgT[b], 0, pimg));
+    }
+    H_TRY(hipMalloc(&h->d_yt, nrays * sizeof(float)));
+    H_TRY(hipMalloc(&h->d_p, nrays * sizeof(float)));
+    H_TRY(hipMalloc(&h->d_w, nrays * sizeof(float)));
+    H_TRY(hipMalloc(&h->d_e, nrays * sizeof(float)));
+    H_TRY(hipMalloc(&h->d_state, sizeof(DevState)));
+    H_TRY(hipHostMalloc(&h->h_state, sizeof(DevState), hipHostMallocDefault));
+    H_TRY(hipMemcpy(h->d_views, T.views.data(), T.views.size() * sizeof(ViewRec), hipMemcpyHostToDevice));
+    H_TRY(hipMemcpy(h->d_raygeo, T.rg.data(), nrays * sizeof(RayGeo), hipMemcpyHostToDevice));
+    H_TRY(hipMemcpy(h->d_raymeta, T.rm.data(), nrays * sizeof(RayMeta), hipMemcpyHostToDevice));
+    H_TRY(hipMemset(h->d_w, 0, nrays * sizeof(float)));
+    H_TRY(hipMemset(h->d_e, 0, nrays * sizeof(float)));
+    H_TRY(hipMemset(h->d_state, 0, sizeof(DevState)));
+    H_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    H_TRY(hipDeviceSynchronize());
+#undef H_TRY
+    *out = h;
+    return RECON_OK;
+}
+
+recon_status recon_destroy(recon_handle* h)
+{
+    if (!h) return RECON_OK;
+    (void)hipDeviceSynchronize();
+    free_handle(h);
+    return RECON_OK;
+}
+
+recon_status recon_subset_size(recon_handle* h, int32_t subset, int32_t* n_views_out)
+{
+    if (!h || !n_views_out) return fail(RECON_INVALID_ARG, "NULL argument");
+    if (subset == -1) {
+        *n_views_out = h->g.n_views;
+        return RECON_OK;
+    }
+    if (subset < 0 || subset >= h->M) return fail(RECON_INVALID_ARG, "subset out of range");
+    *n_views_out = h->subset_count[subset];
+    return RECON_OK;
+}
+
+recon_status recon_set_launch(recon_handle* h, int32_t fp_segments, int32_t reserved)
+{
+    (void)reserved;
+    if (!h) return fail(RECON_INVALID_ARG, "NULL handle");
+    if (fp_segments != 0) {
+        if (fp_segments != 1 && fp_segments != 2 && fp_segments != 4 && fp_segments != 8 && fp_segments != 16)
+            return fail(RECON_INVALID_ARG, "fp_segments must be 1, 2, 4, 8 or 16");
+        h->fp_segments = fp_segments;
+    }
+    drop_graphs(h);
+    return RECON_OK;
+}
+
+recon_status recon_initial_image(recon_handle* h, float* d_img, void* stream)
+{
+    if (!h || !d_img) return fail(RECON_INVALID_ARG, "NULL argument");
+    HIP_TRY(launch_initial_image(d_img, h->g.n, (float)h->p.mu0_per_mm, as_stream(stream)));
+    return RECON_OK;
+}
+
+recon_status recon_project(recon_handle* h, const float* d_img, float* d_sino, int32_t subset, void* stream)
+{
+    if (!h || !d_img || !d_sino) return fail(RECON_INVALID_ARG, "NULL argument");
+    if (subset < -1 || subset >= h->M) return fail(RECON_INVALID_ARG, "subset out of range");
+    hipStream_t s = as_stream(stream);
+    const Geo& G = h->geo;
+    HIP_TRY(launch_pad_image(d_img, h->d_img[0], h->d_imgT[0], G.n, G.P, s));
+    const int q0 = subset < 0 ? 0 : h->subset_start[subset];
+    const int nq = subset < 0 ? G.nv : h->subset_count[subset];
+    HIP_TRY(launch_fp_plain(G, h->fp_segments, h->d_img[0], h->d_imgT[0], h->d_raygeo, h->d_raymeta, h->d_views, q0,
+                            nq, subset < 0 ? 1 : 0, d_sino, s));
+    return RECON_OK;
+}
+
+recon_status recon_backproject(recon_handle* h, const float* d_sino, float* d_img, int32_t subset, void* stream)
+{
+    if (!h || !d_img || !d_sino) return fail(RECON_INVALID_ARG, "NULL argument");
+    if (subset < -1 || subset >= h->M) return fail(RECON_INVALID_ARG, "subset out of range");
+    hipStream_t s = as_stream(stream);
+    const Geo& G = h->geo;
+    const int q0 = subset < 0 ? 0 : h->subset_start[subset];
+    const int nq = subset < 0 ? G.nv : h->subset_count[subset];
+    HIP_TRY(launch_scale_sino(d_sino, h->d_raymeta, q0 * G.nch, nq * G.nch, G.nch, h->d_views, q0,
+                              subset < 0 ? 1 : 0, h->d_w, s));
+    HIP_TRY(launch_bp_plain(G, h->d_views, h->d_raygeo, h->d_w, q0, nq, d_img, s));
+    return RECON_OK;
+}
+
+recon_status recon_tv_grad(recon_handle* h, const float* d_img, float* d_grad, void* stream)
+{
+    if (!h || !d_img || !d_grad) return fail(RECON_INVALID_ARG, "NULL argument");
+    HIP_TRY(launch_tv_grad(d_img, d_grad, h->g.n, (float)h->p.tv_eps_per_mm, as_stream(stream)));
+    return RECON_OK;
+}
+
+recon_status recon_os_iterate(recon_handle* h, const float* d_counts, float i0, float* d_img, int32_t n_iter,
+                              recon_state* state, double* d_trace, const double* d_lambda_schedule, void* stream)
+{
+    if (!h || !d_counts || !d_img) return fail(RECON_INVALID_ARG, "NULL argument");
+    if (!(i0 > 0) || !std::isfinite(i0)) return fail(RECON_INVALID_ARG, "i0 must be finite and > 0");
+    if (n_iter < 0) return fail(RECON_INVALID_ARG, "n_iter must be >= 0");
+    if (state && state->n_done < 0) return fail(RECON_INVALID_ARG, "state->n_done must be >= 0");
+    hipStream_t s = as_stream(stream);
+    const Geo& G = h->geo;
+    const int n_done = state ? state->n_done : 0;
+
+    HIP_TRY(launch_prep_counts(d_counts, h->d_views, G.nv, G.nch, i0, h->d_yt, h->d_p, s));
+    HIP_TRY(launch_pad_image(d_img, h->d_img[0], h->d_imgT[0], G.n, G.P, s));
+    HIP_TRY(launch_set_state(h->d_state, state ? state->lambda : h->p.lambda0, state ? state->f_prev : 0.0, n_done,
+                             state ? state->flags : 0, d_trace, d_lambda_schedule, s));
+
+    int in = 0;
+    int n = 0;
+    while (n < n_iter) {
+        const int sub = (n_done + n) % h->M;
+        if (sub == 0 && n_iter - n >= h->M && !h->graph_bad) {
+            hipGraphExec_t exec = nullptr;
+            if (get_graph(h, in, &exec) == RECON_OK) {
+                HIP_TRY(hipGraphLaunch(exec, s));
+                n += h->M;
+                if (h->M & 1) in = 1 - in;
+                continue;
+            }
+            h->graph_bad = true;  // fall back to direct launches from now on
+        }
+        HIP_TRY(enqueue_subiter(h, sub, in, s));
+        in = 1 - in;
+        ++n;
+    }
+    HIP_TRY(launch_unpad_image(h->d_img[in], d_img, G.n, G.P, s));
+    if (state) {
+        HIP_TRY(hipMemcpyAsync(h->h_state, h->d_state, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        state->n_done = n_done + n_iter;
+        state->flags = h->h_state->flags;
+        state->lambda = h->h_state->lambda;
+        state->f_prev = h->h_state->f_prev;
+        if (state->flags & 1) return fail(RECON_NUMERIC, "non-finite squared difference");
+    }
+    return RECON_OK;
+}
+
+recon_status recon_count_pairs(recon_handle* h, int32_t subset, int64_t* pairs)
+{
+    if (!h || !pairs) return fail(RECON_INVALID_ARG, "NULL argument");
+    if (subset < -1 || subset >= h->M) return fail(RECON_INVALID_ARG, "subset out of range");
+    const Geo& G = h->geo;
+    const int q0 = subset < 0 ? 0 : h->subset_start[subset];
+    const int nq = subset < 0 ? G.nv : h->subset_count[subset];
+    int64_t total = 0;
+    for (size_t r = (size_t)q0 * G.nch; r < (size_t)(q0 + nq) * G.nch; ++r) {
+        const RayGeo g = h->h_raygeo[r];
+        for (int t = 0; t < G.n; ++t) {
+            const float fl = std::floor(ray_offset(g, (float)t, 0.0f));
+            total += (fl >= 0.0f && fl < (float)G.n) + (fl + 1.0f >= 0.0f && fl + 1.0f < (float)G.n);
+        }
+    }
+    *pairs = total;
+    return RECON_OK;
+}
+
+recon_status recon_time_kernels(recon_handle* h, const float* d_counts, float i0, float* d_img, int32_t n_iter,
+                                double* ms_out, void* stream)
+{
+    if (!h || !d_counts || !d_img || !ms_out) return fail(RECON_INVALID_ARG, "NULL argument");
+    if (n_iter < 1 || n_iter > 4096) return fail(RECON_INVALID_ARG, "n_iter must be in [1, 4096]");
+    if (!(i0 > 0)) return fail(RECON_INVALID_ARG, "i0 must be > 0");
+    hipStream_t s = as_stream(stream);
+    const Geo& G = h->geo;
+    HIP_TRY(launch_prep_counts(d_counts, h->d_views, G.nv, G.nch, i0, h->d_yt, h->d_p, s));
+    HIP_TRY(launch_pad_image(d_img, h->d_img[0], h->d_imgT[0], G.n, G.P, s));
+    HIP_TRY(launch_set_state(h->d_state, h->p.lambda0, 0.0, 0, 0, nullptr, nullptr, s));
+    std::vector<hipEvent_t> ev((size_t)n_iter * 4, nullptr);
+    recon_status status = RECON_OK;
+    auto cleanup = [&]() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            cleanup();
+            return fail(RECON_DEVICE, "hipEventCreate failed");
+        }
+    int in = 0;
+    for (int n = 0; n < n_iter && status == RECON_OK; ++n) {
+        const int sub = n % h->M;
+        const int q0 = h->subset_start[sub], nq = h->subset_count[sub];
+        const int ray0 = q0 * G.nch, nrays = nq * G.nch;
+        hipEvent_t* e = &ev[(size_t)n * 4];
+        hipError_t err = hipEventRecord(e[0], s);
+        if (err == hipSuccess)
+            err = launch_fp_os(G, h->fp_segments, h->d_img[in], h->d_imgT[in], h->d_raygeo, h->d_raymeta, ray0,
+                               nrays, h->d_yt, h->d_p, h->d_w, h->d_e, s);
+        if (err == hipSuccess) err = hipEventRecord(e[1], s);
+        if (err == hipSuccess) err = launch_lambda(h->d_e, ray0, nrays, h->d_state, rule_of(h), s);
+        if (err == hipSuccess) err = hipEventRecord(e[2], s);
+        if (err == hipSuccess)
+            err = launch_bp_update(G, h->d_views, h->d_raygeo, h->d_w, q0, nq, h->d_img[in], h->d_img[1 - in],
+                                   h->d_imgT[1 - in], h->d_state, update_const(h), s);
+        if (err == hipSuccess) err = hipEventRecord(e[3], s);
+        if (err != hipSuccess) status = fail(RECON_DEVICE, std::string("timing run: ") + hipGetErrorString(err));
+        in = 1 - in;
+    }
+    if (status == RECON_OK) {
+        hipError_t err = launch_unpad_image(h->d_img[in], d_img, G.n, G.P, s);
+        if (err == hipSuccess) err = hipStreamSynchronize(s);
+        if (err != hipSuccess) status = fail(RECON_DEVICE, std::string("timing run: ") + hipGetErrorString(err));
+    }
+    if (status == RECON_OK) {
+        double acc[3] = {0, 0, 0};
+        for (int n = 0; n < n_iter; ++n)
+            for (int k = 0; k < 3; ++k) {
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, ev[(size_t)n * 4 + k], ev[(size_t)n * 4 + k + 1]);
+                acc[k] += ms;
+            }
+        for (int k = 0; k < 3; ++k) ms_out[k] = acc[k] / n_iter;
+    }
+    cleanup();
+    return status;
+}
+
+// Host-only check of the gather's candidate windows (no GPU needed): for every
+// pixel and view, every ray of the view whose hat weight on the pixel is
+// nonzero must lie inside the window the kernel enumerates, and every ray's
+// sample range must hold all of its nonzero samples.  Returns the number of
+// misses in *missed and the enumerated candidate count in *candidates.
+recon_status recon_check_tables(const recon_geometry* geom, int32_t subsets, int32_t view_stride, int64_t* missed,
+                                int64_t* candidates, int64_t* pairs)
+{
+    if (!missed || !candidates || !pairs) return fail(RECON_INVALID_ARG, "NULL argument");
+    recon_status st = check_geometry(geom, subsets);
+    if (st != RECON_OK) return st;
+    Tables T;
+    st = build_tables(geom, subsets, T);
+    if (st != RECON_OK) return st;
+    const Geo& G = T.geo;
+    const int N = G.n, nch = G.nch;
+    if (view_stride < 1) view_stride = 1;
+    int64_t miss = 0, cand = 0, npairs = 0;
+    for (int q = 0; q < G.nv; q += view_stride) {
+        const ViewRec& v = T.views[q];
+        // sample ranges: weight outside [lo, hi] must vanish
+        for (int k = 0; k < nch; ++k) {
+            const RayGeo g = T.rg[(size_t)q * nch + k];
+            const uint32_t pk = T.rm[(size_t)q * nch + k].packed;
+            const int lo = (int)(pk & 0x7fffu), hi = (int)((pk >> 15) & 0x7fffu);
+            for (int t = 0; t < N; ++t) {
+                const float u = ray_offset(g, (float)t, 0.0f);
+                const bool touches = u > -1.0f && u < (float)N;
+                if (touches && (t < lo || t > hi)) ++miss;
+            }
+        }
+        int x0, x1, y0, y1;
+        major_intervals(v, nch, x0, x1, y0, y1);
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                const PixelView pv = pixel_view(G, v, (float)i - G.c, (float)j - G.c);
+                int lo, hi;
+                candidate_range(pv.kp, pv.hwx, x0, x1, lo, hi);
+                if (x0 < x1) cand += std::max(0, hi - lo + 1);
+                for (int k = x0; k < x1; ++k) {
+                    const float wgt = hat(ray_offset(T.rg[(size_t)q * nch + k], (float)i, (float)j));
+                    if (wgt > 0.0f) {
+                        ++npairs;
+                        if (k < lo || k > hi) ++miss;
+                    }
+                }
+                candidate_range(pv.kp, pv.hwy, y0, y1, lo, hi);
+                if (y0 < y1) cand += std::max(0, hi - lo + 1);
+                for (int k = y0; k < y1; ++k) {
+                    const float wgt = hat(ray_offset(T.rg[(size_t)q * nch + k], (float)j, (float)i));
+                    if (wgt > 0.0f) {
+                        ++npairs;
+                        if (k < lo || k > hi) ++miss;
+                    }
+                }
+            }
+    }
+    *missed = miss;
+    *candidates = cand;
+    *pairs = npairs;
+    return RECON_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,153 @@
+// Internal layout of the reconstruction library: device tables, workspace and
+// kernel launchers.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "recon.h"
+
+namespace recon {
+
+// Images live in the workspace with two zero columns on each side of every row
+// (row stride P = n + 4, element (row, col) at row * P + col + PAD).  The
+// projector clamps its interpolation index to [-PAD, n] so that every read
+// stays inside the row and reads zero outside the image.
+constexpr int PAD = 2;
+
+// One record per view, in subset order (subset 0's views first).  Kernels read
+// it at a wave-uniform index, so the loads go through the scalar cache.
+struct ViewRec {
+    float sx, sy;      // source position in pixel units, relative to the grid centre
+    float cb, sb;      // cos / sin of the source angle
+    int32_t ray0;      // index of channel 0 of this view in the subset-ordered ray arrays
+    int32_t k_split;   // channels [0, k_split) have major axis first_major, the rest the other
+    int32_t first_major;  // 0 = x-major (sampled per column), 1 = y-major (per row)
+    int32_t nat_view;  // natural view index
+};
+
+// Per-ray sampling line: along the ray's major axis, sample line t (a column
+// for x-major rays, a row for y-major rays) is crossed at continuous index
+// u(t) = a + t * slope on the other axis.  In float32 an index near 512 only
+// resolves 6e-5 pixel, so u is split into a lattice part and a small residual:
+//   u(t) = (a_int + t * s_hi) + (a_frac + t * s_lo),
+// with a_int an integer and s_hi a multiple of 2^-q chosen so that the first
+// bracket, and its difference with any integer, is exact in float32; only the
+// residual (|.| ~ 1) is rounded.
+struct RayGeo {
+    float a_int, a_frac, s_hi, s_lo;
+};
+
+// Per-ray constants of the projector: path length per sample line (mm) and the
+// packed sample range lo | hi << 15 | major << 30 (lo > hi: the ray misses).
+struct RayMeta {
+    float scale;
+    uint32_t packed;
+};
+
+// Device-resident iteration state, read and written only by kernels during a
+// run, so that captured graphs replay without host involvement.
+struct DevState {
+    double lambda;          // lambda_n of the current sub-iteration (read by the update)
+    double f_prev;          // f of the previous sub-iteration
+    int32_t n_global;       // global index n of the next sub-iteration
+    int32_t it;             // index into trace / schedule of the next sub-iteration
+    int32_t flags;          // bit 0: non-finite f met
+    int32_t pad;
+    double* trace;          // [n_iter][2] or null
+    const double* schedule; // [n_iter] or null
+};
+
+// Step-rule constants handed to the lambda kernel by value.
+struct StepRule {
+    double lambda0, inc, dec, lmin;
+};
+
+// Constants of the fused backprojection + TV + update kernel.
+struct UpdateConst {
+    float c_l;     // multiplies the likelihood gradient (mm): 1/100 for the cm-unit step
+    float c_r;     // multiplies -dTV/dmu: beta / (10 M)
+    float eps;     // TV smoothing (1/mm)
+    float pad;
+};
+
+struct Geo {
+    int n, P, nv, nch;
+    float c;         // (n - 1) / 2
+    float dg_inv;    // 1 / dgamma
+    float kc;        // (n_channels - 1) / 2
+    float margin;    // channel margin of the gather's candidate window
+    int use_poly;    // 1: |tan| of every pixel's fan angle is small enough for the polynomial atan
+};
+
+}  // namespace recon
+
+struct recon_handle {
+    recon_geometry g;
+    recon_params p;
+    int M;
+    double beta;
+    recon::Geo geo;
+    int device;
+
+    std::vector<int> subset_start;  // first subset-ordered view of subset s
+    std::vector<int> subset_count;  // views in subset s
+    std::vector<int> perm;          // subset-ordered view -> natural view
+    int max_subset_views;
+
+    // device tables
+    recon::ViewRec* d_views = nullptr;
+    recon::RayGeo* d_raygeo = nullptr;
+    recon::RayMeta* d_raymeta = nullptr;
+
+    // workspace
+    float* d_img[2] = {nullptr, nullptr};   // padded [n][P]
+    float* d_imgT[2] = {nullptr, nullptr};  // padded transposed [n][P]
+    float* d_yt = nullptr;                  // y / I0, subset order [nv * nch]
+    float* d_p = nullptr;                   // ln(I0 / max(y, 1)), subset order
+    float* d_w = nullptr;                   // weighted residual per ray, subset order
+    float* d_e = nullptr;                   // squared difference per ray, subset order
+    recon::DevState* d_state = nullptr;
+    recon::DevState* h_state = nullptr;     // pinned read-back
+
+    int fp_segments = 8;
+
+    // host copies of the ray tables (pair counts, checks)
+    std::vector<recon::RayGeo> h_raygeo;
+    std::vector<recon::RayMeta> h_raymeta;
+
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    bool graph_bad = false;
+};
+
+namespace recon {
+
+// kernels.hip
+hipError_t launch_pad_image(const float* src, float* dst, float* dstT, int n, int P, hipStream_t s);
+hipError_t launch_unpad_image(const float* src, float* dst, int n, int P, hipStream_t s);
+hipError_t launch_initial_image(float* dst, int n, float mu0, hipStream_t s);
+hipError_t launch_prep_counts(const float* counts, const ViewRec* views, int nv, int nch, float i0, float* yt,
+                              float* p, hipStream_t s);
+hipError_t launch_scale_sino(const float* sino, const RayMeta* meta, int ray0, int nrays, int nch,
+                             const ViewRec* views, int q0, int natural_rows, float* w, hipStream_t s);
+hipError_t launch_fp_plain(const Geo& geo, int segments, const float* img, const float* imgT, const RayGeo* rg,
+                           const RayMeta* rm, const ViewRec* views, int q0, int nq, int natural_rows, float* out,
+                           hipStream_t s);
+hipError_t launch_fp_os(const Geo& geo, int segments, const float* img, const float* imgT, const RayGeo* rg,
+                        const RayMeta* rm, int ray0, int nrays, const float* yt, const float* p, float* w, float* e,
+                        hipStream_t s);
+hipError_t launch_lambda(const float* e, int ray0, int nrays, DevState* st, StepRule rule, hipStream_t s);
+hipError_t launch_set_state(DevState* st, double lambda, double f_prev, int n_global, int flags, double* trace,
+                            const double* schedule, hipStream_t s);
+hipError_t launch_bp_plain(const Geo& geo, const ViewRec* views, const RayGeo* rg, const float* w, int q0, int nq,
+                           float* out, hipStream_t s);
+hipError_t launch_bp_update(const Geo& geo, const ViewRec* views, const RayGeo* rg, const float* w, int q0, int nq,
+                            const float* img, float* img_out, float* imgT_out, const DevState* st, UpdateConst uc,
+                            hipStream_t s);
+hipError_t launch_tv_grad(const float* img, float* grad, int n, float eps, hipStream_t s);
+
+}  // namespace recon

@@ -1,0 +1,270 @@
+"""Python binding of librecon.so (ctypes).
+
+Argument marshalling only: every step of the reconstruction runs in the
+library's HIP kernels.  Device buffers are torch CUDA tensors (float32,
+contiguous); the library is handed their data pointers and torch's current
+stream.  There is no fallback: if librecon.so is missing or fails to load,
+importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librecon.so")
+
+RECON_OK, RECON_INVALID_ARG, RECON_DEVICE, RECON_NUMERIC, RECON_OOM = range(5)
+
+
+class ReconError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: status {status} ({msg})")
+        self.status = status
+
+
+class Geometry_c(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("pixel_mm", ctypes.c_double),
+                ("n_views", ctypes.c_int32), ("n_channels", ctypes.c_int32),
+                ("sad_mm", ctypes.c_double), ("sdd_mm", ctypes.c_double),
+                ("fan_half_angle_rad", ctypes.c_double), ("start_angle_rad", ctypes.c_double)]
+
+
+class Params_c(ctypes.Structure):
+    _fields_ = [("lambda0", ctypes.c_double), ("lambda_inc", ctypes.c_double), ("lambda_dec", ctypes.c_double),
+                ("lambda_min", ctypes.c_double), ("mu0_per_mm", ctypes.c_double),
+                ("tv_eps_per_mm", ctypes.c_double)]
+
+
+class State_c(ctypes.Structure):
+    _fields_ = [("n_done", ctypes.c_int32), ("flags", ctypes.c_int32), ("lambda_", ctypes.c_double),
+                ("f_prev", ctypes.c_double)]
+
+
+EXPORTS = ["recon_default_params", "recon_status_string", "recon_last_error", "recon_create", "recon_destroy",
+           "recon_project", "recon_backproject", "recon_tv_grad", "recon_os_iterate", "recon_initial_image",
+           "recon_subset_size", "recon_set_launch", "recon_check_tables", "recon_count_pairs",
+           "recon_time_kernels"]
+
+_lib = None
+
+
+def lib():
+    """Loads librecon.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_1903_10088_amd/build.py (or "
+                              "__graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P, vp = ctypes.POINTER, ctypes.c_void_p
+        i32, i64, d, f = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_float
+        L.recon_default_params.argtypes = [P(Params_c)]
+        L.recon_default_params.restype = None
+        L.recon_status_string.argtypes = [ctypes.c_int]
+        L.recon_status_string.restype = ctypes.c_char_p
+        L.recon_last_error.restype = ctypes.c_char_p
+        L.recon_create.argtypes = [P(Geometry_c), i32, d, P(Params_c), P(vp)]
+        L.recon_destroy.argtypes = [vp]
+        L.recon_project.argtypes = [vp, vp, vp, i32, vp]
+        L.recon_backproject.argtypes = [vp, vp, vp, i32, vp]
+        L.recon_tv_grad.argtypes = [vp, vp, vp, vp]
+        L.recon_os_iterate.argtypes = [vp, vp, f, vp, i32, P(State_c), vp, vp, vp]
+        L.recon_initial_image.argtypes = [vp, vp, vp]
+        L.recon_subset_size.argtypes = [vp, i32, P(i32)]
+        L.recon_set_launch.argtypes = [vp, i32, i32]
+        L.recon_check_tables.argtypes = [P(Geometry_c), i32, i32, P(i64), P(i64), P(i64)]
+        L.recon_count_pairs.argtypes = [vp, i32, P(i64)]
+        L.recon_time_kernels.argtypes = [vp, vp, f, vp, i32, P(d), vp]
+        for name in EXPORTS:
+            getattr(L, name)
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != RECON_OK:
+        msg = lib().recon_last_error().decode(errors="replace")
+        raise ReconError(rc, where, msg)
+
+
+def geometry_c(g) -> Geometry_c:
+    """From a phantom.Geometry-like object (n, pixel_mm, n_views, n_channels, sad_mm, sdd_mm, ...)."""
+    return Geometry_c(int(g.n), 0, float(g.pixel_mm), int(g.n_views), int(g.n_channels), float(g.sad_mm),
+                      float(g.sdd_mm), float(g.fan_half_angle_rad), float(g.start_angle_rad))
+
+
+def default_params() -> dict:
+    p = Params_c()
+    lib().recon_default_params(ctypes.byref(p))
+    return {name: getattr(p, name) for name, _ in Params_c._fields_}
+
+
+def check_tables(g, subsets: int, view_stride: int = 1):
+    """Host-only check of the gather's candidate windows: (missed, candidates, pairs)."""
+    m, c, p = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().recon_check_tables(ctypes.byref(geometry_c(g)), subsets, view_stride, ctypes.byref(m),
+                                    ctypes.byref(c), ctypes.byref(p)), "recon_check_tables")
+    return int(m.value), int(c.value), int(p.value)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype=None, shape=None, name="tensor"):
+    torch = _torch()
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class State:
+    """Resumable iteration state (mirrors recon_state)."""
+
+    def __init__(self, n_done: int = 0, lam: float = 0.0, f_prev: float = 0.0, flags: int = 0):
+        self.c = State_c(n_done, flags, lam, f_prev)
+
+    n_done = property(lambda self: self.c.n_done)
+    lam = property(lambda self: self.c.lambda_)
+    f_prev = property(lambda self: self.c.f_prev)
+    flags = property(lambda self: self.c.flags)
+
+
+class Recon:
+    """One geometry, M subsets and TV weight beta on the current HIP device."""
+
+    def __init__(self, geometry, subsets: int, beta: float, params: dict | None = None):
+        self.geometry = geometry
+        self.subsets = int(subsets)
+        self.beta = float(beta)
+        p = default_params()
+        if params:
+            p.update(params)
+        self.params = p
+        pc = Params_c(**p)
+        h = ctypes.c_void_p()
+        _check(lib().recon_create(ctypes.byref(geometry_c(geometry)), self.subsets, self.beta, ctypes.byref(pc),
+                                  ctypes.byref(h)), "recon_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().recon_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ----------------------------------------------------------
+    @property
+    def n(self):
+        return self.geometry.n
+
+    def subset_size(self, subset: int) -> int:
+        out = ctypes.c_int32()
+        _check(lib().recon_subset_size(self._h, subset, ctypes.byref(out)), "recon_subset_size")
+        return int(out.value)
+
+    def count_pairs(self, subset: int = -1) -> int:
+        out = ctypes.c_int64()
+        _check(lib().recon_count_pairs(self._h, subset, ctypes.byref(out)), "recon_count_pairs")
+        return int(out.value)
+
+    def time_kernels(self, counts, i0: float, img, n_iter: int):
+        """Mean kernel durations (ms) over n_iter direct-launch sub-iterations: (fp, lambda, bp_update)."""
+        torch = _torch()
+        g = self.geometry
+        out = (ctypes.c_double * 3)()
+        _check(lib().recon_time_kernels(self._h, _ptr(counts, torch.float32, (g.n_views, g.n_channels), "counts"),
+                                        float(i0), _ptr(img, torch.float32, (g.n, g.n), "img"), int(n_iter), out,
+                                        _stream()), "recon_time_kernels")
+        return tuple(out)
+
+    def set_launch(self, fp_segments: int = 0):
+        _check(lib().recon_set_launch(self._h, fp_segments, 0), "recon_set_launch")
+
+    # -- operators ---------------------------------------------------------
+    def project(self, img, subset: int = -1, out=None):
+        torch = _torch()
+        g = self.geometry
+        rows = self.subset_size(subset)
+        if out is None:
+            out = torch.empty((rows, g.n_channels), dtype=torch.float32, device=img.device)
+        _check(lib().recon_project(self._h, _ptr(img, torch.float32, (g.n, g.n), "img"),
+                                   _ptr(out, torch.float32, (rows, g.n_channels), "sino"), subset, _stream()),
+               "recon_project")
+        return out
+
+    def backproject(self, sino, subset: int = -1, out=None):
+        torch = _torch()
+        g = self.geometry
+        rows = self.subset_size(subset)
+        if out is None:
+            out = torch.empty((g.n, g.n), dtype=torch.float32, device=sino.device)
+        _check(lib().recon_backproject(self._h, _ptr(sino, torch.float32, (rows, g.n_channels), "sino"),
+                                       _ptr(out, torch.float32, (g.n, g.n), "img"), subset, _stream()),
+               "recon_backproject")
+        return out
+
+    def tv_grad(self, img, out=None):
+        torch = _torch()
+        g = self.geometry
+        if out is None:
+            out = torch.empty_like(img)
+        _check(lib().recon_tv_grad(self._h, _ptr(img, torch.float32, (g.n, g.n), "img"),
+                                   _ptr(out, torch.float32, (g.n, g.n), "grad"), _stream()), "recon_tv_grad")
+        return out
+
+    def initial_image(self, device="cuda"):
+        torch = _torch()
+        out = torch.empty((self.n, self.n), dtype=torch.float32, device=device)
+        return self.initial_image_(out)
+
+    def initial_image_(self, out):
+        """Writes the homogeneous start image into `out` ([n][n] float32) and returns it."""
+        torch = _torch()
+        _check(lib().recon_initial_image(self._h, _ptr(out, torch.float32, (self.n, self.n), "img"), _stream()),
+               "recon_initial_image")
+        return out
+
+    def os_iterate(self, counts, i0: float, img=None, n_iter: int = 1, state: State | None = None,
+                   trace: bool = False, lambda_schedule=None):
+        """Runs n_iter sub-iterations in place on img (created from the homogeneous start if None).
+
+        Returns (img, trace) with trace a float64 CUDA tensor [n_iter][2] of (f_n, lambda_n) or None."""
+        torch = _torch()
+        g = self.geometry
+        if img is None:
+            img = self.initial_image(counts.device)
+        tr = torch.empty((n_iter, 2), dtype=torch.float64, device=counts.device) if trace else None
+        sched = None
+        if lambda_schedule is not None:
+            sched = torch.as_tensor(np.asarray(lambda_schedule, dtype=np.float64)).to(counts.device)
+            if sched.numel() < n_iter:
+                raise ValueError("lambda_schedule shorter than n_iter")
+        _check(lib().recon_os_iterate(self._h, _ptr(counts, torch.float32, (g.n_views, g.n_channels), "counts"),
+                                      float(i0), _ptr(img, torch.float32, (g.n, g.n), "img"), int(n_iter),
+                                      ctypes.byref(state.c) if state is not None else None,
+                                      _ptr(tr, torch.float64, None, "trace"),
+                                      _ptr(sched, torch.float64, None, "lambda_schedule"), _stream()),
+               "recon_os_iterate")
+        return img, tr
