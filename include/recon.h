@@ -161,11 +161,14 @@ recon_status recon_initial_image(recon_handle* h, float* d_img, void* stream);
 /* Geometry queries (host, synchronous). */
 recon_status recon_subset_size(recon_handle* h, int32_t subset, int32_t* n_views_out);
 
-/* Per-kernel launch shapes (threads per ray segment split for the projector,
- * pixel tile for the backprojector) are chosen by the library; this pins them
- * for tuning and tests.  fp_segments in {1, 2, 4, 8, 16}; 0 keeps the current
- * value.  Cached graphs are dropped. */
-recon_status recon_set_launch(recon_handle* h, int32_t fp_segments, int32_t reserved);
+/* Launch shapes are chosen by the library; this pins them for tuning and
+ * tests.  fp_segments: threads sharing one ray in the projector, in
+ * {1, 2, 4, 8, 16}.  bp_variant: 1 = one pixel per thread, candidates read
+ * from global memory; 2 = one pixel per thread, candidates staged per 16x16
+ * tile in LDS; 3, 4, 5 = LDS-staged with 1x2, 2x1, 2x2 pixels per thread.  0
+ * keeps the current value.  Every choice gives bitwise identical results.
+ * Cached graphs are dropped. */
+recon_status recon_set_launch(recon_handle* h, int32_t fp_segments, int32_t bp_variant);
 
 
 /* Number of (ray, in-image pixel) interpolation pairs of `subset` (-1 = all
@@ -173,12 +176,13 @@ recon_status recon_set_launch(recon_handle* h, int32_t fp_segments, int32_t rese
  * backprojector, from the handle's own ray tables.  Host, synchronous. */
 recon_status recon_count_pairs(recon_handle* h, int32_t subset, int64_t* pairs);
 
-/* Measurement helper: runs n_iter (1..4096) sub-iterations of recon_os_iterate
- * from d_img with direct launches (no graph, fresh step rule), records HIP
- * events around every kernel on `stream`, and writes the mean duration in ms
- * of the projector, the step-rule and the fused backprojection + update
- * kernels to ms_out[0..2].  d_img is advanced as by recon_os_iterate.  Blocks
- * until done. */
+/* Measurement helper: from d_img (read only) runs one sub-iteration of every
+ * subset, then launches each kernel of a sub-iteration n_iter (1..4096) times
+ * back to back on `stream` (subsets in turn) between two HIP events, and
+ * writes the mean time per launch in ms of the projector to ms_out[0] and of
+ * the fused step-rule + backprojection + update kernel to ms_out[2]
+ * (ms_out[1] = 0: the step rule has no launch of its own).  Blocks until
+ * done. */
 recon_status recon_time_kernels(recon_handle* h, const float* d_counts, float i0, float* d_img, int32_t n_iter,
                                 double* ms_out, void* stream);
 

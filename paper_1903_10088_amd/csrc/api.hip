@@ -137,6 +137,7 @@ recon_status build_tables(const recon_geometry* g, int M, Tables& T)
         V.k_split = k_split;
         V.first_major = major[0];
         V.nat_view = v;
+        V.dist = (float)(g->sad_mm / dpx);
     }
     // Split u(t) = a + t slope into (a_int + t s_hi) + (a_frac + t s_lo): with
     // |a| + N < 2^B, s_hi a multiple of 2^-q and q = 23 - B, every lattice value
@@ -165,10 +166,14 @@ recon_status build_tables(const recon_geometry* g, int M, Tables& T)
     // the candidate window is linear in the pixel offset; its curvature error is
     // at most 1 / (2 r^2 dgamma) channels at source distance r (pixels)
     const double rmin = (g->sad_mm - std::sqrt(2.0) * half) / dpx;
-    G.margin = (float)(0.05 + 1.0 / (rmin * rmin * dg));
     const double max_sin = std::min(1.0, std::sqrt(2.0) * half / g->sad_mm);
     const double max_tan = max_sin / std::sqrt(std::max(1e-12, 1.0 - max_sin * max_sin));
-    G.use_poly = max_tan <= 0.5 ? 1 : 0;
+    G.use_poly = max_tan <= 0.45 ? 1 : 0;
+    // atan series error bound (in channels) when the polynomial is used
+    const double poly_err = G.use_poly ? std::pow(max_tan, 13) / 13.0 / dg : 0.0;
+    // (the curvature term covers offsets up to 1.5 px across and 0.5 px along the
+    // sampling line, as used by the gather over 2x2 pixel blocks)
+    G.margin = (float)(0.05 + 2.5 / (rmin * rmin * dg) + poly_err);
     return RECON_OK;
 }
 
@@ -201,19 +206,42 @@ UpdateConst update_const(const recon_handle* h)
     return uc;
 }
 
-// One sub-iteration on subset s reading image buffer `in`, writing 1 - in.
-hipError_t enqueue_subiter(recon_handle* h, int s, int in, hipStream_t st)
+UpdateArgs update_args(recon_handle* h, int s, int in)
+{
+    UpdateArgs a;
+    a.views = h->d_views;
+    a.rg = h->d_raygeo;
+    a.w = h->d_w;
+    a.q0 = h->subset_start[s];
+    a.nq = h->subset_count[s];
+    a.part = h->d_part;
+    a.nrays = a.nq * h->geo.nch;
+    a.st_in = h->d_state + in;
+    a.st_out = h->d_state + (1 - in);
+    a.rule = rule_of(h);
+    a.img = h->d_img[in];
+    a.img_out = h->d_img[1 - in];
+    a.imgT_out = h->d_imgT[1 - in];
+    a.uc = update_const(h);
+    return a;
+}
+
+hipError_t enqueue_fp(recon_handle* h, int s, int in, hipStream_t st)
 {
     const Geo& G = h->geo;
-    const int q0 = h->subset_start[s], nq = h->subset_count[s];
-    const int ray0 = q0 * G.nch, nrays = nq * G.nch;
-    hipError_t e = launch_fp_os(G, h->fp_segments, h->d_img[in], h->d_imgT[in], h->d_raygeo, h->d_raymeta, ray0,
-                                nrays, h->d_yt, h->d_p, h->d_w, h->d_e, st);
+    const int ray0 = h->subset_start[s] * G.nch, nrays = h->subset_count[s] * G.nch;
+    return launch_fp_os(G, h->fp_segments, h->d_img[in], h->d_imgT[in], h->d_raygeo, h->d_raymeta, ray0, nrays,
+                        h->d_yt, h->d_p, h->d_w, h->d_part, st);
+}
+
+// One sub-iteration on subset s reading image and state buffers `in`, writing
+// 1 - in: the projector with its residual epilogue, then the fused step rule,
+// backprojection, TV gradient and update.
+hipError_t enqueue_subiter(recon_handle* h, int s, int in, hipStream_t st)
+{
+    hipError_t e = enqueue_fp(h, s, in, st);
     if (e != hipSuccess) return e;
-    e = launch_lambda(h->d_e, ray0, nrays, h->d_state, rule_of(h), st);
-    if (e != hipSuccess) return e;
-    return launch_bp_update(G, h->d_views, h->d_raygeo, h->d_w, q0, nq, h->d_img[in], h->d_img[1 - in],
-                            h->d_imgT[1 - in], h->d_state, update_const(h), st);
+    return launch_bp_update(h->geo, h->bp_variant, update_args(h, s, in), st);
 }
 
 // Graph of one full epoch (subsets 0..M-1) starting from buffer `parity`.
@@ -251,7 +279,7 @@ void free_handle(recon_handle* h)
     if (!h) return;
     drop_graphs(h);
     void* ptrs[] = {h->d_views, h->d_raygeo, h->d_raymeta, h->d_img[0], h->d_img[1], h->d_imgT[0], h->d_imgT[1],
-                    h->d_yt,    h->d_p,      h->d_w,       h->d_e,      h->d_state};
+                    h->d_yt,    h->d_p,      h->d_w,       h->d_part,   h->d_state};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (h->h_state) (void)hipHostFree(h->h_state);
@@ -348,15 +376,16 @@ recon_status recon_create(const recon_geometry* geom, int32_t subsets, double be
     H_TRY(hipMalloc(&h->d_yt, nrays * sizeof(float)));
     H_TRY(hipMalloc(&h->d_p, nrays * sizeof(float)));
     H_TRY(hipMalloc(&h->d_w, nrays * sizeof(float)));
-    H_TRY(hipMalloc(&h->d_e, nrays * sizeof(float)));
-    H_TRY(hipMalloc(&h->d_state, sizeof(DevState)));
+    const size_t ngroups = ((size_t)h->max_subset_views * geom->n_channels + SQ_GROUP - 1) / SQ_GROUP;
+    H_TRY(hipMalloc(&h->d_part, ngroups * sizeof(double)));
+    H_TRY(hipMalloc(&h->d_state, 2 * sizeof(DevState)));
     H_TRY(hipHostMalloc(&h->h_state, sizeof(DevState), hipHostMallocDefault));
     H_TRY(hipMemcpy(h->d_views, T.views.data(), T.views.size() * sizeof(ViewRec), hipMemcpyHostToDevice));
     H_TRY(hipMemcpy(h->d_raygeo, T.rg.data(), nrays * sizeof(RayGeo), hipMemcpyHostToDevice));
     H_TRY(hipMemcpy(h->d_raymeta, T.rm.data(), nrays * sizeof(RayMeta), hipMemcpyHostToDevice));
     H_TRY(hipMemset(h->d_w, 0, nrays * sizeof(float)));
-    H_TRY(hipMemset(h->d_e, 0, nrays * sizeof(float)));
-    H_TRY(hipMemset(h->d_state, 0, sizeof(DevState)));
+    H_TRY(hipMemset(h->d_part, 0, ngroups * sizeof(double)));
+    H_TRY(hipMemset(h->d_state, 0, 2 * sizeof(DevState)));
     H_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     H_TRY(hipDeviceSynchronize());
 #undef H_TRY
@@ -384,14 +413,17 @@ recon_status recon_subset_size(recon_handle* h, int32_t subset, int32_t* n_views
     return RECON_OK;
 }
 
-recon_status recon_set_launch(recon_handle* h, int32_t fp_segments, int32_t reserved)
+recon_status recon_set_launch(recon_handle* h, int32_t fp_segments, int32_t bp_variant)
 {
-    (void)reserved;
     if (!h) return fail(RECON_INVALID_ARG, "NULL handle");
     if (fp_segments != 0) {
         if (fp_segments != 1 && fp_segments != 2 && fp_segments != 4 && fp_segments != 8 && fp_segments != 16)
             return fail(RECON_INVALID_ARG, "fp_segments must be 1, 2, 4, 8 or 16");
         h->fp_segments = fp_segments;
+    }
+    if (bp_variant != 0) {
+        if (bp_variant < 1 || bp_variant > 5) return fail(RECON_INVALID_ARG, "bp_variant must be in [0, 5]");
+        h->bp_variant = bp_variant - 1;
     }
     drop_graphs(h);
     return RECON_OK;
@@ -475,7 +507,7 @@ recon_status recon_os_iterate(recon_handle* h, const float* d_counts, float i0, 
     }
     HIP_TRY(launch_unpad_image(h->d_img[in], d_img, G.n, G.P, s));
     if (state) {
-        HIP_TRY(hipMemcpyAsync(h->h_state, h->d_state, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(h->h_state, h->d_state + in, sizeof(DevState), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         state->n_done = n_done + n_iter;
         state->flags = h->h_state->flags;
@@ -516,53 +548,34 @@ recon_status recon_time_kernels(recon_handle* h, const float* d_counts, float i0
     HIP_TRY(launch_prep_counts(d_counts, h->d_views, G.nv, G.nch, i0, h->d_yt, h->d_p, s));
     HIP_TRY(launch_pad_image(d_img, h->d_img[0], h->d_imgT[0], G.n, G.P, s));
     HIP_TRY(launch_set_state(h->d_state, h->p.lambda0, 0.0, 0, 0, nullptr, nullptr, s));
-    std::vector<hipEvent_t> ev((size_t)n_iter * 4, nullptr);
+    // one sub-iteration of every subset first, so residuals and state are realistic
+    for (int sub = 0; sub < h->M; ++sub) HIP_TRY(enqueue_subiter(h, sub, 0, s));
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     recon_status status = RECON_OK;
-    auto cleanup = [&]() {
-        for (hipEvent_t e : ev)
-            if (e) (void)hipEventDestroy(e);
-    };
     for (auto& e : ev)
-        if (hipEventCreate(&e) != hipSuccess) {
-            cleanup();
-            return fail(RECON_DEVICE, "hipEventCreate failed");
+        if (hipEventCreate(&e) != hipSuccess) status = fail(RECON_DEVICE, "hipEventCreate failed");
+    // each kernel n_iter times back to back (subsets in turn) between two events
+    hipError_t err = status == RECON_OK ? hipEventRecord(ev[0], s) : hipSuccess;
+    for (int n = 0; n < n_iter && status == RECON_OK && err == hipSuccess; ++n)
+        err = enqueue_fp(h, n % h->M, 0, s);
+    if (status == RECON_OK && err == hipSuccess) err = hipEventRecord(ev[1], s);
+    // (the step rule has no launch of its own: it runs inside the update kernel)
+    if (status == RECON_OK && err == hipSuccess) err = hipEventRecord(ev[2], s);
+    for (int n = 0; n < n_iter && status == RECON_OK && err == hipSuccess; ++n)
+        err = launch_bp_update(G, h->bp_variant, update_args(h, n % h->M, 0), s);
+    if (status == RECON_OK && err == hipSuccess) err = hipEventRecord(ev[3], s);
+    if (status == RECON_OK && err == hipSuccess) err = hipStreamSynchronize(s);
+    if (status == RECON_OK && err != hipSuccess)
+        status = fail(RECON_DEVICE, std::string("timing run: ") + hipGetErrorString(err));
+    if (status == RECON_OK) {
+        for (int k = 0; k < 3; ++k) {
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+            ms_out[k] = ms / n_iter;
         }
-    int in = 0;
-    for (int n = 0; n < n_iter && status == RECON_OK; ++n) {
-        const int sub = n % h->M;
-        const int q0 = h->subset_start[sub], nq = h->subset_count[sub];
-        const int ray0 = q0 * G.nch, nrays = nq * G.nch;
-        hipEvent_t* e = &ev[(size_t)n * 4];
-        hipError_t err = hipEventRecord(e[0], s);
-        if (err == hipSuccess)
-            err = launch_fp_os(G, h->fp_segments, h->d_img[in], h->d_imgT[in], h->d_raygeo, h->d_raymeta, ray0,
-                               nrays, h->d_yt, h->d_p, h->d_w, h->d_e, s);
-        if (err == hipSuccess) err = hipEventRecord(e[1], s);
-        if (err == hipSuccess) err = launch_lambda(h->d_e, ray0, nrays, h->d_state, rule_of(h), s);
-        if (err == hipSuccess) err = hipEventRecord(e[2], s);
-        if (err == hipSuccess)
-            err = launch_bp_update(G, h->d_views, h->d_raygeo, h->d_w, q0, nq, h->d_img[in], h->d_img[1 - in],
-                                   h->d_imgT[1 - in], h->d_state, update_const(h), s);
-        if (err == hipSuccess) err = hipEventRecord(e[3], s);
-        if (err != hipSuccess) status = fail(RECON_DEVICE, std::string("timing run: ") + hipGetErrorString(err));
-        in = 1 - in;
     }
-    if (status == RECON_OK) {
-        hipError_t err = launch_unpad_image(h->d_img[in], d_img, G.n, G.P, s);
-        if (err == hipSuccess) err = hipStreamSynchronize(s);
-        if (err != hipSuccess) status = fail(RECON_DEVICE, std::string("timing run: ") + hipGetErrorString(err));
-    }
-    if (status == RECON_OK) {
-        double acc[3] = {0, 0, 0};
-        for (int n = 0; n < n_iter; ++n)
-            for (int k = 0; k < 3; ++k) {
-                float ms = 0.0f;
-                (void)hipEventElapsedTime(&ms, ev[(size_t)n * 4 + k], ev[(size_t)n * 4 + k + 1]);
-                acc[k] += ms;
-            }
-        for (int k = 0; k < 3; ++k) ms_out[k] = acc[k] / n_iter;
-    }
-    cleanup();
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
     return status;
 }
 

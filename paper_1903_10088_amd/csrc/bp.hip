@@ -1,0 +1,638 @@
+// Gather backprojection, TV gradient and the fused update of Eq. 3 (gfx950).
+//
+// The backprojector is pixel-driven: every thread owns one pixel and, for each
+// view of the subset, enumerates the window of channels whose rays cross the
+// pixel's sampling line within one pixel of its centre, adding hat weight x
+// path-weighted residual.  It reproduces the projector's weights exactly (same
+// lattice/residual arithmetic), so it is the projector's transpose, and it has
+// no atomics: each pixel's sum runs in a fixed order (views in turn, channels
+// in increasing order) and the result is bitwise deterministic.  Rays in a
+// window whose weight is zero add exactly zero, so the window's width (any
+// margin) does not change the bits.
+//
+// Two variants of the candidate reads:
+//   STAGE = false  each candidate's ray record and residual come from global
+//                  memory (L1/L2 resident);
+//   STAGE = true   a 16x16 tile first stages, for a chunk of views, the
+//                  channels its pixels can touch into LDS, so the candidate
+//                  loop reads LDS; a pixel whose window leaves the staged range
+//                  (or a view whose range does not fit) reads global memory.
+// Both give identical bits.
+#include <hip/hip_runtime.h>
+
+#include "gather.h"
+#include "internal.h"
+
+namespace recon {
+
+namespace {
+
+inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
+
+constexpr int TILE = 16;
+constexpr int STAGE_VIEWS = 8;   // views per LDS chunk
+constexpr int STAGE_SLOTS = 64;  // channels per view that can be staged
+constexpr int STAGE_ROW = STAGE_SLOTS + 4;  // row length: unrolled reads may run 3 past the last slot
+constexpr int UNROLL = 4;        // candidates evaluated without a loop
+
+// Adds the contributions of channels [lo, hi] (lo <= hi) of one view to acc,
+// in increasing channel order.  `t` is the pixel's coordinate along the rays'
+// major axis, `c` its coordinate across.  The first UNROLL candidates are
+// evaluated unconditionally and masked (their reads must be in bounds:
+// read(k) is only called with lo <= k <= lo + UNROLL - 1 or k <= hi); further
+// candidates run in a loop.
+template <class Read>
+__device__ __forceinline__ float add_window(float acc, int lo, int hi, float t, float c, Read read)
+{
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+        float wk;
+        const RayGeo g = read(lo + u, wk);
+        const float h = hat(ray_offset(g, t, c));
+        acc = (lo + u <= hi) ? fmaf(h, wk, acc) : acc;
+    }
+    for (int k = lo + UNROLL; k <= hi; ++k) {
+        float wk;
+        const RayGeo g = read(k, wk);
+        acc = fmaf(hat(ray_offset(g, t, c)), wk, acc);
+    }
+    return acc;
+}
+
+// Reads channel k of one view from global memory, clamped into [lo, hi] so the
+// masked reads of add_window stay inside the view.
+struct GlobalRead {
+    const RayGeo* gv;
+    const float* wv;
+    int hi;
+    __device__ __forceinline__ RayGeo operator()(int k, float& wk) const
+    {
+        const int kk = min(k, hi);
+        wk = wv[kk];
+        return gv[kk];
+    }
+};
+
+// Reads channel k of one view from its LDS row (k0 = first staged channel).
+struct LdsRead {
+    const float4* sg;
+    const float* sw;
+    int k0;
+    __device__ __forceinline__ RayGeo operator()(int k, float& wk) const
+    {
+        const int e = k - k0;
+        wk = sw[e];
+        const float4 f = sg[e];
+        return RayGeo{f.x, f.y, f.z, f.w};
+    }
+};
+
+// g_L at pixel (i, j) from global memory.
+__device__ __forceinline__ float gather_global(const Geo& G, const ViewRec* __restrict__ V,
+                                               const RayGeo* __restrict__ rg, const float* __restrict__ w, int q0,
+                                               int nq, int i, int j)
+{
+    const float X = (float)i - G.c, Y = (float)j - G.c;
+    const float fi = (float)i, fj = (float)j;
+    float acc = 0.0f;
+    for (int q = q0; q < q0 + nq; ++q) {
+        const ViewRec v = V[q];
+        const PixelView pv = pixel_view(G, v, X, Y);
+        int x0, x1, y0, y1;
+        major_intervals(v, G.nch, x0, x1, y0, y1);
+        if (x0 < x1) {
+            int lo, hi;
+            candidate_range(pv.kp, pv.hwx, x0, x1, lo, hi);
+            if (lo <= hi) acc = add_window(acc, lo, hi, fi, fj, GlobalRead{rg + v.ray0, w + v.ray0, hi});
+        }
+        if (y0 < y1) {
+            int lo, hi;
+            candidate_range(pv.kp, pv.hwy, y0, y1, lo, hi);
+            if (lo <= hi) acc = add_window(acc, lo, hi, fj, fi, GlobalRead{rg + v.ray0, w + v.ray0, hi});
+        }
+    }
+    return acc;
+}
+
+struct StageLds {
+    float4 geo[STAGE_VIEWS][STAGE_ROW];
+    float w[STAGE_VIEWS][STAGE_ROW];
+    int k0[STAGE_VIEWS];
+    int cnt[STAGE_VIEWS];  // staged channels, 0 = view not staged
+};
+
+// g_L at pixel (i, j) of a 16x16 tile with LDS staging.  Must be called by all
+// 256 threads of the block (it has barriers); `inside` marks real pixels.
+__device__ __forceinline__ float gather_staged(StageLds& S, const Geo& G, const ViewRec* __restrict__ V,
+                                               const RayGeo* __restrict__ rg, const float* __restrict__ w, int q0,
+                                               int nq, int i, int j, bool inside)
+{
+    const int tid = threadIdx.x;
+    const float X = (float)i - G.c, Y = (float)j - G.c;
+    const float fi = (float)i, fj = (float)j;
+    // tile corners (pixel centres), clipped to the image
+    const int ti0 = blockIdx.x * TILE, tj0 = blockIdx.y * TILE;
+    const int ti1 = min(ti0 + TILE - 1, G.n - 1), tj1 = min(tj0 + TILE - 1, G.n - 1);
+    float acc = 0.0f;
+    for (int c0 = q0; c0 < q0 + nq; c0 += STAGE_VIEWS) {
+        const int cv = min(STAGE_VIEWS, q0 + nq - c0);
+        if (tid < cv) {
+            // channel range of the whole tile: the fan angle over a convex tile is
+            // extreme at its corners; widen by the largest window half-width
+            const ViewRec v = V[c0 + tid];
+            float kmin = 3.0e38f, kmax = -3.0e38f, hw = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float cx = (float)((c & 1) ? ti1 : ti0) - G.c;
+                const float cy = (float)((c & 2) ? tj1 : tj0) - G.c;
+                const PixelView pv = pixel_view(G, v, cx, cy);
+                kmin = fminf(kmin, pv.kp);
+                kmax = fmaxf(kmax, pv.kp);
+                hw = fmaxf(hw, fmaxf(pv.hwx, pv.hwy));
+            }
+            const int k0 = max(0, (int)floorf(kmin - 1.25f * hw) - 1);
+            const int k1 = min(G.nch - 1, (int)ceilf(kmax + 1.25f * hw) + 1);
+            const int cnt = k1 - k0 + 1;
+            S.k0[tid] = k0;
+            S.cnt[tid] = (cnt > 0 && cnt <= STAGE_SLOTS) ? cnt : 0;
+        }
+        __syncthreads();
+        for (int slot = tid; slot < cv * STAGE_SLOTS; slot += 256) {
+            const int cq = slot / STAGE_SLOTS, e = slot - cq * STAGE_SLOTS;
+            if (e < S.cnt[cq]) {
+                const int ray = V[c0 + cq].ray0 + S.k0[cq] + e;
+                const RayGeo g = rg[ray];
+                S.geo[cq][e] = make_float4(g.a_int, g.a_frac, g.s_hi, g.s_lo);
+                S.w[cq][e] = w[ray];
+            }
+        }
+        __syncthreads();
+        if (inside) {
+            for (int cq = 0; cq < cv; ++cq) {
+                const ViewRec v = V[c0 + cq];
+                const int k0 = S.k0[cq], cnt = S.cnt[cq];
+                const PixelView pv = pixel_view(G, v, X, Y);
+                int x0, x1, y0, y1;
+                major_intervals(v, G.nch, x0, x1, y0, y1);
+                const LdsRead lds{S.geo[cq], S.w[cq], k0};
+                if (x0 < x1) {
+                    int lo, hi;
+                    candidate_range(pv.kp, pv.hwx, x0, x1, lo, hi);
+                    if (lo <= hi) {
+                        if (lo >= k0 && hi < k0 + cnt)
+                            acc = add_window(acc, lo, hi, fi, fj, lds);
+                        else
+                            acc = add_window(acc, lo, hi, fi, fj, GlobalRead{rg + v.ray0, w + v.ray0, hi});
+                    }
+                }
+                if (y0 < y1) {
+                    int lo, hi;
+                    candidate_range(pv.kp, pv.hwy, y0, y1, lo, hi);
+                    if (lo <= hi) {
+                        if (lo >= k0 && hi < k0 + cnt)
+                            acc = add_window(acc, lo, hi, fj, fi, lds);
+                        else
+                            acc = add_window(acc, lo, hi, fj, fi, GlobalRead{rg + v.ray0, w + v.ray0, hi});
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    return acc;
+}
+
+// ----------------------------------------------------------------------------
+// Blocked gather: each thread owns PX x PY pixels of a 16x16 tile
+// ----------------------------------------------------------------------------
+
+// One window of channels serves the whole pixel block: centred on the block's
+// centre and widened by its extent (the window half-width is linear in the
+// offset across and along the sampling line).  For every candidate the
+// lattice and residual parts of the crossing are formed once per sampling line
+// of the block and each pixel gets hat(...) x w exactly as in the one-pixel
+// gather, so every pixel's sum has the same terms in the same order (rays of
+// the window that miss a pixel add exactly zero).
+constexpr int BLK_UNROLL = 6;
+constexpr int BLK_ROW = STAGE_SLOTS + BLK_UNROLL;
+
+struct StageLdsBlk {
+    float4 geo[STAGE_VIEWS][BLK_ROW];
+    float w[STAGE_VIEWS][BLK_ROW];
+    int k0[STAGE_VIEWS];
+    int cnt[STAGE_VIEWS];
+};
+
+// Adds channels [lo, hi] (lo <= hi) of one view to the block's accumulators.
+// MAJ_X: rays sampled per column (t = column, centre = row) or per row.
+// Reads of `read` for k in [lo, lo + BLK_UNROLL) must be in bounds; w is
+// replaced by 0 past hi, so those candidates add exactly zero.
+template <int PX, int PY, bool MAJ_X, class Read>
+__device__ __forceinline__ void add_window_blk(float (&acc)[PY][PX], int lo, int hi, int i0, int j0, Read read)
+{
+    constexpr int NT = MAJ_X ? PX : PY;  // sampling lines in the block
+    constexpr int NC = MAJ_X ? PY : PX;  // pixels per sampling line
+    auto body = [&](int k, bool valid) {
+        float wk;
+        const RayGeo g = read(k, wk);
+        wk = valid ? wk : 0.0f;
+#pragma unroll
+        for (int a = 0; a < NT; ++a) {
+            const float t = (float)((MAJ_X ? i0 : j0) + a);
+            const float lat = fmaf(t, g.s_hi, g.a_int);
+            const float res = fmaf(t, g.s_lo, g.a_frac);
+#pragma unroll
+            for (int b = 0; b < NC; ++b) {
+                const float c = (float)((MAJ_X ? j0 : i0) + b);
+                const float h = hat((lat - c) + res);
+                float& A = MAJ_X ? acc[b][a] : acc[a][b];
+                A = fmaf(h, wk, A);
+            }
+        }
+    };
+#pragma unroll
+    for (int u = 0; u < BLK_UNROLL; ++u) body(lo + u, lo + u <= hi);
+    for (int k = lo + BLK_UNROLL; k <= hi; ++k) body(k, true);
+}
+
+// Global reads for the blocked gather, clamped into [lo, hi].
+struct GlobalReadBlk {
+    const RayGeo* gv;
+    const float* wv;
+    int hi;
+    __device__ __forceinline__ RayGeo operator()(int k, float& wk) const
+    {
+        const int kk = min(k, hi);
+        wk = wv[kk];
+        return gv[kk];
+    }
+};
+
+template <int PX, int PY>
+__device__ __forceinline__ void gather_block(StageLdsBlk& S, const Geo& G, const ViewRec* __restrict__ V,
+                                             const RayGeo* __restrict__ rg, const float* __restrict__ w, int q0,
+                                             int nq, int i0, int j0, bool active, float (&acc)[PY][PX])
+{
+    const int tid = threadIdx.x;
+    constexpr int NTH = 256 / (PX * PY);
+    const float Xc = (float)i0 + 0.5f * (PX - 1) - G.c, Yc = (float)j0 + 0.5f * (PY - 1) - G.c;
+    const int ti0 = blockIdx.x * TILE, tj0 = blockIdx.y * TILE;
+    const int ti1 = min(ti0 + TILE - 1, G.n - 1), tj1 = min(tj0 + TILE - 1, G.n - 1);
+    for (int c0 = q0; c0 < q0 + nq; c0 += STAGE_VIEWS) {
+        const int cv = min(STAGE_VIEWS, q0 + nq - c0);
+        if (tid < cv) {
+            const ViewRec v = V[c0 + tid];
+            float kmin = 3.0e38f, kmax = -3.0e38f, hw = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float cx = (float)((c & 1) ? ti1 : ti0) - G.c;
+                const float cy = (float)((c & 2) ? tj1 : tj0) - G.c;
+                const PixelView pv = pixel_view(G, v, cx, cy);
+                kmin = fminf(kmin, pv.kp);
+                kmax = fmaxf(kmax, pv.kp);
+                hw = fmaxf(hw, 1.5f * (pv.ax + pv.ay) + G.margin);
+            }
+            const int k0 = max(0, (int)floorf(kmin - 1.25f * hw) - 1);
+            const int k1 = min(G.nch - 1, (int)ceilf(kmax + 1.25f * hw) + 1);
+            const int cnt = k1 - k0 + 1;
+            S.k0[tid] = k0;
+            S.cnt[tid] = (cnt > 0 && cnt <= STAGE_SLOTS) ? cnt : 0;
+        }
+        __syncthreads();
+        // fill every slot of the chunk's rows (zeros past the staged channels),
+        // so masked reads past a window see finite values
+        for (int slot = tid; slot < cv * BLK_ROW; slot += NTH) {
+            const int cq = slot / BLK_ROW, e = slot - cq * BLK_ROW;
+            float4 gg = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            float ww = 0.0f;
+            if (e < S.cnt[cq]) {
+                const int ray = V[c0 + cq].ray0 + S.k0[cq] + e;
+                const RayGeo g = rg[ray];
+                gg = make_float4(g.a_int, g.a_frac, g.s_hi, g.s_lo);
+                ww = w[ray];
+            }
+            S.geo[cq][e] = gg;
+            S.w[cq][e] = ww;
+        }
+        __syncthreads();
+        if (active) {
+            for (int cq = 0; cq < cv; ++cq) {
+                const ViewRec v = V[c0 + cq];
+                const int k0 = S.k0[cq], cnt = S.cnt[cq];
+                const PixelView pv = pixel_view(G, v, Xc, Yc);
+                int x0, x1, y0, y1;
+                major_intervals(v, G.nch, x0, x1, y0, y1);
+                const LdsRead lds{S.geo[cq], S.w[cq], k0};
+                if (x0 < x1) {
+                    const float hw = pv.ax * (1.0f + 0.5f * (PY - 1)) + pv.ay * (0.5f * (PX - 1)) + G.margin;
+                    int lo, hi;
+                    candidate_range(pv.kp, hw, x0, x1, lo, hi);
+                    if (lo <= hi) {
+                        if (lo >= k0 && hi < k0 + cnt)
+                            add_window_blk<PX, PY, true>(acc, lo, hi, i0, j0, lds);
+                        else
+                            add_window_blk<PX, PY, true>(acc, lo, hi, i0, j0,
+                                                         GlobalReadBlk{rg + v.ray0, w + v.ray0, hi});
+                    }
+                }
+                if (y0 < y1) {
+                    const float hw = pv.ay * (1.0f + 0.5f * (PX - 1)) + pv.ax * (0.5f * (PY - 1)) + G.margin;
+                    int lo, hi;
+                    candidate_range(pv.kp, hw, y0, y1, lo, hi);
+                    if (lo <= hi) {
+                        if (lo >= k0 && hi < k0 + cnt)
+                            add_window_blk<PX, PY, false>(acc, lo, hi, i0, j0, lds);
+                        else
+                            add_window_blk<PX, PY, false>(acc, lo, hi, i0, j0,
+                                                          GlobalReadBlk{rg + v.ray0, w + v.ray0, hi});
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void bp_plain_kernel(Geo G, const ViewRec* __restrict__ V,
+                                                       const RayGeo* __restrict__ rg, const float* __restrict__ w,
+                                                       int q0, int nq, float* __restrict__ out)
+{
+    const int i = blockIdx.x * TILE + (threadIdx.x & 15);
+    const int j = blockIdx.y * TILE + (threadIdx.x >> 4);
+    if (i >= G.n || j >= G.n) return;
+    out[(size_t)j * G.n + i] = gather_global(G, V, rg, w, q0, nq, i, j);
+}
+
+// -dTV/dmu at pixel (i, j) from a tile s holding mu with a one-pixel halo
+// (local position (lx, ly)).  Differences past the last column / row are zero.
+template <int W>
+__device__ __forceinline__ float tv_neg_grad(const float (*s)[W], int lx, int ly, int i, int j, int n, float eps)
+{
+    const float e2 = eps * eps;
+    const float c = s[ly][lx];
+    const bool has_r = i + 1 < n, has_d = j + 1 < n;
+    const float dx = has_r ? s[ly][lx + 1] - c : 0.0f;
+    const float dy = has_d ? s[ly + 1][lx] - c : 0.0f;
+    float d = -(dx + dy) / sqrtf(fmaf(dx, dx, fmaf(dy, dy, e2)));
+    if (i > 0) {
+        const float l = s[ly][lx - 1];
+        const float dxl = c - l;
+        const float dyl = has_d ? s[ly + 1][lx - 1] - l : 0.0f;
+        d += dxl / sqrtf(fmaf(dxl, dxl, fmaf(dyl, dyl, e2)));
+    }
+    if (j > 0) {
+        const float u = s[ly - 1][lx];
+        const float dyu = c - u;
+        const float dxu = has_r ? s[ly - 1][lx + 1] - u : 0.0f;
+        d += dyu / sqrtf(fmaf(dxu, dxu, fmaf(dyu, dyu, e2)));
+    }
+    return -d;
+}
+
+__global__ __launch_bounds__(256) void tv_grad_kernel(const float* __restrict__ img, float* __restrict__ grad, int n,
+                                                      float eps)
+{
+    __shared__ float s[TILE + 2][TILE + 3];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int i = blockIdx.x * TILE + tx, j = blockIdx.y * TILE + ty;
+    for (int e = threadIdx.x; e < (TILE + 2) * (TILE + 2); e += 256) {
+        const int ly = e / (TILE + 2), lx = e - ly * (TILE + 2);
+        const int gj = blockIdx.y * TILE + ly - 1, gi = blockIdx.x * TILE + lx - 1;
+        s[ly][lx] = (gj >= 0 && gj < n && gi >= 0 && gi < n) ? img[(size_t)gj * n + gi] : 0.0f;
+    }
+    __syncthreads();
+    if (i >= n || j >= n) return;
+    grad[(size_t)j * n + i] = tv_neg_grad<TILE + 3>(s, tx + 1, ty + 1, i, j, n, eps);
+}
+
+// Sum of part[0..n) in a fixed order defined on 256 virtual lanes: lane v adds
+// part[v], part[v + 256], ... in turn; each group of 64 lanes combines its sums
+// by an xor butterfly (addition commutes, so every lane holds the same bits);
+// the four group sums are added as (g0 + g1) + (g2 + g3).  A block of NTH
+// threads plays 256 / NTH virtual lanes per thread, so every block size gives
+// the same bits.
+template <int NTH>
+__device__ double block_sum(const double* __restrict__ part, int n, double* red)
+{
+    constexpr int NV = 256 / NTH;
+    const int tid = threadIdx.x;
+    double s[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double acc = 0.0;
+        int r = tid + v * NTH;
+        for (; r + 3 * 256 < n; r += 4 * 256) {
+            double x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) x[u] = part[r + u * 256];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc += x[u];
+        }
+        for (; r < n; r += 256) acc += part[r];
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 64);
+        s[v] = acc;
+    }
+    if ((tid & 63) == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) red[(tid + v * NTH) >> 6] = s[v];
+    }
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Step rule of Eqs. 4-5 with the floor: lambda_0 at n = 0, else +inc when
+// f_n < f_{n-1} (strictly), -dec otherwise; a replay schedule overrides it.
+__device__ __forceinline__ double next_lambda(const DevState& in, const StepRule& R, double f)
+{
+    double lam;
+    if (in.n_global == 0) {
+        lam = R.lambda0;
+    } else {
+        lam = (f < in.f_prev) ? in.lambda + R.inc : in.lambda - R.dec;
+        if (lam < R.lmin) lam = R.lmin;
+    }
+    if (in.schedule) lam = in.schedule[in.it];
+    return lam;
+}
+
+struct UpdateScalars {
+    int q0, nq, nrays;
+    StepRule rule;
+    UpdateConst uc;
+};
+
+// Fused step rule + backprojection + TV + update (Eq. 3):
+//   f_n = mean squared difference of the subset, lambda_n from the step rule,
+//   mu' = mask * max(0, mu + lambda_n (c_l g_L + c_r g_R)), all terms at mu^(n);
+// writes both the row-major and the transposed padded copies of mu'.  Every
+// block evaluates the step rule from the same inputs in the same order, so all
+// use the same lambda_n; block (0, 0) records it in the output state.
+template <bool STAGE>
+__global__ __launch_bounds__(256) void bp_update_kernel(Geo G, const ViewRec* __restrict__ V,
+                                                        const RayGeo* __restrict__ rg, const float* __restrict__ w,
+                                                        const double* __restrict__ part,
+                                                        const DevState* __restrict__ st_in,
+                                                        DevState* __restrict__ st_out, const float* __restrict__ img,
+                                                        float* __restrict__ img_out, float* __restrict__ imgT_out,
+                                                        UpdateScalars sc)
+{
+    __shared__ float s[TILE + 2][TILE + 3];
+    __shared__ float t[TILE][TILE + 1];
+    __shared__ double red[4];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int i = blockIdx.x * TILE + tx, j = blockIdx.y * TILE + ty;
+
+    for (int e = threadIdx.x; e < (TILE + 2) * (TILE + 2); e += 256) {
+        const int ly = e / (TILE + 2), lx = e - ly * (TILE + 2);
+        const int gj = blockIdx.y * TILE + ly - 1, gi = blockIdx.x * TILE + lx - 1;
+        // columns -1 and n sit in the zero padding; rows -1 and n are outside the buffer
+        s[ly][lx] = (gj >= 0 && gj < G.n && gi < G.n + PAD) ? img[(size_t)gj * G.P + gi + PAD] : 0.0f;
+    }
+    const bool inside = i < G.n && j < G.n;
+    float gl = 0.0f;
+    if constexpr (STAGE) {
+        __shared__ StageLds S;
+        gl = gather_staged(S, G, V, rg, w, sc.q0, sc.nq, i, j, inside);  // contains barriers
+    } else {
+        __syncthreads();
+        if (inside) gl = gather_global(G, V, rg, w, sc.q0, sc.nq, i, j);
+    }
+
+    // step rule (needed only for the update, so its loads overlap other waves' gathers)
+    const double f = block_sum<256>(part, (sc.nrays + SQ_GROUP - 1) / SQ_GROUP, red) / (double)sc.nrays;
+    const DevState in = *st_in;
+    const double lam_d = next_lambda(in, sc.rule, f);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        DevState out = in;
+        if (!isfinite(f)) out.flags |= 1;
+        if (in.trace) {
+            in.trace[2 * in.it] = f;
+            in.trace[2 * in.it + 1] = lam_d;
+        }
+        out.lambda = lam_d;
+        out.f_prev = f;
+        out.n_global = in.n_global + 1;
+        out.it = in.it + 1;
+        *st_out = out;
+    }
+    const float lam = (float)lam_d;
+
+    float mu_new = 0.0f;
+    if (inside) {
+        const float gr = tv_neg_grad<TILE + 3>(s, tx + 1, ty + 1, i, j, G.n, sc.uc.eps);
+        const float v = s[ty + 1][tx + 1] + lam * fmaf(sc.uc.c_l, gl, sc.uc.c_r * gr);
+        mu_new = in_disc(i, j, G.n) ? fmaxf(v, 0.0f) : 0.0f;
+        img_out[(size_t)j * G.P + i + PAD] = mu_new;
+    }
+    t[ty][tx] = mu_new;
+    __syncthreads();
+    const int ii = blockIdx.x * TILE + ty, jj = blockIdx.y * TILE + tx;
+    if (ii < G.n && jj < G.n) imgT_out[(size_t)ii * G.P + jj + PAD] = t[tx][ty];
+}
+
+// Blocked form of bp_update_kernel: 256 / (PX PY) threads per 16x16 tile, each
+// owning PX x PY pixels.  Same arithmetic per pixel, same bits.
+template <int PX, int PY>
+__global__ __launch_bounds__(256 / (PX * PY)) void bp_update_block_kernel(
+    Geo G, const ViewRec* __restrict__ V, const RayGeo* __restrict__ rg, const float* __restrict__ w,
+    const double* __restrict__ part, const DevState* __restrict__ st_in, DevState* __restrict__ st_out,
+    const float* __restrict__ img, float* __restrict__ img_out, float* __restrict__ imgT_out, UpdateScalars sc)
+{
+    constexpr int NTH = 256 / (PX * PY);
+    constexpr int BW = TILE / PX;  // pixel blocks per tile row
+    __shared__ float s[TILE + 2][TILE + 3];
+    __shared__ float t[TILE][TILE + 1];
+    __shared__ double red[4];
+    __shared__ StageLdsBlk S;
+    const int tid = threadIdx.x;
+    const int bxl = (tid % BW) * PX, byl = (tid / BW) * PY;  // block origin in the tile
+    const int i0 = blockIdx.x * TILE + bxl, j0 = blockIdx.y * TILE + byl;
+
+    for (int e = tid; e < (TILE + 2) * (TILE + 2); e += NTH) {
+        const int ly = e / (TILE + 2), lx = e - ly * (TILE + 2);
+        const int gj = blockIdx.y * TILE + ly - 1, gi = blockIdx.x * TILE + lx - 1;
+        s[ly][lx] = (gj >= 0 && gj < G.n && gi < G.n + PAD) ? img[(size_t)gj * G.P + gi + PAD] : 0.0f;
+    }
+    float acc[PY][PX];
+#pragma unroll
+    for (int b = 0; b < PY; ++b)
+#pragma unroll
+        for (int a = 0; a < PX; ++a) acc[b][a] = 0.0f;
+    gather_block<PX, PY>(S, G, V, rg, w, sc.q0, sc.nq, i0, j0, i0 < G.n && j0 < G.n, acc);  // has barriers
+
+    const double f = block_sum<NTH>(part, (sc.nrays + SQ_GROUP - 1) / SQ_GROUP, red) / (double)sc.nrays;
+    const DevState in = *st_in;
+    const double lam_d = next_lambda(in, sc.rule, f);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
+        DevState out = in;
+        if (!isfinite(f)) out.flags |= 1;
+        if (in.trace) {
+            in.trace[2 * in.it] = f;
+            in.trace[2 * in.it + 1] = lam_d;
+        }
+        out.lambda = lam_d;
+        out.f_prev = f;
+        out.n_global = in.n_global + 1;
+        out.it = in.it + 1;
+        *st_out = out;
+    }
+    const float lam = (float)lam_d;
+
+#pragma unroll
+    for (int b = 0; b < PY; ++b)
+#pragma unroll
+        for (int a = 0; a < PX; ++a) {
+            const int i = i0 + a, j = j0 + b;
+            float mu_new = 0.0f;
+            if (i < G.n && j < G.n) {
+                const float gr = tv_neg_grad<TILE + 3>(s, bxl + a + 1, byl + b + 1, i, j, G.n, sc.uc.eps);
+                const float v = s[byl + b + 1][bxl + a + 1] + lam * fmaf(sc.uc.c_l, acc[b][a], sc.uc.c_r * gr);
+                mu_new = in_disc(i, j, G.n) ? fmaxf(v, 0.0f) : 0.0f;
+                img_out[(size_t)j * G.P + i + PAD] = mu_new;
+            }
+            t[byl + b][bxl + a] = mu_new;
+        }
+    __syncthreads();
+    for (int e = tid; e < TILE * TILE; e += NTH) {
+        const int ly = e / TILE, lx = e - ly * TILE;  // transposed: row ii, column jj
+        const int ii = blockIdx.x * TILE + ly, jj = blockIdx.y * TILE + lx;
+        if (ii < G.n && jj < G.n) imgT_out[(size_t)ii * G.P + jj + PAD] = t[lx][ly];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_bp_plain(const Geo& geo, const ViewRec* views, const RayGeo* rg, const float* w, int q0, int nq,
+                           float* out, hipStream_t s)
+{
+    dim3 grid(cdiv(geo.n, TILE), cdiv(geo.n, TILE));
+    bp_plain_kernel<<<grid, 256, 0, s>>>(geo, views, rg, w, q0, nq, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_bp_update(const Geo& geo, int variant, const UpdateArgs& a, hipStream_t s)
+{
+    dim3 grid(cdiv(geo.n, TILE), cdiv(geo.n, TILE));
+    const UpdateScalars sc{a.q0, a.nq, a.nrays, a.rule, a.uc};
+#define BP_ARGS geo, a.views, a.rg, a.w, a.part, a.st_in, a.st_out, a.img, a.img_out, a.imgT_out, sc
+    switch (variant) {
+    case 0: bp_update_kernel<false><<<grid, 256, 0, s>>>(BP_ARGS); break;
+    case 1: bp_update_kernel<true><<<grid, 256, 0, s>>>(BP_ARGS); break;
+    case 2: bp_update_block_kernel<1, 2><<<grid, 128, 0, s>>>(BP_ARGS); break;
+    case 3: bp_update_block_kernel<2, 1><<<grid, 128, 0, s>>>(BP_ARGS); break;
+    case 4: bp_update_block_kernel<2, 2><<<grid, 64, 0, s>>>(BP_ARGS); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef BP_ARGS
+    return hipGetLastError();
+}
+
+hipError_t launch_tv_grad(const float* img, float* grad, int n, float eps, hipStream_t s)
+{
+    dim3 grid(cdiv(n, TILE), cdiv(n, TILE));
+    tv_grad_kernel<<<grid, 256, 0, s>>>(img, grad, n, eps);
+    return hipGetLastError();
+}
+
+}  // namespace recon

@@ -10,16 +10,13 @@
 
 namespace recon {
 
-// atan on |t| <= 0.5 by its odd Taylor series through t^19 (error < 3e-8 rad);
-// only used to place the candidate window, whose margin absorbs the error.
+// atan on |t| <= 0.45 by its odd Taylor series through t^11 (error below
+// |t|^13 / 13 < 2.5e-6 rad); only used to place the candidate window, whose
+// margin includes this error.
 __host__ __device__ __forceinline__ float atan_small(float t)
 {
     const float t2 = t * t;
-    float p = -1.0f / 19.0f;
-    p = fmaf(p, t2, 1.0f / 17.0f);
-    p = fmaf(p, t2, -1.0f / 15.0f);
-    p = fmaf(p, t2, 1.0f / 13.0f);
-    p = fmaf(p, t2, -1.0f / 11.0f);
+    float p = -1.0f / 11.0f;
     p = fmaf(p, t2, 1.0f / 9.0f);
     p = fmaf(p, t2, -1.0f / 7.0f);
     p = fmaf(p, t2, 1.0f / 5.0f);
@@ -34,24 +31,41 @@ __host__ __device__ __forceinline__ float atan_small(float t)
 // pixel of its centre (x-major rays) or the row through it (y-major rays).
 struct PixelView {
     float kp, hwx, hwy;
+    float ax, ay;  // channels per pixel of offset along y (|px| s) and along x (|py| s)
 };
+
+__host__ __device__ __forceinline__ float approx_rcp(float x)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    return __builtin_amdgcn_rcpf(x);  // 1 ulp
+#else
+    return 1.0f / x;
+#endif
+}
 
 __host__ __device__ __forceinline__ PixelView pixel_view(const Geo& G, const ViewRec& v, float X, float Y)
 {
+    // with the source at dist * (cb, sb): distance along the central ray (> 0)
+    // and offset towards increasing fan angle, both affine in (X, Y)
+    const float along = fmaf(-X, v.cb, fmaf(-Y, v.sb, v.dist));
+    const float perp = fmaf(X, v.sb, -(Y * v.cb));
     const float px = X - v.sx, py = Y - v.sy;
-    const float along = -(px * v.cb + py * v.sb);  // distance along the central ray (> 0)
-    const float perp = px * v.sb - py * v.cb;      // offset towards increasing fan angle
-    const float tg = perp / along;
+    const float ra = approx_rcp(along);
+    const float tg = perp * ra;
 #ifdef __HIP_DEVICE_COMPILE__
     const float gam = G.use_poly ? atan_small(tg) : atanf(tg);
 #else
     const float gam = G.use_poly ? atan_small(tg) : std::atan(tg);
 #endif
-    const float inv_r2 = 1.0f / fmaf(px, px, py * py);
+    // d(angle)/d(offset across the sampling line) = |px| / r^2 (x-major) or
+    // |py| / r^2 (y-major); 1/along^2 >= 1/r^2 bounds it from above
+    const float s = ra * ra * G.dg_inv;
     PixelView o;
     o.kp = fmaf(gam, G.dg_inv, G.kc);
-    o.hwx = fmaf(fabsf(px) * inv_r2, G.dg_inv, G.margin);
-    o.hwy = fmaf(fabsf(py) * inv_r2, G.dg_inv, G.margin);
+    o.ax = fabsf(px) * s;
+    o.ay = fabsf(py) * s;
+    o.hwx = o.ax + G.margin;
+    o.hwy = o.ay + G.margin;
     return o;
 }
 
@@ -79,6 +93,14 @@ __host__ __device__ __forceinline__ void candidate_range(float kp, float hw, int
     fhi = fminf(fhi, (float)(b - 1));
     lo = (int)flo;
     hi = (int)fhi;
+}
+
+// Reconstruction disc x^2 + y^2 <= (n * pixel / 2)^2, in exact integer
+// arithmetic on doubled offsets from the grid centre.
+__host__ __device__ __forceinline__ bool in_disc(int i, int j, int n)
+{
+    const long a = 2L * i - n + 1, b = 2L * j - n + 1;
+    return a * a + b * b <= (long)n * n;
 }
 
 // u(t) - centre for an integer centre: the lattice part minus the centre is

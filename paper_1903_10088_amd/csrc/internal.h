@@ -18,6 +18,11 @@ namespace recon {
 // stays inside the row and reads zero outside the image.
 constexpr int PAD = 2;
 
+// The squared differences of a subset are summed in groups of this many
+// consecutive rays (in ray order), then over groups in a fixed tree: the
+// order, and so f_n to the last bit, is independent of launch shapes.
+constexpr int SQ_GROUP = 16;
+
 // One record per view, in subset order (subset 0's views first).  Kernels read
 // it at a wave-uniform index, so the loads go through the scalar cache.
 struct ViewRec {
@@ -27,6 +32,8 @@ struct ViewRec {
     int32_t k_split;   // channels [0, k_split) have major axis first_major, the rest the other
     int32_t first_major;  // 0 = x-major (sampled per column), 1 = y-major (per row)
     int32_t nat_view;  // natural view index
+    float dist;        // source distance from the grid centre in pixels (SAD / pixel)
+    int32_t pad[3];
 };
 
 // Per-ray sampling line: along the ray's major axis, sample line t (a column
@@ -109,11 +116,12 @@ struct recon_handle {
     float* d_yt = nullptr;                  // y / I0, subset order [nv * nch]
     float* d_p = nullptr;                   // ln(I0 / max(y, 1)), subset order
     float* d_w = nullptr;                   // weighted residual per ray, subset order
-    float* d_e = nullptr;                   // squared difference per ray, subset order
-    recon::DevState* d_state = nullptr;
+    double* d_part = nullptr;               // squared-difference sums per SQ_GROUP rays of a subset
+    recon::DevState* d_state = nullptr;     // two copies: sub-iteration reads one, writes the other
     recon::DevState* h_state = nullptr;     // pinned read-back
 
     int fp_segments = 8;
+    int bp_variant = 1;      // 0: global candidate reads, 1: LDS-staged
 
     // host copies of the ray tables (pair counts, checks)
     std::vector<recon::RayGeo> h_raygeo;
@@ -138,16 +146,32 @@ hipError_t launch_fp_plain(const Geo& geo, int segments, const float* img, const
                            const RayMeta* rm, const ViewRec* views, int q0, int nq, int natural_rows, float* out,
                            hipStream_t s);
 hipError_t launch_fp_os(const Geo& geo, int segments, const float* img, const float* imgT, const RayGeo* rg,
-                        const RayMeta* rm, int ray0, int nrays, const float* yt, const float* p, float* w, float* e,
-                        hipStream_t s);
-hipError_t launch_lambda(const float* e, int ray0, int nrays, DevState* st, StepRule rule, hipStream_t s);
+                        const RayMeta* rm, int ray0, int nrays, const float* yt, const float* p, float* w,
+                        double* part, hipStream_t s);
 hipError_t launch_set_state(DevState* st, double lambda, double f_prev, int n_global, int flags, double* trace,
                             const double* schedule, hipStream_t s);
 hipError_t launch_bp_plain(const Geo& geo, const ViewRec* views, const RayGeo* rg, const float* w, int q0, int nq,
                            float* out, hipStream_t s);
-hipError_t launch_bp_update(const Geo& geo, const ViewRec* views, const RayGeo* rg, const float* w, int q0, int nq,
-                            const float* img, float* img_out, float* imgT_out, const DevState* st, UpdateConst uc,
-                            hipStream_t s);
+// bp.hip; variant 0 = candidate reads from global memory, 1 = LDS-staged.
+// Reads the step-rule state st_in and the group sums `part` of the subset's
+// nrays rays, applies the step rule (block (0,0) writes st_out), then
+// backprojects, takes the TV gradient and updates the image.
+struct UpdateArgs {
+    const ViewRec* views;
+    const RayGeo* rg;
+    const float* w;
+    int q0, nq;
+    const double* part;
+    int nrays;
+    const DevState* st_in;
+    DevState* st_out;
+    StepRule rule;
+    const float* img;
+    float* img_out;
+    float* imgT_out;
+    UpdateConst uc;
+};
+hipError_t launch_bp_update(const Geo& geo, int variant, const UpdateArgs& a, hipStream_t s);
 hipError_t launch_tv_grad(const float* img, float* grad, int n, float eps, hipStream_t s);
 
 }  // namespace recon

@@ -199,8 +199,9 @@ class Recon:
                                         _stream()), "recon_time_kernels")
         return tuple(out)
 
-    def set_launch(self, fp_segments: int = 0):
-        _check(lib().recon_set_launch(self._h, fp_segments, 0), "recon_set_launch")
+    def set_launch(self, fp_segments: int = 0, bp_variant: int = 0):
+        """fp_segments in {1,2,4,8,16}; bp_variant 1 = global reads, 2 = LDS-staged; 0 keeps."""
+        _check(lib().recon_set_launch(self._h, fp_segments, bp_variant), "recon_set_launch")
 
     # -- operators ---------------------------------------------------------
     def project(self, img, subset: int = -1, out=None):

@@ -114,6 +114,32 @@ def test_resume_is_bitwise_and_deterministic(dev):
     assert st.lam == float(ta[-1, 1]) and st.f_prev == float(ta[-1, 0])
 
 
+@pytest.mark.parametrize("name", ["config0", "config1"])
+def test_launch_shapes_give_identical_bits(dev, name):
+    """Every projector segment count and both backprojector variants (global reads, LDS staging)
+    give the same bits, so launch-shape tuning cannot change a reconstruction."""
+    from paper_1903_10088_amd import recon
+    if name == "config0":
+        g, M, sl, n = ph.config0_geometry(), 10, ph.make_slice(ph.config0_geometry(), 8, 1e4), 20
+    else:
+        g, M, n = ph.config1_geometry(), 20, 40
+        sl = ph.make_slice(g, 101, 2e3, low_contrast=True, supersample=2)
+    counts = torch.from_numpy(sl.counts).to(dev)
+    R = recon.Recon(g, M, 1e-3)
+    ref = None
+    shapes = [(seg, 2) for seg in (1, 2, 4, 8, 16)] + [(8, bpv) for bpv in (1, 3, 4, 5)]
+    for seg, bpv in shapes:
+        if True:
+            print(f"{name}: fp_segments={seg} bp_variant={bpv}", flush=True)
+            R.set_launch(fp_segments=seg, bp_variant=bpv)
+            img, tr = R.os_iterate(counts, sl.i0, None, n, trace=True)
+            if ref is None:
+                ref = (img.clone(), tr.clone())
+            else:
+                assert torch.equal(img, ref[0]), (seg, bpv)
+                assert torch.equal(tr, ref[1]), (seg, bpv)
+
+
 def test_zero_iterations_returns_input(dev):
     from paper_1903_10088_amd import recon
     g = ph.config0_geometry()
