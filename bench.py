@@ -28,6 +28,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE) recorded in profiles/, or None when
+    the kernel's sources have changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic_512x800.json")
+    try:
+        rec = json.load(open(path))["kernels"][kernel]
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest()[:16] != rec["source_sha"]:
+            return None
+        return rec["fetch_bytes"] + rec["write_bytes"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +138,7 @@ def main():
         dom = dict(name="bp_update_kernel", ms=bp_ms, bytes=bp_bytes, gbps=bp_gbps)
     else:
         dom = dict(name="fp_kernel<OS>", ms=fp_ms, bytes=fp_bytes, gbps=fp_gbps)
+    traffic = measured_traffic(dom["name"])
 
     cpu = None
     parity = None
@@ -160,7 +179,7 @@ def main():
                    "image": g.n, "views": g.n_views, "channels": g.n_channels, "subsets": M,
                    "sub_iterations": args.iters, "beta": args.beta, "i0": i0},
         "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": dom["gbps"], "peak": PEAK_HBM_GBPS,
-                     "unit": "GB/s", "frac": dom["gbps"] / PEAK_HBM_GBPS, "traffic": None,
+                     "unit": "GB/s", "frac": dom["gbps"] / PEAK_HBM_GBPS, "traffic": traffic,
                      "alg_bytes_per_launch": dom["bytes"], "avg_launch_us": dom["ms"] * 1e3},
         "cpu_baseline": cpu,
         "projector_gbps": fp_gbps,

@@ -345,7 +345,9 @@ recon_status recon_create(const recon_geometry* geom, int32_t subsets, double be
     h->subset_start = T.start;
     h->subset_count = T.count;
     h->max_subset_views = *std::max_element(T.count.begin(), T.count.end());
-    h->fp_segments = geom->n >= 256 ? 8 : 4;
+    // launch-shape defaults from the sweep on 512^2 x 800 views (more threads per
+    // ray pay off on large images; results are identical for every choice)
+    h->fp_segments = geom->n >= 384 ? 16 : (geom->n >= 192 ? 8 : 4);
     h->h_raygeo = T.rg;
     h->h_raymeta = T.rm;
 
