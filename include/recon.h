@@ -171,6 +171,53 @@ recon_status recon_subset_size(recon_handle* h, int32_t subset, int32_t* n_views
 recon_status recon_set_launch(recon_handle* h, int32_t fp_segments, int32_t bp_variant);
 
 
+/* ------------------------------------------------------------------------
+ * Batches of slices (the many slices of a helical scan, each with its own
+ * image size, view count, channel count and I0).  All slices share the subset
+ * count M, beta and params.  One sub-iteration of every slice runs as one
+ * projector launch plus one update launch over a work table that covers all
+ * slices; each subset epoch is replayed from a captured HIP graph.  Every
+ * slice's result is bitwise equal to recon_os_iterate on that slice alone
+ * (fresh state).
+ * ------------------------------------------------------------------------ */
+typedef struct recon_batch_handle recon_batch_handle;
+
+/* Creates a batch of n_slices geometries (host array) with M = subsets and
+ * TV weight beta (params NULL = defaults): builds every slice's tables and
+ * workspace on the current device and the batch's work tables.  Blocks until
+ * done. */
+recon_status recon_batch_create(const recon_geometry* geoms, int32_t n_slices, int32_t subsets, double beta,
+                                const recon_params* params, recon_batch_handle** out);
+recon_status recon_batch_destroy(recon_batch_handle* b);
+
+/* Writes every slice's homogeneous start image (as recon_initial_image) into
+ * d_imgs, a host array of n_slices device pointers. */
+recon_status recon_batch_initial_images(recon_batch_handle* b, float* const* d_imgs, void* stream);
+
+/* Runs n_iter sub-iterations of every slice from a fresh state.  d_counts,
+ * d_imgs, d_traces are HOST arrays of n_slices DEVICE pointers: counts
+ * [n_views][n_channels] of slice i, image [n][n] of slice i (in: start image,
+ * out: result), trace [n_iter][2] of slice i or NULL (d_traces itself may be
+ * NULL).  i0 is a host array of n_slices blank-scan counts.  Asynchronous. */
+recon_status recon_batch_run(recon_batch_handle* b, const float* const* d_counts, const float* i0, float* const* d_imgs,
+                             int32_t n_iter, double* const* d_traces, void* stream);
+
+/* Autotuner: times the batched projector for 4, 8 and 16 threads per ray and
+ * the batched update for every backprojector variant (reps launches each, on
+ * the batch's own data, from the images in d_imgs, which are not modified),
+ * keeps the fastest of each for later runs and reports them.  Every choice
+ * gives bitwise identical results.  Blocks until done. */
+recon_status recon_batch_tune(recon_batch_handle* b, const float* const* d_counts, const float* i0, float* const* d_imgs,
+                              int32_t reps, int32_t* fp_segments_out, int32_t* bp_variant_out, void* stream);
+
+/* Pins the batch's launch shapes (as recon_set_launch; 0 keeps). */
+recon_status recon_batch_set_launch(recon_batch_handle* b, int32_t fp_segments, int32_t bp_variant);
+
+/* One-shot form: create, run n_iter sub-iterations, wait, destroy. */
+recon_status recon_batch(const recon_geometry* geoms, int32_t n_slices, int32_t subsets, double beta,
+                         const recon_params* params, const float* const* d_counts, const float* i0,
+                         float* const* d_imgs, int32_t n_iter, void* stream);
+
 /* Number of (ray, in-image pixel) interpolation pairs of `subset` (-1 = all
  * views): the pixel reads of the projector and the sinogram reads of the
  * backprojector, from the handle's own ray tables.  Host, synchronous. */

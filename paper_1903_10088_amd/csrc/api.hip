@@ -17,7 +17,7 @@
 
 using namespace recon;
 
-namespace {
+namespace recon {
 
 thread_local std::string g_last_error;
 
@@ -27,13 +27,11 @@ recon_status fail(recon_status s, const std::string& msg)
     return s;
 }
 
-#define HIP_TRY(expr)                                                                                    \
-    do {                                                                                                 \
-        hipError_t _e = (expr);                                                                          \
-        if (_e != hipSuccess)                                                                            \
-            return fail(_e == hipErrorOutOfMemory ? RECON_OOM : RECON_DEVICE,                            \
-                        std::string(#expr) + ": " + hipGetErrorString(_e));                              \
-    } while (0)
+}  // namespace recon
+
+namespace {
+
+#define HIP_TRY RECON_HIP_TRY
 
 constexpr double kPi = 3.14159265358979323846;
 
@@ -177,8 +175,6 @@ recon_status build_tables(const recon_geometry* g, int M, Tables& T)
     return RECON_OK;
 }
 
-hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
-
 void drop_graphs(recon_handle* h)
 {
     for (auto& gexec : h->graph)
@@ -186,6 +182,22 @@ void drop_graphs(recon_handle* h)
             (void)hipGraphExecDestroy(gexec);
             gexec = nullptr;
         }
+}
+
+}  // namespace
+
+namespace recon {
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+recon_status validate_create(const recon_geometry* geom, int subsets, double beta, const recon_params* params)
+{
+    recon_status st = check_geometry(geom, subsets);
+    if (st != RECON_OK) return st;
+    if (!(beta >= 0) || !std::isfinite(beta)) return fail(RECON_INVALID_ARG, "beta must be finite and >= 0");
+    if (params && (!(params->tv_eps_per_mm > 0) || !(params->lambda_min >= 0) || !(params->lambda0 > 0)))
+        return fail(RECON_INVALID_ARG, "bad step-rule or TV parameters");
+    return RECON_OK;
 }
 
 StepRule rule_of(const recon_handle* h)
@@ -205,6 +217,10 @@ UpdateConst update_const(const recon_handle* h)
     uc.pad = 0.0f;
     return uc;
 }
+
+}  // namespace recon
+
+namespace {
 
 UpdateArgs update_args(recon_handle* h, int s, int in)
 {
@@ -321,14 +337,11 @@ recon_status recon_create(const recon_geometry* geom, int32_t subsets, double be
 {
     if (!out) return fail(RECON_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    recon_status st = check_geometry(geom, subsets);
+    recon_status st = validate_create(geom, subsets, beta, params);
     if (st != RECON_OK) return st;
-    if (!(beta >= 0) || !std::isfinite(beta)) return fail(RECON_INVALID_ARG, "beta must be finite and >= 0");
     recon_params p;
     recon_default_params(&p);
     if (params) p = *params;
-    if (!(p.tv_eps_per_mm > 0) || !(p.lambda_min >= 0) || !(p.lambda0 > 0))
-        return fail(RECON_INVALID_ARG, "bad step-rule or TV parameters");
 
     Tables T;
     st = build_tables(geom, subsets, T);

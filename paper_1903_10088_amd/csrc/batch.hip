@@ -1,0 +1,418 @@
+// Batched reconstruction: many slices of different sizes (image size, views,
+// channels, I0) advance together, one projector launch and one update launch
+// per sub-iteration for the whole batch, each subset epoch replayed from a
+// captured HIP graph.
+//
+// Work tables map thread blocks to (slice, ray block) for the projector and to
+// (slice, 16x16 tile) for the update.  Slices are placed on XCDs (the
+// dispatcher hands block b to XCD b mod 8), so a slice's image, residuals and
+// ray tables stay in one XCD's L2; the per-XCD lists are balanced by cost and
+// interleaved, with idle blocks padding the shorter lists.
+//
+// Every slice's arithmetic is exactly that of recon_os_iterate on its own
+// handle (same device functions, same summation orders), so a batched slice
+// is bitwise equal to the same slice reconstructed alone.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "recon.h"
+
+using namespace recon;
+
+struct recon_batch_handle {
+    std::vector<recon_handle*> h;  // one handle (tables + workspace) per slice
+    int M = 1;
+    int fp_segments = 8;
+    int bp_variant = 1;
+    std::vector<int> xcd;  // XCD of each slice
+
+    SliceDesc* d_slices = nullptr;
+    int2* d_subs = nullptr;
+    BpWork* d_bp = nullptr;
+    int n_bp = 0;
+    std::vector<FpWork*> d_fp;  // per subset
+    std::vector<int> n_fp;
+
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    bool graph_bad = false;
+};
+
+namespace {
+
+constexpr int NXCD = 8;
+
+void drop_graphs(recon_batch_handle* b)
+{
+    for (auto& g : b->graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+void free_batch(recon_batch_handle* b)
+{
+    if (!b) return;
+    drop_graphs(b);
+    for (FpWork* p : b->d_fp)
+        if (p) (void)hipFree(p);
+    if (b->d_bp) (void)hipFree(b->d_bp);
+    if (b->d_subs) (void)hipFree(b->d_subs);
+    if (b->d_slices) (void)hipFree(b->d_slices);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    for (recon_handle* h : b->h) recon_destroy(h);
+    delete b;
+}
+
+// Greedy placement of slices on XCDs by cost (pixels x views per subset).
+void assign_xcds(recon_batch_handle* b)
+{
+    const int n = (int)b->h.size();
+    std::vector<int> order(n);
+    std::vector<double> cost(n), load(NXCD, 0.0);
+    for (int i = 0; i < n; ++i) {
+        order[i] = i;
+        cost[i] = (double)b->h[i]->geo.n * b->h[i]->geo.n * b->h[i]->max_subset_views;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+    b->xcd.assign(n, 0);
+    for (int i : order) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        b->xcd[i] = x;
+        load[x] += cost[i];
+    }
+}
+
+// Interleaves per-XCD lists so that block p runs on XCD p mod 8.
+template <class W>
+std::vector<W> interleave(const std::vector<std::vector<W>>& lists, const W& idle)
+{
+    size_t len = 0;
+    for (const auto& l : lists) len = std::max(len, l.size());
+    std::vector<W> out(len * NXCD, idle);
+    for (int x = 0; x < NXCD; ++x)
+        for (size_t k = 0; k < lists[x].size(); ++k) out[k * NXCD + x] = lists[x][k];
+    return out;
+}
+
+recon_status upload_work(recon_batch_handle* b)
+{
+    drop_graphs(b);
+    const int n = (int)b->h.size();
+    // update: every tile of every slice, slice by slice within an XCD
+    std::vector<std::vector<BpWork>> bl(NXCD);
+    for (int i = 0; i < n; ++i) {
+        const int N = b->h[i]->geo.n, T = (N + 15) / 16;
+        for (int ty = 0; ty < T; ++ty)
+            for (int tx = 0; tx < T; ++tx) bl[b->xcd[i]].push_back(BpWork{i, tx * 16, ty * 16, 0});
+    }
+    const std::vector<BpWork> bp = interleave(bl, BpWork{-1, 0, 0, 0});
+    if (b->d_bp) (void)hipFree(b->d_bp);
+    b->d_bp = nullptr;
+    RECON_HIP_TRY(hipMalloc(&b->d_bp, std::max<size_t>(1, bp.size()) * sizeof(BpWork)));
+    RECON_HIP_TRY(hipMemcpy(b->d_bp, bp.data(), bp.size() * sizeof(BpWork), hipMemcpyHostToDevice));
+    b->n_bp = (int)bp.size();
+    // projector: per subset, the subset's rays in blocks of 256 / segments
+    const int rpb = fp_rays_per_block(b->fp_segments);
+    for (FpWork* p : b->d_fp)
+        if (p) (void)hipFree(p);
+    b->d_fp.assign(b->M, nullptr);
+    b->n_fp.assign(b->M, 0);
+    for (int s = 0; s < b->M; ++s) {
+        std::vector<std::vector<FpWork>> fl(NXCD);
+        for (int i = 0; i < n; ++i) {
+            const int nrays = b->h[i]->subset_count[s] * b->h[i]->geo.nch;
+            for (int r0 = 0; r0 < nrays; r0 += rpb) fl[b->xcd[i]].push_back(FpWork{i, r0});
+        }
+        const std::vector<FpWork> fp = interleave(fl, FpWork{-1, 0});
+        RECON_HIP_TRY(hipMalloc(&b->d_fp[s], std::max<size_t>(1, fp.size()) * sizeof(FpWork)));
+        RECON_HIP_TRY(hipMemcpy(b->d_fp[s], fp.data(), fp.size() * sizeof(FpWork), hipMemcpyHostToDevice));
+        b->n_fp[s] = (int)fp.size();
+    }
+    return RECON_OK;
+}
+
+hipError_t enqueue_batch_subiter(recon_batch_handle* b, int s, int in, hipStream_t st)
+{
+    hipError_t e = launch_fp_batch(b->fp_segments, b->d_slices, b->d_fp[s], b->n_fp[s], s, in, st);
+    if (e != hipSuccess) return e;
+    return launch_bp_update_batch(b->bp_variant, b->d_slices, b->d_bp, b->n_bp, s, in, rule_of(b->h[0]), st);
+}
+
+recon_status get_graph(recon_batch_handle* b, int parity, hipGraphExec_t* out)
+{
+    if (b->graph[parity]) {
+        *out = b->graph[parity];
+        return RECON_OK;
+    }
+    hipGraph_t graph = nullptr;
+    RECON_HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    int in = parity;
+    for (int s = 0; s < b->M && err == hipSuccess; ++s) {
+        err = enqueue_batch_subiter(b, s, in, b->cap_stream);
+        in = 1 - in;
+    }
+    hipError_t end = hipStreamEndCapture(b->cap_stream, &graph);
+    if (err != hipSuccess || end != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(RECON_DEVICE,
+                    std::string("batch graph capture failed: ") + hipGetErrorString(err != hipSuccess ? err : end));
+    }
+    hipGraphExec_t exec = nullptr;
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(RECON_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
+    b->graph[parity] = exec;
+    *out = exec;
+    return RECON_OK;
+}
+
+// Per-slice preparation of a run: counts, start image, fresh step-rule state.
+recon_status prepare(recon_batch_handle* b, const float* const* d_counts, const float* i0, float* const* d_imgs,
+                     double* const* d_traces, hipStream_t s)
+{
+    for (size_t i = 0; i < b->h.size(); ++i) {
+        recon_handle* h = b->h[i];
+        const Geo& G = h->geo;
+        if (!d_counts[i] || !d_imgs[i] || !(i0[i] > 0) || !std::isfinite(i0[i]))
+            return fail(RECON_INVALID_ARG, "slice " + std::to_string(i) + ": NULL buffer or bad i0");
+        RECON_HIP_TRY(launch_prep_counts(d_counts[i], h->d_views, G.nv, G.nch, i0[i], h->d_yt, h->d_p, s));
+        RECON_HIP_TRY(launch_pad_image(d_imgs[i], h->d_img[0], h->d_imgT[0], G.n, G.P, s));
+        RECON_HIP_TRY(launch_set_state(h->d_state, h->p.lambda0, 0.0, 0, 0, d_traces ? d_traces[i] : nullptr,
+                                       nullptr, s));
+    }
+    return RECON_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+recon_status recon_batch_create(const recon_geometry* geoms, int32_t n_slices, int32_t subsets, double beta,
+                                const recon_params* params, recon_batch_handle** out)
+{
+    if (!out || !geoms) return fail(RECON_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (n_slices < 1) return fail(RECON_INVALID_ARG, "n_slices must be >= 1");
+    for (int i = 0; i < n_slices; ++i) {
+        recon_status st = validate_create(&geoms[i], subsets, beta, params);
+        if (st != RECON_OK) return fail(st, "slice " + std::to_string(i) + ": " + recon_last_error());
+    }
+    recon_batch_handle* b = new (std::nothrow) recon_batch_handle();
+    if (!b) return fail(RECON_OOM, "host allocation failed");
+    b->M = subsets;
+    for (int i = 0; i < n_slices; ++i) {
+        recon_handle* h = nullptr;
+        recon_status st = recon_create(&geoms[i], subsets, beta, params, &h);
+        if (st != RECON_OK) {
+            std::string msg = recon_last_error();
+            free_batch(b);
+            return fail(st, "slice " + std::to_string(i) + ": " + msg);
+        }
+        b->h.push_back(h);
+    }
+    b->fp_segments = b->h[0]->fp_segments;
+    assign_xcds(b);
+    auto bail = [&](recon_status s) {
+        free_batch(b);
+        return s;
+    };
+    // slice descriptors and subset tables
+    std::vector<int2> subs((size_t)n_slices * subsets);
+    for (int i = 0; i < n_slices; ++i)
+        for (int s = 0; s < subsets; ++s)
+            subs[(size_t)i * subsets + s] = make_int2(b->h[i]->subset_start[s], b->h[i]->subset_count[s]);
+    hipError_t e = hipMalloc(&b->d_subs, subs.size() * sizeof(int2));
+    if (e == hipSuccess) e = hipMemcpy(b->d_subs, subs.data(), subs.size() * sizeof(int2), hipMemcpyHostToDevice);
+    std::vector<SliceDesc> desc(n_slices);
+    for (int i = 0; i < n_slices; ++i) {
+        recon_handle* h = b->h[i];
+        SliceDesc& D = desc[i];
+        D.geo = h->geo;
+        D.pad0 = 0;
+        D.views = h->d_views;
+        D.rg = h->d_raygeo;
+        D.rm = h->d_raymeta;
+        D.img[0] = h->d_img[0];
+        D.img[1] = h->d_img[1];
+        D.imgT[0] = h->d_imgT[0];
+        D.imgT[1] = h->d_imgT[1];
+        D.yt = h->d_yt;
+        D.p = h->d_p;
+        D.w = h->d_w;
+        D.part = h->d_part;
+        D.state = h->d_state;
+        D.subs = b->d_subs + (size_t)i * subsets;
+        D.uc = update_const(h);
+    }
+    if (e == hipSuccess) e = hipMalloc(&b->d_slices, desc.size() * sizeof(SliceDesc));
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_slices, desc.data(), desc.size() * sizeof(SliceDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess)
+        return bail(fail(e == hipErrorOutOfMemory ? RECON_OOM : RECON_DEVICE,
+                         std::string("batch setup: ") + hipGetErrorString(e)));
+    recon_status st = upload_work(b);
+    if (st != RECON_OK) return bail(st);
+    *out = b;
+    return RECON_OK;
+}
+
+recon_status recon_batch_initial_images(recon_batch_handle* b, float* const* d_imgs, void* stream)
+{
+    if (!b || !d_imgs) return fail(RECON_INVALID_ARG, "NULL argument");
+    for (size_t i = 0; i < b->h.size(); ++i) {
+        recon_status st = recon_initial_image(b->h[i], d_imgs[i], stream);
+        if (st != RECON_OK) return st;
+    }
+    return RECON_OK;
+}
+
+recon_status recon_batch_destroy(recon_batch_handle* b)
+{
+    if (!b) return RECON_OK;
+    (void)hipDeviceSynchronize();
+    free_batch(b);
+    return RECON_OK;
+}
+
+recon_status recon_batch_set_launch(recon_batch_handle* b, int32_t fp_segments, int32_t bp_variant)
+{
+    if (!b) return fail(RECON_INVALID_ARG, "NULL batch");
+    if (fp_segments != 0) {
+        if (fp_segments != 1 && fp_segments != 2 && fp_segments != 4 && fp_segments != 8 && fp_segments != 16)
+            return fail(RECON_INVALID_ARG, "fp_segments must be 1, 2, 4, 8 or 16");
+        b->fp_segments = fp_segments;
+    }
+    if (bp_variant != 0) {
+        if (bp_variant < 1 || bp_variant > 5) return fail(RECON_INVALID_ARG, "bp_variant must be in [0, 5]");
+        b->bp_variant = bp_variant - 1;
+    }
+    return upload_work(b);
+}
+
+recon_status recon_batch_run(recon_batch_handle* b, const float* const* d_counts, const float* i0, float* const* d_imgs,
+                             int32_t n_iter, double* const* d_traces, void* stream)
+{
+    if (!b || !d_counts || !i0 || !d_imgs) return fail(RECON_INVALID_ARG, "NULL argument");
+    if (n_iter < 0) return fail(RECON_INVALID_ARG, "n_iter must be >= 0");
+    hipStream_t s = as_stream(stream);
+    recon_status st = prepare(b, d_counts, i0, d_imgs, d_traces, s);
+    if (st != RECON_OK) return st;
+    int in = 0, n = 0;
+    while (n < n_iter) {
+        const int sub = n % b->M;
+        if (sub == 0 && n_iter - n >= b->M && !b->graph_bad) {
+            hipGraphExec_t exec = nullptr;
+            if (get_graph(b, in, &exec) == RECON_OK) {
+                RECON_HIP_TRY(hipGraphLaunch(exec, s));
+                n += b->M;
+                if (b->M & 1) in = 1 - in;
+                continue;
+            }
+            b->graph_bad = true;
+        }
+        RECON_HIP_TRY(enqueue_batch_subiter(b, sub, in, s));
+        in = 1 - in;
+        ++n;
+    }
+    for (size_t i = 0; i < b->h.size(); ++i) {
+        const Geo& G = b->h[i]->geo;
+        RECON_HIP_TRY(launch_unpad_image(b->h[i]->d_img[in], d_imgs[i], G.n, G.P, s));
+    }
+    return RECON_OK;
+}
+
+recon_status recon_batch_tune(recon_batch_handle* b, const float* const* d_counts, const float* i0, float* const* d_imgs,
+                              int32_t reps, int32_t* fp_segments_out, int32_t* bp_variant_out, void* stream)
+{
+    if (!b || !d_counts || !i0 || !d_imgs) return fail(RECON_INVALID_ARG, "NULL argument");
+    if (reps < 1 || reps > 1000) return fail(RECON_INVALID_ARG, "reps must be in [1, 1000]");
+    hipStream_t s = as_stream(stream);
+    recon_status st = prepare(b, d_counts, i0, d_imgs, nullptr, s);
+    if (st != RECON_OK) return st;
+    for (int sub = 0; sub < b->M; ++sub) RECON_HIP_TRY(enqueue_batch_subiter(b, sub, 0, s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    RECON_HIP_TRY(hipEventCreate(&e0));
+    RECON_HIP_TRY(hipEventCreate(&e1));
+    auto timed = [&](auto&& launch, float* ms) -> hipError_t {
+        hipError_t err = launch(0);  // warm
+        if (err == hipSuccess) err = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch(r % b->M);
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        if (err == hipSuccess) err = hipEventElapsedTime(ms, e0, e1);
+        return err;
+    };
+    hipError_t err = hipSuccess;
+    const int segs[] = {4, 8, 16};
+    int best_seg = b->fp_segments;
+    float best_ms = 3.0e38f;
+    for (int seg : segs) {
+        b->fp_segments = seg;
+        st = upload_work(b);
+        if (st != RECON_OK) break;
+        float ms = 0.0f;
+        err = timed([&](int sub) { return launch_fp_batch(seg, b->d_slices, b->d_fp[sub], b->n_fp[sub], sub, 0, s); },
+                    &ms);
+        if (err != hipSuccess) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_seg = seg;
+        }
+    }
+    int best_var = b->bp_variant;
+    if (st == RECON_OK && err == hipSuccess) {
+        best_ms = 3.0e38f;
+        for (int var = 0; var < 5; ++var) {
+            float ms = 0.0f;
+            err = timed(
+                [&](int sub) {
+                    return launch_bp_update_batch(var, b->d_slices, b->d_bp, b->n_bp, sub, 0, rule_of(b->h[0]), s);
+                },
+                &ms);
+            if (err != hipSuccess) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_var = var;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != RECON_OK) return st;
+    if (err != hipSuccess) return fail(RECON_DEVICE, std::string("tuning run: ") + hipGetErrorString(err));
+    b->fp_segments = best_seg;
+    b->bp_variant = best_var;
+    st = upload_work(b);
+    if (st != RECON_OK) return st;
+    if (fp_segments_out) *fp_segments_out = best_seg;
+    if (bp_variant_out) *bp_variant_out = best_var + 1;
+    return RECON_OK;
+}
+
+recon_status recon_batch(const recon_geometry* geoms, int32_t n_slices, int32_t subsets, double beta,
+                         const recon_params* params, const float* const* d_counts, const float* i0,
+                         float* const* d_imgs, int32_t n_iter, void* stream)
+{
+    recon_batch_handle* b = nullptr;
+    recon_status st = recon_batch_create(geoms, n_slices, subsets, beta, params, &b);
+    if (st != RECON_OK) return st;
+    st = recon_batch_run(b, d_counts, i0, d_imgs, n_iter, nullptr, stream);
+    if (st == RECON_OK) {
+        hipError_t e = hipStreamSynchronize(as_stream(stream));
+        if (e != hipSuccess) st = fail(RECON_DEVICE, std::string("recon_batch: ") + hipGetErrorString(e));
+    }
+    recon_batch_destroy(b);
+    return st;
+}
+
+}  // extern "C"

@@ -125,13 +125,12 @@ struct StageLds {
 // 256 threads of the block (it has barriers); `inside` marks real pixels.
 __device__ __forceinline__ float gather_staged(StageLds& S, const Geo& G, const ViewRec* __restrict__ V,
                                                const RayGeo* __restrict__ rg, const float* __restrict__ w, int q0,
-                                               int nq, int i, int j, bool inside)
+                                               int nq, int i, int j, bool inside, int ti0, int tj0)
 {
     const int tid = threadIdx.x;
     const float X = (float)i - G.c, Y = (float)j - G.c;
     const float fi = (float)i, fj = (float)j;
-    // tile corners (pixel centres), clipped to the image
-    const int ti0 = blockIdx.x * TILE, tj0 = blockIdx.y * TILE;
+    // tile corners (pixel centres), clipped to the image; (ti0, tj0) = first pixel of the tile
     const int ti1 = min(ti0 + TILE - 1, G.n - 1), tj1 = min(tj0 + TILE - 1, G.n - 1);
     float acc = 0.0f;
     for (int c0 = q0; c0 < q0 + nq; c0 += STAGE_VIEWS) {
@@ -271,12 +270,12 @@ struct GlobalReadBlk {
 template <int PX, int PY>
 __device__ __forceinline__ void gather_block(StageLdsBlk& S, const Geo& G, const ViewRec* __restrict__ V,
                                              const RayGeo* __restrict__ rg, const float* __restrict__ w, int q0,
-                                             int nq, int i0, int j0, bool active, float (&acc)[PY][PX])
+                                             int nq, int i0, int j0, bool active, float (&acc)[PY][PX], int ti0,
+                                             int tj0)
 {
     const int tid = threadIdx.x;
     constexpr int NTH = 256 / (PX * PY);
     const float Xc = (float)i0 + 0.5f * (PX - 1) - G.c, Yc = (float)j0 + 0.5f * (PY - 1) - G.c;
-    const int ti0 = blockIdx.x * TILE, tj0 = blockIdx.y * TILE;
     const int ti1 = min(ti0 + TILE - 1, G.n - 1), tj1 = min(tj0 + TILE - 1, G.n - 1);
     for (int c0 = q0; c0 < q0 + nq; c0 += STAGE_VIEWS) {
         const int cv = min(STAGE_VIEWS, q0 + nq - c0);
@@ -467,25 +466,24 @@ struct UpdateScalars {
 //   mu' = mask * max(0, mu + lambda_n (c_l g_L + c_r g_R)), all terms at mu^(n);
 // writes both the row-major and the transposed padded copies of mu'.  Every
 // block evaluates the step rule from the same inputs in the same order, so all
-// use the same lambda_n; block (0, 0) records it in the output state.
+// use the same lambda_n; the block of the first tile records it in the output
+// state.  (ti0, tj0) is the tile's first pixel.
 template <bool STAGE>
-__global__ __launch_bounds__(256) void bp_update_kernel(Geo G, const ViewRec* __restrict__ V,
-                                                        const RayGeo* __restrict__ rg, const float* __restrict__ w,
-                                                        const double* __restrict__ part,
-                                                        const DevState* __restrict__ st_in,
-                                                        DevState* __restrict__ st_out, const float* __restrict__ img,
-                                                        float* __restrict__ img_out, float* __restrict__ imgT_out,
-                                                        UpdateScalars sc)
+__device__ __forceinline__ void bp_update_tile(Geo G, const ViewRec* __restrict__ V, const RayGeo* __restrict__ rg,
+                                               const float* __restrict__ w, const double* __restrict__ part,
+                                               const DevState* __restrict__ st_in, DevState* __restrict__ st_out,
+                                               const float* __restrict__ img, float* __restrict__ img_out,
+                                               float* __restrict__ imgT_out, UpdateScalars sc, int ti0, int tj0)
 {
     __shared__ float s[TILE + 2][TILE + 3];
     __shared__ float t[TILE][TILE + 1];
     __shared__ double red[4];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int i = blockIdx.x * TILE + tx, j = blockIdx.y * TILE + ty;
+    const int i = ti0 + tx, j = tj0 + ty;
 
     for (int e = threadIdx.x; e < (TILE + 2) * (TILE + 2); e += 256) {
         const int ly = e / (TILE + 2), lx = e - ly * (TILE + 2);
-        const int gj = blockIdx.y * TILE + ly - 1, gi = blockIdx.x * TILE + lx - 1;
+        const int gj = tj0 + ly - 1, gi = ti0 + lx - 1;
         // columns -1 and n sit in the zero padding; rows -1 and n are outside the buffer
         s[ly][lx] = (gj >= 0 && gj < G.n && gi < G.n + PAD) ? img[(size_t)gj * G.P + gi + PAD] : 0.0f;
     }
@@ -493,7 +491,7 @@ __global__ __launch_bounds__(256) void bp_update_kernel(Geo G, const ViewRec* __
     float gl = 0.0f;
     if constexpr (STAGE) {
         __shared__ StageLds S;
-        gl = gather_staged(S, G, V, rg, w, sc.q0, sc.nq, i, j, inside);  // contains barriers
+        gl = gather_staged(S, G, V, rg, w, sc.q0, sc.nq, i, j, inside, ti0, tj0);  // contains barriers
     } else {
         __syncthreads();
         if (inside) gl = gather_global(G, V, rg, w, sc.q0, sc.nq, i, j);
@@ -503,7 +501,7 @@ __global__ __launch_bounds__(256) void bp_update_kernel(Geo G, const ViewRec* __
     const double f = block_sum<256>(part, (sc.nrays + SQ_GROUP - 1) / SQ_GROUP, red) / (double)sc.nrays;
     const DevState in = *st_in;
     const double lam_d = next_lambda(in, sc.rule, f);
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    if (ti0 == 0 && tj0 == 0 && threadIdx.x == 0) {
         DevState out = in;
         if (!isfinite(f)) out.flags |= 1;
         if (in.trace) {
@@ -527,17 +525,19 @@ __global__ __launch_bounds__(256) void bp_update_kernel(Geo G, const ViewRec* __
     }
     t[ty][tx] = mu_new;
     __syncthreads();
-    const int ii = blockIdx.x * TILE + ty, jj = blockIdx.y * TILE + tx;
+    const int ii = ti0 + ty, jj = tj0 + tx;
     if (ii < G.n && jj < G.n) imgT_out[(size_t)ii * G.P + jj + PAD] = t[tx][ty];
 }
 
-// Blocked form of bp_update_kernel: 256 / (PX PY) threads per 16x16 tile, each
+// Blocked form of bp_update_tile: 256 / (PX PY) threads per 16x16 tile, each
 // owning PX x PY pixels.  Same arithmetic per pixel, same bits.
 template <int PX, int PY>
-__global__ __launch_bounds__(256 / (PX * PY)) void bp_update_block_kernel(
-    Geo G, const ViewRec* __restrict__ V, const RayGeo* __restrict__ rg, const float* __restrict__ w,
-    const double* __restrict__ part, const DevState* __restrict__ st_in, DevState* __restrict__ st_out,
-    const float* __restrict__ img, float* __restrict__ img_out, float* __restrict__ imgT_out, UpdateScalars sc)
+__device__ __forceinline__ void bp_update_tile_blk(Geo G, const ViewRec* __restrict__ V,
+                                                   const RayGeo* __restrict__ rg, const float* __restrict__ w,
+                                                   const double* __restrict__ part,
+                                                   const DevState* __restrict__ st_in, DevState* __restrict__ st_out,
+                                                   const float* __restrict__ img, float* __restrict__ img_out,
+                                                   float* __restrict__ imgT_out, UpdateScalars sc, int ti0, int tj0)
 {
     constexpr int NTH = 256 / (PX * PY);
     constexpr int BW = TILE / PX;  // pixel blocks per tile row
@@ -547,11 +547,11 @@ __global__ __launch_bounds__(256 / (PX * PY)) void bp_update_block_kernel(
     __shared__ StageLdsBlk S;
     const int tid = threadIdx.x;
     const int bxl = (tid % BW) * PX, byl = (tid / BW) * PY;  // block origin in the tile
-    const int i0 = blockIdx.x * TILE + bxl, j0 = blockIdx.y * TILE + byl;
+    const int i0 = ti0 + bxl, j0 = tj0 + byl;
 
     for (int e = tid; e < (TILE + 2) * (TILE + 2); e += NTH) {
         const int ly = e / (TILE + 2), lx = e - ly * (TILE + 2);
-        const int gj = blockIdx.y * TILE + ly - 1, gi = blockIdx.x * TILE + lx - 1;
+        const int gj = tj0 + ly - 1, gi = ti0 + lx - 1;
         s[ly][lx] = (gj >= 0 && gj < G.n && gi < G.n + PAD) ? img[(size_t)gj * G.P + gi + PAD] : 0.0f;
     }
     float acc[PY][PX];
@@ -559,12 +559,13 @@ __global__ __launch_bounds__(256 / (PX * PY)) void bp_update_block_kernel(
     for (int b = 0; b < PY; ++b)
 #pragma unroll
         for (int a = 0; a < PX; ++a) acc[b][a] = 0.0f;
-    gather_block<PX, PY>(S, G, V, rg, w, sc.q0, sc.nq, i0, j0, i0 < G.n && j0 < G.n, acc);  // has barriers
+    gather_block<PX, PY>(S, G, V, rg, w, sc.q0, sc.nq, i0, j0, i0 < G.n && j0 < G.n, acc, ti0,
+                         tj0);  // has barriers
 
     const double f = block_sum<NTH>(part, (sc.nrays + SQ_GROUP - 1) / SQ_GROUP, red) / (double)sc.nrays;
     const DevState in = *st_in;
     const double lam_d = next_lambda(in, sc.rule, f);
-    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
+    if (ti0 == 0 && tj0 == 0 && tid == 0) {
         DevState out = in;
         if (!isfinite(f)) out.flags |= 1;
         if (in.trace) {
@@ -596,9 +597,57 @@ __global__ __launch_bounds__(256 / (PX * PY)) void bp_update_block_kernel(
     __syncthreads();
     for (int e = tid; e < TILE * TILE; e += NTH) {
         const int ly = e / TILE, lx = e - ly * TILE;  // transposed: row ii, column jj
-        const int ii = blockIdx.x * TILE + ly, jj = blockIdx.y * TILE + lx;
+        const int ii = ti0 + ly, jj = tj0 + lx;
         if (ii < G.n && jj < G.n) imgT_out[(size_t)ii * G.P + jj + PAD] = t[lx][ly];
     }
+}
+
+// Update body for variant VAR (0 global, 1 LDS-staged, 2 1x2, 3 2x1, 4 2x2).
+template <int VAR>
+__device__ __forceinline__ void bp_update_any(Geo G, const ViewRec* __restrict__ V, const RayGeo* __restrict__ rg,
+                                              const float* __restrict__ w, const double* __restrict__ part,
+                                              const DevState* __restrict__ st_in, DevState* __restrict__ st_out,
+                                              const float* __restrict__ img, float* __restrict__ img_out,
+                                              float* __restrict__ imgT_out, UpdateScalars sc, int ti0, int tj0)
+{
+    if constexpr (VAR == 0) bp_update_tile<false>(G, V, rg, w, part, st_in, st_out, img, img_out, imgT_out, sc, ti0, tj0);
+    if constexpr (VAR == 1) bp_update_tile<true>(G, V, rg, w, part, st_in, st_out, img, img_out, imgT_out, sc, ti0, tj0);
+    if constexpr (VAR == 2)
+        bp_update_tile_blk<1, 2>(G, V, rg, w, part, st_in, st_out, img, img_out, imgT_out, sc, ti0, tj0);
+    if constexpr (VAR == 3)
+        bp_update_tile_blk<2, 1>(G, V, rg, w, part, st_in, st_out, img, img_out, imgT_out, sc, ti0, tj0);
+    if constexpr (VAR == 4)
+        bp_update_tile_blk<2, 2>(G, V, rg, w, part, st_in, st_out, img, img_out, imgT_out, sc, ti0, tj0);
+}
+
+constexpr int bp_threads(int var) { return var == 4 ? 64 : (var >= 2 ? 128 : 256); }
+
+// One slice: the grid covers its tiles.
+template <int VAR>
+__global__ __launch_bounds__(bp_threads(VAR)) void bp_update_kernel(
+    Geo G, const ViewRec* __restrict__ V, const RayGeo* __restrict__ rg, const float* __restrict__ w,
+    const double* __restrict__ part, const DevState* __restrict__ st_in, DevState* __restrict__ st_out,
+    const float* __restrict__ img, float* __restrict__ img_out, float* __restrict__ imgT_out, UpdateScalars sc)
+{
+    bp_update_any<VAR>(G, V, rg, w, part, st_in, st_out, img, img_out, imgT_out, sc, blockIdx.x * TILE,
+                       blockIdx.y * TILE);
+}
+
+// A batch of slices: block b updates tile work[b] of slice work[b].slice with
+// that slice's subset s, reading image/state buffers `in` and writing 1 - in.
+template <int VAR>
+__global__ __launch_bounds__(bp_threads(VAR)) void bp_update_batch_kernel(const SliceDesc* __restrict__ slices,
+                                                                          const BpWork* __restrict__ work, int s,
+                                                                          int in, StepRule rule)
+{
+    const BpWork wk = work[blockIdx.x];
+    if (wk.slice < 0) return;
+    const SliceDesc* __restrict__ D = slices + wk.slice;
+    const int2 sq = D->subs[s];
+    const UpdateScalars sc{sq.x, sq.y, sq.y * D->geo.nch, rule, D->uc};
+    bp_update_any<VAR>(D->geo, as_global(D->views), as_global(D->rg), as_global(D->w), as_global(D->part),
+                       as_global(D->state + in), as_global(D->state + (1 - in)), as_global(D->img[in]),
+                       as_global(D->img[1 - in]), as_global(D->imgT[1 - in]), sc, wk.ti0, wk.tj0);
 }
 
 }  // namespace
@@ -617,14 +666,29 @@ hipError_t launch_bp_update(const Geo& geo, int variant, const UpdateArgs& a, hi
     const UpdateScalars sc{a.q0, a.nq, a.nrays, a.rule, a.uc};
 #define BP_ARGS geo, a.views, a.rg, a.w, a.part, a.st_in, a.st_out, a.img, a.img_out, a.imgT_out, sc
     switch (variant) {
-    case 0: bp_update_kernel<false><<<grid, 256, 0, s>>>(BP_ARGS); break;
-    case 1: bp_update_kernel<true><<<grid, 256, 0, s>>>(BP_ARGS); break;
-    case 2: bp_update_block_kernel<1, 2><<<grid, 128, 0, s>>>(BP_ARGS); break;
-    case 3: bp_update_block_kernel<2, 1><<<grid, 128, 0, s>>>(BP_ARGS); break;
-    case 4: bp_update_block_kernel<2, 2><<<grid, 64, 0, s>>>(BP_ARGS); break;
+    case 0: bp_update_kernel<0><<<grid, bp_threads(0), 0, s>>>(BP_ARGS); break;
+    case 1: bp_update_kernel<1><<<grid, bp_threads(1), 0, s>>>(BP_ARGS); break;
+    case 2: bp_update_kernel<2><<<grid, bp_threads(2), 0, s>>>(BP_ARGS); break;
+    case 3: bp_update_kernel<3><<<grid, bp_threads(3), 0, s>>>(BP_ARGS); break;
+    case 4: bp_update_kernel<4><<<grid, bp_threads(4), 0, s>>>(BP_ARGS); break;
     default: return hipErrorInvalidValue;
     }
 #undef BP_ARGS
+    return hipGetLastError();
+}
+
+hipError_t launch_bp_update_batch(int variant, const SliceDesc* slices, const BpWork* work, int nblocks, int sub,
+                                  int in, StepRule rule, hipStream_t s)
+{
+    if (nblocks <= 0) return hipSuccess;
+    switch (variant) {
+    case 0: bp_update_batch_kernel<0><<<nblocks, bp_threads(0), 0, s>>>(slices, work, sub, in, rule); break;
+    case 1: bp_update_batch_kernel<1><<<nblocks, bp_threads(1), 0, s>>>(slices, work, sub, in, rule); break;
+    case 2: bp_update_batch_kernel<2><<<nblocks, bp_threads(2), 0, s>>>(slices, work, sub, in, rule); break;
+    case 3: bp_update_batch_kernel<3><<<nblocks, bp_threads(3), 0, s>>>(slices, work, sub, in, rule); break;
+    case 4: bp_update_batch_kernel<4><<<nblocks, bp_threads(4), 0, s>>>(slices, work, sub, in, rule); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

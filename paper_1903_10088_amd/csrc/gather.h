@@ -95,6 +95,15 @@ __host__ __device__ __forceinline__ void candidate_range(float kp, float hw, int
     hi = (int)fhi;
 }
 
+// A pointer read from device memory is generic to the compiler (flat loads);
+// passing it through the global address space lets the loads be global ones.
+template <class T>
+__device__ __forceinline__ T* as_global(T* p)
+{
+    const unsigned long long a = (unsigned long long)p;
+    return (T*)((__attribute__((address_space(1))) T*)a);
+}
+
 // Reconstruction disc x^2 + y^2 <= (n * pixel / 2)^2, in exact integer
 // arithmetic on doubled offsets from the grid centre.
 __host__ __device__ __forceinline__ bool in_disc(int i, int j, int n)

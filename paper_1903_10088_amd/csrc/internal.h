@@ -90,6 +90,36 @@ struct Geo {
     int use_poly;    // 1: |tan| of every pixel's fan angle is small enough for the polynomial atan
 };
 
+// Everything a batched kernel needs about one slice (device memory, read at
+// wave-uniform addresses).
+struct SliceDesc {
+    Geo geo;
+    int pad0;
+    const ViewRec* views;
+    const RayGeo* rg;
+    const RayMeta* rm;
+    float* img[2];
+    float* imgT[2];
+    const float* yt;
+    const float* p;
+    float* w;
+    double* part;
+    DevState* state;   // two copies
+    const int2* subs;  // per subset: (first subset-ordered view, number of views)
+    UpdateConst uc;
+};
+
+// Work items of the batched kernels: one per thread block.  slice < 0 = idle.
+struct FpWork {
+    int slice;
+    int r0;  // first ray of the block within the slice's subset
+};
+struct BpWork {
+    int slice;
+    int ti0, tj0;  // first pixel of the tile
+    int pad;
+};
+
 }  // namespace recon
 
 struct recon_handle {
@@ -134,6 +164,22 @@ struct recon_handle {
 
 namespace recon {
 
+// api.hip: error reporting and per-handle constants shared with batch.hip
+recon_status fail(recon_status s, const std::string& msg);
+hipStream_t as_stream(void* s);
+// Argument checks of recon_create (geometry, subset count, beta, params), no device work.
+recon_status validate_create(const recon_geometry* geom, int subsets, double beta, const recon_params* params);
+StepRule rule_of(const recon_handle* h);
+UpdateConst update_const(const recon_handle* h);
+
+#define RECON_HIP_TRY(expr)                                                                              \
+    do {                                                                                                 \
+        hipError_t _e = (expr);                                                                          \
+        if (_e != hipSuccess)                                                                            \
+            return ::recon::fail(_e == hipErrorOutOfMemory ? RECON_OOM : RECON_DEVICE,                   \
+                                 std::string(#expr) + ": " + hipGetErrorString(_e));                     \
+    } while (0)
+
 // kernels.hip
 hipError_t launch_pad_image(const float* src, float* dst, float* dstT, int n, int P, hipStream_t s);
 hipError_t launch_unpad_image(const float* src, float* dst, int n, int P, hipStream_t s);
@@ -172,6 +218,13 @@ struct UpdateArgs {
     UpdateConst uc;
 };
 hipError_t launch_bp_update(const Geo& geo, int variant, const UpdateArgs& a, hipStream_t s);
+hipError_t launch_bp_update_batch(int variant, const SliceDesc* slices, const BpWork* work, int nblocks, int sub,
+                                  int in, StepRule rule, hipStream_t s);
+// kernels.hip, batched projector: block b projects rays [r0, r0 + 256/segments)
+// of slice work[b].slice's subset s from image buffer `in`.
+hipError_t launch_fp_batch(int segments, const SliceDesc* slices, const FpWork* work, int nblocks, int sub, int in,
+                           hipStream_t s);
+int fp_rays_per_block(int segments);
 hipError_t launch_tv_grad(const float* img, float* grad, int n, float eps, hipStream_t s);
 
 }  // namespace recon

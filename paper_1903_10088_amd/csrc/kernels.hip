@@ -168,14 +168,15 @@ __device__ __forceinline__ float chunk_sum(const float* __restrict__ base, int P
 // prologue.  (Finishing it in the projector's last block instead would need
 // every block to write back its XCD's L2 before taking a ticket, which costs
 // more than it saves.)
+// rblock: first ray (within A's ray range) of this block's 256 / SEG rays.
 template <int SEG, bool OS>
-__global__ __launch_bounds__(256) void fp_kernel(FpArgs A)
+__device__ __forceinline__ void fp_body(const FpArgs& A, int rblock)
 {
     constexpr int RPB = 256 / SEG;
     const int tid = threadIdx.x;
     const int seg = tid / RPB;
     const int lr = tid - seg * RPB;
-    const int r = blockIdx.x * RPB + lr;
+    const int r = rblock + lr;
     // The line integral is summed in chunks of `ch` sample lines, each chunk in
     // line order, and the chunk sums are added in chunk order.  Segments cover
     // whole chunks, so the result does not depend on SEG.
@@ -243,6 +244,39 @@ __global__ __launch_bounds__(256) void fp_kernel(FpArgs A)
             A.part[r / SQ_GROUP] = s;
         }
     }
+}
+
+template <int SEG, bool OS>
+__global__ __launch_bounds__(256) void fp_kernel(FpArgs A)
+{
+    fp_body<SEG, OS>(A, blockIdx.x * (256 / SEG));
+}
+
+// A batch of slices: block b projects the rays work[b].r0 ... of slice
+// work[b].slice's subset s (OS mode) from image buffer `in`.
+template <int SEG>
+__global__ __launch_bounds__(256) void fp_batch_kernel(const SliceDesc* __restrict__ slices,
+                                                       const FpWork* __restrict__ work, int s, int in)
+{
+    const FpWork wk = work[blockIdx.x];
+    if (wk.slice < 0) return;
+    const SliceDesc* __restrict__ D = slices + wk.slice;
+    const int2 sq = D->subs[s];
+    FpArgs A{};
+    A.img = as_global(D->img[in]);
+    A.imgT = as_global(D->imgT[in]);
+    A.rg = as_global(D->rg);
+    A.rm = as_global(D->rm);
+    A.ray0 = sq.x * D->geo.nch;
+    A.nrays = sq.y * D->geo.nch;
+    A.n = D->geo.n;
+    A.P = D->geo.P;
+    A.nch = D->geo.nch;
+    A.yt = as_global(D->yt);
+    A.p = as_global(D->p);
+    A.w = as_global(D->w);
+    A.part = as_global(D->part);
+    fp_body<SEG, true>(A, wk.r0);
 }
 
 template <bool OS>
@@ -358,6 +392,23 @@ hipError_t launch_fp_os(const Geo& geo, int segments, const float* img, const fl
     a.w = w;
     a.part = part;
     return launch_fp<true>(segments, a, s);
+}
+
+int fp_rays_per_block(int segments) { return 256 / segments; }
+
+hipError_t launch_fp_batch(int segments, const SliceDesc* slices, const FpWork* work, int nblocks, int sub, int in,
+                           hipStream_t s)
+{
+    if (nblocks <= 0) return hipSuccess;
+    switch (segments) {
+    case 1: fp_batch_kernel<1><<<nblocks, 256, 0, s>>>(slices, work, sub, in); break;
+    case 2: fp_batch_kernel<2><<<nblocks, 256, 0, s>>>(slices, work, sub, in); break;
+    case 4: fp_batch_kernel<4><<<nblocks, 256, 0, s>>>(slices, work, sub, in); break;
+    case 8: fp_batch_kernel<8><<<nblocks, 256, 0, s>>>(slices, work, sub, in); break;
+    case 16: fp_batch_kernel<16><<<nblocks, 256, 0, s>>>(slices, work, sub, in); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_set_state(DevState* st, double lambda, double f_prev, int n_global, int flags, double* trace,

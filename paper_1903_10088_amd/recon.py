@@ -46,7 +46,8 @@ class State_c(ctypes.Structure):
 EXPORTS = ["recon_default_params", "recon_status_string", "recon_last_error", "recon_create", "recon_destroy",
            "recon_project", "recon_backproject", "recon_tv_grad", "recon_os_iterate", "recon_initial_image",
            "recon_subset_size", "recon_set_launch", "recon_check_tables", "recon_count_pairs",
-           "recon_time_kernels"]
+           "recon_time_kernels", "recon_batch_create", "recon_batch_destroy", "recon_batch_initial_images",
+           "recon_batch_run", "recon_batch_tune", "recon_batch_set_launch", "recon_batch"]
 
 _lib = None
 
@@ -78,6 +79,14 @@ def lib():
         L.recon_check_tables.argtypes = [P(Geometry_c), i32, i32, P(i64), P(i64), P(i64)]
         L.recon_count_pairs.argtypes = [vp, i32, P(i64)]
         L.recon_time_kernels.argtypes = [vp, vp, f, vp, i32, P(d), vp]
+        PP = P(vp)
+        L.recon_batch_create.argtypes = [P(Geometry_c), i32, i32, d, P(Params_c), P(vp)]
+        L.recon_batch_destroy.argtypes = [vp]
+        L.recon_batch_initial_images.argtypes = [vp, PP, vp]
+        L.recon_batch_run.argtypes = [vp, PP, P(f), PP, i32, PP, vp]
+        L.recon_batch_tune.argtypes = [vp, PP, P(f), PP, i32, P(i32), P(i32), vp]
+        L.recon_batch_set_launch.argtypes = [vp, i32, i32]
+        L.recon_batch.argtypes = [P(Geometry_c), i32, i32, d, P(Params_c), PP, P(f), PP, i32, vp]
         for name in EXPORTS:
             getattr(L, name)
         _lib = L
@@ -269,3 +278,87 @@ class Recon:
                                       _ptr(sched, torch.float64, None, "lambda_schedule"), _stream()),
                "recon_os_iterate")
         return img, tr
+
+
+def _ptr_array(tensors, dtype, shapes, name):
+    arr = (ctypes.c_void_p * len(tensors))()
+    for i, (t, shp) in enumerate(zip(tensors, shapes)):
+        arr[i] = _ptr(t, dtype, shp, f"{name}[{i}]")
+    return arr
+
+
+class Batch:
+    """Many slices of different geometry reconstructed together (one launch per kernel per sub-iteration)."""
+
+    def __init__(self, geometries, subsets: int, beta: float, params: dict | None = None):
+        self.geometries = list(geometries)
+        self.subsets = int(subsets)
+        self.beta = float(beta)
+        p = default_params()
+        if params:
+            p.update(params)
+        self.params = p
+        n = len(self.geometries)
+        garr = (Geometry_c * n)(*[geometry_c(g) for g in self.geometries])
+        h = ctypes.c_void_p()
+        _check(lib().recon_batch_create(garr, n, self.subsets, self.beta, ctypes.byref(Params_c(**p)),
+                                        ctypes.byref(h)), "recon_batch_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().recon_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self):
+        return len(self.geometries)
+
+    def _img_shapes(self):
+        return [(g.n, g.n) for g in self.geometries]
+
+    def _count_shapes(self):
+        return [(g.n_views, g.n_channels) for g in self.geometries]
+
+    def initial_images(self, device="cuda"):
+        torch = _torch()
+        imgs = [torch.empty((g.n, g.n), dtype=torch.float32, device=device) for g in self.geometries]
+        _check(lib().recon_batch_initial_images(self._h, _ptr_array(imgs, torch.float32, self._img_shapes(), "img"),
+                                                _stream()), "recon_batch_initial_images")
+        return imgs
+
+    def run(self, counts, i0s, imgs=None, n_iter: int = 1, trace: bool = False):
+        """Runs n_iter sub-iterations of every slice (fresh state); imgs updated in place.
+
+        Returns (imgs, traces) with traces a list of float64 [n_iter][2] tensors or None."""
+        torch = _torch()
+        if imgs is None:
+            imgs = self.initial_images(counts[0].device)
+        traces = None
+        tarr = None
+        if trace:
+            traces = [torch.empty((n_iter, 2), dtype=torch.float64, device=counts[0].device) for _ in counts]
+            tarr = _ptr_array(traces, torch.float64, [None] * len(traces), "trace")
+        i0 = (ctypes.c_float * len(i0s))(*[float(x) for x in i0s])
+        _check(lib().recon_batch_run(self._h, _ptr_array(counts, torch.float32, self._count_shapes(), "counts"), i0,
+                                     _ptr_array(imgs, torch.float32, self._img_shapes(), "img"), int(n_iter), tarr,
+                                     _stream()), "recon_batch_run")
+        return imgs, traces
+
+    def tune(self, counts, i0s, imgs, reps: int = 20):
+        """Autotunes launch shapes on this batch's data; returns (fp_segments, bp_variant)."""
+        torch = _torch()
+        i0 = (ctypes.c_float * len(i0s))(*[float(x) for x in i0s])
+        fs, bv = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().recon_batch_tune(self._h, _ptr_array(counts, torch.float32, self._count_shapes(), "counts"), i0,
+                                      _ptr_array(imgs, torch.float32, self._img_shapes(), "img"), int(reps),
+                                      ctypes.byref(fs), ctypes.byref(bv), _stream()), "recon_batch_tune")
+        return int(fs.value), int(bv.value)
+
+    def set_launch(self, fp_segments: int = 0, bp_variant: int = 0):
+        _check(lib().recon_batch_set_launch(self._h, fp_segments, bp_variant), "recon_batch_set_launch")

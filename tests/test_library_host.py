@@ -63,6 +63,22 @@ def test_create_rejects_bad_subsets_and_beta(subsets, beta):
     assert rc == recon.RECON_INVALID_ARG
 
 
+def test_batch_binding_validates_before_the_device():
+    """The batch binding marshals its arguments (host arrays of geometries) and the library rejects
+    an invalid slice before touching the device."""
+    good = ph.config0_geometry()
+    bad = ph.Geometry(n=128, pixel_mm=3.125, n_views=180, n_channels=192, sad_mm=250.0)
+    with pytest.raises(recon.ReconError) as ei:
+        recon.Batch([good, bad], 10, 1e-3)
+    assert ei.value.status == recon.RECON_INVALID_ARG
+    with pytest.raises(recon.ReconError) as ei:
+        recon.Batch([], 10, 1e-3)
+    assert ei.value.status == recon.RECON_INVALID_ARG
+    L = recon.lib()
+    assert L.recon_batch_run(None, None, None, None, 1, None, None) == recon.RECON_INVALID_ARG
+    assert L.recon_batch_destroy(None) == recon.RECON_OK
+
+
 def test_null_handle_calls_are_rejected():
     L = recon.lib()
     assert L.recon_project(None, None, None, -1, None) == recon.RECON_INVALID_ARG
