@@ -158,6 +158,18 @@ recon_status recon_os_iterate(recon_handle* h, const float* d_counts, float i0, 
  * reconstruction disc, 0 outside. */
 recon_status recon_initial_image(recon_handle* h, float* d_img, void* stream);
 
+/* Data consistency of an image against the counts of all views:
+ *   d_out[0] = mean over every ray of (l_i - p_i)^2, l = A mu (d_img, 1/mm),
+ *              p = ln(I0 / max(y, 1))  (the squared difference of section
+ *              3.C.2 taken over the whole sinogram instead of one subset);
+ *   d_out[1] = mean over every ray of 1 / max(y, 1), the variance of p under
+ *              Poisson noise to first order: the level d_out[0] settles near
+ *              once the image explains the data.
+ * d_out: device double[2].  Uses the handle's workspace: do not overlap with
+ * other calls on the same handle. */
+recon_status recon_data_residual(recon_handle* h, const float* d_counts, float i0, const float* d_img, double* d_out,
+                                 void* stream);
+
 /* Geometry queries (host, synchronous). */
 recon_status recon_subset_size(recon_handle* h, int32_t subset, int32_t* n_views_out);
 
@@ -217,6 +229,29 @@ recon_status recon_batch_set_launch(recon_batch_handle* b, int32_t fp_segments, 
 recon_status recon_batch(const recon_geometry* geoms, int32_t n_slices, int32_t subsets, double beta,
                          const recon_params* params, const float* const* d_counts, const float* i0,
                          float* const* d_imgs, int32_t n_iter, void* stream);
+
+/* Learned warm start for a batch (the network is declared in recon_cnn.h):
+ *   1. every slice runs n_pre sub-iterations from the homogeneous start;
+ *   2. the network maps each early iterate to an estimate of the converged
+ *      image, projected onto the constraints (zero outside the disc,
+ *      non-negative); its max_n must cover every slice;
+ *   3. n_refine sub-iterations refine that image with a fresh step-rule state
+ *      (lambda_0, subsets from 0);
+ *   4. the full-data residual r and noise level v of each result are taken as
+ *      in recon_data_residual;
+ *   5. every slice with r > residual_ratio * v (the level the plain iteration
+ *      reaches, calibrated on its own converged images) is reconstructed again
+ *      from the homogeneous start with n_cold sub-iterations.
+ * d_counts, d_imgs: host arrays of device pointers as in recon_batch_run
+ * (d_imgs receive the results); i0: host array.  h_residual, h_floor (host
+ * double[n_slices]) and h_fallback (host int32[n_slices], 1 = cold start used)
+ * may be NULL.  Blocks until done (the fallback decision is taken on the
+ * host). */
+struct recon_cnn;
+recon_status recon_warm_start(recon_batch_handle* b, struct recon_cnn* net, const float* const* d_counts,
+                              const float* i0, float* const* d_imgs, int32_t n_pre, int32_t n_refine, int32_t n_cold,
+                              double residual_ratio, double* h_residual, double* h_floor, int32_t* h_fallback,
+                              void* stream);
 
 /* Number of (ray, in-image pixel) interpolation pairs of `subset` (-1 = all
  * views): the pixel reads of the projector and the sinogram reads of the

@@ -13,7 +13,7 @@ Network (8 layers, 3x3 kernels, 32 channels, zero "same" padding):
     z_l  = conv(a_{l-1}, bf(W_l)) + b_l            l = 1..8
     a_l  = bf(relu(z_l))                            l = 1..7
     y    = x + z_8                                  (residual output)
-    mu'  = mu_scale * y
+    mu'  = mu + mu_scale * z_8                      (= mu_scale * y)
 conv is the 2-D cross-correlation summed over input channels,
     conv(a, W)[o, i, j] = sum_c sum_{dy,dx in -1..1} W[o, c, dy+1, dx+1] a[c, i+dy, j+dx],
 with a read as 0 outside the image.  bf() rounds to bfloat16 (8 significant
@@ -92,43 +92,55 @@ def _r(x, emulate: bool):
 # The three convolution forms (batched: arrays are [B][C][H][W])
 # ---------------------------------------------------------------------------
 
-def conv(a: np.ndarray, W: np.ndarray) -> np.ndarray:
-    """Cross-correlation with zero padding: [B][C][H][W] x [O][C][3][3] -> [B][O][H][W]."""
-    B, C, H, Wd = a.shape
-    ap = np.zeros((B, C, H + 2, Wd + 2))
-    ap[:, :, 1:-1, 1:-1] = a
-    z = np.zeros((B, W.shape[0], H, Wd))
+def _pad(x: np.ndarray) -> np.ndarray:
+    B, Cc, H, Wd = x.shape
+    xp = np.zeros((B, Cc, H + 2, Wd + 2))
+    xp[:, :, 1:-1, 1:-1] = np.asarray(x, dtype=np.float64)
+    return xp
+
+
+def _windows(x: np.ndarray, flip: bool = False) -> np.ndarray:
+    """[B][C][H][W] -> [B][C*9][H*W]: row (c, ky, kx) holds x shifted by (dy, dx) = (ky - 1, kx - 1),
+    i.e. X[b, (c, ky, kx), (i, j)] = x[b, c, i + dy, j + dx] (0 outside); flip=True shifts by
+    (-dy, -dx) instead."""
+    B, Cc, H, Wd = x.shape
+    xp = _pad(x)
+    X = np.empty((B, Cc, 3, 3, H * Wd))
     for ky in range(3):
         for kx in range(3):
-            z += np.einsum("oc,bchw->bohw", W[:, :, ky, kx], ap[:, :, ky:ky + H, kx:kx + Wd])
-    return z
+            oy, ox = (2 - ky, 2 - kx) if flip else (ky, kx)
+            X[:, :, ky, kx] = xp[:, :, oy:oy + H, ox:ox + Wd].reshape(B, Cc, H * Wd)
+    return X.reshape(B, Cc * 9, H * Wd)
+
+
+def conv(a: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """Cross-correlation with zero padding: [B][C][H][W] x [O][C][3][3] -> [B][O][H][W].
+
+    z[o, p] = sum over (c, ky, kx) of W[o, c, ky, kx] times a[c] at p + (ky - 1, kx - 1):
+    one matrix product of W (as [O][C*9]) with the shifted copies of a."""
+    B, Cc, H, Wd = a.shape
+    z = np.matmul(W.reshape(W.shape[0], Cc * 9), _windows(a))
+    return z.reshape(B, W.shape[0], H, Wd)
 
 
 def conv_t(g: np.ndarray, W: np.ndarray) -> np.ndarray:
     """Adjoint of conv in its input: [B][O][H][W] x [O][C][3][3] -> [B][C][H][W].
 
-    Output pixel (i, j) collects g at (i - dy, j - dx) for every tap (dy, dx)."""
+    a[c, p] = sum over (o, ky, kx) of W[o, c, ky, kx] times g[o] at p - (ky - 1, kx - 1)."""
     B, O, H, Wd = g.shape
-    gp = np.zeros((B, O, H + 2, Wd + 2))
-    gp[:, :, 1:-1, 1:-1] = g
-    a = np.zeros((B, W.shape[1], H, Wd))
-    for ky in range(3):
-        for kx in range(3):
-            dy, dx = ky - 1, kx - 1
-            a += np.einsum("oc,bohw->bchw", W[:, :, ky, kx], gp[:, :, 1 - dy:1 - dy + H, 1 - dx:1 - dx + Wd])
-    return a
+    Wt = np.ascontiguousarray(W.transpose(1, 0, 2, 3)).reshape(W.shape[1], O * 9)
+    a = np.matmul(Wt, _windows(g, flip=True))
+    return a.reshape(B, W.shape[1], H, Wd)
 
 
 def wgrad(a: np.ndarray, g: np.ndarray) -> np.ndarray:
-    """Adjoint of conv in its weights: [B][C][H][W], [B][O][H][W] -> [O][C][3][3]."""
-    B, C, H, Wd = a.shape
-    ap = np.zeros((B, C, H + 2, Wd + 2))
-    ap[:, :, 1:-1, 1:-1] = a
-    dW = np.zeros((g.shape[1], C, 3, 3))
-    for ky in range(3):
-        for kx in range(3):
-            dW[:, :, ky, kx] = np.einsum("bohw,bchw->oc", g, ap[:, :, ky:ky + H, kx:kx + Wd])
-    return dW
+    """Adjoint of conv in its weights: [B][C][H][W], [B][O][H][W] -> [O][C][3][3].
+
+    dW[o, c, ky, kx] = sum over images and pixels p of g[o, p] times a[c] at p + (ky - 1, kx - 1)."""
+    B, Cc, H, Wd = a.shape
+    gf = np.asarray(g, dtype=np.float64).reshape(B, g.shape[1], H * Wd)
+    dW = np.matmul(gf, _windows(a).transpose(0, 2, 1)).sum(axis=0)
+    return dW.reshape(g.shape[1], Cc, 3, 3)
 
 
 # ---------------------------------------------------------------------------
@@ -153,7 +165,7 @@ def forward(theta, mu, mu_scale: float, emulate_bf16: bool = True):
         acts.append(_r(np.maximum(z, 0.0), emulate_bf16))
     z8 = conv(acts[-1], Wr[7]) + layers[7][1][None, :, None, None]
     y = x + z8[:, 0]
-    return mu_scale * y, dict(x=x, acts=acts, Wr=Wr, y=y)
+    return np.asarray(mu, dtype=np.float64) + mu_scale * z8[:, 0], dict(x=x, acts=acts, Wr=Wr, y=y)
 
 
 def loss_and_grad(theta, mu, target, mu_scale: float, emulate_bf16: bool = True):

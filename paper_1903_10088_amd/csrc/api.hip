@@ -295,7 +295,7 @@ void free_handle(recon_handle* h)
     if (!h) return;
     drop_graphs(h);
     void* ptrs[] = {h->d_views, h->d_raygeo, h->d_raymeta, h->d_img[0], h->d_img[1], h->d_imgT[0], h->d_imgT[1],
-                    h->d_yt,    h->d_p,      h->d_w,       h->d_part,   h->d_state};
+                    h->d_yt,    h->d_p,      h->d_w,       h->d_part,   h->d_state,  h->d_part_all};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (h->h_state) (void)hipHostFree(h->h_state);
@@ -393,6 +393,7 @@ recon_status recon_create(const recon_geometry* geom, int32_t subsets, double be
     H_TRY(hipMalloc(&h->d_w, nrays * sizeof(float)));
     const size_t ngroups = ((size_t)h->max_subset_views * geom->n_channels + SQ_GROUP - 1) / SQ_GROUP;
     H_TRY(hipMalloc(&h->d_part, ngroups * sizeof(double)));
+    H_TRY(hipMalloc(&h->d_part_all, (nrays + SQ_GROUP - 1) / SQ_GROUP * sizeof(double)));
     H_TRY(hipMalloc(&h->d_state, 2 * sizeof(DevState)));
     H_TRY(hipHostMalloc(&h->h_state, sizeof(DevState), hipHostMallocDefault));
     H_TRY(hipMemcpy(h->d_views, T.views.data(), T.views.size() * sizeof(ViewRec), hipMemcpyHostToDevice));
@@ -530,6 +531,23 @@ recon_status recon_os_iterate(recon_handle* h, const float* d_counts, float i0, 
         state->f_prev = h->h_state->f_prev;
         if (state->flags & 1) return fail(RECON_NUMERIC, "non-finite squared difference");
     }
+    return RECON_OK;
+}
+
+recon_status recon_data_residual(recon_handle* h, const float* d_counts, float i0, const float* d_img, double* d_out,
+                                 void* stream)
+{
+    if (!h || !d_counts || !d_img || !d_out) return fail(RECON_INVALID_ARG, "NULL argument");
+    if (!(i0 > 0) || !std::isfinite(i0)) return fail(RECON_INVALID_ARG, "i0 must be finite and > 0");
+    hipStream_t s = as_stream(stream);
+    const Geo& G = h->geo;
+    const long nrays = (long)G.nv * G.nch;
+    HIP_TRY(launch_prep_counts(d_counts, h->d_views, G.nv, G.nch, i0, h->d_yt, h->d_p, s));
+    HIP_TRY(launch_pad_image(d_img, h->d_img[0], h->d_imgT[0], G.n, G.P, s));
+    // all views are one contiguous ray range in subset order
+    HIP_TRY(launch_fp_os(G, h->fp_segments, h->d_img[0], h->d_imgT[0], h->d_raygeo, h->d_raymeta, 0, (int)nrays,
+                         h->d_yt, h->d_p, h->d_w, h->d_part_all, s));
+    HIP_TRY(launch_residual_final(h->d_part_all, (int)((nrays + SQ_GROUP - 1) / SQ_GROUP), d_counts, nrays, d_out, s));
     return RECON_OK;
 }
 

@@ -22,6 +22,7 @@
 
 #include "internal.h"
 #include "recon.h"
+#include "recon_cnn.h"
 
 using namespace recon;
 
@@ -413,6 +414,53 @@ recon_status recon_batch(const recon_geometry* geoms, int32_t n_slices, int32_t 
     }
     recon_batch_destroy(b);
     return st;
+}
+
+recon_status recon_warm_start(recon_batch_handle* b, recon_cnn* net, const float* const* d_counts, const float* i0,
+                              float* const* d_imgs, int32_t n_pre, int32_t n_refine, int32_t n_cold,
+                              double residual_ratio, double* h_residual, double* h_floor, int32_t* h_fallback,
+                              void* stream)
+{
+    if (!b || !net || !d_counts || !i0 || !d_imgs) return fail(RECON_INVALID_ARG, "NULL argument");
+    if (n_pre < 0 || n_refine < 0 || n_cold < 0) return fail(RECON_INVALID_ARG, "iteration counts must be >= 0");
+    if (!(residual_ratio > 0)) return fail(RECON_INVALID_ARG, "residual_ratio must be > 0");
+    hipStream_t s = as_stream(stream);
+    const int n = (int)b->h.size();
+    // 1. early iterate of every slice from the homogeneous start
+    recon_status st = recon_batch_initial_images(b, d_imgs, stream);
+    if (st == RECON_OK) st = recon_batch_run(b, d_counts, i0, d_imgs, n_pre, nullptr, stream);
+    // 2. network estimate of the converged image, projected onto the constraints
+    for (int i = 0; i < n && st == RECON_OK; ++i)
+        st = recon_cnn_forward(net, d_imgs[i], d_imgs[i], 1, b->h[i]->geo.n, 1, stream);
+    // 3. refinement by the plain iteration, fresh step-rule state
+    if (st == RECON_OK) st = recon_batch_run(b, d_counts, i0, d_imgs, n_refine, nullptr, stream);
+    if (st != RECON_OK) return st;
+    // 4. full-data residual and its noise level per slice
+    double* d_res = nullptr;
+    RECON_HIP_TRY(hipMalloc(&d_res, 2 * sizeof(double) * n));
+    std::vector<double> res(2 * (size_t)n);
+    for (int i = 0; i < n && st == RECON_OK; ++i)
+        st = recon_data_residual(b->h[i], d_counts[i], i0[i], d_imgs[i], d_res + 2 * i, stream);
+    hipError_t e = hipSuccess;
+    if (st == RECON_OK) e = hipMemcpyAsync(res.data(), d_res, 2 * sizeof(double) * n, hipMemcpyDeviceToHost, s);
+    if (st == RECON_OK && e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_res);
+    if (st != RECON_OK) return st;
+    if (e != hipSuccess) return fail(RECON_DEVICE, std::string("residual read-back: ") + hipGetErrorString(e));
+    // 5. cold start for every slice whose data residual exceeds the limit
+    for (int i = 0; i < n; ++i) {
+        const bool fb = !(res[2 * i] <= residual_ratio * res[2 * i + 1]);
+        if (h_residual) h_residual[i] = res[2 * i];
+        if (h_floor) h_floor[i] = res[2 * i + 1];
+        if (h_fallback) h_fallback[i] = fb ? 1 : 0;
+        if (!fb) continue;
+        st = recon_initial_image(b->h[i], d_imgs[i], stream);
+        if (st == RECON_OK) st = recon_os_iterate(b->h[i], d_counts[i], i0[i], d_imgs[i], n_cold, nullptr, nullptr,
+                                                  nullptr, stream);
+        if (st != RECON_OK) return st;
+    }
+    RECON_HIP_TRY(hipStreamSynchronize(s));
+    return RECON_OK;
 }
 
 }  // extern "C"

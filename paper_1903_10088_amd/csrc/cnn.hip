@@ -1,0 +1,1044 @@
+// Learned warm start: residual CNN inference and training kernels for gfx950.
+//
+// Layout: hidden activations and backward signals are bfloat16, channels last
+// ([batch][row][col][32], 64 bytes per pixel), so one 16-byte load holds 8
+// channels of a pixel.  The 32 -> 32 convolutions (forward, and the input
+// gradient "dgrad", which is the same convolution with flipped taps and
+// transposed channel blocks) run on the matrix cores as implicit GEMMs:
+//   D[out channel][pixel] += W_tap[out][in] x A_shifted[in][pixel]
+// with v_mfma_f32_16x16x32_bf16 (M = 16 output channels, N = 16 pixels of a
+// tile row, K = the 32 input channels of one tap).  A 16x16-pixel output tile
+// and its one-pixel halo are staged in LDS (80-byte pixel stride: the 16-byte
+// reads of 16 lanes hit distinct banks); each wave keeps all 9 x 2 weight
+// fragments in registers and computes 4 output rows, so each staged input
+// fragment feeds up to 3 output rows.
+//
+// The weight gradient of a 32 -> 32 layer is a GEMM over pixels:
+//   dW_tap[out][in] = sum_p G[out][p] x A[in][p + tap]
+// also on the matrix cores, with K = 32 pixels per instruction.  Its operands
+// must hold 8 consecutive pixels of one channel per lane, so the tile is
+// transposed into channel-major LDS rows (the activation tile three times,
+// shifted by dx = -1, 0, 1, so every read is aligned).  Blocks loop over a
+// fixed set of tiles and write partial sums; a second kernel adds the
+// partials in a fixed order, so gradients are bitwise deterministic.
+//
+// The 1 -> 32 and 32 -> 1 layers (0.6% of the work) run in float32 on the
+// vector ALUs.  None of the path uses atomics.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gather.h"
+#include "internal.h"
+#include "recon_cnn.h"
+
+using namespace recon;
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int C = 32;           // hidden channels
+constexpr int T = 16;           // output tile edge
+constexpr int HALO = T + 2;     // staged tile edge
+constexpr int LDS_PIX = 40;     // bf16 per staged pixel (32 + 8 pad)
+constexpr int NHID = 6;         // 32 -> 32 layers (layers 2..7)
+constexpr int W32 = 9 * C * C;  // weights of one 32 -> 32 layer
+constexpr int P32 = W32 + C;    // weights + bias of one 32 -> 32 layer
+// offsets of the parameter vector
+constexpr int OFF_W1 = 0, OFF_B1 = 288;
+constexpr int OFF_HID = 320;  // layer 2 starts here; layer l (2..7) at OFF_HID + (l - 2) * P32
+constexpr int OFF_W8 = OFF_HID + NHID * P32, OFF_B8 = OFF_W8 + 288;
+constexpr int NPARAM = OFF_B8 + 1;
+static_assert(NPARAM == 56097, "parameter count");
+constexpr int WG_BLOCKS = 512;  // blocks of the weight-gradient kernels (fixed: fixes the summation order)
+constexpr int P_IN = 320;       // partial row of the first layer (288 weights + 32 biases)
+constexpr int P_OUT = 289;      // partial row of the last layer
+
+// Adam constants; 1 - beta is given directly (1.0f - 0.999f is 4.7e-5 off in float32)
+constexpr float kB1 = 0.9f, kB2 = 0.999f, kOneMinusB1 = 0.1f, kOneMinusB2 = 0.001f, kEps = 1e-8f;
+
+inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
+
+__device__ __forceinline__ uint32_t f2bf(float f)
+{
+    // round to nearest even (finite inputs)
+    const uint32_t u = __float_as_uint(f);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf2f(uint32_t h) { return __uint_as_float(h << 16); }
+__device__ __forceinline__ float bfround(float f) { return bf2f(f2bf(f)); }
+__device__ __forceinline__ float bf_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
+__device__ __forceinline__ bf16x8 as_bf8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Block index -> tile, XCD-aware: the dispatcher sends block b to XCD b mod 8;
+// tile order is remapped so every XCD works on one contiguous run of tiles
+// (neighbouring tiles share halos in that XCD's L2).
+struct Tile {
+    int b, i0, j0;  // image, first row, first column
+};
+__device__ __forceinline__ Tile tile_of(int bid, int nblocks, int tiles_x, int tiles_per_img)
+{
+    const int x = bid & 7, k = bid >> 3;
+    const int q = nblocks >> 3, r = nblocks & 7;
+    const int t = x * q + min(x, r) + k;
+    const int b = t / tiles_per_img;
+    const int rem = t - b * tiles_per_img;
+    const int ty = rem / tiles_x;
+    return Tile{b, ty * T, (rem - ty * tiles_x) * T};
+}
+__device__ __forceinline__ Tile tile_plain(int t, int tiles_x, int tiles_per_img)
+{
+    const int b = t / tiles_per_img;
+    const int rem = t - b * tiles_per_img;
+    const int ty = rem / tiles_x;
+    return Tile{b, ty * T, (rem - ty * tiles_x) * T};
+}
+
+__device__ __forceinline__ size_t pix(int b, int i, int j, int n) { return ((size_t)b * n + i) * n + j; }
+
+// Stages the (T+2)^2 halo tile of a channels-last bf16 tensor into LDS (zeros
+// outside the image).
+__device__ __forceinline__ void load_halo(uint16_t (*s)[HALO][LDS_PIX], const uint16_t* __restrict__ act, Tile t,
+                                          int n)
+{
+    for (int e = threadIdx.x; e < HALO * HALO * 4; e += blockDim.x) {
+        const int p = e >> 2, q = e & 3;
+        const int ly = p / HALO, lx = p - ly * HALO;
+        const int gi = t.i0 + ly - 1, gj = t.j0 + lx - 1;
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (gi >= 0 && gi < n && gj >= 0 && gj < n) v = *(const u32x4*)(act + pix(t.b, gi, gj, n) * C + q * 8);
+        *(u32x4*)(&s[ly][lx][q * 8]) = v;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Weight preparation: float32 master -> bfloat16 copies in kernel layouts
+// ----------------------------------------------------------------------------
+
+// wf[l][tap][o][c] = bf(W[o][c][tap]); wt[l][tap][c][o] = bf(W[o][c][8 - tap])
+// (the dgrad convolution); w1r[o][tap], w8r[c][tap] = bf(W) as float.
+__global__ __launch_bounds__(256) void prep_weights_kernel(const float* __restrict__ th, uint16_t* __restrict__ wf,
+                                                           uint16_t* __restrict__ wt, float* __restrict__ w1r,
+                                                           float* __restrict__ w8r)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < NHID * W32) {
+        const int l = k / W32, r = k - l * W32;
+        const int tap = r / (C * C), oc = r - tap * C * C;
+        const int a = oc / C, bq = oc - a * C;  // wf: a = o, bq = c; wt: a = c, bq = o
+        const float* W = th + OFF_HID + l * P32;
+        wf[k] = (uint16_t)f2bf(W[(a * C + bq) * 9 + tap]);
+        wt[k] = (uint16_t)f2bf(W[(bq * C + a) * 9 + (8 - tap)]);
+    } else if (k < NHID * W32 + 288) {
+        const int r = k - NHID * W32;  // o * 9 + tap
+        w1r[r] = bfround(th[OFF_W1 + r]);
+    } else if (k < NHID * W32 + 576) {
+        const int r = k - NHID * W32 - 288;  // c * 9 + tap
+        w8r[r] = bfround(th[OFF_W8 + r]);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Forward
+// ----------------------------------------------------------------------------
+
+// Layer 1 (1 -> 32): a0 = bf(mu / scale), a1 = bf(relu(b1 + sum_tap w1 a0)).
+__global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ mu, float inv_scale,
+                                                      const float* __restrict__ w1r, const float* __restrict__ b1,
+                                                      uint16_t* __restrict__ a0, uint16_t* __restrict__ a1, int n,
+                                                      long total)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int j = (int)(idx % n);
+    const long bi = idx / n;
+    const int i = (int)(bi % n);
+    const int b = (int)(bi / n);
+    float xn[9];
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+            const int gi = i + ky - 1, gj = j + kx - 1;
+            xn[ky * 3 + kx] =
+                (gi >= 0 && gi < n && gj >= 0 && gj < n) ? bfround(mu[pix(b, gi, gj, n)] * inv_scale) : 0.0f;
+        }
+    a0[idx] = (uint16_t)f2bf(mu[idx] * inv_scale);
+    uint32_t pk[16];
+#pragma unroll
+    for (int o = 0; o < C; o += 2) {
+        float z0 = b1[o], z1 = b1[o + 1];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            z0 = fmaf(w1r[o * 9 + t], xn[t], z0);
+            z1 = fmaf(w1r[(o + 1) * 9 + t], xn[t], z1);
+        }
+        pk[o >> 1] = f2bf(fmaxf(z0, 0.0f)) | (f2bf(fmaxf(z1, 0.0f)) << 16);
+    }
+    u32x4* dst = (u32x4*)(a1 + (size_t)idx * C);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[q] = u32x4{pk[4 * q], pk[4 * q + 1], pk[4 * q + 2], pk[4 * q + 3]};
+}
+
+// 32 -> 32 convolution on the matrix cores.  MODE 0 (forward): out =
+// bf(relu(conv(in, W) + bias)).  MODE 1 (dgrad): out = bf(conv(in, Wt) *
+// [mask > 0]) with Wt the flipped, transposed taps.  wts: [9][32 out][32 in]
+// bfloat16.
+template <int MODE>
+__global__ __launch_bounds__(256) void conv32_kernel(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wts,
+                                                     const float* __restrict__ bias, const uint16_t* __restrict__ mask,
+                                                     uint16_t* __restrict__ out, int n, int tiles_x,
+                                                     int tiles_per_img, int nblocks)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t s[HALO][HALO][LDS_PIX];
+    const Tile tl = tile_of(blockIdx.x, nblocks, tiles_x, tiles_per_img);
+    load_halo(s, in, tl, n);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    // A operands: lane (m, g) holds W_tap[h*16 + m][8g .. 8g+7]
+    bf16x8 A[9][2];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) A[tap][h] = as_bf8(*(const u32x4*)(wts + ((tap * C) + h * 16 + m) * C + g * 8));
+    __syncthreads();
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r][0] = acc[r][1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int r0 = wave * 4;  // this wave's output rows (tile-local); it reads staged rows r0 .. r0 + 5
+#pragma unroll
+    for (int R = 0; R < 6; ++R)
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+            // B operand: lane (m, g) holds channels 8g .. 8g+7 of staged pixel (r0 + R, m + kx)
+            const bf16x8 Bf = as_bf8(*(const u32x4*)(&s[r0 + R][m + kx][g * 8]));
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int ky = R - rr;
+                if (ky >= 0 && ky < 3) {
+                    acc[rr][0] = mfma(A[ky * 3 + kx][0], Bf, acc[rr][0]);
+                    acc[rr][1] = mfma(A[ky * 3 + kx][1], Bf, acc[rr][1]);
+                }
+            }
+        }
+    // D[4g + i][m]: output channels h*16 + 4g + i of pixel column m
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int gi = tl.i0 + r0 + rr, gj = tl.j0 + m;
+        if (gi >= n || gj >= n) continue;
+        const size_t base = pix(tl.b, gi, gj, n) * C;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int o0 = h * 16 + g * 4;
+            float v[4];
+            if constexpr (MODE == 0) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[rr][h][i] + bias[o0 + i], 0.0f);
+            } else {
+                const u32x2 mk = *(const u32x2*)(mask + base + o0);
+                v[0] = bf_lo(mk.x) > 0.0f ? acc[rr][h][0] : 0.0f;
+                v[1] = bf_hi(mk.x) > 0.0f ? acc[rr][h][1] : 0.0f;
+                v[2] = bf_lo(mk.y) > 0.0f ? acc[rr][h][2] : 0.0f;
+                v[3] = bf_hi(mk.y) > 0.0f ? acc[rr][h][3] : 0.0f;
+            }
+            *(u32x2*)(out + base + o0) = u32x2{f2bf(v[0]) | (f2bf(v[1]) << 16), f2bf(v[2]) | (f2bf(v[3]) << 16)};
+        }
+    }
+}
+
+// Layer 8 (32 -> 1): z = b8 + sum_tap sum_c w8 a7, y = x + z with x = mu / scale
+// (float32).  mu_out (optional) = mu + scale * z, projected onto the
+// constraints when asked.
+__global__ __launch_bounds__(256) void conv_out_kernel(const uint16_t* __restrict__ a7, const float* __restrict__ w8r,
+                                                       const float* __restrict__ b8, const float* __restrict__ mu,
+                                                       float inv_scale, float scale, float* __restrict__ y,
+                                                       float* __restrict__ mu_out, int project, int n, int tiles_x,
+                                                       int tiles_per_img, int nblocks)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t s[HALO][HALO][LDS_PIX];
+    const Tile tl = tile_of(blockIdx.x, nblocks, tiles_x, tiles_per_img);
+    load_halo(s, a7, tl, n);
+    __syncthreads();
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+    const int i = tl.i0 + ty, j = tl.j0 + tx;
+    if (i >= n || j >= n) return;
+    float z = b8[0];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int ky = tap / 3, kx = tap - ky * 3;
+        const u32x4* src = (const u32x4*)(&s[ty + ky][tx + kx][0]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const u32x4 v = src[q];
+            const int c = q * 8;
+            z = fmaf(w8r[(c + 0) * 9 + tap], bf_lo(v.x), z);
+            z = fmaf(w8r[(c + 1) * 9 + tap], bf_hi(v.x), z);
+            z = fmaf(w8r[(c + 2) * 9 + tap], bf_lo(v.y), z);
+            z = fmaf(w8r[(c + 3) * 9 + tap], bf_hi(v.y), z);
+            z = fmaf(w8r[(c + 4) * 9 + tap], bf_lo(v.z), z);
+            z = fmaf(w8r[(c + 5) * 9 + tap], bf_hi(v.z), z);
+            z = fmaf(w8r[(c + 6) * 9 + tap], bf_lo(v.w), z);
+            z = fmaf(w8r[(c + 7) * 9 + tap], bf_hi(v.w), z);
+        }
+    }
+    const size_t p = pix(tl.b, i, j, n);
+    const float xin = mu[p];
+    if (y) y[p] = fmaf(xin, inv_scale, z);
+    if (mu_out) {
+        // mu + scale * z = scale * y, formed so that z = 0 returns mu exactly
+        const float m = fmaf(scale, z, xin);
+        mu_out[p] = project ? (in_disc(j, i, n) ? fmaxf(m, 0.0f) : 0.0f) : m;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Loss and backward
+// ----------------------------------------------------------------------------
+
+// g8 = 2 (y - t) [p in disc] / count; per-block sums of (y - t)^2 over the disc
+// (FP64, fixed tree).
+__global__ __launch_bounds__(256) void loss_kernel(const float* __restrict__ y, const float* __restrict__ target,
+                                                   float inv_scale, float two_over_count, float* __restrict__ g8,
+                                                   double* __restrict__ part, int n, long total)
+{
+    __shared__ double red[256];
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double sq = 0.0;
+    if (idx < total) {
+        const int j = (int)(idx % n);
+        const int i = (int)((idx / n) % n);
+        const float d = in_disc(j, i, n) ? y[idx] - target[idx] * inv_scale : 0.0f;
+        g8[idx] = d * two_over_count;
+        sq = (double)d * (double)d;
+    }
+    red[threadIdx.x] = sq;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// loss = (sum of part[0..nparts)) / count, one block, fixed order.
+__global__ __launch_bounds__(256) void loss_final_kernel(const double* __restrict__ part, int nparts, double count,
+                                                         double* __restrict__ loss)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += 256) s += part[k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = red[0] / count;
+}
+
+// Layer 8 dgrad: g7[p][c] = bf([a7 > 0] sum_tap w8[c][tap] g8[p - tap]).
+__global__ __launch_bounds__(256) void dgrad_out_kernel(const float* __restrict__ g8, const float* __restrict__ w8r,
+                                                        const uint16_t* __restrict__ a7, uint16_t* __restrict__ g7,
+                                                        int n, long total)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int j = (int)(idx % n);
+    const long bi = idx / n;
+    const int i = (int)(bi % n);
+    const int b = (int)(bi / n);
+    float gn[9];  // g8 at (i - dy, j - dx) for tap (dy + 1, dx + 1)
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+            const int gi = i - (ky - 1), gj = j - (kx - 1);
+            gn[ky * 3 + kx] = (gi >= 0 && gi < n && gj >= 0 && gj < n) ? g8[pix(b, gi, gj, n)] : 0.0f;
+        }
+    const u32x4* msk = (const u32x4*)(a7 + (size_t)idx * C);
+    u32x4* dst = (u32x4*)(g7 + (size_t)idx * C);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const u32x4 mv = msk[q];
+        const uint32_t mw[4] = {mv.x, mv.y, mv.z, mv.w};
+        uint32_t pk[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int c = q * 8 + e * 2;
+            float d0 = 0.0f, d1 = 0.0f;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                d0 = fmaf(w8r[c * 9 + t], gn[t], d0);
+                d1 = fmaf(w8r[(c + 1) * 9 + t], gn[t], d1);
+            }
+            d0 = bf_lo(mw[e]) > 0.0f ? d0 : 0.0f;
+            d1 = bf_hi(mw[e]) > 0.0f ? d1 : 0.0f;
+            pk[e] = f2bf(d0) | (f2bf(d1) << 16);
+        }
+        dst[q] = u32x4{pk[0], pk[1], pk[2], pk[3]};
+    }
+}
+
+// Weight gradient of a 32 -> 32 layer on the matrix cores:
+//   dW[o][c][tap] = sum_p g[p][o] a[p + tap][c],  db[o] = sum_p g[p][o].
+// Block k handles tiles k, k + gridDim.x, ... in turn and writes its partial
+// sums (parameter layout, 9216 weights then 32 biases) to part[k].
+constexpr int GT_ROW = T * T + 8;       // bf16 per channel row of the transposed g tile (528 B)
+constexpr int AS_CH = HALO * T + 8;     // bf16 per channel of one shifted activation copy (592 B)
+
+__global__ __launch_bounds__(256) void wgrad32_kernel(const uint16_t* __restrict__ g, const uint16_t* __restrict__ a,
+                                                      float* __restrict__ part, int n, int tiles_x, int tiles_per_img,
+                                                      int ntiles)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t gT[C][GT_ROW];
+    __shared__ __attribute__((aligned(16))) uint16_t aS[3][C][AS_CH];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = lane & 15, g4 = lane >> 4;
+    f32x4 acc[9][2][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) acc[t][h][0] = acc[t][h][1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    float bacc = 0.0f;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const Tile tl = tile_plain(t, tiles_x, tiles_per_img);
+        __syncthreads();  // the previous tile's reads are done
+        {
+            // g tile, transposed: gT[c][pixel]
+            const int li = tid >> 4, lj = tid & 15;
+            const int gi = tl.i0 + li, gj = tl.j0 + lj;
+            u32x4 v[4] = {{0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}};
+            if (gi < n && gj < n) {
+                const u32x4* src = (const u32x4*)(g + pix(tl.b, gi, gj, n) * C);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = src[q];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t w[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    gT[q * 8 + 2 * e][tid] = (uint16_t)(w[e] & 0xffffu);
+                    gT[q * 8 + 2 * e + 1][tid] = (uint16_t)(w[e] >> 16);
+                }
+            }
+        }
+        for (int e = tid; e < HALO * HALO; e += 256) {
+            // activation halo, transposed into three copies shifted by kx: aS[kx][c][row][col] = a[row - 1][col + kx - 1]
+            const int ly = e / HALO, lx = e - ly * HALO;
+            const int gi = tl.i0 + ly - 1, gj = tl.j0 + lx - 1;
+            u32x4 v[4] = {{0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}};
+            if (gi >= 0 && gi < n && gj >= 0 && gj < n) {
+                const u32x4* src = (const u32x4*)(a + pix(tl.b, gi, gj, n) * C);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = src[q];
+            }
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                const int col = lx - kx;
+                if (col < 0 || col >= T) continue;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t w[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
+#pragma unroll
+                    for (int e2 = 0; e2 < 4; ++e2) {
+                        aS[kx][q * 8 + 2 * e2][ly * T + col] = (uint16_t)(w[e2] & 0xffffu);
+                        aS[kx][q * 8 + 2 * e2 + 1][ly * T + col] = (uint16_t)(w[e2] >> 16);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < C) {
+            float s = 0.0f;
+            for (int p = 0; p < T * T; ++p) s += bf2f(gT[tid][p]);
+            bacc += s;
+        }
+        // this wave: pixel blocks kb = 2 wave, 2 wave + 1 (32 pixels = tile rows 2kb, 2kb + 1)
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            const int kb = 2 * wave + kk;
+            bf16x8 Af[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) Af[h] = as_bf8(*(const u32x4*)(&gT[h * 16 + m][kb * 32 + g4 * 8]));
+            const int R = 2 * kb + (g4 >> 1), c0 = 8 * (g4 & 1);
+#pragma unroll
+            for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+                for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+                    for (int h2 = 0; h2 < 2; ++h2) {
+                        const bf16x8 Bf = as_bf8(*(const u32x4*)(&aS[kx][h2 * 16 + m][(R + ky) * T + c0]));
+                        acc[ky * 3 + kx][0][h2] = mfma(Af[0], Bf, acc[ky * 3 + kx][0][h2]);
+                        acc[ky * 3 + kx][1][h2] = mfma(Af[1], Bf, acc[ky * 3 + kx][1][h2]);
+                    }
+        }
+    }
+    // add the four waves' sums in wave order, in LDS (reusing the activation copies)
+    __syncthreads();
+    float* red = (float*)&aS[0][0][0];
+    for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int o = h * 16 + g4 * 4 + i, c = h2 * 16 + m;
+                            const int idx = (o * C + c) * 9 + tap;
+                            red[idx] = (w == 0 ? 0.0f : red[idx]) + acc[tap][h][h2][i];
+                        }
+        }
+        __syncthreads();
+    }
+    float* dst = part + (size_t)blockIdx.x * P32;
+    for (int k = tid; k < W32; k += 256) dst[k] = red[k];
+    if (tid < C) dst[W32 + tid] = bacc;
+}
+
+// Weight gradients of the first layer (g1 x a0; 288 weights + 32 biases) and
+// of the last (g8 x a7; 288 weights + 1 bias), float32 on the vector ALUs.
+// 320 threads; thread k owns output k of the partial row.
+__global__ __launch_bounds__(320) void wgrad_in_kernel(const uint16_t* __restrict__ g1, const uint16_t* __restrict__ a0,
+                                                       float* __restrict__ part, int n, int tiles_x,
+                                                       int tiles_per_img, int ntiles)
+{
+    __shared__ float gs[T * T][C + 1];
+    __shared__ float as[HALO][HALO];
+    const int tid = threadIdx.x;
+    float acc = 0.0f;
+    const int o = tid < 288 ? tid / 9 : tid - 288;
+    const int tap = tid < 288 ? tid - (tid / 9) * 9 : 0;
+    const int ky = tap / 3, kx = tap - ky * 3;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const Tile tl = tile_plain(t, tiles_x, tiles_per_img);
+        __syncthreads();
+        for (int e = tid; e < T * T * 4; e += 320) {
+            const int p = e >> 2, q = e & 3;
+            const int gi = tl.i0 + (p >> 4), gj = tl.j0 + (p & 15);
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (gi < n && gj < n) v = *(const u32x4*)(g1 + pix(tl.b, gi, gj, n) * C + q * 8);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e2 = 0; e2 < 4; ++e2) {
+                gs[p][q * 8 + 2 * e2] = bf_lo(w[e2]);
+                gs[p][q * 8 + 2 * e2 + 1] = bf_hi(w[e2]);
+            }
+        }
+        for (int e = tid; e < HALO * HALO; e += 320) {
+            const int ly = e / HALO, lx = e - ly * HALO;
+            const int gi = tl.i0 + ly - 1, gj = tl.j0 + lx - 1;
+            as[ly][lx] = (gi >= 0 && gi < n && gj >= 0 && gj < n) ? bf2f(a0[pix(tl.b, gi, gj, n)]) : 0.0f;
+        }
+        __syncthreads();
+        float s = 0.0f;
+        if (tid < 288) {
+            for (int p = 0; p < T * T; ++p) s = fmaf(gs[p][o], as[(p >> 4) + ky][(p & 15) + kx], s);
+        } else {
+            for (int p = 0; p < T * T; ++p) s += gs[p][o];
+        }
+        acc += s;
+    }
+    part[(size_t)blockIdx.x * P_IN + tid] = acc;
+}
+
+__global__ __launch_bounds__(320) void wgrad_out_kernel(const float* __restrict__ g8, const uint16_t* __restrict__ a7,
+                                                        float* __restrict__ part, int n, int tiles_x,
+                                                        int tiles_per_img, int ntiles)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t s[HALO][HALO][LDS_PIX];
+    __shared__ float gs[T * T];
+    const int tid = threadIdx.x;
+    float acc = 0.0f;
+    const int c = tid < 288 ? tid / 9 : 0;
+    const int tap = tid < 288 ? tid - (tid / 9) * 9 : 0;
+    const int ky = tap / 3, kx = tap - ky * 3;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const Tile tl = tile_plain(t, tiles_x, tiles_per_img);
+        __syncthreads();
+        load_halo(s, a7, tl, n);
+        for (int p = tid; p < T * T; p += 320) {
+            const int gi = tl.i0 + (p >> 4), gj = tl.j0 + (p & 15);
+            gs[p] = (gi < n && gj < n) ? g8[pix(tl.b, gi, gj, n)] : 0.0f;
+        }
+        __syncthreads();
+        float sum = 0.0f;
+        if (tid < 288) {
+            for (int p = 0; p < T * T; ++p) sum = fmaf(gs[p], bf2f(s[(p >> 4) + ky][(p & 15) + kx][c]), sum);
+        } else if (tid == 288) {
+            for (int p = 0; p < T * T; ++p) sum += gs[p];
+        }
+        acc += sum;
+    }
+    if (tid < P_OUT) part[(size_t)blockIdx.x * P_OUT + tid] = acc;
+}
+
+// out[k] = sum over blocks b = 0, 1, ... of part[b][k] (fixed order).
+__global__ __launch_bounds__(256) void reduce_part_kernel(const float* __restrict__ part, int nblocks, int row,
+                                                          float* __restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= row) return;
+    float s = 0.0f;
+    for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * row + k];
+    out[k] = s;
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ th, float* __restrict__ m,
+                                                   float* __restrict__ v, const float* __restrict__ g, int np, float lr,
+                                                   float c1, float c2)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    const float gk = g[k];
+    const float mk = kB1 * m[k] + kOneMinusB1 * gk;
+    const float vk = kB2 * v[k] + kOneMinusB2 * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    th[k] -= lr * (mk * c1) / (sqrtf(vk * c2) + kEps);
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// Handle
+// ----------------------------------------------------------------------------
+
+struct recon_cnn {
+    int max_batch = 0, max_n = 0;
+    float mu_scale = 1.0f;
+    int step = 0;
+    float* d_theta = nullptr;
+    float* d_m = nullptr;
+    float* d_v = nullptr;
+    float* d_grad = nullptr;
+    uint16_t* d_wf = nullptr;  // [6][9][32][32]
+    uint16_t* d_wt = nullptr;  // [6][9][32][32]
+    float* d_w1r = nullptr;    // [32][9]
+    float* d_w8r = nullptr;    // [32][9]
+    uint16_t* d_a0 = nullptr;  // [B][n][n]
+    uint16_t* d_act[8] = {};   // 1..7: [B][n][n][32]
+    uint16_t* d_g[8] = {};     // 1..7: [B][n][n][32]
+    float* d_y = nullptr;      // [B][n][n]
+    float* d_g8 = nullptr;     // [B][n][n]
+    float* d_part = nullptr;   // [WG_BLOCKS][P32]
+    double* d_loss_part = nullptr;
+    int last_batch = 0, last_n = 0;  // shape of the tensors held
+};
+
+namespace {
+
+struct Shape {
+    int batch, n, tiles_x, tiles_per_img, ntiles;
+    long pixels;
+};
+Shape shape_of(int batch, int n)
+{
+    Shape s;
+    s.batch = batch;
+    s.n = n;
+    s.tiles_x = (n + T - 1) / T;
+    s.tiles_per_img = s.tiles_x * s.tiles_x;
+    s.ntiles = s.tiles_per_img * batch;
+    s.pixels = (long)batch * n * n;
+    return s;
+}
+
+void free_cnn(recon_cnn* c)
+{
+    if (!c) return;
+    void* ptrs[] = {c->d_theta, c->d_m, c->d_v, c->d_grad, c->d_wf, c->d_wt, c->d_w1r, c->d_w8r,
+                    c->d_a0, c->d_y, c->d_g8, c->d_part, c->d_loss_part};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    for (int l = 0; l < 8; ++l) {
+        if (c->d_act[l]) (void)hipFree(c->d_act[l]);
+        if (c->d_g[l]) (void)hipFree(c->d_g[l]);
+    }
+    delete c;
+}
+
+hipError_t launch_prep(recon_cnn* c, hipStream_t s)
+{
+    prep_weights_kernel<<<cdiv(NHID * W32 + 576, 256), 256, 0, s>>>(c->d_theta, c->d_wf, c->d_wt, c->d_w1r,
+                                                                     c->d_w8r);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv32(int mode, const uint16_t* in, const uint16_t* w, const float* bias, const uint16_t* mask,
+                         uint16_t* out, const Shape& S, hipStream_t s)
+{
+    if (mode == 0)
+        conv32_kernel<0><<<S.ntiles, 256, 0, s>>>(in, w, bias, mask, out, S.n, S.tiles_x, S.tiles_per_img, S.ntiles);
+    else
+        conv32_kernel<1><<<S.ntiles, 256, 0, s>>>(in, w, bias, mask, out, S.n, S.tiles_x, S.tiles_per_img, S.ntiles);
+    return hipGetLastError();
+}
+
+// Forward pass of `batch` images (batch <= max_batch) from mu; y and mu_out optional.
+hipError_t enqueue_forward(recon_cnn* c, const float* mu, float* mu_out, int project, const Shape& S, hipStream_t s)
+{
+    const float inv = 1.0f / c->mu_scale;
+    conv_in_kernel<<<cdiv(S.pixels, 256), 256, 0, s>>>(mu, inv, c->d_w1r, c->d_theta + OFF_B1, c->d_a0, c->d_act[1],
+                                                        S.n, S.pixels);
+    hipError_t e = hipGetLastError();
+    for (int l = 2; l <= 7 && e == hipSuccess; ++l)
+        e = launch_conv32(0, c->d_act[l - 1], c->d_wf + (size_t)(l - 2) * W32,
+                          c->d_theta + OFF_HID + (l - 2) * P32 + W32, nullptr, c->d_act[l], S, s);
+    if (e != hipSuccess) return e;
+    conv_out_kernel<<<S.ntiles, 256, 0, s>>>(c->d_act[7], c->d_w8r, c->d_theta + OFF_B8, mu, inv, c->mu_scale, c->d_y,
+                                             mu_out, project, S.n, S.tiles_x, S.tiles_per_img, S.ntiles);
+    return hipGetLastError();
+}
+
+int wg_blocks(const Shape& S) { return S.ntiles < WG_BLOCKS ? S.ntiles : WG_BLOCKS; }
+
+hipError_t enqueue_wgrad32(recon_cnn* c, int l, const Shape& S, hipStream_t s)
+{
+    const int nb = wg_blocks(S);
+    wgrad32_kernel<<<nb, 256, 0, s>>>(c->d_g[l], c->d_act[l - 1], c->d_part, S.n, S.tiles_x, S.tiles_per_img,
+                                      S.ntiles);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    reduce_part_kernel<<<cdiv(P32, 256), 256, 0, s>>>(c->d_part, nb, P32, c->d_grad + OFF_HID + (l - 2) * P32);
+    return hipGetLastError();
+}
+
+// Loss and gradient (into d_grad) for a batch held in the workspace.
+hipError_t enqueue_loss_grad(recon_cnn* c, const float* mu, const float* target, double* d_loss, const Shape& S,
+                             hipStream_t s)
+{
+    hipError_t e = enqueue_forward(c, mu, nullptr, 0, S, s);
+    if (e != hipSuccess) return e;
+    long disc = 0;
+    for (int i = 0; i < S.n; ++i)
+        for (int j = 0; j < S.n; ++j) disc += in_disc(j, i, S.n) ? 1 : 0;
+    const double count = (double)disc * S.batch;
+    const unsigned nlb = cdiv(S.pixels, 256);
+    loss_kernel<<<nlb, 256, 0, s>>>(c->d_y, target, 1.0f / c->mu_scale, (float)(2.0 / count), c->d_g8,
+                                    c->d_loss_part, S.n, S.pixels);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (d_loss) {
+        loss_final_kernel<<<1, 256, 0, s>>>(c->d_loss_part, (int)nlb, count, d_loss);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    // layer 8: weights from g8 x a7, then g7
+    const int nb = wg_blocks(S);
+    wgrad_out_kernel<<<nb, 320, 0, s>>>(c->d_g8, c->d_act[7], c->d_part, S.n, S.tiles_x, S.tiles_per_img, S.ntiles);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    reduce_part_kernel<<<cdiv(P_OUT, 256), 256, 0, s>>>(c->d_part, nb, P_OUT, c->d_grad + OFF_W8);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    dgrad_out_kernel<<<cdiv(S.pixels, 256), 256, 0, s>>>(c->d_g8, c->d_w8r, c->d_act[7], c->d_g[7], S.n, S.pixels);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // layers 7 .. 2
+    for (int l = 7; l >= 2; --l) {
+        if ((e = enqueue_wgrad32(c, l, S, s)) != hipSuccess) return e;
+        if ((e = launch_conv32(1, c->d_g[l], c->d_wt + (size_t)(l - 2) * W32, nullptr, c->d_act[l - 1],
+                               c->d_g[l - 1], S, s)) != hipSuccess)
+            return e;
+    }
+    // layer 1
+    wgrad_in_kernel<<<nb, 320, 0, s>>>(c->d_g[1], c->d_a0, c->d_part, S.n, S.tiles_x, S.tiles_per_img, S.ntiles);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    reduce_part_kernel<<<cdiv(P_IN, 256), 256, 0, s>>>(c->d_part, nb, P_IN, c->d_grad + OFF_W1);
+    return hipGetLastError();
+}
+
+recon_status check_batch(recon_cnn* net, int batch, int n, bool training)
+{
+    if (!net) return fail(RECON_INVALID_ARG, "NULL network");
+    if (n < 1 || n > net->max_n) return fail(RECON_INVALID_ARG, "n must be in [1, max_n]");
+    if (batch < 1 || (training && batch > net->max_batch))
+        return fail(RECON_INVALID_ARG, training ? "batch must be in [1, max_batch]" : "batch must be >= 1");
+    return RECON_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t recon_cnn_param_count(void) { return NPARAM; }
+
+recon_status recon_cnn_create(const float* h_params, int32_t max_batch, int32_t max_n, float mu_scale,
+                              recon_cnn** out)
+{
+    if (!out) return fail(RECON_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (max_batch < 1 || max_n < 1 || max_n > 16384) return fail(RECON_INVALID_ARG, "bad max_batch or max_n");
+    if (!(mu_scale > 0) || !std::isfinite(mu_scale)) return fail(RECON_INVALID_ARG, "mu_scale must be > 0");
+    if ((double)max_batch * max_n * max_n * C * 2 > 64.0 * (1ull << 30))
+        return fail(RECON_INVALID_ARG, "workspace above 64 GiB per tensor");
+    recon_cnn* c = new (std::nothrow) recon_cnn();
+    if (!c) return fail(RECON_OOM, "host allocation failed");
+    c->max_batch = max_batch;
+    c->max_n = max_n;
+    c->mu_scale = mu_scale;
+    auto bail = [&](hipError_t e, const char* what) {
+        free_cnn(c);
+        return fail(e == hipErrorOutOfMemory ? RECON_OOM : RECON_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    const size_t px = (size_t)max_batch * max_n * max_n;
+    hipError_t e = hipSuccess;
+#define C_TRY(expr)                          \
+    do {                                     \
+        e = (expr);                          \
+        if (e != hipSuccess) return bail(e, #expr); \
+    } while (0)
+    C_TRY(hipMalloc(&c->d_theta, NPARAM * sizeof(float)));
+    C_TRY(hipMalloc(&c->d_m, NPARAM * sizeof(float)));
+    C_TRY(hipMalloc(&c->d_v, NPARAM * sizeof(float)));
+    C_TRY(hipMalloc(&c->d_grad, NPARAM * sizeof(float)));
+    C_TRY(hipMalloc(&c->d_wf, NHID * W32 * sizeof(uint16_t)));
+    C_TRY(hipMalloc(&c->d_wt, NHID * W32 * sizeof(uint16_t)));
+    C_TRY(hipMalloc(&c->d_w1r, 288 * sizeof(float)));
+    C_TRY(hipMalloc(&c->d_w8r, 288 * sizeof(float)));
+    C_TRY(hipMalloc(&c->d_a0, px * sizeof(uint16_t)));
+    for (int l = 1; l <= 7; ++l) {
+        C_TRY(hipMalloc(&c->d_act[l], px * C * sizeof(uint16_t)));
+        C_TRY(hipMalloc(&c->d_g[l], px * C * sizeof(uint16_t)));
+    }
+    C_TRY(hipMalloc(&c->d_y, px * sizeof(float)));
+    C_TRY(hipMalloc(&c->d_g8, px * sizeof(float)));
+    C_TRY(hipMalloc(&c->d_part, (size_t)WG_BLOCKS * P32 * sizeof(float)));
+    C_TRY(hipMalloc(&c->d_loss_part, cdiv((long)px, 256) * sizeof(double)));
+    if (h_params)
+        C_TRY(hipMemcpy(c->d_theta, h_params, NPARAM * sizeof(float), hipMemcpyHostToDevice));
+    else
+        C_TRY(hipMemset(c->d_theta, 0, NPARAM * sizeof(float)));
+    C_TRY(hipMemset(c->d_m, 0, NPARAM * sizeof(float)));
+    C_TRY(hipMemset(c->d_v, 0, NPARAM * sizeof(float)));
+    C_TRY(hipMemset(c->d_grad, 0, NPARAM * sizeof(float)));
+    C_TRY(launch_prep(c, nullptr));
+    C_TRY(hipDeviceSynchronize());
+#undef C_TRY
+    *out = c;
+    return RECON_OK;
+}
+
+recon_status recon_cnn_destroy(recon_cnn* net)
+{
+    if (!net) return RECON_OK;
+    (void)hipDeviceSynchronize();
+    free_cnn(net);
+    return RECON_OK;
+}
+
+recon_status recon_cnn_get_state(recon_cnn* net, float* h_params, float* h_m, float* h_v, int32_t* h_step)
+{
+    if (!net) return fail(RECON_INVALID_ARG, "NULL network");
+    RECON_HIP_TRY(hipDeviceSynchronize());
+    if (h_params) RECON_HIP_TRY(hipMemcpy(h_params, net->d_theta, NPARAM * sizeof(float), hipMemcpyDeviceToHost));
+    if (h_m) RECON_HIP_TRY(hipMemcpy(h_m, net->d_m, NPARAM * sizeof(float), hipMemcpyDeviceToHost));
+    if (h_v) RECON_HIP_TRY(hipMemcpy(h_v, net->d_v, NPARAM * sizeof(float), hipMemcpyDeviceToHost));
+    if (h_step) *h_step = net->step;
+    return RECON_OK;
+}
+
+recon_status recon_cnn_set_state(recon_cnn* net, const float* h_params, const float* h_m, const float* h_v,
+                                 int32_t step)
+{
+    if (!net) return fail(RECON_INVALID_ARG, "NULL network");
+    if (step < 0) return fail(RECON_INVALID_ARG, "step must be >= 0");
+    RECON_HIP_TRY(hipDeviceSynchronize());
+    if (h_params) RECON_HIP_TRY(hipMemcpy(net->d_theta, h_params, NPARAM * sizeof(float), hipMemcpyHostToDevice));
+    if (h_m) RECON_HIP_TRY(hipMemcpy(net->d_m, h_m, NPARAM * sizeof(float), hipMemcpyHostToDevice));
+    if (h_v) RECON_HIP_TRY(hipMemcpy(net->d_v, h_v, NPARAM * sizeof(float), hipMemcpyHostToDevice));
+    net->step = step;
+    RECON_HIP_TRY(launch_prep(net, nullptr));
+    RECON_HIP_TRY(hipDeviceSynchronize());
+    return RECON_OK;
+}
+
+recon_status recon_cnn_save(recon_cnn* net, const char* path)
+{
+    if (!net || !path) return fail(RECON_INVALID_ARG, "NULL argument");
+    std::vector<float> buf(3 * (size_t)NPARAM);
+    int32_t step = 0;
+    recon_status st = recon_cnn_get_state(net, buf.data(), buf.data() + NPARAM, buf.data() + 2 * NPARAM, &step);
+    if (st != RECON_OK) return st;
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(RECON_INVALID_ARG, std::string("cannot open ") + path);
+    const int64_t np = NPARAM;
+    const int32_t zero = 0;
+    bool ok = std::fwrite("RCNNv001", 1, 8, f) == 8 && std::fwrite(&np, 8, 1, f) == 1 &&
+              std::fwrite(&step, 4, 1, f) == 1 && std::fwrite(&zero, 4, 1, f) == 1 &&
+              std::fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? RECON_OK : fail(RECON_INVALID_ARG, std::string("write failed: ") + path);
+}
+
+recon_status recon_cnn_load(recon_cnn* net, const char* path)
+{
+    if (!net || !path) return fail(RECON_INVALID_ARG, "NULL argument");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(RECON_INVALID_ARG, std::string("cannot open ") + path);
+    char magic[8];
+    int64_t np = 0;
+    int32_t step = 0, zero = 0;
+    std::vector<float> buf(3 * (size_t)NPARAM);
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "RCNNv001", 8) == 0 &&
+              std::fread(&np, 8, 1, f) == 1 && np == NPARAM && std::fread(&step, 4, 1, f) == 1 &&
+              std::fread(&zero, 4, 1, f) == 1 && step >= 0 &&
+              std::fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    std::fclose(f);
+    if (!ok) return fail(RECON_INVALID_ARG, std::string("not a network file of this version: ") + path);
+    return recon_cnn_set_state(net, buf.data(), buf.data() + NPARAM, buf.data() + 2 * NPARAM, step);
+}
+
+recon_status recon_cnn_forward(recon_cnn* net, const float* d_mu, float* d_mu_out, int32_t batch, int32_t n,
+                               int32_t project, void* stream)
+{
+    recon_status st = check_batch(net, batch, n, false);
+    if (st != RECON_OK) return st;
+    if (!d_mu || !d_mu_out) return fail(RECON_INVALID_ARG, "NULL image");
+    hipStream_t s = as_stream(stream);
+    const size_t img = (size_t)n * n;
+    for (int b0 = 0; b0 < batch; b0 += net->max_batch) {
+        const int nb = batch - b0 < net->max_batch ? batch - b0 : net->max_batch;
+        const Shape S = shape_of(nb, n);
+        RECON_HIP_TRY(enqueue_forward(net, d_mu + b0 * img, d_mu_out + b0 * img, project ? 1 : 0, S, s));
+        net->last_batch = nb;
+        net->last_n = n;
+    }
+    return RECON_OK;
+}
+
+recon_status recon_cnn_loss_grad(recon_cnn* net, const float* d_mu, const float* d_target, int32_t batch, int32_t n,
+                                 float* d_grad, double* d_loss, void* stream)
+{
+    recon_status st = check_batch(net, batch, n, true);
+    if (st != RECON_OK) return st;
+    if (!d_mu || !d_target) return fail(RECON_INVALID_ARG, "NULL image");
+    hipStream_t s = as_stream(stream);
+    const Shape S = shape_of(batch, n);
+    RECON_HIP_TRY(enqueue_loss_grad(net, d_mu, d_target, d_loss, S, s));
+    net->last_batch = batch;
+    net->last_n = n;
+    if (d_grad)
+        RECON_HIP_TRY(hipMemcpyAsync(d_grad, net->d_grad, NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s));
+    return RECON_OK;
+}
+
+recon_status recon_cnn_adam_step(recon_cnn* net, float lr, void* stream)
+{
+    if (!net) return fail(RECON_INVALID_ARG, "NULL network");
+    if (!(lr >= 0) || !std::isfinite(lr)) return fail(RECON_INVALID_ARG, "lr must be finite and >= 0");
+    hipStream_t s = as_stream(stream);
+    const int t = net->step + 1;
+    const float c1 = (float)(1.0 / (1.0 - std::pow(0.9, t)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow(0.999, t)));
+    adam_kernel<<<cdiv(NPARAM, 256), 256, 0, s>>>(net->d_theta, net->d_m, net->d_v, net->d_grad, NPARAM, lr, c1, c2);
+    RECON_HIP_TRY(hipGetLastError());
+    RECON_HIP_TRY(launch_prep(net, s));
+    net->step = t;
+    return RECON_OK;
+}
+
+recon_status recon_cnn_train_step(recon_cnn* net, const float* d_mu, const float* d_target, int32_t batch, int32_t n,
+                                  float lr, double* d_loss, void* stream)
+{
+    recon_status st = recon_cnn_loss_grad(net, d_mu, d_target, batch, n, nullptr, d_loss, stream);
+    if (st != RECON_OK) return st;
+    return recon_cnn_adam_step(net, lr, stream);
+}
+
+recon_status recon_cnn_tensor(recon_cnn* net, int32_t kind, int32_t layer, void* d_dst, int64_t bytes, void* stream)
+{
+    if (!net || !d_dst) return fail(RECON_INVALID_ARG, "NULL argument");
+    if (net->last_batch == 0) return fail(RECON_INVALID_ARG, "no forward pass has run");
+    const size_t px = (size_t)net->last_batch * net->last_n * net->last_n;
+    const void* src = nullptr;
+    size_t size = 0;
+    if (kind == 0 && layer == 0) {
+        src = net->d_a0;
+        size = px * 2;
+    } else if (kind == 0 && layer >= 1 && layer <= 7) {
+        src = net->d_act[layer];
+        size = px * C * 2;
+    } else if (kind == 1 && layer >= 1 && layer <= 7) {
+        src = net->d_g[layer];
+        size = px * C * 2;
+    } else if (kind == 2) {
+        src = net->d_y;
+        size = px * 4;
+    } else if (kind == 3) {
+        src = net->d_g8;
+        size = px * 4;
+    } else {
+        return fail(RECON_INVALID_ARG, "bad tensor kind or layer");
+    }
+    if (bytes < (int64_t)size) return fail(RECON_INVALID_ARG, "destination too small");
+    RECON_HIP_TRY(hipMemcpyAsync(d_dst, src, size, hipMemcpyDeviceToDevice, as_stream(stream)));
+    return RECON_OK;
+}
+
+recon_status recon_cnn_time_kernels(recon_cnn* net, const float* d_mu, const float* d_target, int32_t batch, int32_t n,
+                                    int32_t reps, double* ms_out, void* stream)
+{
+    recon_status st = check_batch(net, batch, n, true);
+    if (st != RECON_OK) return st;
+    if (!d_mu || !d_target || !ms_out) return fail(RECON_INVALID_ARG, "NULL argument");
+    if (reps < 1 || reps > 10000) return fail(RECON_INVALID_ARG, "reps must be in [1, 10000]");
+    hipStream_t s = as_stream(stream);
+    const Shape S = shape_of(batch, n);
+    RECON_HIP_TRY(enqueue_loss_grad(net, d_mu, d_target, nullptr, S, s));
+    net->last_batch = batch;
+    net->last_n = n;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    RECON_HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(RECON_DEVICE, "hipEventCreate failed");
+    }
+    hipError_t err = hipSuccess;
+    auto timed = [&](auto&& launch, double* out) {
+        if (err != hipSuccess) return;
+        err = launch();
+        if (err == hipSuccess) err = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch();
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        *out = (double)ms / reps;
+    };
+    // layer 4 stands for every 32 -> 32 layer (same shapes)
+    timed([&] { return launch_conv32(0, net->d_act[3], net->d_wf + 2 * W32, net->d_theta + OFF_HID + 2 * P32 + W32,
+                                     nullptr, net->d_act[4], S, s); },
+          &ms_out[0]);
+    timed([&] { return launch_conv32(1, net->d_g[4], net->d_wt + 2 * W32, nullptr, net->d_act[3], net->d_g[3], S, s); },
+          &ms_out[1]);
+    timed([&] {
+        const int nb = wg_blocks(S);
+        wgrad32_kernel<<<nb, 256, 0, s>>>(net->d_g[4], net->d_act[3], net->d_part, S.n, S.tiles_x, S.tiles_per_img,
+                                          S.ntiles);
+        return hipGetLastError();
+    }, &ms_out[2]);
+    timed([&] { return enqueue_forward(net, d_mu, nullptr, 0, S, s); }, &ms_out[3]);
+    timed([&] { return enqueue_loss_grad(net, d_mu, d_target, nullptr, S, s); }, &ms_out[4]);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(RECON_DEVICE, std::string("timing run: ") + hipGetErrorString(err));
+    return RECON_OK;
+}
+
+}  // extern "C"

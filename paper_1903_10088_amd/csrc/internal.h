@@ -147,6 +147,7 @@ struct recon_handle {
     float* d_p = nullptr;                   // ln(I0 / max(y, 1)), subset order
     float* d_w = nullptr;                   // weighted residual per ray, subset order
     double* d_part = nullptr;               // squared-difference sums per SQ_GROUP rays of a subset
+    double* d_part_all = nullptr;           // the same over all views (full-data residual)
     recon::DevState* d_state = nullptr;     // two copies: sub-iteration reads one, writes the other
     recon::DevState* h_state = nullptr;     // pinned read-back
 
@@ -226,5 +227,8 @@ hipError_t launch_fp_batch(int segments, const SliceDesc* slices, const FpWork* 
                            hipStream_t s);
 int fp_rays_per_block(int segments);
 hipError_t launch_tv_grad(const float* img, float* grad, int n, float eps, hipStream_t s);
+// kernels.hip: out[0] = (sum of part[0..ngroups)) / nrays, out[1] = mean of 1 / max(y, 1) over counts.
+hipError_t launch_residual_final(const double* part, int ngroups, const float* counts, long nrays, double* out,
+                                 hipStream_t s);
 
 }  // namespace recon

@@ -312,6 +312,32 @@ __global__ void set_state_kernel(DevState* st, double lambda, double f_prev, int
     st->schedule = schedule;
 }
 
+// Full-data residual: one block, fixed summation order (thread-strided sums,
+// then a tree over the 256 threads).
+__global__ __launch_bounds__(256) void residual_final_kernel(const double* __restrict__ part, int ngroups,
+                                                             const float* __restrict__ counts, long nrays,
+                                                             double* __restrict__ out)
+{
+    __shared__ double r0[256], r1[256];
+    double s0 = 0.0, s1 = 0.0;
+    for (int k = threadIdx.x; k < ngroups; k += 256) s0 += part[k];
+    for (long k = threadIdx.x; k < nrays; k += 256) s1 += 1.0 / (double)fmaxf(counts[k], 1.0f);
+    r0[threadIdx.x] = s0;
+    r1[threadIdx.x] = s1;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            r0[threadIdx.x] += r0[threadIdx.x + w];
+            r1[threadIdx.x] += r1[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = r0[0] / (double)nrays;
+        out[1] = r1[0] / (double)nrays;
+    }
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------------------
@@ -415,6 +441,13 @@ hipError_t launch_set_state(DevState* st, double lambda, double f_prev, int n_gl
                             const double* schedule, hipStream_t s)
 {
     set_state_kernel<<<1, 64, 0, s>>>(st, lambda, f_prev, n_global, flags, trace, schedule);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_final(const double* part, int ngroups, const float* counts, long nrays, double* out,
+                                 hipStream_t s)
+{
+    residual_final_kernel<<<1, 256, 0, s>>>(part, ngroups, counts, nrays, out);
     return hipGetLastError();
 }
 

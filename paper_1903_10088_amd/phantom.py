@@ -235,3 +235,29 @@ def random_batch_geometry(seed: int, *, sizes=(256, 512), views=(600, 900), chan
     nc = int(rng.integers(channels[0], channels[1] + 1))
     i0 = float(10 ** rng.uniform(3, 4))
     return Geometry(n=n, pixel_mm=400.0 / n, n_views=nv, n_channels=nc), i0
+
+
+# ---------------------------------------------------------------------------
+# Seeded initial parameters of the warm-start network
+# ---------------------------------------------------------------------------
+
+CNN_LAYERS = [(1, 32)] + [(32, 32)] * 6 + [(32, 1)]
+
+
+def cnn_initial_params(seed: int, *, zero_last: bool = True, last_std: float = 0.0) -> np.ndarray:
+    """Float32 parameter vector (layout: per layer W [out][in][3][3] then b [out]).
+
+    Hidden layers: He-normal weights (std sqrt(2 / (9 in))), zero biases.  Last
+    layer: zero (the network starts as the identity map) unless zero_last is
+    False, then normal with std last_std (or He-normal when last_std is 0)."""
+    rng = np.random.default_rng([seed, 11])
+    parts = []
+    for k, (c, o) in enumerate(CNN_LAYERS):
+        std = math.sqrt(2.0 / (9 * c))
+        last = k == len(CNN_LAYERS) - 1
+        if last and zero_last:
+            W = np.zeros((o, c, 3, 3))
+        else:
+            W = rng.normal(0.0, last_std if (last and last_std > 0) else std, (o, c, 3, 3))
+        parts += [W.ravel(), np.zeros(o)]
+    return np.concatenate(parts).astype(np.float32)

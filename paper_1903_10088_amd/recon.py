@@ -47,7 +47,11 @@ EXPORTS = ["recon_default_params", "recon_status_string", "recon_last_error", "r
            "recon_project", "recon_backproject", "recon_tv_grad", "recon_os_iterate", "recon_initial_image",
            "recon_subset_size", "recon_set_launch", "recon_check_tables", "recon_count_pairs",
            "recon_time_kernels", "recon_batch_create", "recon_batch_destroy", "recon_batch_initial_images",
-           "recon_batch_run", "recon_batch_tune", "recon_batch_set_launch", "recon_batch"]
+           "recon_batch_run", "recon_batch_tune", "recon_batch_set_launch", "recon_batch",
+           "recon_cnn_param_count", "recon_cnn_create", "recon_cnn_destroy", "recon_cnn_get_state",
+           "recon_cnn_set_state", "recon_cnn_save", "recon_cnn_load", "recon_cnn_forward", "recon_cnn_loss_grad",
+           "recon_cnn_adam_step", "recon_cnn_train_step", "recon_cnn_tensor", "recon_cnn_time_kernels",
+           "recon_data_residual", "recon_warm_start"]
 
 _lib = None
 
@@ -87,6 +91,22 @@ def lib():
         L.recon_batch_tune.argtypes = [vp, PP, P(f), PP, i32, P(i32), P(i32), vp]
         L.recon_batch_set_launch.argtypes = [vp, i32, i32]
         L.recon_batch.argtypes = [P(Geometry_c), i32, i32, d, P(Params_c), PP, P(f), PP, i32, vp]
+        L.recon_data_residual.argtypes = [vp, vp, f, vp, vp, vp]
+        L.recon_warm_start.argtypes = [vp, vp, PP, P(f), PP, i32, i32, i32, d, P(d), P(d), P(i32), vp]
+        L.recon_cnn_param_count.argtypes = []
+        L.recon_cnn_param_count.restype = i64
+        L.recon_cnn_create.argtypes = [P(f), i32, i32, f, P(vp)]
+        L.recon_cnn_destroy.argtypes = [vp]
+        L.recon_cnn_get_state.argtypes = [vp, P(f), P(f), P(f), P(i32)]
+        L.recon_cnn_set_state.argtypes = [vp, P(f), P(f), P(f), i32]
+        L.recon_cnn_save.argtypes = [vp, ctypes.c_char_p]
+        L.recon_cnn_load.argtypes = [vp, ctypes.c_char_p]
+        L.recon_cnn_forward.argtypes = [vp, vp, vp, i32, i32, i32, vp]
+        L.recon_cnn_loss_grad.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp]
+        L.recon_cnn_adam_step.argtypes = [vp, f, vp]
+        L.recon_cnn_train_step.argtypes = [vp, vp, vp, i32, i32, f, vp, vp]
+        L.recon_cnn_tensor.argtypes = [vp, i32, i32, vp, i64, vp]
+        L.recon_cnn_time_kernels.argtypes = [vp, vp, vp, i32, i32, i32, P(d), vp]
         for name in EXPORTS:
             getattr(L, name)
         _lib = L
@@ -197,6 +217,16 @@ class Recon:
         out = ctypes.c_int64()
         _check(lib().recon_count_pairs(self._h, subset, ctypes.byref(out)), "recon_count_pairs")
         return int(out.value)
+
+    def data_residual(self, counts, i0: float, img):
+        """(mean (l - p)^2 over all rays, mean 1 / max(y, 1)) as a float64 CUDA tensor [2]."""
+        torch = _torch()
+        g = self.geometry
+        out = torch.empty(2, dtype=torch.float64, device=img.device)
+        _check(lib().recon_data_residual(self._h, _ptr(counts, torch.float32, (g.n_views, g.n_channels), "counts"),
+                                         float(i0), _ptr(img, torch.float32, (g.n, g.n), "img"),
+                                         _ptr(out, torch.float64, (2,), "out"), _stream()), "recon_data_residual")
+        return out
 
     def time_kernels(self, counts, i0: float, img, n_iter: int):
         """Mean kernel durations (ms) over n_iter direct-launch sub-iterations: (fp, lambda, bp_update)."""
@@ -332,6 +362,13 @@ class Batch:
                                                 _stream()), "recon_batch_initial_images")
         return imgs
 
+    def initial_images_into(self, imgs):
+        """Writes every slice's homogeneous start image into the given [n][n] tensors."""
+        torch = _torch()
+        _check(lib().recon_batch_initial_images(self._h, _ptr_array(imgs, torch.float32, self._img_shapes(), "img"),
+                                                _stream()), "recon_batch_initial_images")
+        return imgs
+
     def run(self, counts, i0s, imgs=None, n_iter: int = 1, trace: bool = False):
         """Runs n_iter sub-iterations of every slice (fresh state); imgs updated in place.
 
@@ -362,3 +399,139 @@ class Batch:
 
     def set_launch(self, fp_segments: int = 0, bp_variant: int = 0):
         _check(lib().recon_batch_set_launch(self._h, fp_segments, bp_variant), "recon_batch_set_launch")
+
+    def warm_start(self, net, counts, i0s, imgs=None, n_pre: int = 10, n_refine: int = 40, n_cold: int = 500,
+                   residual_ratio: float = 1.0):
+        """recon_warm_start: returns (imgs, residual, floor, fallback) with numpy per-slice arrays."""
+        torch = _torch()
+        n = len(self.geometries)
+        if imgs is None:
+            imgs = [torch.empty((g.n, g.n), dtype=torch.float32, device=counts[0].device) for g in self.geometries]
+        i0 = (ctypes.c_float * n)(*[float(x) for x in i0s])
+        res, flo = np.zeros(n), np.zeros(n)
+        fb = np.zeros(n, dtype=np.int32)
+        _check(lib().recon_warm_start(self._h, net._h, _ptr_array(counts, torch.float32, self._count_shapes(), "counts"),
+                                      i0, _ptr_array(imgs, torch.float32, self._img_shapes(), "img"), int(n_pre),
+                                      int(n_refine), int(n_cold), float(residual_ratio),
+                                      res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      flo.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      fb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _stream()),
+               "recon_warm_start")
+        return imgs, res, flo, fb
+
+
+def _fptr(a):
+    """Host float32 numpy array -> ctypes float pointer (None passes NULL)."""
+    if a is None:
+        return None
+    if a.dtype != np.float32 or not a.flags["C_CONTIGUOUS"]:
+        raise ValueError("host arrays must be contiguous float32")
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class Cnn:
+    """The warm-start network (recon_cnn.h) on the current HIP device."""
+
+    def __init__(self, params=None, max_batch: int = 8, max_n: int = 512, mu_scale: float = 0.0049):
+        self.max_batch, self.max_n, self.mu_scale = int(max_batch), int(max_n), float(mu_scale)
+        p = None
+        if params is not None:
+            p = np.ascontiguousarray(params, dtype=np.float32)
+            if p.size != self.param_count():
+                raise ValueError(f"params must have {self.param_count()} floats")
+        h = ctypes.c_void_p()
+        _check(lib().recon_cnn_create(_fptr(p), self.max_batch, self.max_n, self.mu_scale, ctypes.byref(h)),
+               "recon_cnn_create")
+        self._h = h
+
+    @staticmethod
+    def param_count() -> int:
+        return int(lib().recon_cnn_param_count())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().recon_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_state(self):
+        """(params, adam_m, adam_v, step) as host float32 arrays."""
+        n = self.param_count()
+        th, m, v = (np.empty(n, np.float32) for _ in range(3))
+        st = ctypes.c_int32()
+        _check(lib().recon_cnn_get_state(self._h, _fptr(th), _fptr(m), _fptr(v), ctypes.byref(st)),
+               "recon_cnn_get_state")
+        return th, m, v, int(st.value)
+
+    def set_state(self, params=None, adam_m=None, adam_v=None, step: int = 0):
+        conv = [None if a is None else np.ascontiguousarray(a, dtype=np.float32) for a in (params, adam_m, adam_v)]
+        _check(lib().recon_cnn_set_state(self._h, *[_fptr(a) for a in conv], int(step)), "recon_cnn_set_state")
+
+    def save(self, path: str):
+        _check(lib().recon_cnn_save(self._h, os.fsencode(path)), "recon_cnn_save")
+
+    def load(self, path: str):
+        _check(lib().recon_cnn_load(self._h, os.fsencode(path)), "recon_cnn_load")
+
+    def forward(self, mu, out=None, project: bool = False):
+        """mu: float32 CUDA tensor [B][n][n] (1/mm); returns mu_scale * y (in place if out is mu)."""
+        torch = _torch()
+        B, n, _ = mu.shape
+        if out is None:
+            out = torch.empty_like(mu)
+        _check(lib().recon_cnn_forward(self._h, _ptr(mu, torch.float32, (B, n, n), "mu"),
+                                       _ptr(out, torch.float32, (B, n, n), "out"), B, n, int(bool(project)),
+                                       _stream()), "recon_cnn_forward")
+        return out
+
+    def loss_grad(self, mu, target, grad=None, loss=None):
+        """Loss and gradient at the current parameters; grad (float32 [P]) and loss (float64 [1])
+        are optional CUDA tensors that receive them."""
+        torch = _torch()
+        B, n, _ = mu.shape
+        _check(lib().recon_cnn_loss_grad(self._h, _ptr(mu, torch.float32, (B, n, n), "mu"),
+                                         _ptr(target, torch.float32, (B, n, n), "target"), B, n,
+                                         _ptr(grad, torch.float32, (self.param_count(),), "grad"),
+                                         _ptr(loss, torch.float64, (1,), "loss"), _stream()), "recon_cnn_loss_grad")
+        return grad, loss
+
+    def adam_step(self, lr: float):
+        _check(lib().recon_cnn_adam_step(self._h, float(lr), _stream()), "recon_cnn_adam_step")
+
+    def train_step(self, mu, target, lr: float, loss=None):
+        torch = _torch()
+        B, n, _ = mu.shape
+        _check(lib().recon_cnn_train_step(self._h, _ptr(mu, torch.float32, (B, n, n), "mu"),
+                                          _ptr(target, torch.float32, (B, n, n), "target"), B, n, float(lr),
+                                          _ptr(loss, torch.float64, (1,), "loss"), _stream()),
+               "recon_cnn_train_step")
+        return loss
+
+    def tensor(self, kind: int, layer: int, batch: int, n: int):
+        """Internal tensor of the last call (recon_cnn_tensor): bf16 kinds come back as float32."""
+        torch = _torch()
+        if kind in (0, 1):
+            shape = (batch, n, n) if (kind == 0 and layer == 0) else (batch, n, n, 32)
+            raw = torch.empty(shape, dtype=torch.int16, device="cuda")
+        else:
+            raw = torch.empty((batch, n, n), dtype=torch.float32, device="cuda")
+        _check(lib().recon_cnn_tensor(self._h, int(kind), int(layer), ctypes.c_void_p(raw.data_ptr()),
+                                      raw.numel() * raw.element_size(), _stream()), "recon_cnn_tensor")
+        if kind in (0, 1):
+            return raw.view(torch.bfloat16).float()
+        return raw
+
+    def time_kernels(self, mu, target, reps: int = 20):
+        """Mean ms per launch: (conv32 forward, conv32 dgrad, wgrad32, forward pass, loss_grad)."""
+        torch = _torch()
+        B, n, _ = mu.shape
+        out = (ctypes.c_double * 5)()
+        _check(lib().recon_cnn_time_kernels(self._h, _ptr(mu, torch.float32, (B, n, n), "mu"),
+                                            _ptr(target, torch.float32, (B, n, n), "target"), B, n, int(reps), out,
+                                            _stream()), "recon_cnn_time_kernels")
+        return tuple(out)

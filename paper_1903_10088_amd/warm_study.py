@@ -1,0 +1,195 @@
+"""Trains the warm-start network and evaluates the warm-start pipeline against the plain method.
+
+  python -m paper_1903_10088_amd.warm_study train --out DIR     (training set + training + calibration)
+  python -m paper_1903_10088_amd.warm_study eval --weights FILE --out DIR   (full-study evaluation)
+
+train: 2000 seeded clinical-scale slices (512^2 at 0.78125 mm, 800 views, 738
+channels, I0 2e3; seeds 10000-11999, 11800-11999 held out); network input =
+the plain iterate after 10 sub-iterations, target = after 500 (20 subsets,
+beta 1e-3), both from the homogeneous start.  Writes DIR/warm_cnn.bin (the
+network file of recon_cnn_save) and DIR/train.json (losses, the calibrated
+residual limit, timings).
+
+eval: 256 full-study slices (512^2, views U{600..900}, 738 channels, I0
+log-uniform in [1e3, 1e4]; seeds 20000+): each slice's converged image (500
+sub-iterations), the plain method's RMSE to it after n sub-iterations, and the
+warm-start pipeline (10 + network + 40 refining sub-iterations, cold fallback)
+timed in batches, with per-slice latency.  Writes DIR/eval.json.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import phantom as ph
+from . import recon
+from . import warmstart as ws
+
+MU_W = ph.MU_WATER_PER_MM
+
+
+def cmd_train(args):
+    import torch
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    seeds = list(range(10000, 10000 + args.slices))
+    n_hold = args.slices // 10
+    items = ws.config3_items(seeds)
+    ws.log(f"train: generating {len(items)} count sinograms ...")
+    counts = ws.make_counts(items, workers=args.workers)
+    ws.log(f"train: counts in {time.time() - t0:.1f} s")
+    t1 = time.time()
+    runs = ws.plain_runs(items, counts, [args.n_pre, args.n_final], chunk=args.chunk, device=dev)
+    t_plain = time.time() - t1
+    ws.log(f"train: plain pairs in {t_plain:.1f} s")
+    x, y = runs[args.n_pre], runs[args.n_final]
+    ntr = len(items) - n_hold
+    xtr, ytr, xva, yva = x[:ntr], y[:ntr], x[ntr:], y[ntr:]
+    net = recon.Cnn(ph.cnn_initial_params(args.seed), max_batch=args.batch, max_n=512, mu_scale=MU_W)
+    base_val = ws.evaluate_loss(net, xva, yva, batch=args.batch)
+    ws.log(f"train: held-out loss of the identity map {base_val:.4e}")
+    # time one epoch-sized probe to fit the epoch count into the budget
+    probe = ws.train(net, xtr[:args.batch * 8], ytr[:args.batch * 8], epochs=1, batch=args.batch, lr=0.0,
+                     lr_final=0.0, seed=args.seed, augment=False)
+    torch.cuda.synchronize()
+    tp = time.time()
+    ws.train(net, xtr[:args.batch * 8], ytr[:args.batch * 8], epochs=1, batch=args.batch, lr=0.0, lr_final=0.0,
+             seed=args.seed, augment=True)
+    torch.cuda.synchronize()
+    step_s = (time.time() - tp) / 8
+    epochs = max(1, min(args.max_epochs, int(args.train_seconds / (step_s * (ntr // args.batch)))))
+    ws.log(f"train: {step_s * 1e3:.1f} ms per step of {args.batch} slices; {epochs} epochs")
+    net.set_state(ph.cnn_initial_params(args.seed), np.zeros(recon.Cnn.param_count(), np.float32),
+                  np.zeros(recon.Cnn.param_count(), np.float32), 0)
+    t2 = time.time()
+    hist = ws.train(net, xtr, ytr, epochs=epochs, batch=args.batch, lr=args.lr, lr_final=args.lr * 0.02,
+                    seed=args.seed, augment=True, val=(xva, yva))
+    t_train = time.time() - t2
+    os.makedirs(args.out, exist_ok=True)
+    wpath = os.path.join(args.out, "warm_cnn.bin")
+    net.save(wpath)
+    # fallback limit from the plain method's converged training images
+    cal = list(range(0, ntr, max(1, ntr // args.calibrate)))[:args.calibrate]
+    ratio, ratios = ws.calibrate_ratio([items[i] for i in cal], [counts[i] for i in cal], [y[i] for i in cal])
+    # held-out RMSE to the converged image: network alone, and after refinement
+    out = torch.empty_like(xva)
+    net.forward(xva, out, project=True)
+    r_in = ws.disc_rmse(xva, yva, 512) / MU_W
+    r_net = ws.disc_rmse(out, yva, 512) / MU_W
+    rec = dict(slices=len(items), held_out=n_hold, n_pre=args.n_pre, n_final=args.n_final, epochs=epochs,
+               batch=args.batch, lr=args.lr, step_ms=step_s * 1e3, train_s=t_train, plain_pairs_s=t_plain,
+               loss_identity_val=base_val, history=hist, residual_ratio_limit=ratio,
+               residual_ratios=dict(min=float(ratios.min()), median=float(np.median(ratios)),
+                                    max=float(ratios.max())),
+               val_rmse_over_muw=dict(input=float(np.mean(r_in)), network=float(np.mean(r_net))),
+               weights=os.path.basename(wpath))
+    json.dump(rec, open(os.path.join(args.out, "train.json"), "w"), indent=1)
+    ws.log(json.dumps({k: v for k, v in rec.items() if k != "history"}))
+
+
+def cmd_eval(args):
+    import torch
+
+    dev = torch.device("cuda:0")
+    items = ws.config4_items(range(20000, 20000 + args.slices))
+    ws.log(f"eval: generating {len(items)} count sinograms ...")
+    counts = ws.make_counts(items, workers=args.workers)
+    lim = json.load(open(args.train_json))["residual_ratio_limit"] if args.train_json else args.ratio
+    # converged images and the plain method's RMSE curve
+    iters = sorted(set(args.curve + [args.n_final]))
+    runs = ws.plain_runs(items, counts, iters, chunk=args.chunk, device=dev)
+    conv = runs[args.n_final]
+    curve = {k: float(np.mean(ws.disc_rmse(runs[k], conv, 512)) / MU_W) for k in iters}
+    ws.log(f"eval: plain RMSE-to-converged curve {curve}")
+    del runs
+    net = recon.Cnn(None, max_batch=8, max_n=512, mu_scale=MU_W)
+    net.load(args.weights)
+    res = dict(slices=len(items), residual_ratio_limit=lim, plain_curve=curve, batches=[])
+    warm_imgs = torch.empty_like(conv)
+    lat, fb_all, r_all = [], [], []
+    t_total = 0.0
+    for c0 in range(0, len(items), args.chunk):
+        sub = items[c0:c0 + args.chunk]
+        B = recon.Batch([g for g, _, _ in sub], 20, 1e-3)
+        cts = [torch.from_numpy(c).to(dev) for c in counts[c0:c0 + args.chunk]]
+        i0s = [i0 for _, _, i0 in sub]
+        imgs = [warm_imgs[c0 + i] for i in range(len(sub))]
+        B.warm_start(net, cts, i0s, imgs, args.n_pre, args.n_refine, args.n_final, lim)  # warm-up
+        (_, rr, fl, fb), dt = ws.timed(lambda: B.warm_start(net, cts, i0s, imgs, args.n_pre, args.n_refine,
+                                                            args.n_final, lim))
+        t_total += dt
+        lat += [dt] * len(sub)
+        fb_all += list(map(int, fb))
+        r_all += list((rr / fl).tolist())
+        res["batches"].append(dict(first=c0, slices=len(sub), seconds=dt, fallbacks=int(fb.sum())))
+        B.close()
+        ws.log(f"eval: warm batch {c0}: {dt:.3f} s, {int(fb.sum())} fallbacks")
+    r_warm = ws.disc_rmse(warm_imgs, conv, 512) / MU_W
+    rmse_w = float(np.mean(r_warm))
+    n_eq = next((k for k in iters if curve[k] <= rmse_w), args.n_final)
+    # plain batched throughput at n_eq sub-iterations (same batches, same timing)
+    t_plain = 0.0
+    for c0 in range(0, len(items), args.chunk):
+        sub = items[c0:c0 + args.chunk]
+        B = recon.Batch([g for g, _, _ in sub], 20, 1e-3)
+        cts = [torch.from_numpy(c).to(dev) for c in counts[c0:c0 + args.chunk]]
+        i0s = [i0 for _, _, i0 in sub]
+        imgs = B.initial_images(dev)
+        B.run(cts, i0s, imgs, n_eq)
+        imgs = B.initial_images(dev)
+        _, dt = ws.timed(lambda: B.run(cts, i0s, imgs, n_eq))
+        t_plain += dt
+        B.close()
+    res.update(warm=dict(rmse_to_converged_over_muw=rmse_w, slices_per_s=len(items) / t_total,
+                         latency_p50_s=float(np.percentile(lat, 50)), latency_p99_s=float(np.percentile(lat, 99)),
+                         fallbacks=int(sum(fb_all)), residual_ratio=dict(median=float(np.median(r_all)),
+                                                                         max=float(np.max(r_all)))),
+               plain_equal_rmse=dict(sub_iterations=n_eq, rmse_to_converged_over_muw=curve[n_eq],
+                                     slices_per_s=len(items) / t_plain),
+               speedup=(len(items) / t_total) / (len(items) / t_plain))
+    os.makedirs(args.out, exist_ok=True)
+    json.dump(res, open(os.path.join(args.out, "eval.json"), "w"), indent=1)
+    ws.log(json.dumps({k: v for k, v in res.items() if k != "batches"}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sp = ap.add_subparsers(dest="cmd", required=True)
+    t = sp.add_parser("train")
+    t.add_argument("--out", required=True)
+    t.add_argument("--slices", type=int, default=2000)
+    t.add_argument("--n-pre", type=int, default=10)
+    t.add_argument("--n-final", type=int, default=500)
+    t.add_argument("--batch", type=int, default=8)
+    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--train-seconds", type=float, default=300.0)
+    t.add_argument("--max-epochs", type=int, default=60)
+    t.add_argument("--calibrate", type=int, default=64)
+    t.add_argument("--chunk", type=int, default=64)
+    t.add_argument("--workers", type=int, default=12)
+    t.add_argument("--seed", type=int, default=0)
+    e = sp.add_parser("eval")
+    e.add_argument("--out", required=True)
+    e.add_argument("--weights", required=True)
+    e.add_argument("--train-json", default=None)
+    e.add_argument("--ratio", type=float, default=1.05)
+    e.add_argument("--slices", type=int, default=256)
+    e.add_argument("--n-pre", type=int, default=10)
+    e.add_argument("--n-refine", type=int, default=40)
+    e.add_argument("--n-final", type=int, default=500)
+    e.add_argument("--curve", type=int, nargs="*",
+                   default=[10, 20, 30, 40, 50, 60, 80, 100, 125, 150, 200, 250, 300, 400])
+    e.add_argument("--chunk", type=int, default=32)
+    e.add_argument("--workers", type=int, default=12)
+    args = ap.parse_args()
+    {"train": cmd_train, "eval": cmd_eval}[args.cmd](args)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,200 @@
+"""Learned warm start: training-set generation, training and evaluation driver.
+
+Orchestration only.  Every reconstruction step runs in the library's kernels
+(recon_batch_run, recon_cnn_train_step, recon_cnn_forward, recon_warm_start,
+recon_data_residual); this module draws the seeded inputs, schedules the
+calls, and measures the results.
+
+Workflow (the network is trained only on images the plain iteration produced):
+  1. `plain_runs`: for each seeded slice, the iterate after n_pre
+     sub-iterations (network input) and after n_final (target), both from the
+     homogeneous start, by the batched plain method;
+  2. `train`: Adam on random minibatches of (input, target) pairs, with the
+     eight symmetries of the square (rotations by 90 degrees and flips, which
+     map the reconstruction disc onto itself) as augmentation;
+  3. `calibrate_ratio`: the largest ratio of full-data residual to noise level
+     (recon_data_residual) over the plain method's converged training images,
+     widened by a margin: the limit above which the warm start falls back to a
+     cold start;
+  4. `disc_rmse` / `timed`: RMSE to each slice's converged image and
+     throughput of the warm-start pipeline (recon_warm_start) and of the plain
+     batched method (warm_study.py runs the comparison).
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import math
+import os
+import time
+
+import numpy as np
+
+from . import phantom as ph
+from . import recon
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# Seeded slices (CPU, process pool)
+# ---------------------------------------------------------------------------
+
+def _counts_job(args):
+    g, seed, i0 = args
+    sl = ph.make_slice(g, seed, i0, low_contrast=True, supersample=1)
+    return sl.counts
+
+
+def make_counts(items, workers: int = 12):
+    """items: list of (Geometry, seed, I0) -> list of float32 count sinograms (numpy).  Workers are
+    spawned (not forked), so they never inherit the parent's GPU state; they use no GPU."""
+    import multiprocessing as mp
+
+    workers = max(1, min(workers, len(items), os.cpu_count() or 1))
+    if workers == 1:
+        return [_counts_job(it) for it in items]
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_counts_job, items, chunksize=4))
+
+
+def config3_items(seeds):
+    """The clinical-scale slice (512^2, 800 views, 738 channels, I0 2e3) for each seed."""
+    g = ph.config1_geometry()
+    return [(g, int(s), 2e3) for s in seeds]
+
+
+def config4_items(seeds):
+    """Full-study slices: 512^2 at 0.78125 mm, views U{600..900}, 738 channels, I0 log-uniform in [1e3, 1e4]."""
+    out = []
+    for s in seeds:
+        rng = np.random.default_rng([int(s), 7])
+        nv = int(rng.integers(600, 901))
+        i0 = float(10 ** rng.uniform(3, 4))
+        out.append((ph.Geometry(n=512, pixel_mm=400.0 / 512, n_views=nv, n_channels=738), int(s), i0))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Plain-method pairs
+# ---------------------------------------------------------------------------
+
+def plain_runs(items, counts, iters, subsets: int = 20, beta: float = 1e-3, chunk: int = 64, device="cuda"):
+    """Batched plain reconstructions of every slice from the homogeneous start for each count in
+    `iters` (each a fresh run).  Returns {n_iter: float32 CUDA tensor [S][n][n]} (all slices must
+    share n)."""
+    torch = _torch()
+    n = items[0][0].n
+    out = {k: torch.empty((len(items), n, n), dtype=torch.float32, device=device) for k in iters}
+    for c0 in range(0, len(items), chunk):
+        sub = items[c0:c0 + chunk]
+        B = recon.Batch([g for g, _, _ in sub], subsets, beta)
+        cts = [torch.from_numpy(c).to(device) for c in counts[c0:c0 + chunk]]
+        i0s = [i0 for _, _, i0 in sub]
+        for k in iters:
+            imgs = [out[k][c0 + i] for i in range(len(sub))]
+            B.initial_images_into(imgs)
+            B.run(cts, i0s, imgs, k)
+        torch.cuda.synchronize()
+        B.close()
+        log(f"plain: {min(c0 + chunk, len(items))}/{len(items)} slices")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Training
+# ---------------------------------------------------------------------------
+
+def _symmetry(x, k: int):
+    """One of the eight symmetries of the square on [B][n][n] (index ops only)."""
+    torch = _torch()
+    if k >= 4:
+        x = torch.flip(x, dims=(2,))
+    return torch.rot90(x, k % 4, dims=(1, 2))
+
+
+def train(net, inputs, targets, *, epochs: int, batch: int, lr: float, lr_final: float, seed: int = 0,
+          augment: bool = True, val=None, log_every: int = 1):
+    """Adam on random minibatches; cosine learning-rate decay from lr to lr_final.  val: optional
+    (inputs, targets) evaluated (loss only) after every epoch.  Returns a list of per-epoch
+    (train_loss, val_loss)."""
+    torch = _torch()
+    S = inputs.shape[0]
+    rng = np.random.default_rng([seed, 3])
+    steps_per_epoch = S // batch
+    total = epochs * steps_per_epoch
+    loss = torch.empty(1, dtype=torch.float64, device=inputs.device)
+    hist = []
+    step = 0
+    for ep in range(epochs):
+        perm = rng.permutation(S)
+        tl = 0.0
+        for b in range(steps_per_epoch):
+            idx = torch.from_numpy(perm[b * batch:(b + 1) * batch]).to(inputs.device)
+            x, t = inputs[idx], targets[idx]
+            if augment:
+                k = int(rng.integers(8))
+                x, t = _symmetry(x, k).contiguous(), _symmetry(t, k).contiguous()
+            cur = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * step / max(1, total)))
+            net.train_step(x, t, cur, loss)
+            tl += loss.item() if b == steps_per_epoch - 1 or b % 16 == 0 else 0.0
+            step += 1
+        vl = evaluate_loss(net, *val, batch=batch) if val is not None else float("nan")
+        hist.append((loss.item(), vl))
+        if (ep + 1) % log_every == 0:
+            log(f"train: epoch {ep + 1}/{epochs} last-batch loss {loss.item():.4e} val loss {vl:.4e}")
+    return hist
+
+
+def evaluate_loss(net, inputs, targets, batch: int = 8):
+    """Mean of the per-minibatch losses (recon_cnn_loss_grad) over a set (no update)."""
+    torch = _torch()
+    loss = torch.empty(1, dtype=torch.float64, device=inputs.device)
+    tot, cnt = 0.0, 0
+    for b in range(0, inputs.shape[0] - batch + 1, batch):
+        net.loss_grad(inputs[b:b + batch], targets[b:b + batch], None, loss)
+        tot += loss.item()
+        cnt += 1
+    return tot / max(cnt, 1)
+
+
+def calibrate_ratio(items, counts, finals, margin: float = 0.02, device="cuda"):
+    """max over slices of (full-data residual / noise level) of the plain method's converged images,
+    times (1 + margin)."""
+    torch = _torch()
+    ratios = []
+    for (g, _, i0), c, img in zip(items, counts, finals):
+        R = recon.Recon(g, 20, 1e-3)
+        r = R.data_residual(torch.from_numpy(c).to(device), i0, img.contiguous()).cpu().numpy()
+        ratios.append(r[0] / r[1])
+        R.close()
+    ratios = np.asarray(ratios)
+    return float(ratios.max() * (1 + margin)), ratios
+
+
+# ---------------------------------------------------------------------------
+# Evaluation
+# ---------------------------------------------------------------------------
+
+def disc_rmse(a, b, n):
+    """Root-mean-square difference over the reconstruction disc, per slice (CUDA tensors [S][n][n])."""
+    torch = _torch()
+    c = torch.arange(n, device=a.device, dtype=torch.float64) - 0.5 * (n - 1)
+    D = (c[None, :] ** 2 + c[:, None] ** 2) <= (0.5 * n) ** 2
+    d = (a.double() - b.double())[:, D]
+    return torch.sqrt((d * d).mean(dim=1)).cpu().numpy()
+
+
+def timed(fn):
+    torch = _torch()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t

@@ -1,0 +1,89 @@
+"""The warm-start pipeline on the GPU: the full-data residual against the oracle's projector, and
+the pipeline's composition (early iterate -> network -> refinement -> residual test -> cold
+fallback) against the same steps run one by one, bit for bit, with the fallback forced both
+ways from the host through the residual limit."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_10088_amd import phantom as ph
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1903_10088_amd import recon
+    recon.lib()
+    return torch.device("cuda:0")
+
+
+def small_batch():
+    geoms = [ph.config0_geometry(),
+             ph.Geometry(n=96, pixel_mm=400 / 96, n_views=123, n_channels=150),
+             ph.Geometry(n=64, pixel_mm=6.25, n_views=64, n_channels=97)]
+    slices = [ph.make_slice(g, 500 + i, 10 ** (3.2 + 0.3 * i), low_contrast=True, supersample=1)
+              for i, g in enumerate(geoms)]
+    return geoms, slices
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_data_residual_matches_oracle(dev, k):
+    from paper_1903_10088_amd import recon
+    geoms, slices = small_batch()
+    g, sl = geoms[k], slices[k]
+    R = recon.Recon(g, 5, 1e-3)
+    counts = torch.from_numpy(sl.counts).to(dev)
+    img, _ = R.os_iterate(counts, sl.i0, None, 7)
+    out = R.data_residual(counts, sl.i0, img).cpu().numpy()
+    ell = oracle.project(g, img.cpu().numpy().astype(np.float64))
+    p = np.log(sl.i0 / np.maximum(sl.counts.astype(np.float64), 1.0))
+    ref = np.mean((ell - p) ** 2)
+    floor = np.mean(1.0 / np.maximum(sl.counts.astype(np.float64), 1.0))
+    print(f"slice {k}: residual {out[0]:.6e} (oracle {ref:.6e}), floor {out[1]:.6e}", flush=True)
+    assert abs(out[0] - ref) <= 1e-5 * ref
+    assert abs(out[1] - floor) <= 1e-12 * floor
+
+
+def test_pipeline_equals_its_steps(dev):
+    """Identity network: pipeline = n_pre plain sub-iterations, then n_refine from that image with a
+    fresh state; no fallback when the limit is generous."""
+    from paper_1903_10088_amd import recon
+    geoms, slices = small_batch()
+    M, beta, n_pre, n_ref = 5, 1e-3, 7, 11
+    B = recon.Batch(geoms, M, beta)
+    net = recon.Cnn(None, max_batch=2, max_n=128, mu_scale=ph.MU_WATER_PER_MM)
+    counts = [torch.from_numpy(s.counts).to(dev) for s in slices]
+    i0s = [s.i0 for s in slices]
+    imgs, res, flo, fb = B.warm_start(net, counts, i0s, None, n_pre, n_ref, 20, 1e6)
+    assert not fb.any()
+    ref, _ = B.run(counts, i0s, None, n_pre)
+    ref = [r.clone() for r in ref]
+    ref, _ = B.run(counts, i0s, ref, n_ref)
+    for a, b in zip(imgs, ref):
+        assert torch.equal(a, b)
+    for k, (g, sl) in enumerate(zip(geoms, slices)):
+        R = recon.Recon(g, M, beta)
+        r = R.data_residual(counts[k], sl.i0, imgs[k]).cpu().numpy()
+        assert r[0] == res[k] and r[1] == flo[k]
+
+
+def test_pipeline_falls_back_to_a_cold_start(dev):
+    """A limit below every residual sends every slice to the cold start: the result is the plain
+    n_cold-sub-iteration reconstruction from the homogeneous start."""
+    from paper_1903_10088_amd import recon
+    geoms, slices = small_batch()
+    M, beta = 5, 1e-3
+    B = recon.Batch(geoms, M, beta)
+    theta = ph.cnn_initial_params(3, zero_last=False, last_std=0.05)
+    net = recon.Cnn(theta, max_batch=2, max_n=128, mu_scale=ph.MU_WATER_PER_MM)
+    counts = [torch.from_numpy(s.counts).to(dev) for s in slices]
+    imgs, res, flo, fb = B.warm_start(net, counts, [s.i0 for s in slices], None, 4, 6, 13, 1e-9)
+    assert fb.all()
+    for k, (g, sl) in enumerate(zip(geoms, slices)):
+        R = recon.Recon(g, M, beta)
+        cold, _ = R.os_iterate(counts[k], sl.i0, None, 13)
+        assert torch.equal(imgs[k], cold)

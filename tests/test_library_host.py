@@ -99,3 +99,26 @@ def test_gather_window_covers_every_weight(name, geom, M, stride):
     assert pairs > 0
     if name != "wide-fan":  # the source grazes the grid there, so the window margin is wide
         assert cand < 1.25 * pairs  # the window is tight: few enumerated rays carry no weight
+
+
+def test_cnn_entry_points_validate_before_the_device():
+    L = recon.lib()
+    assert L.recon_cnn_param_count() == 56097
+    h = ctypes.c_void_p()
+    for args in [(0, 512, 0.0049), (8, 0, 0.0049), (8, 512, 0.0), (8, 512, float("nan")), (8, 20000, 0.0049)]:
+        assert L.recon_cnn_create(None, args[0], args[1], args[2], ctypes.byref(h)) == recon.RECON_INVALID_ARG
+        assert h.value is None
+    assert L.recon_cnn_forward(None, None, None, 1, 8, 0, None) == recon.RECON_INVALID_ARG
+    assert L.recon_cnn_loss_grad(None, None, None, 1, 8, None, None, None) == recon.RECON_INVALID_ARG
+    assert L.recon_cnn_adam_step(None, 1e-3, None) == recon.RECON_INVALID_ARG
+    assert L.recon_cnn_tensor(None, 0, 0, None, 0, None) == recon.RECON_INVALID_ARG
+    assert L.recon_cnn_save(None, b"/tmp/x") == recon.RECON_INVALID_ARG
+    assert L.recon_cnn_destroy(None) == recon.RECON_OK
+
+
+def test_cnn_initial_params_layout():
+    th = ph.cnn_initial_params(0)
+    assert th.dtype.name == "float32" and th.size == 56097
+    assert not th[-289:].any()  # last layer zero: the network starts as the identity
+    w2 = th[320:320 + 9216]
+    assert abs(w2.std() - (2.0 / 288) ** 0.5) < 0.005
