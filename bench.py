@@ -53,11 +53,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--iters", type=int, default=500, help="sub-iterations per reconstruction")
     ap.add_argument("--beta", type=float, default=1e-3)
-    ap.add_argument("--cpu-iters", type=int, default=100,
+    ap.add_argument("--cpu-iters", type=int, default=500,
                     help="sub-iterations of the oracle timed for the CPU baseline (0 = skip)")
     ap.add_argument("--time-iters", type=int, default=100, help="sub-iterations of the per-kernel timing pass")
     ap.add_argument("--fp-segments", type=int, default=0)
     ap.add_argument("--bp-variant", type=int, default=0, help="1 = global reads, 2 = LDS-staged (0 = default)")
+    ap.add_argument("--cnn-batch", type=int, default=8,
+                    help="slices per timed CNN kernel launch (512 x 512; 0 = skip the CNN leg)")
+    ap.add_argument("--warm-slices", type=int, default=32,
+                    help="full-study slices for the warm-start leg (0 = skip; needs trained weights)")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1903_10088_amd", "weights", "warm_cnn.bin"))
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 10 plain device copies of MIB MiB (reference for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -121,8 +126,9 @@ def main():
     else:
         fp_ms = bp_ms = float("nan")
     # Algorithmic bytes per launch (per unit: 4 B per ray-pixel interpolation
-    # pair read; projector 12 B per ray for y/I0 and p read and w written;
-    # update 8 B per pixel for mu read and mu' written), averaged over subsets.
+    # pair read, over every in-image pixel of the projector's matrix; projector
+    # 12 B per ray for y/I0 and p read and w written; update 8 B per pixel for
+    # mu read and mu' written), averaged over subsets.
     n_rays = [R.subset_size(s) * g.n_channels for s in range(M)]
     pairs = [R.count_pairs(s) for s in range(M)]
     npix = g.n * g.n
@@ -161,6 +167,9 @@ def main():
                   "tolerance_per_mm": 1e-4 * ph.MU_WATER_PER_MM, "ok": rmse <= 1e-4 * ph.MU_WATER_PER_MM}
         log(f"bench: cpu {cpu['value']:.4f} slices/s; GPU vs oracle rmse after {n_cpu} sub-iterations {rmse:.2e}")
 
+    cnn = cnn_leg(args.cnn_batch, dev) if args.cnn_batch > 0 else None
+    warm = warm_leg(args.warm_slices, args.weights, dev) if args.warm_slices > 0 else None
+
     out = {
         "metric": "512² slices/s to oracle RMSE: plain OS-TV vs CNN warm start; projector GB/s",
         "value": slices_per_s,
@@ -188,10 +197,104 @@ def main():
         "kernel_us": {"fp": fp_ms * 1e3, "bp_update": bp_ms * 1e3,
                       "graph_sub_iteration": sub_ms * 1e3},
         "parity": parity,
+        "cnn_kernels": cnn,
+        "warm_start": warm,
         "paper_context": {"s_per_slice": PAPER_S_PER_SLICE, "hardware": "GeForce GTX 1080 Ti",
                           "thinning": "1/20", "note": "context only; channel count and precision not stated"},
     }
     print(json.dumps(out), flush=True)
+
+
+PEAK_BF16_TFLOPS = 2500.0  # dense bf16 matrix-core peak
+
+
+def cnn_leg(batch: int, dev):
+    """Warm-start network kernels on `batch` 512 x 512 slices: mean launch time (HIP events over
+    back-to-back launches on the library's stream) of the 32-channel convolution forward, its
+    input-gradient form and the weight-gradient kernel, against the bf16 matrix-core peak and the
+    HBM peak; plus a whole forward pass and a whole loss-and-gradient pass."""
+    import numpy as np
+    import torch
+
+    from paper_1903_10088_amd import phantom as ph
+    from paper_1903_10088_amd import recon
+
+    n = 512
+    rng = np.random.default_rng(5)
+    mu = torch.from_numpy((ph.MU_WATER_PER_MM * (1 + 0.05 * rng.standard_normal((batch, n, n)))).astype(np.float32))
+    mu = mu.to(dev)
+    tgt = (mu * 1.01).contiguous()
+    net = recon.Cnn(ph.cnn_initial_params(0, zero_last=False, last_std=0.05), max_batch=batch, max_n=n,
+                    mu_scale=ph.MU_WATER_PER_MM)
+    ms = net.time_kernels(mu, tgt, reps=20)
+    torch.cuda.synchronize()
+    flops = 2.0 * 9 * 32 * 32 * batch * n * n           # one 32 -> 32 layer
+    hbm = 2.0 * batch * n * n * 32 * 2                     # bf16 activations in and out
+    out = {"batch": batch, "n": n}
+    for name, t in zip(("conv32_forward", "conv32_dgrad", "wgrad32"), ms[:3]):
+        out[name] = {"us": t * 1e3, "tflops": flops / (t * 1e-3) / 1e12,
+                     "frac_of_bf16_peak": flops / (t * 1e-3) / 1e12 / PEAK_BF16_TFLOPS,
+                     "gbps_compulsory": hbm / (t * 1e-3) / 1e9,
+                     "frac_of_hbm_peak": hbm / (t * 1e-3) / 1e9 / PEAK_HBM_GBPS}
+    out["forward_ms"] = ms[3]
+    out["loss_grad_ms"] = ms[4]
+    out["forward_slices_per_s"] = batch / (ms[3] * 1e-3)
+    log(f"bench: cnn conv32 fwd {ms[0] * 1e3:.1f} us ({out['conv32_forward']['tflops']:.0f} TFLOP/s), dgrad "
+        f"{ms[1] * 1e3:.1f} us, wgrad {ms[2] * 1e3:.1f} us; forward {ms[3]:.2f} ms, loss+grad {ms[4]:.2f} ms "
+        f"for {batch} slices")
+    return out
+
+
+def warm_leg(n_slices: int, weights: str, dev):
+    """Warm-start pipeline (10 sub-iterations, network, 40 refining, cold fallback) on full-study
+    slices (512^2, views U{600..900}, 738 channels, I0 log-uniform 1e3..1e4), against the plain
+    batched method run to the smallest sub-iteration count that reaches the same mean RMSE to each
+    slice's converged (500-sub-iteration) image."""
+    import json as _json
+
+    import numpy as np
+    import torch
+
+    from paper_1903_10088_amd import phantom as ph
+    from paper_1903_10088_amd import recon
+    from paper_1903_10088_amd import warmstart as ws
+
+    if not os.path.exists(weights):
+        log(f"bench: no trained weights at {weights}; warm-start leg skipped")
+        return None
+    meta = os.path.join(os.path.dirname(weights), "train.json")
+    ratio = _json.load(open(meta))["residual_ratio_limit"] if os.path.exists(meta) else 1.05
+    items = ws.config4_items(range(30000, 30000 + n_slices))
+    log(f"bench: warm-start leg: {n_slices} slices ...")
+    counts = ws.make_counts(items, workers=8)
+    iters = [10, 20, 30, 40, 50, 60, 80, 100, 125, 150, 200, 250, 300, 400, 500]
+    runs = ws.plain_runs(items, counts, iters, chunk=n_slices, device=dev)
+    conv = runs[500]
+    curve = {k: float(np.mean(ws.disc_rmse(runs[k], conv, 512)) / ph.MU_WATER_PER_MM) for k in iters}
+    del runs
+    net = recon.Cnn(None, max_batch=8, max_n=512, mu_scale=ph.MU_WATER_PER_MM)
+    net.load(weights)
+    B = recon.Batch([g for g, _, _ in items], 20, 1e-3)
+    cts = [torch.from_numpy(c).to(dev) for c in counts]
+    i0s = [i0 for _, _, i0 in items]
+    imgs = [torch.empty((512, 512), dtype=torch.float32, device=dev) for _ in items]
+    B.warm_start(net, cts, i0s, imgs, 10, 40, 500, ratio)
+    (_, res, flo, fb), t_warm = ws.timed(lambda: B.warm_start(net, cts, i0s, imgs, 10, 40, 500, ratio))
+    rmse_w = float(np.mean(ws.disc_rmse(torch.stack(imgs), conv, 512)) / ph.MU_WATER_PER_MM)
+    n_eq = next((k for k in iters if curve[k] <= rmse_w), 500)
+    pimgs = B.initial_images(dev)
+    B.run(cts, i0s, pimgs, n_eq)
+    pimgs = B.initial_images(dev)
+    _, t_plain = ws.timed(lambda: B.run(cts, i0s, pimgs, n_eq))
+    out = {"slices": n_slices, "warm_slices_per_s": n_slices / t_warm, "warm_rmse_to_converged_over_muw": rmse_w,
+           "fallbacks": int(fb.sum()), "residual_ratio_limit": ratio,
+           "plain_sub_iterations_at_equal_rmse": n_eq, "plain_rmse_to_converged_over_muw": curve[n_eq],
+           "plain_slices_per_s_at_equal_rmse": n_slices / t_plain, "speedup": t_plain / t_warm,
+           "plain_curve": curve}
+    log(f"bench: warm start {out['warm_slices_per_s']:.1f} slices/s at RMSE {rmse_w:.4f} mu_w "
+        f"({out['fallbacks']} fallbacks); plain needs {n_eq} sub-iterations: "
+        f"{out['plain_slices_per_s_at_equal_rmse']:.1f} slices/s; speedup {out['speedup']:.2f}")
+    return out
 
 
 if __name__ == "__main__":

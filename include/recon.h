@@ -143,7 +143,8 @@ recon_status recon_tv_grad(recon_handle* h, const float* d_img, float* d_grad, v
  * d_counts: [n_views][n_channels] transmission counts y (natural view order);
  * i0: blank-scan counts (> 0).  d_img: in = mu^(n_done) in 1/mm (pass the
  * homogeneous start from recon_initial_image for a fresh run), out = the
- * final iterate.  state: NULL = fresh run (nothing returned), else read and
+ * final iterate; the start is taken as zero outside the reconstruction disc,
+ * where the iterate is held at zero.  state: NULL = fresh run (nothing returned), else read and
  * updated (blocks until the run has finished).  d_trace: NULL or device
  * double [n_iter][2] receiving (f_n, lambda_n).  d_lambda_schedule: NULL or
  * device double [n_iter] replacing the step rule (a replay hook for parity
@@ -255,8 +256,10 @@ recon_status recon_warm_start(recon_batch_handle* b, struct recon_cnn* net, cons
 
 /* Number of (ray, in-image pixel) interpolation pairs of `subset` (-1 = all
  * views): the pixel reads of the projector and the sinogram reads of the
- * backprojector, from the handle's own ray tables.  Host, synchronous. */
-recon_status recon_count_pairs(recon_handle* h, int32_t subset, int64_t* pairs);
+ * backprojector, from the handle's own ray tables.  disc_only = 1 counts only
+ * pairs whose pixel lies in the reconstruction disc (the pixels where an
+ * iteration's iterate can be nonzero).  Host, synchronous. */
+recon_status recon_count_pairs(recon_handle* h, int32_t subset, int32_t disc_only, int64_t* pairs);
 
 /* Measurement helper: from d_img (read only) runs one sub-iteration of every
  * subset, then launches each kernel of a sub-iteration n_iter (1..4096) times

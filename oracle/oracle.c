@@ -392,7 +392,9 @@ int oracle_initial_image(const og_geometry* g, double mu0_per_mm, double* img)
  * reprojection and projection (section 3.C.2), compared with the previous
  * sub-iteration's f to step lambda (Eqs. 4-5).
  *
- * counts: [n_views][n_ch] in natural view order.  img: in/out, 1/mm.
+ * counts: [n_views][n_ch] in natural view order.  img: in/out, 1/mm; the
+ * start image is taken as zero outside the reconstruction disc (the iterate is
+ * held there at zero, reading of Eq. 1's support).
  * state: NULL for a fresh run, else resumed and updated.  trace: NULL or
  * [n_iter][2] = (f_n, lambda_n).  lambda_schedule: NULL, or [n_iter] values
  * that replace the step rule (f is still tracked). */
@@ -422,7 +424,8 @@ int oracle_os_iterate(const og_geometry* g, int32_t subsets, double beta, const 
             double x = (i - c) * g->pixel_mm, y = (j - c) * g->pixel_mm;
             mask[(size_t)j * N + i] = (x * x + y * y <= Rmm * Rmm);
         }
-    for (size_t r = 0; r < npix; ++r) mu[r] = 10.0 * img[r];
+    /* the iterate is held at zero outside the reconstruction disc, the start image included */
+    for (size_t r = 0; r < npix; ++r) mu[r] = mask[r] ? 10.0 * img[r] : 0.0;
 
     int n_done = state ? state->n_done : 0;
     double lambda = state ? state->lambda : p->lambda0;

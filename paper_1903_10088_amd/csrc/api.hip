@@ -499,7 +499,7 @@ recon_status recon_os_iterate(recon_handle* h, const float* d_counts, float i0, 
     const int n_done = state ? state->n_done : 0;
 
     HIP_TRY(launch_prep_counts(d_counts, h->d_views, G.nv, G.nch, i0, h->d_yt, h->d_p, s));
-    HIP_TRY(launch_pad_image(d_img, h->d_img[0], h->d_imgT[0], G.n, G.P, s));
+    HIP_TRY(launch_pad_image(d_img, h->d_img[0], h->d_imgT[0], G.n, G.P, s, true));
     HIP_TRY(launch_set_state(h->d_state, state ? state->lambda : h->p.lambda0, state ? state->f_prev : 0.0, n_done,
                              state ? state->flags : 0, d_trace, d_lambda_schedule, s));
 
@@ -551,7 +551,7 @@ recon_status recon_data_residual(recon_handle* h, const float* d_counts, float i
     return RECON_OK;
 }
 
-recon_status recon_count_pairs(recon_handle* h, int32_t subset, int64_t* pairs)
+recon_status recon_count_pairs(recon_handle* h, int32_t subset, int32_t disc_only, int64_t* pairs)
 {
     if (!h || !pairs) return fail(RECON_INVALID_ARG, "NULL argument");
     if (subset < -1 || subset >= h->M) return fail(RECON_INVALID_ARG, "subset out of range");
@@ -562,8 +562,9 @@ recon_status recon_count_pairs(recon_handle* h, int32_t subset, int64_t* pairs)
     for (size_t r = (size_t)q0 * G.nch; r < (size_t)(q0 + nq) * G.nch; ++r) {
         const RayGeo g = h->h_raygeo[r];
         for (int t = 0; t < G.n; ++t) {
-            const float fl = std::floor(ray_offset(g, (float)t, 0.0f));
-            total += (fl >= 0.0f && fl < (float)G.n) + (fl + 1.0f >= 0.0f && fl + 1.0f < (float)G.n);
+            const int fl = (int)std::floor(ray_offset(g, (float)t, 0.0f));
+            for (int u = fl; u <= fl + 1; ++u)
+                if (u >= 0 && u < G.n && (!disc_only || in_disc(t, u, G.n))) ++total;
         }
     }
     *pairs = total;
@@ -579,7 +580,7 @@ recon_status recon_time_kernels(recon_handle* h, const float* d_counts, float i0
     hipStream_t s = as_stream(stream);
     const Geo& G = h->geo;
     HIP_TRY(launch_prep_counts(d_counts, h->d_views, G.nv, G.nch, i0, h->d_yt, h->d_p, s));
-    HIP_TRY(launch_pad_image(d_img, h->d_img[0], h->d_imgT[0], G.n, G.P, s));
+    HIP_TRY(launch_pad_image(d_img, h->d_img[0], h->d_imgT[0], G.n, G.P, s, true));
     HIP_TRY(launch_set_state(h->d_state, h->p.lambda0, 0.0, 0, 0, nullptr, nullptr, s));
     // one sub-iteration of every subset first, so residuals and state are realistic
     for (int sub = 0; sub < h->M; ++sub) HIP_TRY(enqueue_subiter(h, sub, 0, s));

@@ -186,7 +186,7 @@ recon_status prepare(recon_batch_handle* b, const float* const* d_counts, const 
         if (!d_counts[i] || !d_imgs[i] || !(i0[i] > 0) || !std::isfinite(i0[i]))
             return fail(RECON_INVALID_ARG, "slice " + std::to_string(i) + ": NULL buffer or bad i0");
         RECON_HIP_TRY(launch_prep_counts(d_counts[i], h->d_views, G.nv, G.nch, i0[i], h->d_yt, h->d_p, s));
-        RECON_HIP_TRY(launch_pad_image(d_imgs[i], h->d_img[0], h->d_imgT[0], G.n, G.P, s));
+        RECON_HIP_TRY(launch_pad_image(d_imgs[i], h->d_img[0], h->d_imgT[0], G.n, G.P, s, true));
         RECON_HIP_TRY(launch_set_state(h->d_state, h->p.lambda0, 0.0, 0, 0, d_traces ? d_traces[i] : nullptr,
                                        nullptr, s));
     }

@@ -182,7 +182,9 @@ UpdateConst update_const(const recon_handle* h);
     } while (0)
 
 // kernels.hip
-hipError_t launch_pad_image(const float* src, float* dst, float* dstT, int n, int P, hipStream_t s);
+// mask_disc: zero outside the reconstruction disc (the iteration's start image)
+hipError_t launch_pad_image(const float* src, float* dst, float* dstT, int n, int P, hipStream_t s,
+                            bool mask_disc = false);
 hipError_t launch_unpad_image(const float* src, float* dst, int n, int P, hipStream_t s);
 hipError_t launch_initial_image(float* dst, int n, float mu0, hipStream_t s);
 hipError_t launch_prep_counts(const float* counts, const ViewRec* views, int nv, int nch, float i0, float* yt,

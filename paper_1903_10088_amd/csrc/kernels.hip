@@ -31,7 +31,7 @@ inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 // [n][n] image -> padded row-major and padded transposed copies (32x32 tiles
 // transposed through LDS so both writes are coalesced).
 __global__ __launch_bounds__(256) void pad_image_kernel(const float* __restrict__ src, float* __restrict__ dst,
-                                                        float* __restrict__ dstT, int n, int P)
+                                                        float* __restrict__ dstT, int n, int P, int mask_disc)
 {
     __shared__ float tile[32][33];
     const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void pad_image_kernel(const float* __restrict_
         const int j = by + r, i = bx + tx;
         float v = 0.0f;
         if (j < n && i < n) {
-            v = src[(size_t)j * n + i];
+            v = (mask_disc && !in_disc(i, j, n)) ? 0.0f : src[(size_t)j * n + i];
             dst[(size_t)j * P + i + PAD] = v;
         }
         tile[r][tx] = v;
@@ -344,10 +344,10 @@ __global__ __launch_bounds__(256) void residual_final_kernel(const double* __res
 // Launchers
 // ----------------------------------------------------------------------------
 
-hipError_t launch_pad_image(const float* src, float* dst, float* dstT, int n, int P, hipStream_t s)
+hipError_t launch_pad_image(const float* src, float* dst, float* dstT, int n, int P, hipStream_t s, bool mask_disc)
 {
     dim3 grid(cdiv(n, 32), cdiv(n, 32));
-    pad_image_kernel<<<grid, 256, 0, s>>>(src, dst, dstT, n, P);
+    pad_image_kernel<<<grid, 256, 0, s>>>(src, dst, dstT, n, P, mask_disc ? 1 : 0);
     return hipGetLastError();
 }
 

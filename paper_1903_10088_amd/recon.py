@@ -81,7 +81,7 @@ def lib():
         L.recon_subset_size.argtypes = [vp, i32, P(i32)]
         L.recon_set_launch.argtypes = [vp, i32, i32]
         L.recon_check_tables.argtypes = [P(Geometry_c), i32, i32, P(i64), P(i64), P(i64)]
-        L.recon_count_pairs.argtypes = [vp, i32, P(i64)]
+        L.recon_count_pairs.argtypes = [vp, i32, i32, P(i64)]
         L.recon_time_kernels.argtypes = [vp, vp, f, vp, i32, P(d), vp]
         PP = P(vp)
         L.recon_batch_create.argtypes = [P(Geometry_c), i32, i32, d, P(Params_c), P(vp)]
@@ -213,9 +213,10 @@ class Recon:
         _check(lib().recon_subset_size(self._h, subset, ctypes.byref(out)), "recon_subset_size")
         return int(out.value)
 
-    def count_pairs(self, subset: int = -1) -> int:
+    def count_pairs(self, subset: int = -1, disc_only: bool = False) -> int:
         out = ctypes.c_int64()
-        _check(lib().recon_count_pairs(self._h, subset, ctypes.byref(out)), "recon_count_pairs")
+        _check(lib().recon_count_pairs(self._h, subset, int(bool(disc_only)), ctypes.byref(out)),
+               "recon_count_pairs")
         return int(out.value)
 
     def data_residual(self, counts, i0: float, img):

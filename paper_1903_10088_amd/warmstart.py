@@ -153,15 +153,17 @@ def train(net, inputs, targets, *, epochs: int, batch: int, lr: float, lr_final:
 
 
 def evaluate_loss(net, inputs, targets, batch: int = 8):
-    """Mean of the per-minibatch losses (recon_cnn_loss_grad) over a set (no update)."""
+    """Loss (recon_cnn_loss_grad, no update) over a whole set: the minibatch losses weighted by
+    their sizes (every image has the same disc, so this is the loss of the set)."""
     torch = _torch()
     loss = torch.empty(1, dtype=torch.float64, device=inputs.device)
-    tot, cnt = 0.0, 0
-    for b in range(0, inputs.shape[0] - batch + 1, batch):
-        net.loss_grad(inputs[b:b + batch], targets[b:b + batch], None, loss)
-        tot += loss.item()
-        cnt += 1
-    return tot / max(cnt, 1)
+    tot = 0.0
+    S = inputs.shape[0]
+    for b in range(0, S, batch):
+        e = min(S, b + batch)
+        net.loss_grad(inputs[b:e].contiguous(), targets[b:e].contiguous(), None, loss)
+        tot += loss.item() * (e - b)
+    return tot / max(S, 1)
 
 
 def calibrate_ratio(items, counts, finals, margin: float = 0.02, device="cuda"):
