@@ -239,10 +239,11 @@ recon_status recon_batch(const recon_geometry* geoms, int32_t n_slices, int32_t 
  *   3. n_refine sub-iterations refine that image with a fresh step-rule state
  *      (lambda_0, subsets from 0);
  *   4. the full-data residual r and noise level v of each result are taken as
- *      in recon_data_residual;
+ *      in recon_data_residual (one projection of every view);
  *   5. every slice with r > residual_ratio * v (the level the plain iteration
  *      reaches, calibrated on its own converged images) is reconstructed again
- *      from the homogeneous start with n_cold sub-iterations.
+ *      from the homogeneous start with n_cold sub-iterations (alone, or as a
+ *      batch when there are many).
  * d_counts, d_imgs: host arrays of device pointers as in recon_batch_run
  * (d_imgs receive the results); i0: host array.  h_residual, h_floor (host
  * double[n_slices]) and h_fallback (host int32[n_slices], 1 = cold start used)

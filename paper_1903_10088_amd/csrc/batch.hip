@@ -28,7 +28,9 @@ using namespace recon;
 
 struct recon_batch_handle {
     std::vector<recon_handle*> h;  // one handle (tables + workspace) per slice
+    bool owns = true;              // destroy the handles with the batch
     int M = 1;
+    int last_in = 0;               // image / state buffer holding the last run's result
     int fp_segments = 8;
     int bp_variant = 1;
     std::vector<int> xcd;  // XCD of each slice
@@ -39,6 +41,8 @@ struct recon_batch_handle {
     int n_bp = 0;
     std::vector<FpWork*> d_fp;  // per subset
     std::vector<int> n_fp;
+    FpWork* d_fp_all = nullptr;  // every ray of every slice (full-data residual)
+    int n_fp_all = 0;
 
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -64,11 +68,13 @@ void free_batch(recon_batch_handle* b)
     drop_graphs(b);
     for (FpWork* p : b->d_fp)
         if (p) (void)hipFree(p);
+    if (b->d_fp_all) (void)hipFree(b->d_fp_all);
     if (b->d_bp) (void)hipFree(b->d_bp);
     if (b->d_subs) (void)hipFree(b->d_subs);
     if (b->d_slices) (void)hipFree(b->d_slices);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-    for (recon_handle* h : b->h) recon_destroy(h);
+    if (b->owns)
+        for (recon_handle* h : b->h) recon_destroy(h);
     delete b;
 }
 
@@ -137,7 +143,61 @@ recon_status upload_work(recon_batch_handle* b)
         RECON_HIP_TRY(hipMemcpy(b->d_fp[s], fp.data(), fp.size() * sizeof(FpWork), hipMemcpyHostToDevice));
         b->n_fp[s] = (int)fp.size();
     }
+    {
+        std::vector<std::vector<FpWork>> fl(NXCD);
+        for (int i = 0; i < n; ++i) {
+            const int nrays = b->h[i]->geo.nv * b->h[i]->geo.nch;
+            for (int r0 = 0; r0 < nrays; r0 += rpb) fl[b->xcd[i]].push_back(FpWork{i, r0});
+        }
+        const std::vector<FpWork> fp = interleave(fl, FpWork{-1, 0});
+        if (b->d_fp_all) (void)hipFree(b->d_fp_all);
+        b->d_fp_all = nullptr;
+        RECON_HIP_TRY(hipMalloc(&b->d_fp_all, std::max<size_t>(1, fp.size()) * sizeof(FpWork)));
+        RECON_HIP_TRY(hipMemcpy(b->d_fp_all, fp.data(), fp.size() * sizeof(FpWork), hipMemcpyHostToDevice));
+        b->n_fp_all = (int)fp.size();
+    }
     return RECON_OK;
+}
+
+// Slice descriptors, subset tables, XCD placement and work tables of a batch
+// whose handles are in b->h; fp_segments 0 takes the first handle's default.
+recon_status setup_batch(recon_batch_handle* b, int fp_segments)
+{
+    const int n_slices = (int)b->h.size(), subsets = b->M;
+    b->fp_segments = fp_segments > 0 ? fp_segments : b->h[0]->fp_segments;
+    assign_xcds(b);
+    std::vector<int2> subs((size_t)n_slices * subsets);
+    for (int i = 0; i < n_slices; ++i)
+        for (int s = 0; s < subsets; ++s)
+            subs[(size_t)i * subsets + s] = make_int2(b->h[i]->subset_start[s], b->h[i]->subset_count[s]);
+    RECON_HIP_TRY(hipMalloc(&b->d_subs, subs.size() * sizeof(int2)));
+    RECON_HIP_TRY(hipMemcpy(b->d_subs, subs.data(), subs.size() * sizeof(int2), hipMemcpyHostToDevice));
+    std::vector<SliceDesc> desc(n_slices);
+    for (int i = 0; i < n_slices; ++i) {
+        recon_handle* h = b->h[i];
+        SliceDesc& D = desc[i];
+        D.geo = h->geo;
+        D.pad0 = 0;
+        D.views = h->d_views;
+        D.rg = h->d_raygeo;
+        D.rm = h->d_raymeta;
+        D.img[0] = h->d_img[0];
+        D.img[1] = h->d_img[1];
+        D.imgT[0] = h->d_imgT[0];
+        D.imgT[1] = h->d_imgT[1];
+        D.yt = h->d_yt;
+        D.p = h->d_p;
+        D.w = h->d_w;
+        D.part = h->d_part;
+        D.part_all = h->d_part_all;
+        D.state = h->d_state;
+        D.subs = b->d_subs + (size_t)i * subsets;
+        D.uc = update_const(h);
+    }
+    RECON_HIP_TRY(hipMalloc(&b->d_slices, desc.size() * sizeof(SliceDesc)));
+    RECON_HIP_TRY(hipMemcpy(b->d_slices, desc.data(), desc.size() * sizeof(SliceDesc), hipMemcpyHostToDevice));
+    RECON_HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    return upload_work(b);
 }
 
 hipError_t enqueue_batch_subiter(recon_batch_handle* b, int s, int in, hipStream_t st)
@@ -220,49 +280,11 @@ recon_status recon_batch_create(const recon_geometry* geoms, int32_t n_slices, i
         }
         b->h.push_back(h);
     }
-    b->fp_segments = b->h[0]->fp_segments;
-    assign_xcds(b);
-    auto bail = [&](recon_status s) {
+    recon_status st = setup_batch(b, 0);
+    if (st != RECON_OK) {
         free_batch(b);
-        return s;
-    };
-    // slice descriptors and subset tables
-    std::vector<int2> subs((size_t)n_slices * subsets);
-    for (int i = 0; i < n_slices; ++i)
-        for (int s = 0; s < subsets; ++s)
-            subs[(size_t)i * subsets + s] = make_int2(b->h[i]->subset_start[s], b->h[i]->subset_count[s]);
-    hipError_t e = hipMalloc(&b->d_subs, subs.size() * sizeof(int2));
-    if (e == hipSuccess) e = hipMemcpy(b->d_subs, subs.data(), subs.size() * sizeof(int2), hipMemcpyHostToDevice);
-    std::vector<SliceDesc> desc(n_slices);
-    for (int i = 0; i < n_slices; ++i) {
-        recon_handle* h = b->h[i];
-        SliceDesc& D = desc[i];
-        D.geo = h->geo;
-        D.pad0 = 0;
-        D.views = h->d_views;
-        D.rg = h->d_raygeo;
-        D.rm = h->d_raymeta;
-        D.img[0] = h->d_img[0];
-        D.img[1] = h->d_img[1];
-        D.imgT[0] = h->d_imgT[0];
-        D.imgT[1] = h->d_imgT[1];
-        D.yt = h->d_yt;
-        D.p = h->d_p;
-        D.w = h->d_w;
-        D.part = h->d_part;
-        D.state = h->d_state;
-        D.subs = b->d_subs + (size_t)i * subsets;
-        D.uc = update_const(h);
+        return st;
     }
-    if (e == hipSuccess) e = hipMalloc(&b->d_slices, desc.size() * sizeof(SliceDesc));
-    if (e == hipSuccess)
-        e = hipMemcpy(b->d_slices, desc.data(), desc.size() * sizeof(SliceDesc), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
-    if (e != hipSuccess)
-        return bail(fail(e == hipErrorOutOfMemory ? RECON_OOM : RECON_DEVICE,
-                         std::string("batch setup: ") + hipGetErrorString(e)));
-    recon_status st = upload_work(b);
-    if (st != RECON_OK) return bail(st);
     *out = b;
     return RECON_OK;
 }
@@ -329,6 +351,7 @@ recon_status recon_batch_run(recon_batch_handle* b, const float* const* d_counts
         const Geo& G = b->h[i]->geo;
         RECON_HIP_TRY(launch_unpad_image(b->h[i]->d_img[in], d_imgs[i], G.n, G.P, s));
     }
+    b->last_in = in;
     return RECON_OK;
 }
 
@@ -429,37 +452,104 @@ recon_status recon_warm_start(recon_batch_handle* b, recon_cnn* net, const float
     // 1. early iterate of every slice from the homogeneous start
     recon_status st = recon_batch_initial_images(b, d_imgs, stream);
     if (st == RECON_OK) st = recon_batch_run(b, d_counts, i0, d_imgs, n_pre, nullptr, stream);
-    // 2. network estimate of the converged image, projected onto the constraints
-    for (int i = 0; i < n && st == RECON_OK; ++i)
-        st = recon_cnn_forward(net, d_imgs[i], d_imgs[i], 1, b->h[i]->geo.n, 1, stream);
-    // 3. refinement by the plain iteration, fresh step-rule state
-    if (st == RECON_OK) st = recon_batch_run(b, d_counts, i0, d_imgs, n_refine, nullptr, stream);
     if (st != RECON_OK) return st;
-    // 4. full-data residual and its noise level per slice
+    // 2. network estimate of the converged image, projected onto the constraints:
+    //    slices of one size go through the network together (staged contiguously)
+    std::vector<int> sizes;
+    for (recon_handle* h : b->h)
+        if (std::find(sizes.begin(), sizes.end(), h->geo.n) == sizes.end()) sizes.push_back(h->geo.n);
+    size_t stage_floats = 0;
+    for (int sz : sizes) {
+        size_t cnt = 0;
+        for (recon_handle* h : b->h) cnt += (h->geo.n == sz);
+        stage_floats = std::max(stage_floats, cnt * (size_t)sz * sz);
+    }
+    float* d_stage = nullptr;
     double* d_res = nullptr;
-    RECON_HIP_TRY(hipMalloc(&d_res, 2 * sizeof(double) * n));
+    const float** d_cptr = nullptr;
+    auto cleanup = [&]() {
+        if (d_stage) (void)hipFree(d_stage);
+        if (d_res) (void)hipFree(d_res);
+        if (d_cptr) (void)hipFree(d_cptr);
+    };
+    hipError_t e = hipMalloc(&d_stage, stage_floats * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&d_res, 2 * sizeof(double) * n);
+    if (e == hipSuccess) e = hipMalloc((void**)&d_cptr, sizeof(float*) * n);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_cptr, d_counts, sizeof(float*) * n, hipMemcpyHostToDevice, s);
+    for (size_t k = 0; k < sizes.size() && e == hipSuccess && st == RECON_OK; ++k) {
+        const int sz = sizes[k];
+        const size_t img = (size_t)sz * sz;
+        int cnt = 0;
+        for (int i = 0; i < n && e == hipSuccess; ++i)
+            if (b->h[i]->geo.n == sz)
+                e = hipMemcpyAsync(d_stage + (cnt++) * img, d_imgs[i], img * sizeof(float), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) break;
+        st = recon_cnn_forward(net, d_stage, d_stage, cnt, sz, 1, stream);
+        cnt = 0;
+        for (int i = 0; i < n && e == hipSuccess && st == RECON_OK; ++i)
+            if (b->h[i]->geo.n == sz)
+                e = hipMemcpyAsync(d_imgs[i], d_stage + (cnt++) * img, img * sizeof(float), hipMemcpyDeviceToDevice, s);
+    }
+    // 3. refinement by the plain iteration, fresh step-rule state
+    if (e == hipSuccess && st == RECON_OK) st = recon_batch_run(b, d_counts, i0, d_imgs, n_refine, nullptr, stream);
+    // 4. full-data residual and its noise level, every slice at once from the final iterate
+    //    (one projection of every view; the last refining epoch's own squared differences lag
+    //    the still-moving iterate and would not be comparable with converged images)
+    if (e == hipSuccess && st == RECON_OK)
+        e = launch_fp_batch(b->fp_segments, b->d_slices, b->d_fp_all, b->n_fp_all, -1, b->last_in, s);
+    if (e == hipSuccess && st == RECON_OK) e = launch_residual_final_batch(b->d_slices, d_cptr, n, d_res, s);
     std::vector<double> res(2 * (size_t)n);
-    for (int i = 0; i < n && st == RECON_OK; ++i)
-        st = recon_data_residual(b->h[i], d_counts[i], i0[i], d_imgs[i], d_res + 2 * i, stream);
-    hipError_t e = hipSuccess;
-    if (st == RECON_OK) e = hipMemcpyAsync(res.data(), d_res, 2 * sizeof(double) * n, hipMemcpyDeviceToHost, s);
-    if (st == RECON_OK && e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(d_res);
+    if (e == hipSuccess && st == RECON_OK)
+        e = hipMemcpyAsync(res.data(), d_res, 2 * sizeof(double) * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && st == RECON_OK) e = hipStreamSynchronize(s);
+    cleanup();
     if (st != RECON_OK) return st;
-    if (e != hipSuccess) return fail(RECON_DEVICE, std::string("residual read-back: ") + hipGetErrorString(e));
-    // 5. cold start for every slice whose data residual exceeds the limit
+    if (e != hipSuccess) return fail(RECON_DEVICE, std::string("warm start: ") + hipGetErrorString(e));
+    // 5. cold start, batched, for every slice whose data residual exceeds the limit
+    std::vector<int> fb;
     for (int i = 0; i < n; ++i) {
-        const bool fb = !(res[2 * i] <= residual_ratio * res[2 * i + 1]);
+        const bool bad = !(res[2 * i] <= residual_ratio * res[2 * i + 1]);
         if (h_residual) h_residual[i] = res[2 * i];
         if (h_floor) h_floor[i] = res[2 * i + 1];
-        if (h_fallback) h_fallback[i] = fb ? 1 : 0;
-        if (!fb) continue;
-        st = recon_initial_image(b->h[i], d_imgs[i], stream);
-        if (st == RECON_OK) st = recon_os_iterate(b->h[i], d_counts[i], i0[i], d_imgs[i], n_cold, nullptr, nullptr,
-                                                  nullptr, stream);
-        if (st != RECON_OK) return st;
+        if (h_fallback) h_fallback[i] = bad ? 1 : 0;
+        if (bad) fb.push_back(i);
     }
-    RECON_HIP_TRY(hipStreamSynchronize(s));
+    if (fb.empty()) return RECON_OK;
+    // A few slices run alone on their own handles (cached graphs, no set-up);
+    // many go through a batch over their handles.  Both give the same bits.
+    constexpr size_t kSubBatchMin = 8;
+    if (fb.size() < kSubBatchMin) {
+        for (int i : fb) {
+            st = recon_initial_image(b->h[i], d_imgs[i], stream);
+            if (st == RECON_OK)
+                st = recon_os_iterate(b->h[i], d_counts[i], i0[i], d_imgs[i], n_cold, nullptr, nullptr, nullptr,
+                                      stream);
+            if (st != RECON_OK) return st;
+        }
+        RECON_HIP_TRY(hipStreamSynchronize(s));
+        return RECON_OK;
+    }
+    recon_batch_handle* sub = new (std::nothrow) recon_batch_handle();
+    if (!sub) return fail(RECON_OOM, "host allocation failed");
+    sub->owns = false;
+    sub->M = b->M;
+    sub->bp_variant = b->bp_variant;
+    std::vector<const float*> c_sub;
+    std::vector<float> i0_sub;
+    std::vector<float*> img_sub;
+    for (int i : fb) {
+        sub->h.push_back(b->h[i]);
+        c_sub.push_back(d_counts[i]);
+        i0_sub.push_back(i0[i]);
+        img_sub.push_back(d_imgs[i]);
+    }
+    st = setup_batch(sub, b->fp_segments);
+    if (st == RECON_OK) st = recon_batch_initial_images(sub, img_sub.data(), stream);
+    if (st == RECON_OK) st = recon_batch_run(sub, c_sub.data(), i0_sub.data(), img_sub.data(), n_cold, nullptr, stream);
+    hipError_t se = hipStreamSynchronize(s);
+    free_batch(sub);
+    if (st != RECON_OK) return st;
+    if (se != hipSuccess) return fail(RECON_DEVICE, std::string("cold start: ") + hipGetErrorString(se));
     return RECON_OK;
 }
 

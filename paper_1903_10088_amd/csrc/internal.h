@@ -104,6 +104,7 @@ struct SliceDesc {
     const float* p;
     float* w;
     double* part;
+    double* part_all;  // squared-difference sums per SQ_GROUP rays over all views
     DevState* state;   // two copies
     const int2* subs;  // per subset: (first subset-ordered view, number of views)
     UpdateConst uc;
@@ -224,7 +225,8 @@ hipError_t launch_bp_update(const Geo& geo, int variant, const UpdateArgs& a, hi
 hipError_t launch_bp_update_batch(int variant, const SliceDesc* slices, const BpWork* work, int nblocks, int sub,
                                   int in, StepRule rule, hipStream_t s);
 // kernels.hip, batched projector: block b projects rays [r0, r0 + 256/segments)
-// of slice work[b].slice's subset s from image buffer `in`.
+// of slice work[b].slice's subset s (s = -1: all views, sums into part_all)
+// from image buffer `in`.
 hipError_t launch_fp_batch(int segments, const SliceDesc* slices, const FpWork* work, int nblocks, int sub, int in,
                            hipStream_t s);
 int fp_rays_per_block(int segments);
@@ -232,5 +234,8 @@ hipError_t launch_tv_grad(const float* img, float* grad, int n, float eps, hipSt
 // kernels.hip: out[0] = (sum of part[0..ngroups)) / nrays, out[1] = mean of 1 / max(y, 1) over counts.
 hipError_t launch_residual_final(const double* part, int ngroups, const float* counts, long nrays, double* out,
                                  hipStream_t s);
+// kernels.hip: the same for every slice of a batch (block i -> out[2i], out[2i + 1]).
+hipError_t launch_residual_final_batch(const SliceDesc* slices, const float* const* counts, int n_slices,
+                                       double* out, hipStream_t s);
 
 }  // namespace recon

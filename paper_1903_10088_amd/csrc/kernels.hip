@@ -261,7 +261,7 @@ __global__ __launch_bounds__(256) void fp_batch_kernel(const SliceDesc* __restri
     const FpWork wk = work[blockIdx.x];
     if (wk.slice < 0) return;
     const SliceDesc* __restrict__ D = slices + wk.slice;
-    const int2 sq = D->subs[s];
+    const int2 sq = s >= 0 ? D->subs[s] : make_int2(0, D->geo.nv);
     FpArgs A{};
     A.img = as_global(D->img[in]);
     A.imgT = as_global(D->imgT[in]);
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(256) void fp_batch_kernel(const SliceDesc* __restri
     A.yt = as_global(D->yt);
     A.p = as_global(D->p);
     A.w = as_global(D->w);
-    A.part = as_global(D->part);
+    A.part = as_global(s >= 0 ? D->part : D->part_all);
     fp_body<SEG, true>(A, wk.r0);
 }
 
@@ -335,6 +335,36 @@ __global__ __launch_bounds__(256) void residual_final_kernel(const double* __res
     if (threadIdx.x == 0) {
         out[0] = r0[0] / (double)nrays;
         out[1] = r1[0] / (double)nrays;
+    }
+}
+
+// Batched full-data residual: block i reduces slice i.
+__global__ __launch_bounds__(256) void residual_final_batch_kernel(const SliceDesc* __restrict__ slices,
+                                                                   const float* const* __restrict__ counts,
+                                                                   double* __restrict__ out)
+{
+    __shared__ double r0[256], r1[256];
+    const SliceDesc* __restrict__ D = slices + blockIdx.x;
+    const long nrays = (long)D->geo.nv * D->geo.nch;
+    const int ngroups = (int)((nrays + SQ_GROUP - 1) / SQ_GROUP);
+    const double* __restrict__ part = D->part_all;
+    const float* __restrict__ y = counts[blockIdx.x];
+    double s0 = 0.0, s1 = 0.0;
+    for (int k = threadIdx.x; k < ngroups; k += 256) s0 += part[k];
+    for (long k = threadIdx.x; k < nrays; k += 256) s1 += 1.0 / (double)fmaxf(y[k], 1.0f);
+    r0[threadIdx.x] = s0;
+    r1[threadIdx.x] = s1;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            r0[threadIdx.x] += r0[threadIdx.x + w];
+            r1[threadIdx.x] += r1[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x] = r0[0] / (double)nrays;
+        out[2 * blockIdx.x + 1] = r1[0] / (double)nrays;
     }
 }
 
@@ -448,6 +478,14 @@ hipError_t launch_residual_final(const double* part, int ngroups, const float* c
                                  hipStream_t s)
 {
     residual_final_kernel<<<1, 256, 0, s>>>(part, ngroups, counts, nrays, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_final_batch(const SliceDesc* slices, const float* const* counts, int n_slices,
+                                       double* out, hipStream_t s)
+{
+    if (n_slices <= 0) return hipSuccess;
+    residual_final_batch_kernel<<<n_slices, 256, 0, s>>>(slices, counts, out);
     return hipGetLastError();
 }
 

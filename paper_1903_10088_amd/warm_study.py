@@ -76,7 +76,7 @@ def cmd_train(args):
     net.save(wpath)
     # fallback limit from the plain method's converged training images
     cal = list(range(0, ntr, max(1, ntr // args.calibrate)))[:args.calibrate]
-    ratio, ratios = ws.calibrate_ratio([items[i] for i in cal], [counts[i] for i in cal], [y[i] for i in cal])
+    ratio, ratios = ws.calibrate_ratio([items[i] for i in cal], [counts[i] for i in cal], n_final=args.n_final)
     # held-out RMSE to the converged image: network alone, and after refinement
     out = torch.empty_like(xva)
     net.forward(xva, out, project=True)
@@ -91,6 +91,24 @@ def cmd_train(args):
                weights=os.path.basename(wpath))
     json.dump(rec, open(os.path.join(args.out, "train.json"), "w"), indent=1)
     ws.log(json.dumps({k: v for k, v in rec.items() if k != "history"}))
+
+
+def cmd_calibrate(args):
+    """Recomputes the fallback limit of a trained network's record from the plain method's
+    converged images of training slices (the first `calibrate` training seeds)."""
+    rec = json.load(open(args.train_json))
+    n_hold = rec["slices"] // 10
+    ntr = rec["slices"] - n_hold
+    seeds = [10000 + i for i in range(0, ntr, max(1, ntr // args.calibrate))][:args.calibrate]
+    items = ws.config3_items(seeds)
+    counts = ws.make_counts(items, workers=args.workers)
+    ratio, ratios = ws.calibrate_ratio(items, counts, n_final=rec["n_final"])
+    rec["residual_ratio_limit"] = ratio
+    rec["residual_ratios"] = dict(min=float(ratios.min()), median=float(np.median(ratios)), max=float(ratios.max()))
+    rec["residual_statistic"] = "full-data mean (l - p)^2 / mean 1/max(y,1) (recon_data_residual)"
+    os.makedirs(args.out, exist_ok=True)
+    json.dump(rec, open(os.path.join(args.out, "train.json"), "w"), indent=1)
+    ws.log(json.dumps({k: rec[k] for k in ("residual_ratio_limit", "residual_ratios")}))
 
 
 def cmd_eval(args):
@@ -174,6 +192,11 @@ def main():
     t.add_argument("--chunk", type=int, default=64)
     t.add_argument("--workers", type=int, default=12)
     t.add_argument("--seed", type=int, default=0)
+    c = sp.add_parser("calibrate")
+    c.add_argument("--out", required=True)
+    c.add_argument("--train-json", required=True)
+    c.add_argument("--calibrate", type=int, default=64)
+    c.add_argument("--workers", type=int, default=12)
     e = sp.add_parser("eval")
     e.add_argument("--out", required=True)
     e.add_argument("--weights", required=True)
@@ -188,7 +211,7 @@ def main():
     e.add_argument("--chunk", type=int, default=32)
     e.add_argument("--workers", type=int, default=12)
     args = ap.parse_args()
-    {"train": cmd_train, "eval": cmd_eval}[args.cmd](args)
+    {"train": cmd_train, "calibrate": cmd_calibrate, "eval": cmd_eval}[args.cmd](args)
 
 
 if __name__ == "__main__":

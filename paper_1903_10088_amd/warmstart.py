@@ -166,16 +166,22 @@ def evaluate_loss(net, inputs, targets, batch: int = 8):
     return tot / max(S, 1)
 
 
-def calibrate_ratio(items, counts, finals, margin: float = 0.02, device="cuda"):
-    """max over slices of (full-data residual / noise level) of the plain method's converged images,
-    times (1 + margin)."""
+def calibrate_ratio(items, counts, subsets: int = 20, beta: float = 1e-3, n_final: int = 500,
+                    margin: float = 0.02, device="cuda"):
+    """Largest (full-data residual / noise floor) (recon_data_residual) of the plain method's
+    converged images, times (1 + margin): the limit above which the warm start falls back to a cold
+    start."""
     torch = _torch()
+    B = recon.Batch([g for g, _, _ in items], subsets, beta)
+    cts = [torch.from_numpy(c).to(device) for c in counts]
+    imgs, _ = B.run(cts, [i0 for _, _, i0 in items], None, n_final)
     ratios = []
-    for (g, _, i0), c, img in zip(items, counts, finals):
-        R = recon.Recon(g, 20, 1e-3)
-        r = R.data_residual(torch.from_numpy(c).to(device), i0, img.contiguous()).cpu().numpy()
+    for (g, _, i0), c, img in zip(items, cts, imgs):
+        R = recon.Recon(g, subsets, beta)
+        r = R.data_residual(c, i0, img).cpu().numpy()
         ratios.append(r[0] / r[1])
         R.close()
+    B.close()
     ratios = np.asarray(ratios)
     return float(ratios.max() * (1 + margin)), ratios
 

@@ -87,3 +87,22 @@ def test_pipeline_falls_back_to_a_cold_start(dev):
         R = recon.Recon(g, M, beta)
         cold, _ = R.os_iterate(counts[k], sl.i0, None, 13)
         assert torch.equal(imgs[k], cold)
+
+
+def test_many_fallbacks_go_through_a_batch(dev):
+    """Nine slices, all sent to the cold start (the batched cold-start path): each equals its own
+    single-slice cold reconstruction."""
+    from paper_1903_10088_amd import recon
+    geoms = [ph.Geometry(n=48 + 8 * (i % 3), pixel_mm=6.0, n_views=40 + 3 * i, n_channels=70 + i)
+             for i in range(9)]
+    slices = [ph.make_slice(g, 700 + i, 5e3, low_contrast=True, supersample=1) for i, g in enumerate(geoms)]
+    M, beta = 4, 1e-3
+    B = recon.Batch(geoms, M, beta)
+    net = recon.Cnn(None, max_batch=4, max_n=64, mu_scale=ph.MU_WATER_PER_MM)
+    counts = [torch.from_numpy(s.counts).to(dev) for s in slices]
+    imgs, _, _, fb = B.warm_start(net, counts, [s.i0 for s in slices], None, 3, 5, 9, 1e-9)
+    assert fb.all()
+    for k, (g, sl) in enumerate(zip(geoms, slices)):
+        R = recon.Recon(g, M, beta)
+        cold, _ = R.os_iterate(counts[k], sl.i0, None, 9)
+        assert torch.equal(imgs[k], cold), k
