@@ -25,6 +25,7 @@ from __future__ import annotations
 import concurrent.futures as cf
 import math
 import os
+import sys
 import time
 
 import numpy as np
@@ -39,7 +40,8 @@ def _torch():
 
 
 def log(*a):
-    print(*a, flush=True)
+    """Progress lines go to stderr (stdout stays free for results)."""
+    print(*a, file=sys.stderr, flush=True)
 
 
 # ---------------------------------------------------------------------------
