@@ -274,8 +274,9 @@ recon_status recon_time_kernels(recon_handle* h, const float* d_counts, float i0
 
 /* Host-only self-check of the ray tables (no GPU needed): for every
  * view_stride-th view and every pixel, counts the (pixel, ray) pairs with a
- * nonzero interpolation weight that the backprojector's candidate window would
- * miss (*missed, must be 0), the candidates it enumerates (*candidates) and
+ * nonzero interpolation weight that the backprojector's candidate windows
+ * (the per-pixel windows and the per-tile linear windows of the LDS-staged
+ * gather) would miss (*missed, must be 0), the per-pixel candidates (*candidates) and
  * the nonzero pairs (*pairs); also counts projector samples outside a ray's
  * stored sample range into *missed. */
 recon_status recon_check_tables(const recon_geometry* geom, int32_t subsets, int32_t view_stride, int64_t* missed,

@@ -646,6 +646,27 @@ recon_status recon_check_tables(const recon_geometry* geom, int32_t subsets, int
         }
         int x0, x1, y0, y1;
         major_intervals(v, nch, x0, x1, y0, y1);
+        // the staged gather's per-tile linear windows
+        for (int tj0 = 0; tj0 < N; tj0 += 16)
+            for (int ti0 = 0; ti0 < N; ti0 += 16) {
+                const TileView tv = tile_view(G, v, (float)ti0 + 7.5f - G.c, (float)tj0 + 7.5f - G.c);
+                for (int j = tj0; j < std::min(N, tj0 + 16); ++j)
+                    for (int i = ti0; i < std::min(N, ti0 + 16); ++i) {
+                        const float dX = (float)(i - ti0) - 7.5f, dY = (float)(j - tj0) - 7.5f;
+                        const float kp = fmaf(tv.gx, dX, fmaf(tv.gy, dY, tv.kpc));
+                        int lo, hi;
+                        candidate_range(kp, tv.hwx, x0, x1, lo, hi);
+                        for (int k = x0; k < x1; ++k)
+                            if (hat(ray_offset(T.rg[(size_t)q * nch + k], (float)i, (float)j)) > 0.0f &&
+                                (k < lo || k > hi))
+                                ++miss;
+                        candidate_range(kp, tv.hwy, y0, y1, lo, hi);
+                        for (int k = y0; k < y1; ++k)
+                            if (hat(ray_offset(T.rg[(size_t)q * nch + k], (float)j, (float)i)) > 0.0f &&
+                                (k < lo || k > hi))
+                                ++miss;
+                    }
+            }
         for (int j = 0; j < N; ++j)
             for (int i = 0; i < N; ++i) {
                 const PixelView pv = pixel_view(G, v, (float)i - G.c, (float)j - G.c);

@@ -119,6 +119,7 @@ struct StageLds {
     float w[STAGE_VIEWS][STAGE_ROW];
     int k0[STAGE_VIEWS];
     int cnt[STAGE_VIEWS];  // staged channels, 0 = view not staged
+    TileView tv[STAGE_VIEWS];
 };
 
 // g_L at pixel (i, j) of a 16x16 tile with LDS staging.  Must be called by all
@@ -128,32 +129,25 @@ __device__ __forceinline__ float gather_staged(StageLds& S, const Geo& G, const 
                                                int nq, int i, int j, bool inside, int ti0, int tj0)
 {
     const int tid = threadIdx.x;
-    const float X = (float)i - G.c, Y = (float)j - G.c;
     const float fi = (float)i, fj = (float)j;
-    // tile corners (pixel centres), clipped to the image; (ti0, tj0) = first pixel of the tile
-    const int ti1 = min(ti0 + TILE - 1, G.n - 1), tj1 = min(tj0 + TILE - 1, G.n - 1);
+    // offsets from the tile centre (exact in float32)
+    const float dX = (float)(i - ti0) - 7.5f, dY = (float)(j - tj0) - 7.5f;
+    const float Xc = (float)ti0 + 7.5f - G.c, Yc = (float)tj0 + 7.5f - G.c;
     float acc = 0.0f;
     for (int c0 = q0; c0 < q0 + nq; c0 += STAGE_VIEWS) {
         const int cv = min(STAGE_VIEWS, q0 + nq - c0);
         if (tid < cv) {
-            // channel range of the whole tile: the fan angle over a convex tile is
-            // extreme at its corners; widen by the largest window half-width
+            // the view's linear channel model over the tile and the channel range
+            // that holds every pixel's window
             const ViewRec v = V[c0 + tid];
-            float kmin = 3.0e38f, kmax = -3.0e38f, hw = 0.0f;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const float cx = (float)((c & 1) ? ti1 : ti0) - G.c;
-                const float cy = (float)((c & 2) ? tj1 : tj0) - G.c;
-                const PixelView pv = pixel_view(G, v, cx, cy);
-                kmin = fminf(kmin, pv.kp);
-                kmax = fmaxf(kmax, pv.kp);
-                hw = fmaxf(hw, fmaxf(pv.hwx, pv.hwy));
-            }
-            const int k0 = max(0, (int)floorf(kmin - 1.25f * hw) - 1);
-            const int k1 = min(G.nch - 1, (int)ceilf(kmax + 1.25f * hw) + 1);
+            const TileView tv = tile_view(G, v, Xc, Yc);
+            const float spread = (fabsf(tv.gx) + fabsf(tv.gy)) * 7.5f + fmaxf(tv.hwx, tv.hwy);
+            const int k0 = max(0, (int)floorf(tv.kpc - spread) - 1);
+            const int k1 = min(G.nch - 1, (int)ceilf(tv.kpc + spread) + 1);
             const int cnt = k1 - k0 + 1;
             S.k0[tid] = k0;
             S.cnt[tid] = (cnt > 0 && cnt <= STAGE_SLOTS) ? cnt : 0;
+            S.tv[tid] = tv;
         }
         __syncthreads();
         for (int slot = tid; slot < cv * STAGE_SLOTS; slot += 256) {
@@ -170,13 +164,14 @@ __device__ __forceinline__ float gather_staged(StageLds& S, const Geo& G, const 
             for (int cq = 0; cq < cv; ++cq) {
                 const ViewRec v = V[c0 + cq];
                 const int k0 = S.k0[cq], cnt = S.cnt[cq];
-                const PixelView pv = pixel_view(G, v, X, Y);
+                const TileView tv = S.tv[cq];
+                const float kp = fmaf(tv.gx, dX, fmaf(tv.gy, dY, tv.kpc));
                 int x0, x1, y0, y1;
                 major_intervals(v, G.nch, x0, x1, y0, y1);
                 const LdsRead lds{S.geo[cq], S.w[cq], k0};
                 if (x0 < x1) {
                     int lo, hi;
-                    candidate_range(pv.kp, pv.hwx, x0, x1, lo, hi);
+                    candidate_range(kp, tv.hwx, x0, x1, lo, hi);
                     if (lo <= hi) {
                         if (lo >= k0 && hi < k0 + cnt)
                             acc = add_window(acc, lo, hi, fi, fj, lds);
@@ -186,7 +181,7 @@ __device__ __forceinline__ float gather_staged(StageLds& S, const Geo& G, const 
                 }
                 if (y0 < y1) {
                     int lo, hi;
-                    candidate_range(pv.kp, pv.hwy, y0, y1, lo, hi);
+                    candidate_range(kp, tv.hwy, y0, y1, lo, hi);
                     if (lo <= hi) {
                         if (lo >= k0 && hi < k0 + cnt)
                             acc = add_window(acc, lo, hi, fj, fi, lds);

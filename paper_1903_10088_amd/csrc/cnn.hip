@@ -272,8 +272,13 @@ __global__ __launch_bounds__(256) void conv_out_kernel(const uint16_t* __restric
                                                        int tiles_per_img, int nblocks)
 {
     __shared__ __attribute__((aligned(16))) uint16_t s[HALO][HALO][LDS_PIX];
+    __shared__ __attribute__((aligned(16))) float wt[9][C];  // tap-major: 8 channels per two 16-byte reads
     const Tile tl = tile_of(blockIdx.x, nblocks, tiles_x, tiles_per_img);
     load_halo(s, a7, tl, n);
+    for (int e = threadIdx.x; e < 9 * C; e += blockDim.x) {
+        const int c = e / 9, tap = e - c * 9;
+        wt[tap][c] = w8r[e];
+    }
     __syncthreads();
     const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
     const int i = tl.i0 + ty, j = tl.j0 + tx;
@@ -283,18 +288,19 @@ __global__ __launch_bounds__(256) void conv_out_kernel(const uint16_t* __restric
     for (int tap = 0; tap < 9; ++tap) {
         const int ky = tap / 3, kx = tap - ky * 3;
         const u32x4* src = (const u32x4*)(&s[ty + ky][tx + kx][0]);
+        const float4* wv = (const float4*)(&wt[tap][0]);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const u32x4 v = src[q];
-            const int c = q * 8;
-            z = fmaf(w8r[(c + 0) * 9 + tap], bf_lo(v.x), z);
-            z = fmaf(w8r[(c + 1) * 9 + tap], bf_hi(v.x), z);
-            z = fmaf(w8r[(c + 2) * 9 + tap], bf_lo(v.y), z);
-            z = fmaf(w8r[(c + 3) * 9 + tap], bf_hi(v.y), z);
-            z = fmaf(w8r[(c + 4) * 9 + tap], bf_lo(v.z), z);
-            z = fmaf(w8r[(c + 5) * 9 + tap], bf_hi(v.z), z);
-            z = fmaf(w8r[(c + 6) * 9 + tap], bf_lo(v.w), z);
-            z = fmaf(w8r[(c + 7) * 9 + tap], bf_hi(v.w), z);
+            const float4 w0 = wv[2 * q], w1 = wv[2 * q + 1];
+            z = fmaf(w0.x, bf_lo(v.x), z);
+            z = fmaf(w0.y, bf_hi(v.x), z);
+            z = fmaf(w0.z, bf_lo(v.y), z);
+            z = fmaf(w0.w, bf_hi(v.y), z);
+            z = fmaf(w1.x, bf_lo(v.z), z);
+            z = fmaf(w1.y, bf_hi(v.z), z);
+            z = fmaf(w1.z, bf_lo(v.w), z);
+            z = fmaf(w1.w, bf_hi(v.w), z);
         }
     }
     const size_t p = pix(tl.b, i, j, n);
@@ -517,79 +523,141 @@ __global__ __launch_bounds__(256) void wgrad32_kernel(const uint16_t* __restrict
 
 // Weight gradients of the first layer (g1 x a0; 288 weights + 32 biases) and
 // of the last (g8 x a7; 288 weights + 1 bias), float32 on the vector ALUs.
-// 320 threads; thread k owns output k of the partial row.
-__global__ __launch_bounds__(320) void wgrad_in_kernel(const uint16_t* __restrict__ g1, const uint16_t* __restrict__ a0,
+// Thread t owns a channel pair cp = t mod 16 and a tile row r = t / 16: for
+// each pixel of its row it loads the pair once and each of the 9 neighbours
+// once and adds into 9 x 2 register accumulators.  At the end the 16 rows'
+// sums are added in row order through LDS.
+__global__ __launch_bounds__(256) void wgrad_in_kernel(const uint16_t* __restrict__ g1, const uint16_t* __restrict__ a0,
                                                        float* __restrict__ part, int n, int tiles_x,
                                                        int tiles_per_img, int ntiles)
 {
-    __shared__ float gs[T * T][C + 1];
-    __shared__ float as[HALO][HALO];
-    const int tid = threadIdx.x;
-    float acc = 0.0f;
-    const int o = tid < 288 ? tid / 9 : tid - 288;
-    const int tap = tid < 288 ? tid - (tid / 9) * 9 : 0;
-    const int ky = tap / 3, kx = tap - ky * 3;
+    __shared__ float as[HALO][HALO + 1];
+    __shared__ float red[T][T][19];
+    const int tid = threadIdx.x, cp = tid & 15, r = tid >> 4;
+    float acc[9][2], bacc[2] = {0.0f, 0.0f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t][0] = acc[t][1] = 0.0f;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const Tile tl = tile_plain(t, tiles_x, tiles_per_img);
         __syncthreads();
-        for (int e = tid; e < T * T * 4; e += 320) {
-            const int p = e >> 2, q = e & 3;
-            const int gi = tl.i0 + (p >> 4), gj = tl.j0 + (p & 15);
-            u32x4 v = {0u, 0u, 0u, 0u};
-            if (gi < n && gj < n) v = *(const u32x4*)(g1 + pix(tl.b, gi, gj, n) * C + q * 8);
-            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int e2 = 0; e2 < 4; ++e2) {
-                gs[p][q * 8 + 2 * e2] = bf_lo(w[e2]);
-                gs[p][q * 8 + 2 * e2 + 1] = bf_hi(w[e2]);
-            }
-        }
-        for (int e = tid; e < HALO * HALO; e += 320) {
+        for (int e = tid; e < HALO * HALO; e += 256) {
             const int ly = e / HALO, lx = e - ly * HALO;
             const int gi = tl.i0 + ly - 1, gj = tl.j0 + lx - 1;
             as[ly][lx] = (gi >= 0 && gi < n && gj >= 0 && gj < n) ? bf2f(a0[pix(tl.b, gi, gj, n)]) : 0.0f;
         }
         __syncthreads();
-        float s = 0.0f;
-        if (tid < 288) {
-            for (int p = 0; p < T * T; ++p) s = fmaf(gs[p][o], as[(p >> 4) + ky][(p & 15) + kx], s);
-        } else {
-            for (int p = 0; p < T * T; ++p) s += gs[p][o];
+        const int gi = tl.i0 + r;
+        if (gi < n) {
+            for (int x = 0; x < T; ++x) {
+                const int gj = tl.j0 + x;
+                if (gj >= n) break;
+                const uint32_t gw = *(const uint32_t*)(g1 + pix(tl.b, gi, gj, n) * C + 2 * cp);
+                const float g0 = bf_lo(gw), gq = bf_hi(gw);
+                bacc[0] += g0;
+                bacc[1] += gq;
+#pragma unroll
+                for (int tap = 0; tap < 9; ++tap) {
+                    const float av = as[r + tap / 3][x + tap % 3];
+                    acc[tap][0] = fmaf(g0, av, acc[tap][0]);
+                    acc[tap][1] = fmaf(gq, av, acc[tap][1]);
+                }
+            }
         }
-        acc += s;
     }
-    part[(size_t)blockIdx.x * P_IN + tid] = acc;
+    __syncthreads();
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        red[r][cp][tap] = acc[tap][0];
+        red[r][cp][9 + tap] = acc[tap][1];
+    }
+    red[r][cp][18] = 0.0f;
+    __syncthreads();
+    // part row: W1[o][tap] at o * 9 + tap, then b1[o] at 288 + o
+    for (int k = tid; k < P_IN; k += 256) {
+        float sum = 0.0f;
+        if (k < 288) {
+            const int o = k / 9, tap = k - o * 9;
+            for (int rr = 0; rr < T; ++rr) sum += red[rr][o >> 1][(o & 1) * 9 + tap];
+        }
+        part[(size_t)blockIdx.x * P_IN + k] = sum;
+    }
+    __syncthreads();
+    red[r][cp][0] = bacc[0];
+    red[r][cp][1] = bacc[1];
+    __syncthreads();
+    if (tid < C) {
+        float sum = 0.0f;
+        for (int rr = 0; rr < T; ++rr) sum += red[rr][tid >> 1][tid & 1];
+        part[(size_t)blockIdx.x * P_IN + 288 + tid] = sum;
+    }
 }
 
-__global__ __launch_bounds__(320) void wgrad_out_kernel(const float* __restrict__ g8, const uint16_t* __restrict__ a7,
+__global__ __launch_bounds__(256) void wgrad_out_kernel(const float* __restrict__ g8, const uint16_t* __restrict__ a7,
                                                         float* __restrict__ part, int n, int tiles_x,
                                                         int tiles_per_img, int ntiles)
 {
     __shared__ __attribute__((aligned(16))) uint16_t s[HALO][HALO][LDS_PIX];
-    __shared__ float gs[T * T];
-    const int tid = threadIdx.x;
-    float acc = 0.0f;
-    const int c = tid < 288 ? tid / 9 : 0;
-    const int tap = tid < 288 ? tid - (tid / 9) * 9 : 0;
-    const int ky = tap / 3, kx = tap - ky * 3;
+    __shared__ float gs[T][T];
+    __shared__ float red[T][T][19];
+    const int tid = threadIdx.x, cp = tid & 15, r = tid >> 4;
+    float acc[9][2], bacc = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t][0] = acc[t][1] = 0.0f;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const Tile tl = tile_plain(t, tiles_x, tiles_per_img);
         __syncthreads();
         load_halo(s, a7, tl, n);
-        for (int p = tid; p < T * T; p += 320) {
-            const int gi = tl.i0 + (p >> 4), gj = tl.j0 + (p & 15);
-            gs[p] = (gi < n && gj < n) ? g8[pix(tl.b, gi, gj, n)] : 0.0f;
+        {
+            const int gi = tl.i0 + r, gj = tl.j0 + cp;
+            gs[r][cp] = (gi < n && gj < n) ? g8[pix(tl.b, gi, gj, n)] : 0.0f;
         }
         __syncthreads();
-        float sum = 0.0f;
-        if (tid < 288) {
-            for (int p = 0; p < T * T; ++p) sum = fmaf(gs[p], bf2f(s[(p >> 4) + ky][(p & 15) + kx][c]), sum);
-        } else if (tid == 288) {
-            for (int p = 0; p < T * T; ++p) sum += gs[p];
+        for (int x = 0; x < T; ++x) {
+            const float g = gs[r][x];
+            bacc += g;
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const uint32_t w = *(const uint32_t*)(&s[r + tap / 3][x + tap % 3][2 * cp]);
+                acc[tap][0] = fmaf(g, bf_lo(w), acc[tap][0]);
+                acc[tap][1] = fmaf(g, bf_hi(w), acc[tap][1]);
+            }
         }
-        acc += sum;
     }
-    if (tid < P_OUT) part[(size_t)blockIdx.x * P_OUT + tid] = acc;
+    __syncthreads();
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        red[r][cp][tap] = acc[tap][0];
+        red[r][cp][9 + tap] = acc[tap][1];
+    }
+    red[r][cp][18] = bacc;
+    __syncthreads();
+    // part row: W8[0][c][tap] at c * 9 + tap, then b8 at 288
+    for (int k = tid; k < P_OUT; k += 256) {
+        float sum = 0.0f;
+        if (k < 288) {
+            const int c = k / 9, tap = k - c * 9;
+            for (int rr = 0; rr < T; ++rr) sum += red[rr][c >> 1][(c & 1) * 9 + tap];
+        } else {
+            for (int rr = 0; rr < T; ++rr) sum += red[rr][0][18];
+        }
+        part[(size_t)blockIdx.x * P_OUT + k] = sum;
+    }
+}
+
+// Partial rows are added in two fixed-order stages: groups of RG consecutive
+// block rows, then the groups (the single-stage sum was one long dependent
+// chain of loads per output).
+constexpr int RG = 32;
+
+__global__ __launch_bounds__(256) void reduce_group_kernel(const float* __restrict__ part, int nblocks, int row,
+                                                           float* __restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= row) return;
+    const int b0 = blockIdx.y * RG, b1 = min(b0 + RG, nblocks);
+    float s = 0.0f;
+    for (int b = b0; b < b1; ++b) s += part[(size_t)b * row + k];
+    out[(size_t)blockIdx.y * row + k] = s;
 }
 
 // out[k] = sum over blocks b = 0, 1, ... of part[b][k] (fixed order).
@@ -641,6 +709,7 @@ struct recon_cnn {
     float* d_y = nullptr;      // [B][n][n]
     float* d_g8 = nullptr;     // [B][n][n]
     float* d_part = nullptr;   // [WG_BLOCKS][P32]
+    float* d_part2 = nullptr;  // [WG_BLOCKS / RG][P32], first stage of the fixed-order reduction
     double* d_loss_part = nullptr;
     int last_batch = 0, last_n = 0;  // shape of the tensors held
 };
@@ -667,7 +736,7 @@ void free_cnn(recon_cnn* c)
 {
     if (!c) return;
     void* ptrs[] = {c->d_theta, c->d_m, c->d_v, c->d_grad, c->d_wf, c->d_wt, c->d_w1r, c->d_w8r,
-                    c->d_a0, c->d_y, c->d_g8, c->d_part, c->d_loss_part};
+                    c->d_a0, c->d_y, c->d_g8, c->d_part, c->d_part2, c->d_loss_part};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (int l = 0; l < 8; ++l) {
@@ -712,6 +781,17 @@ hipError_t enqueue_forward(recon_cnn* c, const float* mu, float* mu_out, int pro
 
 int wg_blocks(const Shape& S) { return S.ntiles < WG_BLOCKS ? S.ntiles : WG_BLOCKS; }
 
+// out[k] = sum of part[b][k] over the nb partial rows: groups of RG rows, then the groups.
+hipError_t enqueue_reduce(recon_cnn* c, int nb, int row, float* out, hipStream_t s)
+{
+    const int groups = (nb + RG - 1) / RG;
+    reduce_group_kernel<<<dim3(cdiv(row, 256), groups), 256, 0, s>>>(c->d_part, nb, row, c->d_part2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    reduce_part_kernel<<<cdiv(row, 256), 256, 0, s>>>(c->d_part2, groups, row, out);
+    return hipGetLastError();
+}
+
 hipError_t enqueue_wgrad32(recon_cnn* c, int l, const Shape& S, hipStream_t s)
 {
     const int nb = wg_blocks(S);
@@ -719,8 +799,7 @@ hipError_t enqueue_wgrad32(recon_cnn* c, int l, const Shape& S, hipStream_t s)
                                       S.ntiles);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    reduce_part_kernel<<<cdiv(P32, 256), 256, 0, s>>>(c->d_part, nb, P32, c->d_grad + OFF_HID + (l - 2) * P32);
-    return hipGetLastError();
+    return enqueue_reduce(c, nb, P32, c->d_grad + OFF_HID + (l - 2) * P32, s);
 }
 
 // Loss and gradient (into d_grad) for a batch held in the workspace.
@@ -743,10 +822,9 @@ hipError_t enqueue_loss_grad(recon_cnn* c, const float* mu, const float* target,
     }
     // layer 8: weights from g8 x a7, then g7
     const int nb = wg_blocks(S);
-    wgrad_out_kernel<<<nb, 320, 0, s>>>(c->d_g8, c->d_act[7], c->d_part, S.n, S.tiles_x, S.tiles_per_img, S.ntiles);
+    wgrad_out_kernel<<<nb, 256, 0, s>>>(c->d_g8, c->d_act[7], c->d_part, S.n, S.tiles_x, S.tiles_per_img, S.ntiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    reduce_part_kernel<<<cdiv(P_OUT, 256), 256, 0, s>>>(c->d_part, nb, P_OUT, c->d_grad + OFF_W8);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = enqueue_reduce(c, nb, P_OUT, c->d_grad + OFF_W8, s)) != hipSuccess) return e;
     dgrad_out_kernel<<<cdiv(S.pixels, 256), 256, 0, s>>>(c->d_g8, c->d_w8r, c->d_act[7], c->d_g[7], S.n, S.pixels);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // layers 7 .. 2
@@ -757,10 +835,9 @@ hipError_t enqueue_loss_grad(recon_cnn* c, const float* mu, const float* target,
             return e;
     }
     // layer 1
-    wgrad_in_kernel<<<nb, 320, 0, s>>>(c->d_g[1], c->d_a0, c->d_part, S.n, S.tiles_x, S.tiles_per_img, S.ntiles);
+    wgrad_in_kernel<<<nb, 256, 0, s>>>(c->d_g[1], c->d_a0, c->d_part, S.n, S.tiles_x, S.tiles_per_img, S.ntiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    reduce_part_kernel<<<cdiv(P_IN, 256), 256, 0, s>>>(c->d_part, nb, P_IN, c->d_grad + OFF_W1);
-    return hipGetLastError();
+    return enqueue_reduce(c, nb, P_IN, c->d_grad + OFF_W1, s);
 }
 
 recon_status check_batch(recon_cnn* net, int batch, int n, bool training)
@@ -819,6 +896,7 @@ recon_status recon_cnn_create(const float* h_params, int32_t max_batch, int32_t 
     C_TRY(hipMalloc(&c->d_y, px * sizeof(float)));
     C_TRY(hipMalloc(&c->d_g8, px * sizeof(float)));
     C_TRY(hipMalloc(&c->d_part, (size_t)WG_BLOCKS * P32 * sizeof(float)));
+    C_TRY(hipMalloc(&c->d_part2, (size_t)(WG_BLOCKS / RG) * P32 * sizeof(float)));
     C_TRY(hipMalloc(&c->d_loss_part, cdiv((long)px, 256) * sizeof(double)));
     if (h_params)
         C_TRY(hipMemcpy(c->d_theta, h_params, NPARAM * sizeof(float), hipMemcpyHostToDevice));

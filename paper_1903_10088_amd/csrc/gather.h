@@ -69,6 +69,46 @@ __host__ __device__ __forceinline__ PixelView pixel_view(const Geo& G, const Vie
     return o;
 }
 
+// Per (view, 16x16 tile) linear model of the channel coordinate, for the
+// LDS-staged gather: for a pixel at offset (dX, dY) from the tile centre
+// (Xc, Yc), kp ~ kpc + gx dX + gy dY.  The polar angle seen from the source has
+// a Hessian of norm 1/r^2, so over the tile (|d|^2 <= 2 * 7.5^2) the linear
+// model is within 56.25 / r_min^2 radians of the angle, r_min >= along - 10.61
+// (the tile's half-diagonal); that error, in channels, and the tile's largest
+// window half-width (|offset from the source| <= |centre offset| + 7.5) are
+// folded into hwx / hwy together with G.margin.  Every ray with a nonzero
+// weight on a pixel of the tile therefore lies in [kp - hw, kp + hw].
+struct TileView {
+    float kpc, gx, gy, hwx, hwy;
+};
+
+__host__ __device__ __forceinline__ TileView tile_view(const Geo& G, const ViewRec& v, float Xc, float Yc)
+{
+    const float along = fmaf(-Xc, v.cb, fmaf(-Yc, v.sb, v.dist));
+    const float perp = fmaf(Xc, v.sb, -(Yc * v.cb));
+    const float ra = approx_rcp(along);
+    const float tg = perp * ra;
+#ifdef __HIP_DEVICE_COMPILE__
+    const float gam = G.use_poly ? atan_small(tg) : atanf(tg);
+#else
+    const float gam = G.use_poly ? atan_small(tg) : std::atan(tg);
+#endif
+    const float r2 = fmaf(along, along, perp * perp);
+    const float ir2 = G.dg_inv / r2;
+    // (a tile within 10.61 px of the source, possible only for very wide fans,
+    // gets a window spanning the whole interval)
+    const float rmin = fmaxf(along - 10.61f, 1e-3f);
+    const float irmin2 = G.dg_inv / (rmin * rmin);
+    const float lin_err = 56.25f * irmin2;
+    TileView t;
+    t.kpc = fmaf(gam, G.dg_inv, G.kc);
+    t.gx = fmaf(along, v.sb, perp * v.cb) * ir2;
+    t.gy = fmaf(perp, v.sb, -(along * v.cb)) * ir2;
+    t.hwx = (fabsf(Xc - v.sx) + 7.5f) * irmin2 + G.margin + lin_err;
+    t.hwy = (fabsf(Yc - v.sy) + 7.5f) * irmin2 + G.margin + lin_err;
+    return t;
+}
+
 // Channel intervals [x0, x1) of x-major and [y0, y1) of y-major rays in a view.
 __host__ __device__ __forceinline__ void major_intervals(const ViewRec& v, int nch, int& x0, int& x1, int& y0,
                                                          int& y1)
