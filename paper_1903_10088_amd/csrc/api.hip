@@ -294,7 +294,7 @@ void free_handle(recon_handle* h)
 {
     if (!h) return;
     drop_graphs(h);
-    void* ptrs[] = {h->d_views, h->d_raygeo, h->d_raymeta, h->d_img[0], h->d_img[1], h->d_imgT[0], h->d_imgT[1],
+    void* ptrs[] = {h->d_views, h->d_raygeo, h->d_raymeta, h->d_img[0], h->d_img[1],
                     h->d_yt,    h->d_p,      h->d_w,       h->d_part,   h->d_state,  h->d_part_all};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -383,10 +383,10 @@ recon_status recon_create(const recon_geometry* geom, int32_t subsets, double be
     H_TRY(hipMalloc(&h->d_raygeo, nrays * sizeof(RayGeo)));
     H_TRY(hipMalloc(&h->d_raymeta, nrays * sizeof(RayMeta)));
     for (int b = 0; b < 2; ++b) {
-        H_TRY(hipMalloc(&h->d_img[b], pimg));
-        H_TRY(hipMalloc(&h->d_imgT[b], pimg));
-        H_TRY(hipMemset(h->d_img[b], 0, pimg));
-        H_TRY(hipMemset(h->d_imgT[b], 0, pimg));
+        // one allocation per buffer: the row-major copy, then the transposed one
+        H_TRY(hipMalloc(&h->d_img[b], 2 * pimg));
+        H_TRY(hipMemset(h->d_img[b], 0, 2 * pimg));
+        h->d_imgT[b] = h->d_img[b] + (size_t)geom->n * h->geo.P;
     }
     H_TRY(hipMalloc(&h->d_yt, nrays * sizeof(float)));
     H_TRY(hipMalloc(&h->d_p, nrays * sizeof(float)));

@@ -13,8 +13,10 @@
 namespace recon {
 
 // Images live in the workspace with two zero columns on each side of every row
-// (row stride P = n + 4, element (row, col) at row * P + col + PAD).  The
-// projector clamps its interpolation index to [-PAD, n] so that every read
+// (row stride P = n + 4, element (row, col) at row * P + col + PAD); each
+// buffer holds the row-major copy followed by the transposed one (n P floats
+// later), so the projector addresses both with 32-bit offsets from one base.
+// The projector clamps its interpolation index to [-PAD, n] so that every read
 // stays inside the row and reads zero outside the image.
 constexpr int PAD = 2;
 
@@ -142,8 +144,8 @@ struct recon_handle {
     recon::RayMeta* d_raymeta = nullptr;
 
     // workspace
-    float* d_img[2] = {nullptr, nullptr};   // padded [n][P]
-    float* d_imgT[2] = {nullptr, nullptr};  // padded transposed [n][P]
+    float* d_img[2] = {nullptr, nullptr};   // padded [n][P], followed by the transposed copy
+    float* d_imgT[2] = {nullptr, nullptr};  // padded transposed [n][P] (= d_img + n P, same allocation)
     float* d_yt = nullptr;                  // y / I0, subset order [nv * nch]
     float* d_p = nullptr;                   // ln(I0 / max(y, 1)), subset order
     float* d_w = nullptr;                   // weighted residual per ray, subset order

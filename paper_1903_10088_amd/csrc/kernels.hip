@@ -101,8 +101,8 @@ __global__ __launch_bounds__(256) void scale_sino_kernel(const float* __restrict
 // ----------------------------------------------------------------------------
 
 struct FpArgs {
-    const float* img;   // padded row-major: sampled by y-major rays along rows
-    const float* imgT;  // padded transposed: sampled by x-major rays along columns
+    const float* img;   // padded row-major (sampled by y-major rays along rows), followed by
+                        // the padded transposed copy (sampled by x-major rays along columns)
     const RayGeo* rg;
     const RayMeta* rm;
     const ViewRec* views;
@@ -118,40 +118,56 @@ struct FpArgs {
 // u(t) = lattice + residual; lattice - floor(u) is exact, so the interpolation
 // fraction keeps the residual's precision.  Four lines' loads are issued before
 // their additions.  The index clamp to [-PAD, n] keeps every read inside the
-// padded row, where out-of-image entries are zero.
-__device__ __forceinline__ float chunk_sum(const float* __restrict__ base, int P, int n, const RayGeo& g, int t0,
-                                           int t1)
+// padded row, where out-of-image entries are zero.  img is the buffer's base
+// (wave-uniform) and off0 the 32-bit element offset of column 0 of line 0 of
+// the copy this ray samples, so addresses are 32-bit offsets from one base.
+// two neighbouring floats at any 4-byte-aligned address
+typedef float f32x2u __attribute__((ext_vector_type(2), aligned(4)));
+
+__device__ __forceinline__ f32x2u pair_at(const float* __restrict__ img, uint32_t idx)
+{
+    // 32-bit byte offset from a wave-uniform base
+    return *(const f32x2u*)((const char*)img + (idx << 2));
+}
+
+__device__ __forceinline__ float chunk_sum(const float* __restrict__ img, uint32_t off0, int P, int n,
+                                           const RayGeo& g, int t0, int t1)
 {
     float acc = 0.0f;
     int t = t0;
+    float ft0 = (float)t0;  // exact: t < 2^24
+    uint32_t row = off0 + (uint32_t)(t0 * P);
     for (; t + 3 < t1; t += 4) {
         float v0[4], v1[4], f[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const float ft = (float)(t + u);
+            const float ft = ft0 + (float)u;
             const float lat = fmaf(ft, g.s_hi, g.a_int);
             const float res = fmaf(ft, g.s_lo, g.a_frac);
             const float fl = floorf(lat + res);
             f[u] = (lat - fl) + res;
             const int j0 = min(max((int)fl, -PAD), n);
-            const float* row = base + (size_t)(t + u) * P + j0;
-            v0[u] = row[0];
-            v1[u] = row[1];
+            const f32x2u v = pair_at(img, row + (uint32_t)(u * P) + (uint32_t)j0);
+            v0[u] = v.x;
+            v1[u] = v.y;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc += fmaf(f[u], v1[u] - v0[u], v0[u]);
+        ft0 += 4.0f;
+        row += (uint32_t)(4 * P);
     }
     for (; t < t1; ++t) {
-        const float ft = (float)t;
-        const float lat = fmaf(ft, g.s_hi, g.a_int);
-        const float res = fmaf(ft, g.s_lo, g.a_frac);
+        const float lat = fmaf(ft0, g.s_hi, g.a_int);
+        const float res = fmaf(ft0, g.s_lo, g.a_frac);
         const float fl = floorf(lat + res);
         const float f = (lat - fl) + res;
         const int j0 = min(max((int)fl, -PAD), n);
-        const float* row = base + (size_t)t * P + j0;
-        const float v0 = row[0];
-        const float v1 = row[1];
+        const f32x2u v = pair_at(img, row + (uint32_t)j0);
+        const float v0 = v.x;
+        const float v1 = v.y;
         acc += fmaf(f, v1 - v0, v0);
+        ft0 += 1.0f;
+        row += (uint32_t)P;
     }
     return acc;
 }
@@ -196,12 +212,14 @@ __device__ __forceinline__ void fp_body(const FpArgs& A, int rblock)
         const int lo = (int)(m.packed & 0x7fffu);
         const int hi = (int)((m.packed >> 15) & 0x7fffu);
         const int major = (int)(m.packed >> 30);
-        const float* base = (major ? A.img : A.imgT) + PAD;
+        // y-major rays sample rows of the row-major copy, x-major rays rows of
+        // the transposed copy (n P floats after it)
+        const uint32_t off0 = (major ? 0u : (uint32_t)(A.n * A.P)) + (uint32_t)PAD;
         const int c_begin = seg * cps, c_end = min(nchunk, c_begin + cps);
         for (int c = c_begin; c < c_end; ++c) {
             const int t0 = max(lo, c * ch);
             const int t1 = min(min(hi + 1, (c + 1) * ch), A.n);
-            const float acc = chunk_sum(base, A.P, A.n, g, t0, t1);
+            const float acc = chunk_sum(A.img, off0, A.P, A.n, g, t0, t1);
             if constexpr (SEG == 1) {
                 total += acc;
             } else {
@@ -264,7 +282,6 @@ __global__ __launch_bounds__(256) void fp_batch_kernel(const SliceDesc* __restri
     const int2 sq = s >= 0 ? D->subs[s] : make_int2(0, D->geo.nv);
     FpArgs A{};
     A.img = as_global(D->img[in]);
-    A.imgT = as_global(D->imgT[in]);
     A.rg = as_global(D->rg);
     A.rm = as_global(D->rm);
     A.ray0 = sq.x * D->geo.nch;
@@ -413,8 +430,7 @@ hipError_t launch_fp_plain(const Geo& geo, int segments, const float* img, const
                            hipStream_t s)
 {
     FpArgs a{};
-    a.img = img;
-    a.imgT = imgT;
+    a.img = img;  // imgT is img + n P (one allocation)
     a.rg = rg;
     a.rm = rm;
     a.views = views;
@@ -434,8 +450,7 @@ hipError_t launch_fp_os(const Geo& geo, int segments, const float* img, const fl
                         double* part, hipStream_t s)
 {
     FpArgs a{};
-    a.img = img;
-    a.imgT = imgT;
+    a.img = img;  // imgT is img + n P (one allocation)
     a.rg = rg;
     a.rm = rm;
     a.ray0 = ray0;
