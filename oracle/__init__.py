@@ -38,16 +38,19 @@ class _Geom(ctypes.Structure):
 class _Params(ctypes.Structure):
     _fields_ = [("lambda0", ctypes.c_double), ("lambda_inc", ctypes.c_double),
                 ("lambda_dec", ctypes.c_double), ("lambda_min", ctypes.c_double),
-                ("mu0_per_mm", ctypes.c_double), ("tv_eps_per_mm", ctypes.c_double)]
+                ("mu0_per_mm", ctypes.c_double), ("tv_eps_per_mm", ctypes.c_double),
+                ("lambda_compare", ctypes.c_int32), ("keep_best", ctypes.c_int32)]
 
 
 class _State(ctypes.Structure):
     _fields_ = [("n_done", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("lambda_", ctypes.c_double), ("f_prev", ctypes.c_double)]
+                ("lambda_", ctypes.c_double), ("f_prev", ctypes.c_double),
+                ("best_f", ctypes.c_double), ("epoch_sum", ctypes.c_double),
+                ("best_n", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 DEFAULT_PARAMS = dict(lambda0=0.01, lambda_inc=1e-4, lambda_dec=2e-4, lambda_min=1e-4,
-                      mu0_per_mm=0.005, tv_eps_per_mm=1e-5)
+                      mu0_per_mm=0.005, tv_eps_per_mm=1e-5, lambda_compare=0, keep_best=0)
 
 _lib = None
 
@@ -71,7 +74,7 @@ def lib():
         L.oracle_lambda_next.restype = d
         L.oracle_initial_image.argtypes = [P(_Geom), d, P(d)]
         L.oracle_os_iterate.argtypes = [P(_Geom), i32, d, P(_Params), P(d), d, P(d), i32, P(_State),
-                                        P(d), P(d)]
+                                        P(d), P(d), P(d), P(d)]
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_set_num_threads.argtypes = [i32]
         _lib = L
@@ -177,7 +180,15 @@ class State:
     """Resumable iteration state (sub-iterations done, lambda, previous f, flags)."""
 
     def __init__(self):
-        self._s = _State(0, 0, 0.0, 0.0)
+        self._s = _State(0, 0, 0.0, 0.0, 0.0, 0.0, 0, 0)
+
+    @property
+    def best_f(self):
+        return self._s.best_f
+
+    @property
+    def best_n(self):
+        return self._s.best_n
 
     @property
     def n_done(self):
@@ -198,8 +209,11 @@ class State:
 
 def os_iterate(geom, subsets: int, beta: float, counts, i0: float, img=None, n_iter: int = 1,
                state: State | None = None, lambda_schedule=None, params=None, want_trace=True,
-               allow_numeric=False):
-    """Ordered-subset TV gradient iteration (Eq. 3 with Eqs. 4-5).  Returns (img, trace[n_iter][2])."""
+               allow_numeric=False, f_hist=None, best=None):
+    """Ordered-subset TV gradient iteration (Eq. 3 with Eqs. 4-5).  Returns (img, trace[n_iter][2]).
+
+    f_hist: None or float64 [M] in/out (per-subset f, read by lambda_compare = 1); best: None or
+    float64 [n][n] receiving the kept iterate when params['keep_best'] is 1."""
     p = dict(DEFAULT_PARAMS)
     if params:
         p.update(params)
@@ -213,10 +227,16 @@ def os_iterate(geom, subsets: int, beta: float, counts, i0: float, img=None, n_i
     if lambda_schedule is not None:
         sched = np.ascontiguousarray(lambda_schedule, dtype=np.float64)
         assert sched.size >= n_iter
+    if f_hist is not None:
+        assert f_hist.dtype == np.float64 and f_hist.size == subsets and f_hist.flags["C_CONTIGUOUS"]
+    if best is not None:
+        assert best.dtype == np.float64 and best.shape == (geom.n, geom.n) and best.flags["C_CONTIGUOUS"]
     rc = lib().oracle_os_iterate(ctypes.byref(_g(geom)), subsets, beta, ctypes.byref(cp), _dp(counts), i0,
                                  _dp(img), n_iter, ctypes.byref(state._s) if state else None,
                                  _dp(trace) if trace is not None else None,
-                                 _dp(sched) if sched is not None else None)
+                                 _dp(sched) if sched is not None else None,
+                                 _dp(f_hist) if f_hist is not None else None,
+                                 _dp(best) if best is not None else None)
     if rc == 3 and allow_numeric:
         return img, trace
     _check(rc, "os_iterate")

@@ -48,6 +48,10 @@ typedef struct {
     double lambda_min;     /* floor; the paper gives none (reading: 1e-4) */
     double mu0_per_mm;     /* homogeneous initial image, 0.05/cm = 0.005/mm (section 3.C.2) */
     double tv_eps_per_mm;  /* TV smoothing, 1e-5/mm (reading) */
+    int32_t lambda_compare; /* 0: compare f_n with the previous sub-iteration's f (literal reading);
+                               1: with the same subset's f one epoch earlier (during the first epoch,
+                               with the previous sub-iteration's) */
+    int32_t keep_best;      /* 1: keep the iterate that ends the epoch of least summed f (section 4.B) */
 } og_params;
 
 /* Resumable iteration state. */
@@ -56,6 +60,10 @@ typedef struct {
     int32_t flags;    /* bit 0: a non-finite value was met */
     double lambda;    /* lambda of the last sub-iteration */
     double f_prev;    /* squared difference of the last sub-iteration */
+    double best_f;    /* least epoch sum of f so far (keep_best; +inf before the first epoch ends) */
+    double epoch_sum; /* sum of f over the current, unfinished epoch */
+    int32_t best_n;   /* sub-iterations that produced the kept iterate (0: none yet) */
+    int32_t pad;
 } og_state;
 
 enum { OG_OK = 0, OG_INVALID = 1, OG_NUMERIC = 3 };
@@ -395,15 +403,24 @@ int oracle_initial_image(const og_geometry* g, double mu0_per_mm, double* img)
  * counts: [n_views][n_ch] in natural view order.  img: in/out, 1/mm; the
  * start image is taken as zero outside the reconstruction disc (the iterate is
  * held there at zero, reading of Eq. 1's support).
+ *
+ * Best iterate (section 4.B: the image at the minimum of the oscillating
+ * squared difference is kept): with keep_best, f is summed over each complete
+ * epoch (sub-iterations n with n mod M = 0 .. M-1, n counted from the fresh
+ * start); when an epoch's sum is below every earlier one, the image that epoch
+ * ends with, mu^(n+1), is copied to best_img (1/mm).  f_hist: NULL or [M]
+ * in/out, f of each subset's latest sub-iteration (lambda_compare = 1 reads
+ * it, so a resumed run passes it back).
+ *
  * state: NULL for a fresh run, else resumed and updated.  trace: NULL or
  * [n_iter][2] = (f_n, lambda_n).  lambda_schedule: NULL, or [n_iter] values
  * that replace the step rule (f is still tracked). */
 int oracle_os_iterate(const og_geometry* g, int32_t subsets, double beta, const og_params* p,
                       const double* counts, double i0, double* img, int32_t n_iter, og_state* state,
-                      double* trace, const double* lambda_schedule)
+                      double* trace, const double* lambda_schedule, double* f_hist, double* best_img)
 {
     if (!geometry_ok(g) || !p || !counts || !img || subsets < 1 || subsets > g->n_views || beta < 0 ||
-        i0 <= 0 || n_iter < 0)
+        i0 <= 0 || n_iter < 0 || (p->keep_best && !best_img))
         return OG_INVALID;
     const int N = g->n, nch = g->n_channels, M = subsets;
     const size_t npix = (size_t)N * N;
@@ -431,6 +448,10 @@ int oracle_os_iterate(const og_geometry* g, int32_t subsets, double beta, const 
     double lambda = state ? state->lambda : p->lambda0;
     double f_prev = state ? state->f_prev : 0.0;
     int flags = state ? state->flags : 0;
+    double best_f = (state && n_done > 0) ? state->best_f : INFINITY;
+    double epoch_sum = (state && n_done > 0) ? state->epoch_sum : 0.0;
+    int best_n = (state && n_done > 0) ? state->best_n : 0;
+    double* hist = f_hist ? f_hist : (double*)calloc((size_t)M, sizeof(double));
     int status = OG_OK;
 
     for (int it = 0; it < n_iter; ++it) {
@@ -453,14 +474,28 @@ int oracle_os_iterate(const og_geometry* g, int32_t subsets, double beta, const 
             }
         double f_n = fsum / ((double)nv * nch);
 
-        lambda = oracle_lambda_next(p, n == 0, lambda, f_n, f_prev);
+        const double f_ref = (p->lambda_compare && n >= M) ? hist[s] : f_prev;
+        lambda = oracle_lambda_next(p, n == 0, lambda, f_n, f_ref);
         if (lambda_schedule) lambda = lambda_schedule[it];
         if (trace) {
             trace[2 * it] = f_n;
             trace[2 * it + 1] = lambda;
         }
         f_prev = f_n;
+        hist[s] = f_n;
         if (!isfinite(f_n)) flags |= 1;
+        int keep = 0;
+        if ((n + 1) % M == 0) {
+            const double e = epoch_sum + f_n;
+            if (e < best_f) {
+                best_f = e;
+                best_n = n + 1;
+                keep = 1;
+            }
+            epoch_sum = 0.0;
+        } else {
+            epoch_sum += f_n;
+        }
 
         /* likelihood gradient A_s^T (exp(-l) - y/I0) */
         for (int vs = 0; vs < nv; ++vs)
@@ -480,6 +515,8 @@ int oracle_os_iterate(const og_geometry* g, int32_t subsets, double beta, const 
             if (!(v > 0.0)) v = 0.0;
             mu[r] = mask[r] ? v : 0.0;
         }
+        if (keep && p->keep_best)
+            for (size_t r = 0; r < npix; ++r) best_img[r] = mu[r] / 10.0;
     }
 
     for (size_t r = 0; r < npix; ++r) img[r] = mu[r] / 10.0;
@@ -488,7 +525,11 @@ int oracle_os_iterate(const og_geometry* g, int32_t subsets, double beta, const 
         state->lambda = lambda;
         state->f_prev = f_prev;
         state->flags = flags;
+        state->best_f = best_f;
+        state->epoch_sum = epoch_sum;
+        state->best_n = best_n;
     }
+    if (!f_hist) free(hist);
     if (flags & 1) status = OG_NUMERIC;
     free(mu);
     free(gl);
