@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--bp-variant", type=int, default=0, help="1 = global reads, 2 = LDS-staged (0 = default)")
     ap.add_argument("--cnn-batch", type=int, default=8,
                     help="slices per timed CNN kernel launch (512 x 512; 0 = skip the CNN leg)")
+    ap.add_argument("--batch-slices", type=int, default=64,
+                    help="mixed 256/512 slices for the batched-plain leg (0 = skip)")
     ap.add_argument("--warm-slices", type=int, default=32,
                     help="full-study slices for the warm-start leg (0 = skip; needs trained weights)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1903_10088_amd", "weights", "warm_cnn.bin"))
@@ -167,6 +169,7 @@ def main():
                   "tolerance_per_mm": 1e-4 * ph.MU_WATER_PER_MM, "ok": rmse <= 1e-4 * ph.MU_WATER_PER_MM}
         log(f"bench: cpu {cpu['value']:.4f} slices/s; GPU vs oracle rmse after {n_cpu} sub-iterations {rmse:.2e}")
 
+    batch = batch_leg(args.batch_slices, args.iters, dev) if args.batch_slices > 0 else None
     cnn = cnn_leg(args.cnn_batch, dev) if args.cnn_batch > 0 else None
     warm = warm_leg(args.warm_slices, args.weights, dev) if args.warm_slices > 0 else None
 
@@ -197,12 +200,49 @@ def main():
         "kernel_us": {"fp": fp_ms * 1e3, "bp_update": bp_ms * 1e3,
                       "graph_sub_iteration": sub_ms * 1e3},
         "parity": parity,
+        "batched_plain": batch,
         "cnn_kernels": cnn,
         "warm_start": warm,
         "paper_context": {"s_per_slice": PAPER_S_PER_SLICE, "hardware": "GeForce GTX 1080 Ti",
                           "thinning": "1/20", "note": "context only; channel count and precision not stated"},
     }
     print(json.dumps(out), flush=True)
+
+
+def batch_leg(n_slices: int, iters: int, dev):
+    """Batched plain method on helical-rebinned-like slices (256^2 or 512^2 over 400 mm, 600-900
+    views, 520-738 channels, I0 log-uniform 1e3..1e4; 20 subsets, beta 1e-3): launch shapes
+    autotuned on the batch, then `iters` sub-iterations of every slice from the homogeneous
+    start, timed over 3 runs (best)."""
+    import torch
+
+    from paper_1903_10088_amd import phantom as ph
+    from paper_1903_10088_amd import recon
+    from paper_1903_10088_amd import warmstart as ws
+
+    geoms, i0s, items = [], [], []
+    for i in range(n_slices):
+        g, i0 = ph.random_batch_geometry(1000 + i)
+        geoms.append(g)
+        i0s.append(i0)
+        items.append((g, 1000 + i, i0))
+    log(f"bench: batched leg: {n_slices} slices ...")
+    counts = ws.make_counts(items, workers=8)
+    B = recon.Batch(geoms, 20, 1e-3)
+    cts = [torch.from_numpy(c).to(dev) for c in counts]
+    seg, var = B.tune(cts, i0s, B.initial_images(dev), reps=20)
+    best = None
+    for _ in range(3):
+        imgs = B.initial_images(dev)
+        _, dt = ws.timed(lambda: B.run(cts, i0s, imgs, iters))
+        best = dt if best is None else min(best, dt)
+    n512 = sum(1 for g in geoms if g.n == 512)
+    out = {"slices": n_slices, "slices_512": n512, "slices_256": n_slices - n512, "sub_iterations": iters,
+           "tuned_fp_segments": seg, "tuned_bp_variant": var, "seconds": best, "slices_per_s": n_slices / best}
+    log(f"bench: batched plain {out['slices_per_s']:.1f} slices/s ({n512} of {n_slices} at 512^2; "
+        f"fp_segments {seg}, bp variant {var})")
+    B.close()
+    return out
 
 
 PEAK_BF16_TFLOPS = 2500.0  # dense bf16 matrix-core peak
