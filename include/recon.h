@@ -71,7 +71,19 @@ typedef struct {
 /* Step rule and prior parameters (section 3.C).  Defaults (recon_default_params):
  * lambda0 0.01, lambda_inc 1e-4 (Eq. 4), lambda_dec 2e-4 (Eq. 5), lambda_min 1e-4
  * (floor; not in the paper), mu0_per_mm 0.005 (0.05/cm, section 3.C.2),
- * tv_eps_per_mm 1e-5 (smoothing of the TV norm; not in the paper). */
+ * tv_eps_per_mm 1e-5 (smoothing of the TV norm; not in the paper),
+ * lambda_compare 0, keep_best 0.
+ * lambda_compare: 0 = Eqs. 4-5 compare f_n with the previous sub-iteration's
+ *   f (the literal reading); 1 = with the f of the same subset one epoch (M
+ *   sub-iterations) earlier, from the second epoch on (the first epoch
+ *   compares with the previous sub-iteration).  Both readings take a tie as
+ *   "not decreased".
+ * keep_best: 1 = also keep the iterate at the minimum of the oscillating
+ *   squared difference (section 4.B), taken per epoch: f summed over the
+ *   sub-iterations n = eM .. eM + M - 1 (n counted from the fresh start); when
+ *   an epoch's sum is below every earlier epoch's, the image that epoch ends
+ *   with, mu^((e+1)M), is written to the caller's best-image buffer
+ *   (recon_os_iterate_ex).  Not available to the batched entry points. */
 typedef struct {
     double lambda0;
     double lambda_inc;
@@ -79,15 +91,22 @@ typedef struct {
     double lambda_min;
     double mu0_per_mm;
     double tv_eps_per_mm;
+    int32_t lambda_compare;
+    int32_t keep_best;
 } recon_params;
 
 /* Resumable iteration state (host memory).  A zero-filled struct with
- * n_done = 0 starts a fresh run. */
+ * n_done = 0 starts a fresh run (best_f, epoch_sum and best_n are then
+ * ignored and start at +infinity, 0 and 0). */
 typedef struct {
-    int32_t n_done;  /* sub-iterations completed so far */
-    int32_t flags;   /* bit 0: a non-finite squared difference was met */
-    double lambda;   /* convergence parameter of the last sub-iteration */
-    double f_prev;   /* squared difference of the last sub-iteration */
+    int32_t n_done;   /* sub-iterations completed so far */
+    int32_t flags;    /* bit 0: a non-finite squared difference was met */
+    double lambda;    /* convergence parameter of the last sub-iteration */
+    double f_prev;    /* squared difference of the last sub-iteration */
+    double best_f;    /* least epoch sum of f so far (+infinity before the first epoch ends) */
+    double epoch_sum; /* sum of f over the current, unfinished epoch */
+    int32_t best_n;   /* sub-iterations that produced the kept iterate (0: no epoch ended yet) */
+    int32_t reserved;
 } recon_state;
 
 typedef struct recon_handle recon_handle;
@@ -154,6 +173,22 @@ recon_status recon_tv_grad(recon_handle* h, const float* d_img, float* d_grad, v
 recon_status recon_os_iterate(recon_handle* h, const float* d_counts, float i0, float* d_img, int32_t n_iter,
                               recon_state* state, double* d_trace, const double* d_lambda_schedule,
                               void* stream);
+
+/* recon_os_iterate with the two step-rule options of recon_params:
+ * d_f_hist: NULL or device double [M], in/out: the f of each subset's latest
+ *   sub-iteration, read by lambda_compare = 1.  A fresh run needs none (the
+ *   handle's own buffer is used when NULL); a resumed run (state->n_done > 0)
+ *   with lambda_compare = 1 and M > 1 must pass the array the earlier calls
+ *   filled (RECON_INVALID_ARG otherwise).
+ * d_best: device float [n][n], 1/mm; required when keep_best = 1 and must be
+ *   NULL otherwise (RECON_INVALID_ARG).  Written when an epoch ends with a new
+ *   least sum (state->best_n reports which iterate it holds); left untouched
+ *   otherwise, so a resumed run passes the same buffer.
+ * Every other argument is as for recon_os_iterate, which is this call with
+ * both pointers NULL. */
+recon_status recon_os_iterate_ex(recon_handle* h, const float* d_counts, float i0, float* d_img, int32_t n_iter,
+                                 recon_state* state, double* d_trace, const double* d_lambda_schedule,
+                                 double* d_f_hist, float* d_best, void* stream);
 
 /* Writes the homogeneous start image (section 3.C.2): mu0_per_mm inside the
  * reconstruction disc, 0 outside. */

@@ -197,12 +197,15 @@ recon_status validate_create(const recon_geometry* geom, int subsets, double bet
     if (!(beta >= 0) || !std::isfinite(beta)) return fail(RECON_INVALID_ARG, "beta must be finite and >= 0");
     if (params && (!(params->tv_eps_per_mm > 0) || !(params->lambda_min >= 0) || !(params->lambda0 > 0)))
         return fail(RECON_INVALID_ARG, "bad step-rule or TV parameters");
+    if (params && (params->lambda_compare < 0 || params->lambda_compare > 1 || params->keep_best < 0 ||
+                   params->keep_best > 1))
+        return fail(RECON_INVALID_ARG, "lambda_compare and keep_best must be 0 or 1");
     return RECON_OK;
 }
 
 StepRule rule_of(const recon_handle* h)
 {
-    return StepRule{h->p.lambda0, h->p.lambda_inc, h->p.lambda_dec, h->p.lambda_min};
+    return StepRule{h->p.lambda0, h->p.lambda_inc, h->p.lambda_dec, h->p.lambda_min, h->M, h->p.lambda_compare};
 }
 
 UpdateConst update_const(const recon_handle* h)
@@ -295,7 +298,8 @@ void free_handle(recon_handle* h)
     if (!h) return;
     drop_graphs(h);
     void* ptrs[] = {h->d_views, h->d_raygeo, h->d_raymeta, h->d_img[0], h->d_img[1],
-                    h->d_yt,    h->d_p,      h->d_w,       h->d_part,   h->d_state,  h->d_part_all};
+                    h->d_yt,    h->d_p,      h->d_w,       h->d_part,   h->d_state,  h->d_part_all,
+                    h->d_fhist};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (h->h_state) (void)hipHostFree(h->h_state);
@@ -304,6 +308,10 @@ void free_handle(recon_handle* h)
 }
 
 }  // namespace
+
+// ABI layout of the public structs (mirrored by the Python binding)
+static_assert(sizeof(recon_params) == 56 && offsetof(recon_params, keep_best) == 52, "recon_params layout");
+static_assert(sizeof(recon_state) == 48 && offsetof(recon_state, best_n) == 40, "recon_state layout");
 
 extern "C" {
 
@@ -316,6 +324,8 @@ void recon_default_params(recon_params* out)
     out->lambda_min = 1e-4;
     out->mu0_per_mm = 0.005;
     out->tv_eps_per_mm = 1e-5;
+    out->lambda_compare = 0;
+    out->keep_best = 0;
 }
 
 const char* recon_status_string(recon_status s)
@@ -395,6 +405,7 @@ recon_status recon_create(const recon_geometry* geom, int32_t subsets, double be
     H_TRY(hipMalloc(&h->d_part, ngroups * sizeof(double)));
     H_TRY(hipMalloc(&h->d_part_all, (nrays + SQ_GROUP - 1) / SQ_GROUP * sizeof(double)));
     H_TRY(hipMalloc(&h->d_state, 2 * sizeof(DevState)));
+    H_TRY(hipMalloc(&h->d_fhist, (size_t)subsets * sizeof(double)));
     H_TRY(hipHostMalloc(&h->h_state, sizeof(DevState), hipHostMallocDefault));
     H_TRY(hipMemcpy(h->d_views, T.views.data(), T.views.size() * sizeof(ViewRec), hipMemcpyHostToDevice));
     H_TRY(hipMemcpy(h->d_raygeo, T.rg.data(), nrays * sizeof(RayGeo), hipMemcpyHostToDevice));
@@ -402,6 +413,7 @@ recon_status recon_create(const recon_geometry* geom, int32_t subsets, double be
     H_TRY(hipMemset(h->d_w, 0, nrays * sizeof(float)));
     H_TRY(hipMemset(h->d_part, 0, ngroups * sizeof(double)));
     H_TRY(hipMemset(h->d_state, 0, 2 * sizeof(DevState)));
+    H_TRY(hipMemset(h->d_fhist, 0, (size_t)subsets * sizeof(double)));
     H_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     H_TRY(hipDeviceSynchronize());
 #undef H_TRY
@@ -490,18 +502,44 @@ recon_status recon_tv_grad(recon_handle* h, const float* d_img, float* d_grad, v
 recon_status recon_os_iterate(recon_handle* h, const float* d_counts, float i0, float* d_img, int32_t n_iter,
                               recon_state* state, double* d_trace, const double* d_lambda_schedule, void* stream)
 {
+    return recon_os_iterate_ex(h, d_counts, i0, d_img, n_iter, state, d_trace, d_lambda_schedule, nullptr, nullptr,
+                               stream);
+}
+
+recon_status recon_os_iterate_ex(recon_handle* h, const float* d_counts, float i0, float* d_img, int32_t n_iter,
+                                 recon_state* state, double* d_trace, const double* d_lambda_schedule,
+                                 double* d_f_hist, float* d_best, void* stream)
+{
     if (!h || !d_counts || !d_img) return fail(RECON_INVALID_ARG, "NULL argument");
     if (!(i0 > 0) || !std::isfinite(i0)) return fail(RECON_INVALID_ARG, "i0 must be finite and > 0");
     if (n_iter < 0) return fail(RECON_INVALID_ARG, "n_iter must be >= 0");
     if (state && state->n_done < 0) return fail(RECON_INVALID_ARG, "state->n_done must be >= 0");
+    if ((h->p.keep_best != 0) != (d_best != nullptr))
+        return fail(RECON_INVALID_ARG, "d_best must be given exactly when keep_best is set");
+    const int n_done = state ? state->n_done : 0;
+    if (h->p.lambda_compare && h->M > 1 && n_done > 0 && !d_f_hist)
+        return fail(RECON_INVALID_ARG, "a resumed run with lambda_compare needs the subset history d_f_hist");
     hipStream_t s = as_stream(stream);
     const Geo& G = h->geo;
-    const int n_done = state ? state->n_done : 0;
+
+    DevState v = fresh_state(h->p.lambda0);
+    if (state && n_done > 0) {
+        v.lambda = state->lambda;
+        v.f_prev = state->f_prev;
+        v.best_f = state->best_f;
+        v.epoch_sum = state->epoch_sum;
+        v.best_n = state->best_n;
+    }
+    v.flags = state ? state->flags : 0;
+    v.n_global = n_done;
+    v.trace = d_trace;
+    v.schedule = d_lambda_schedule;
+    v.fhist = h->p.lambda_compare ? (d_f_hist ? d_f_hist : h->d_fhist) : nullptr;
+    v.best = d_best;
 
     HIP_TRY(launch_prep_counts(d_counts, h->d_views, G.nv, G.nch, i0, h->d_yt, h->d_p, s));
     HIP_TRY(launch_pad_image(d_img, h->d_img[0], h->d_imgT[0], G.n, G.P, s, true));
-    HIP_TRY(launch_set_state(h->d_state, state ? state->lambda : h->p.lambda0, state ? state->f_prev : 0.0, n_done,
-                             state ? state->flags : 0, d_trace, d_lambda_schedule, s));
+    HIP_TRY(launch_set_state(h->d_state, v, s));
 
     int in = 0;
     int n = 0;
@@ -521,14 +559,20 @@ recon_status recon_os_iterate(recon_handle* h, const float* d_counts, float i0, 
         in = 1 - in;
         ++n;
     }
+    if (v.fhist) HIP_TRY(launch_flush_hist(h->d_state + in, h->M, s));
     HIP_TRY(launch_unpad_image(h->d_img[in], d_img, G.n, G.P, s));
     if (state) {
         HIP_TRY(hipMemcpyAsync(h->h_state, h->d_state + in, sizeof(DevState), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        const DevState& r = *h->h_state;
         state->n_done = n_done + n_iter;
-        state->flags = h->h_state->flags;
-        state->lambda = h->h_state->lambda;
-        state->f_prev = h->h_state->f_prev;
+        state->flags = r.flags;
+        state->lambda = r.lambda;
+        state->f_prev = r.f_prev;
+        state->best_f = r.best_f;
+        state->epoch_sum = r.epoch_sum;
+        state->best_n = r.best_n;
+        state->reserved = 0;
         if (state->flags & 1) return fail(RECON_NUMERIC, "non-finite squared difference");
     }
     return RECON_OK;
@@ -581,7 +625,7 @@ recon_status recon_time_kernels(recon_handle* h, const float* d_counts, float i0
     const Geo& G = h->geo;
     HIP_TRY(launch_prep_counts(d_counts, h->d_views, G.nv, G.nch, i0, h->d_yt, h->d_p, s));
     HIP_TRY(launch_pad_image(d_img, h->d_img[0], h->d_imgT[0], G.n, G.P, s, true));
-    HIP_TRY(launch_set_state(h->d_state, h->p.lambda0, 0.0, 0, 0, nullptr, nullptr, s));
+    HIP_TRY(launch_set_state(h->d_state, fresh_state(h->p.lambda0), s));
     // one sub-iteration of every subset first, so residuals and state are realistic
     for (int sub = 0; sub < h->M; ++sub) HIP_TRY(enqueue_subiter(h, sub, 0, s));
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};

@@ -247,8 +247,9 @@ recon_status prepare(recon_batch_handle* b, const float* const* d_counts, const 
             return fail(RECON_INVALID_ARG, "slice " + std::to_string(i) + ": NULL buffer or bad i0");
         RECON_HIP_TRY(launch_prep_counts(d_counts[i], h->d_views, G.nv, G.nch, i0[i], h->d_yt, h->d_p, s));
         RECON_HIP_TRY(launch_pad_image(d_imgs[i], h->d_img[0], h->d_imgT[0], G.n, G.P, s, true));
-        RECON_HIP_TRY(launch_set_state(h->d_state, h->p.lambda0, 0.0, 0, 0, d_traces ? d_traces[i] : nullptr,
-                                       nullptr, s));
+        DevState v = fresh_state(h->p.lambda0);
+        v.trace = d_traces ? d_traces[i] : nullptr;
+        RECON_HIP_TRY(launch_set_state(h->d_state, v, s));
     }
     return RECON_OK;
 }
@@ -263,6 +264,8 @@ recon_status recon_batch_create(const recon_geometry* geoms, int32_t n_slices, i
     if (!out || !geoms) return fail(RECON_INVALID_ARG, "NULL argument");
     *out = nullptr;
     if (n_slices < 1) return fail(RECON_INVALID_ARG, "n_slices must be >= 1");
+    if (params && (params->lambda_compare || params->keep_best))
+        return fail(RECON_INVALID_ARG, "lambda_compare and keep_best are single-slice options (recon_os_iterate_ex)");
     for (int i = 0; i < n_slices; ++i) {
         recon_status st = validate_create(&geoms[i], subsets, beta, params);
         if (st != RECON_OK) return fail(st, "slice " + std::to_string(i) + ": " + recon_last_error());

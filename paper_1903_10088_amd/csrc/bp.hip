@@ -436,18 +436,61 @@ __device__ double block_sum(const double* __restrict__ part, int n, double* red)
 }
 
 // Step rule of Eqs. 4-5 with the floor: lambda_0 at n = 0, else +inc when
-// f_n < f_{n-1} (strictly), -dec otherwise; a replay schedule overrides it.
-__device__ __forceinline__ double next_lambda(const DevState& in, const StepRule& R, double f)
-{
+// f_n < f_ref (strictly), -dec otherwise; a replay schedule overrides it.
+// f_ref is the previous sub-iteration's f, or with `compare` (from the second
+// epoch on) the same subset's f one epoch earlier (fhist; with M = 1 that is
+// the previous sub-iteration again).  keep: this sub-iteration ends an epoch
+// whose summed f is below every earlier epoch's (section 4.B), and a kept
+// image is wanted.
+struct StepDecision {
     double lam;
+    bool keep;
+};
+
+__device__ __forceinline__ StepDecision step_rule(const DevState& in, const StepRule& R, double f)
+{
+    StepDecision d;
     if (in.n_global == 0) {
-        lam = R.lambda0;
+        d.lam = R.lambda0;
     } else {
-        lam = (f < in.f_prev) ? in.lambda + R.inc : in.lambda - R.dec;
-        if (lam < R.lmin) lam = R.lmin;
+        const bool same_subset = R.compare && R.M > 1 && in.n_global >= R.M;
+        const double f_ref = same_subset ? in.fhist[in.n_global % R.M] : in.f_prev;
+        d.lam = (f < f_ref) ? in.lambda + R.inc : in.lambda - R.dec;
+        if (d.lam < R.lmin) d.lam = R.lmin;
     }
-    if (in.schedule) lam = in.schedule[in.it];
-    return lam;
+    if (in.schedule) d.lam = in.schedule[in.it];
+    d.keep = in.best != nullptr && (in.n_global + 1) % R.M == 0 && in.epoch_sum + f < in.best_f;
+    return d;
+}
+
+// The next state after sub-iteration in.n_global (written by one thread):
+// trace row, the one-late history entry, the epoch sum and the least one.
+__device__ __forceinline__ void record_state(const DevState& in, const StepRule& R, double f, double lam,
+                                             DevState* st_out)
+{
+    DevState out = in;
+    if (!isfinite(f)) out.flags |= 1;
+    if (in.trace) {
+        in.trace[2 * in.it] = f;
+        in.trace[2 * in.it + 1] = lam;
+    }
+    // slot (n - 1) mod M differs from the slot n mod M that step_rule reads when M > 1
+    if (in.fhist && in.n_global >= 1) in.fhist[(in.n_global - 1) % R.M] = in.f_prev;
+    if ((in.n_global + 1) % R.M == 0) {
+        const double e = in.epoch_sum + f;
+        if (e < in.best_f) {
+            out.best_f = e;
+            out.best_n = in.n_global + 1;
+        }
+        out.epoch_sum = 0.0;
+    } else {
+        out.epoch_sum = in.epoch_sum + f;
+    }
+    out.lambda = lam;
+    out.f_prev = f;
+    out.n_global = in.n_global + 1;
+    out.it = in.it + 1;
+    *st_out = out;
 }
 
 struct UpdateScalars {
@@ -495,21 +538,9 @@ __device__ __forceinline__ void bp_update_tile(Geo G, const ViewRec* __restrict_
     // step rule (needed only for the update, so its loads overlap other waves' gathers)
     const double f = block_sum<256>(part, (sc.nrays + SQ_GROUP - 1) / SQ_GROUP, red) / (double)sc.nrays;
     const DevState in = *st_in;
-    const double lam_d = next_lambda(in, sc.rule, f);
-    if (ti0 == 0 && tj0 == 0 && threadIdx.x == 0) {
-        DevState out = in;
-        if (!isfinite(f)) out.flags |= 1;
-        if (in.trace) {
-            in.trace[2 * in.it] = f;
-            in.trace[2 * in.it + 1] = lam_d;
-        }
-        out.lambda = lam_d;
-        out.f_prev = f;
-        out.n_global = in.n_global + 1;
-        out.it = in.it + 1;
-        *st_out = out;
-    }
-    const float lam = (float)lam_d;
+    const StepDecision dec = step_rule(in, sc.rule, f);
+    if (ti0 == 0 && tj0 == 0 && threadIdx.x == 0) record_state(in, sc.rule, f, dec.lam, st_out);
+    const float lam = (float)dec.lam;
 
     float mu_new = 0.0f;
     if (inside) {
@@ -517,6 +548,7 @@ __device__ __forceinline__ void bp_update_tile(Geo G, const ViewRec* __restrict_
         const float v = s[ty + 1][tx + 1] + lam * fmaf(sc.uc.c_l, gl, sc.uc.c_r * gr);
         mu_new = in_disc(i, j, G.n) ? fmaxf(v, 0.0f) : 0.0f;
         img_out[(size_t)j * G.P + i + PAD] = mu_new;
+        if (dec.keep) in.best[(size_t)j * G.n + i] = mu_new;
     }
     t[ty][tx] = mu_new;
     __syncthreads();
@@ -559,21 +591,9 @@ __device__ __forceinline__ void bp_update_tile_blk(Geo G, const ViewRec* __restr
 
     const double f = block_sum<NTH>(part, (sc.nrays + SQ_GROUP - 1) / SQ_GROUP, red) / (double)sc.nrays;
     const DevState in = *st_in;
-    const double lam_d = next_lambda(in, sc.rule, f);
-    if (ti0 == 0 && tj0 == 0 && tid == 0) {
-        DevState out = in;
-        if (!isfinite(f)) out.flags |= 1;
-        if (in.trace) {
-            in.trace[2 * in.it] = f;
-            in.trace[2 * in.it + 1] = lam_d;
-        }
-        out.lambda = lam_d;
-        out.f_prev = f;
-        out.n_global = in.n_global + 1;
-        out.it = in.it + 1;
-        *st_out = out;
-    }
-    const float lam = (float)lam_d;
+    const StepDecision dec = step_rule(in, sc.rule, f);
+    if (ti0 == 0 && tj0 == 0 && tid == 0) record_state(in, sc.rule, f, dec.lam, st_out);
+    const float lam = (float)dec.lam;
 
 #pragma unroll
     for (int b = 0; b < PY; ++b)
@@ -586,6 +606,7 @@ __device__ __forceinline__ void bp_update_tile_blk(Geo G, const ViewRec* __restr
                 const float v = s[byl + b + 1][bxl + a + 1] + lam * fmaf(sc.uc.c_l, acc[b][a], sc.uc.c_r * gr);
                 mu_new = in_disc(i, j, G.n) ? fmaxf(v, 0.0f) : 0.0f;
                 img_out[(size_t)j * G.P + i + PAD] = mu_new;
+                if (dec.keep) in.best[(size_t)j * G.n + i] = mu_new;
             }
             t[byl + b][bxl + a] = mu_new;
         }

@@ -65,14 +65,23 @@ struct DevState {
     int32_t n_global;       // global index n of the next sub-iteration
     int32_t it;             // index into trace / schedule of the next sub-iteration
     int32_t flags;          // bit 0: non-finite f met
-    int32_t pad;
+    int32_t best_n;         // sub-iterations behind the kept iterate (0: none)
+    double best_f;          // least epoch sum of f so far
+    double epoch_sum;       // sum of f over the current epoch's earlier sub-iterations
     double* trace;          // [n_iter][2] or null
     const double* schedule; // [n_iter] or null
+    // [M] f of each subset's latest sub-iteration, or null.  Written one
+    // sub-iteration late (sub-iteration n stores f_{n-1}, which it holds as
+    // f_prev), so that a launch never reads the slot it writes.
+    double* fhist;
+    float* best;            // [n][n] kept iterate (1/mm) or null
 };
 
-// Step-rule constants handed to the lambda kernel by value.
+// Step-rule constants handed to the update kernel by value.
 struct StepRule {
     double lambda0, inc, dec, lmin;
+    int M;        // subsets per epoch
+    int compare;  // 1: compare with the same subset one epoch earlier
 };
 
 // Constants of the fused backprojection + TV + update kernel.
@@ -153,6 +162,7 @@ struct recon_handle {
     double* d_part_all = nullptr;           // the same over all views (full-data residual)
     recon::DevState* d_state = nullptr;     // two copies: sub-iteration reads one, writes the other
     recon::DevState* h_state = nullptr;     // pinned read-back
+    double* d_fhist = nullptr;              // [M] subset history of a fresh run with lambda_compare
 
     int fp_segments = 8;
     int bp_variant = 1;      // 0: global candidate reads, 1: LDS-staged
@@ -200,8 +210,12 @@ hipError_t launch_fp_plain(const Geo& geo, int segments, const float* img, const
 hipError_t launch_fp_os(const Geo& geo, int segments, const float* img, const float* imgT, const RayGeo* rg,
                         const RayMeta* rm, int ray0, int nrays, const float* yt, const float* p, float* w,
                         double* part, hipStream_t s);
-hipError_t launch_set_state(DevState* st, double lambda, double f_prev, int n_global, int flags, double* trace,
-                            const double* schedule, hipStream_t s);
+// Writes v to *st on the stream (it = 0 at the start of every run).
+hipError_t launch_set_state(DevState* st, const DevState& v, hipStream_t s);
+// State of a fresh run: lambda_0, no epoch ended yet, no trace, history or kept image.
+DevState fresh_state(double lambda0);
+// Completes the one-late history of the state st (fhist[(n - 1) mod M] = f_prev).
+hipError_t launch_flush_hist(const DevState* st, int M, hipStream_t s);
 hipError_t launch_bp_plain(const Geo& geo, const ViewRec* views, const RayGeo* rg, const float* w, int q0, int nq,
                            float* out, hipStream_t s);
 // bp.hip; variant 0 = candidate reads from global memory, 1 = LDS-staged.

@@ -315,18 +315,18 @@ hipError_t launch_fp(int segments, const FpArgs& a, hipStream_t s)
 // Iteration state
 // ----------------------------------------------------------------------------
 
-__global__ void set_state_kernel(DevState* st, double lambda, double f_prev, int n_global, int flags, double* trace,
-                                 const double* schedule)
+__global__ void set_state_kernel(DevState* st, DevState v)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    st->lambda = lambda;
-    st->f_prev = f_prev;
-    st->n_global = n_global;
-    st->it = 0;
-    st->flags = flags;
-    st->pad = 0;
-    st->trace = trace;
-    st->schedule = schedule;
+    v.it = 0;
+    *st = v;
+}
+
+__global__ void flush_hist_kernel(const DevState* st, int M)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const DevState v = *st;
+    if (v.fhist && v.n_global >= 1) v.fhist[(v.n_global - 1) % M] = v.f_prev;
 }
 
 // Full-data residual: one block, fixed summation order (thread-strided sums,
@@ -482,10 +482,23 @@ hipError_t launch_fp_batch(int segments, const SliceDesc* slices, const FpWork* 
     return hipGetLastError();
 }
 
-hipError_t launch_set_state(DevState* st, double lambda, double f_prev, int n_global, int flags, double* trace,
-                            const double* schedule, hipStream_t s)
+hipError_t launch_set_state(DevState* st, const DevState& v, hipStream_t s)
 {
-    set_state_kernel<<<1, 64, 0, s>>>(st, lambda, f_prev, n_global, flags, trace, schedule);
+    set_state_kernel<<<1, 64, 0, s>>>(st, v);
+    return hipGetLastError();
+}
+
+DevState fresh_state(double lambda0)
+{
+    DevState v{};
+    v.lambda = lambda0;
+    v.best_f = INFINITY;
+    return v;
+}
+
+hipError_t launch_flush_hist(const DevState* st, int M, hipStream_t s)
+{
+    flush_hist_kernel<<<1, 64, 0, s>>>(st, M);
     return hipGetLastError();
 }
 

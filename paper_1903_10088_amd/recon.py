@@ -35,16 +35,19 @@ class Geometry_c(ctypes.Structure):
 class Params_c(ctypes.Structure):
     _fields_ = [("lambda0", ctypes.c_double), ("lambda_inc", ctypes.c_double), ("lambda_dec", ctypes.c_double),
                 ("lambda_min", ctypes.c_double), ("mu0_per_mm", ctypes.c_double),
-                ("tv_eps_per_mm", ctypes.c_double)]
+                ("tv_eps_per_mm", ctypes.c_double), ("lambda_compare", ctypes.c_int32),
+                ("keep_best", ctypes.c_int32)]
 
 
 class State_c(ctypes.Structure):
     _fields_ = [("n_done", ctypes.c_int32), ("flags", ctypes.c_int32), ("lambda_", ctypes.c_double),
-                ("f_prev", ctypes.c_double)]
+                ("f_prev", ctypes.c_double), ("best_f", ctypes.c_double), ("epoch_sum", ctypes.c_double),
+                ("best_n", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 EXPORTS = ["recon_default_params", "recon_status_string", "recon_last_error", "recon_create", "recon_destroy",
-           "recon_project", "recon_backproject", "recon_tv_grad", "recon_os_iterate", "recon_initial_image",
+           "recon_project", "recon_backproject", "recon_tv_grad", "recon_os_iterate", "recon_os_iterate_ex",
+           "recon_initial_image",
            "recon_subset_size", "recon_set_launch", "recon_check_tables", "recon_count_pairs",
            "recon_time_kernels", "recon_batch_create", "recon_batch_destroy", "recon_batch_initial_images",
            "recon_batch_run", "recon_batch_tune", "recon_batch_set_launch", "recon_batch",
@@ -77,6 +80,7 @@ def lib():
         L.recon_backproject.argtypes = [vp, vp, vp, i32, vp]
         L.recon_tv_grad.argtypes = [vp, vp, vp, vp]
         L.recon_os_iterate.argtypes = [vp, vp, f, vp, i32, P(State_c), vp, vp, vp]
+        L.recon_os_iterate_ex.argtypes = [vp, vp, f, vp, i32, P(State_c), vp, vp, vp, vp, vp]
         L.recon_initial_image.argtypes = [vp, vp, vp]
         L.recon_subset_size.argtypes = [vp, i32, P(i32)]
         L.recon_set_launch.argtypes = [vp, i32, i32]
@@ -167,12 +171,15 @@ class State:
     """Resumable iteration state (mirrors recon_state)."""
 
     def __init__(self, n_done: int = 0, lam: float = 0.0, f_prev: float = 0.0, flags: int = 0):
-        self.c = State_c(n_done, flags, lam, f_prev)
+        self.c = State_c(n_done, flags, lam, f_prev, 0.0, 0.0, 0, 0)
 
     n_done = property(lambda self: self.c.n_done)
     lam = property(lambda self: self.c.lambda_)
     f_prev = property(lambda self: self.c.f_prev)
     flags = property(lambda self: self.c.flags)
+    best_f = property(lambda self: self.c.best_f)
+    best_n = property(lambda self: self.c.best_n)
+    epoch_sum = property(lambda self: self.c.epoch_sum)
 
 
 class Recon:
@@ -288,9 +295,12 @@ class Recon:
         return out
 
     def os_iterate(self, counts, i0: float, img=None, n_iter: int = 1, state: State | None = None,
-                   trace: bool = False, lambda_schedule=None):
+                   trace: bool = False, lambda_schedule=None, f_hist=None, best=None):
         """Runs n_iter sub-iterations in place on img (created from the homogeneous start if None).
 
+        f_hist: None or a float64 CUDA tensor [M], the per-subset history that params lambda_compare
+        reads (pass the same tensor again to resume).  best: float32 CUDA tensor [n][n] receiving the
+        kept iterate; required exactly when params keep_best is set (recon_os_iterate_ex).
         Returns (img, trace) with trace a float64 CUDA tensor [n_iter][2] of (f_n, lambda_n) or None."""
         torch = _torch()
         g = self.geometry
@@ -302,12 +312,14 @@ class Recon:
             sched = torch.as_tensor(np.asarray(lambda_schedule, dtype=np.float64)).to(counts.device)
             if sched.numel() < n_iter:
                 raise ValueError("lambda_schedule shorter than n_iter")
-        _check(lib().recon_os_iterate(self._h, _ptr(counts, torch.float32, (g.n_views, g.n_channels), "counts"),
-                                      float(i0), _ptr(img, torch.float32, (g.n, g.n), "img"), int(n_iter),
-                                      ctypes.byref(state.c) if state is not None else None,
-                                      _ptr(tr, torch.float64, None, "trace"),
-                                      _ptr(sched, torch.float64, None, "lambda_schedule"), _stream()),
-               "recon_os_iterate")
+        _check(lib().recon_os_iterate_ex(self._h, _ptr(counts, torch.float32, (g.n_views, g.n_channels), "counts"),
+                                         float(i0), _ptr(img, torch.float32, (g.n, g.n), "img"), int(n_iter),
+                                         ctypes.byref(state.c) if state is not None else None,
+                                         _ptr(tr, torch.float64, None, "trace"),
+                                         _ptr(sched, torch.float64, None, "lambda_schedule"),
+                                         _ptr(f_hist, torch.float64, (self.subsets,), "f_hist"),
+                                         _ptr(best, torch.float32, (g.n, g.n), "best"), _stream()),
+               "recon_os_iterate_ex")
         return img, tr
 
 

@@ -83,6 +83,8 @@ def test_null_handle_calls_are_rejected():
     L = recon.lib()
     assert L.recon_project(None, None, None, -1, None) == recon.RECON_INVALID_ARG
     assert L.recon_os_iterate(None, None, 1.0, None, 1, None, None, None, None) == recon.RECON_INVALID_ARG
+    assert L.recon_os_iterate_ex(None, None, 1.0, None, 1, None, None, None, None, None,
+                                 None) == recon.RECON_INVALID_ARG
     assert L.recon_destroy(None) == recon.RECON_OK
 
 
@@ -122,3 +124,34 @@ def test_cnn_initial_params_layout():
     assert not th[-289:].any()  # last layer zero: the network starts as the identity
     w2 = th[320:320 + 9216]
     assert abs(w2.std() - (2.0 / 288) ** 0.5) < 0.005
+
+
+def test_step_rule_options_are_validated_before_the_device():
+    """lambda_compare and keep_best take 0 or 1; the batched entry points refuse both (they are
+    single-slice options), all before any device work."""
+    L = recon.lib()
+    g = recon.geometry_c(ph.config0_geometry())
+    assert recon.default_params()["lambda_compare"] == 0 and recon.default_params()["keep_best"] == 0
+    for bad in [dict(lambda_compare=2), dict(keep_best=-1)]:
+        p = recon.default_params()
+        p.update(bad)
+        h = ctypes.c_void_p()
+        assert L.recon_create(ctypes.byref(g), 10, 1e-3, ctypes.byref(recon.Params_c(**p)),
+                              ctypes.byref(h)) == recon.RECON_INVALID_ARG
+        assert h.value is None
+    for opt in [dict(lambda_compare=1), dict(keep_best=1)]:
+        p = recon.default_params()
+        p.update(opt)
+        h = ctypes.c_void_p()
+        garr = (recon.Geometry_c * 1)(g)
+        assert L.recon_batch_create(garr, 1, 10, 1e-3, ctypes.byref(recon.Params_c(**p)),
+                                    ctypes.byref(h)) == recon.RECON_INVALID_ARG
+        assert h.value is None
+        assert "single-slice" in L.recon_last_error().decode()
+
+
+def test_abi_struct_sizes():
+    """The ctypes mirrors have the C layout (the library asserts the same sizes at compile time)."""
+    assert ctypes.sizeof(recon.Params_c) == 56
+    assert ctypes.sizeof(recon.State_c) == 48
+    assert recon.State_c.best_n.offset == 40
