@@ -312,8 +312,9 @@ recon_status recon_time_kernels(recon_handle* h, const float* d_counts, float i0
  * nonzero interpolation weight that the backprojector's candidate windows
  * (the per-pixel windows and the per-tile linear windows of the LDS-staged
  * gather) would miss (*missed, must be 0), the per-pixel candidates (*candidates) and
- * the nonzero pairs (*pairs); also counts projector samples outside a ray's
- * stored sample range into *missed. */
+ * the nonzero pairs (*pairs); also counts into *missed projector samples
+ * outside a ray's stored sample range and per-tile windows outside the
+ * channel range the staged gather holds in LDS. */
 recon_status recon_check_tables(const recon_geometry* geom, int32_t subsets, int32_t view_stride, int64_t* missed,
                                 int64_t* candidates, int64_t* pairs);
 

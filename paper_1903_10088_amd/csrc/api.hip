@@ -694,17 +694,23 @@ recon_status recon_check_tables(const recon_geometry* geom, int32_t subsets, int
         for (int tj0 = 0; tj0 < N; tj0 += 16)
             for (int ti0 = 0; ti0 < N; ti0 += 16) {
                 const TileView tv = tile_view(G, v, (float)ti0 + 7.5f - G.c, (float)tj0 + 7.5f - G.c);
+                // the staged channel range, when the view is staged, holds every window
+                int k0, cnt;
+                stage_range(tv, nch, STAGE_SLOTS, k0, cnt);
+                auto outside_stage = [&](int lo, int hi) { return cnt > 0 && lo <= hi && (lo < k0 || hi >= k0 + cnt); };
                 for (int j = tj0; j < std::min(N, tj0 + 16); ++j)
                     for (int i = ti0; i < std::min(N, ti0 + 16); ++i) {
                         const float dX = (float)(i - ti0) - 7.5f, dY = (float)(j - tj0) - 7.5f;
                         const float kp = fmaf(tv.gx, dX, fmaf(tv.gy, dY, tv.kpc));
                         int lo, hi;
                         candidate_range(kp, tv.hwx, x0, x1, lo, hi);
+                        if (x0 < x1 && outside_stage(lo, hi)) ++miss;
                         for (int k = x0; k < x1; ++k)
                             if (hat(ray_offset(T.rg[(size_t)q * nch + k], (float)i, (float)j)) > 0.0f &&
                                 (k < lo || k > hi))
                                 ++miss;
                         candidate_range(kp, tv.hwy, y0, y1, lo, hi);
+                        if (y0 < y1 && outside_stage(lo, hi)) ++miss;
                         for (int k = y0; k < y1; ++k)
                             if (hat(ray_offset(T.rg[(size_t)q * nch + k], (float)j, (float)i)) > 0.0f &&
                                 (k < lo || k > hi))

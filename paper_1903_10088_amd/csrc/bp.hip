@@ -31,9 +31,9 @@ inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
 constexpr int TILE = 16;
 constexpr int STAGE_VIEWS = 8;   // views per LDS chunk
-constexpr int STAGE_SLOTS = 64;  // channels per view that can be staged
-constexpr int STAGE_ROW = STAGE_SLOTS + 4;  // row length: unrolled reads may run 3 past the last slot
 constexpr int UNROLL = 4;        // candidates evaluated without a loop
+constexpr int STAGE_GAP = UNROLL - 1;  // zero-weight slots after each major-axis part of a staged row
+constexpr int STAGE_ROW = STAGE_SLOTS + 2 * STAGE_GAP;
 
 // Adds the contributions of channels [lo, hi] (lo <= hi) of one view to acc,
 // in increasing channel order.  `t` is the pixel's coordinate along the rays'
@@ -73,7 +73,31 @@ struct GlobalRead {
     }
 };
 
-// Reads channel k of one view from its LDS row (k0 = first staged channel).
+// Adds channels [lo, hi] (lo <= hi) of one view from its staged LDS row with
+// no masking: the first UNROLL candidates are always evaluated.  A candidate
+// past hi is either a ray of the same major axis outside the pixel's window,
+// whose weight is exactly zero (the window holds every ray with nonzero
+// weight), or one of the zero-weight slots that follow each major-axis part of
+// the row; either adds exactly zero, so the sum has the bits of the masked
+// form.
+template <class Read>
+__device__ __forceinline__ float add_window_padded(float acc, int lo, int hi, float t, float c, Read read)
+{
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+        float wk;
+        const RayGeo g = read(lo + u, wk);
+        acc = fmaf(hat(ray_offset(g, t, c)), wk, acc);
+    }
+    for (int k = lo + UNROLL; k <= hi; ++k) {
+        float wk;
+        const RayGeo g = read(k, wk);
+        acc = fmaf(hat(ray_offset(g, t, c)), wk, acc);
+    }
+    return acc;
+}
+
+// Reads channel k of one view from its LDS row (slot k - k0).
 struct LdsRead {
     const float4* sg;
     const float* sw;
@@ -114,13 +138,86 @@ __device__ __forceinline__ float gather_global(const Geo& G, const ViewRec* __re
     return acc;
 }
 
+// A staged row holds channels [k0, k0 + cnt) in order, with STAGE_GAP
+// zero-weight slots inserted before channel k_split when the range straddles
+// it (the boundary between the two major axes) and STAGE_GAP more after the
+// last channel: channel k sits in slot k - k0 below k_split and k - kb from it
+// on (kb = k0 - STAGE_GAP when there is a gap, else k0).  Rows are double
+// buffered: chunk c is read from buffer c & 1 while chunk c + 1's rays are in
+// flight from L2.
+constexpr int STAGE_TABLE = 64;  // views whose tile models are formed together, one per thread
+constexpr int STAGE_LOADS = STAGE_VIEWS * STAGE_SLOTS / 256;  // staged slots per thread and chunk
+
 struct StageLds {
-    float4 geo[STAGE_VIEWS][STAGE_ROW];
-    float w[STAGE_VIEWS][STAGE_ROW];
-    int k0[STAGE_VIEWS];
-    int cnt[STAGE_VIEWS];  // staged channels, 0 = view not staged
-    TileView tv[STAGE_VIEWS];
+    float4 geo[2][STAGE_VIEWS][STAGE_ROW];
+    float w[2][STAGE_VIEWS][STAGE_ROW];
+    TileView tv[STAGE_TABLE];
+    int k0[STAGE_TABLE];
+    int kb[STAGE_TABLE];
+    int cnt[STAGE_TABLE];  // staged channels, 0 = view not staged
+    int ray0[STAGE_TABLE];
+    int ks[STAGE_TABLE];
 };
+
+// One thread's share of a chunk's staged rays, held in registers between the
+// load and the LDS store.
+struct StagePrefetch {
+    float4 g[STAGE_LOADS];
+    float w[STAGE_LOADS];
+    int slot[STAGE_LOADS];  // row slot, -1 = nothing to store
+};
+
+// Loads this thread's slots of the chunk of views [t0, t0 + cv) of the table.
+__device__ __forceinline__ void stage_load(const StageLds& S, const RayGeo* __restrict__ rg,
+                                           const float* __restrict__ w, int t0, int cv, StagePrefetch& P)
+{
+#pragma unroll
+    for (int r = 0; r < STAGE_LOADS; ++r) {
+        const int sl = threadIdx.x + 256 * r;
+        const int cq = sl / STAGE_SLOTS, e = sl - cq * STAGE_SLOTS;
+        P.slot[r] = -1;
+        if (cq < cv) {
+            const int t = t0 + cq;
+            if (e < S.cnt[t]) {
+                const int k = S.k0[t] + e;
+                const RayGeo g = rg[S.ray0[t] + k];
+                P.g[r] = make_float4(g.a_int, g.a_frac, g.s_hi, g.s_lo);
+                P.w[r] = w[S.ray0[t] + k];
+                P.slot[r] = cq * STAGE_ROW + (k < S.ks[t] ? e : k - S.kb[t]);
+            }
+        }
+    }
+}
+
+// Stores the prefetched slots into buffer b and writes the zero-weight slots.
+__device__ __forceinline__ void stage_store(StageLds& S, int b, int t0, int cv, const StagePrefetch& P)
+{
+    float4* geo = &S.geo[b][0][0];
+    float* wr = &S.w[b][0][0];
+#pragma unroll
+    for (int r = 0; r < STAGE_LOADS; ++r)
+        if (P.slot[r] >= 0) {
+            geo[P.slot[r]] = P.g[r];
+            wr[P.slot[r]] = P.w[r];
+        }
+    const int tid = threadIdx.x;
+    if (tid < cv * 2 * STAGE_GAP) {
+        const int cq = tid / (2 * STAGE_GAP), m = tid - cq * (2 * STAGE_GAP);
+        const int t = t0 + cq;
+        const int k0 = S.k0[t], kb = S.kb[t], cnt = S.cnt[t];
+        int pos = -1;
+        if (cnt > 0) {
+            if (m < STAGE_GAP)
+                pos = cnt + (k0 - kb) + m;
+            else if (kb != k0)
+                pos = S.ks[t] - k0 + (m - STAGE_GAP);
+        }
+        if (pos >= 0) {
+            S.geo[b][cq][pos] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            S.w[b][cq][pos] = 0.0f;
+        }
+    }
+}
 
 // g_L at pixel (i, j) of a 16x16 tile with LDS staging.  Must be called by all
 // 256 threads of the block (it has barriers); `inside` marks real pixels.
@@ -134,64 +231,68 @@ __device__ __forceinline__ float gather_staged(StageLds& S, const Geo& G, const 
     const float dX = (float)(i - ti0) - 7.5f, dY = (float)(j - tj0) - 7.5f;
     const float Xc = (float)ti0 + 7.5f - G.c, Yc = (float)tj0 + 7.5f - G.c;
     float acc = 0.0f;
-    for (int c0 = q0; c0 < q0 + nq; c0 += STAGE_VIEWS) {
-        const int cv = min(STAGE_VIEWS, q0 + nq - c0);
-        if (tid < cv) {
-            // the view's linear channel model over the tile and the channel range
-            // that holds every pixel's window
-            const ViewRec v = V[c0 + tid];
+    for (int s0 = q0; s0 < q0 + nq; s0 += STAGE_TABLE) {
+        const int sn = min(STAGE_TABLE, q0 + nq - s0);
+        if (tid < sn) {
+            // each view's linear channel model over the tile and the channel
+            // range that holds every pixel's window
+            const ViewRec v = V[s0 + tid];
             const TileView tv = tile_view(G, v, Xc, Yc);
-            const float spread = (fabsf(tv.gx) + fabsf(tv.gy)) * 7.5f + fmaxf(tv.hwx, tv.hwy);
-            const int k0 = max(0, (int)floorf(tv.kpc - spread) - 1);
-            const int k1 = min(G.nch - 1, (int)ceilf(tv.kpc + spread) + 1);
-            const int cnt = k1 - k0 + 1;
-            S.k0[tid] = k0;
-            S.cnt[tid] = (cnt > 0 && cnt <= STAGE_SLOTS) ? cnt : 0;
+            int k0, cnt;
+            stage_range(tv, G.nch, STAGE_SLOTS, k0, cnt);
+            const bool gap = k0 < v.k_split && v.k_split < k0 + cnt;
             S.tv[tid] = tv;
+            S.k0[tid] = k0;
+            S.kb[tid] = gap ? k0 - STAGE_GAP : k0;
+            S.cnt[tid] = cnt;
+            S.ray0[tid] = v.ray0;
+            S.ks[tid] = v.k_split;
         }
         __syncthreads();
-        for (int slot = tid; slot < cv * STAGE_SLOTS; slot += 256) {
-            const int cq = slot / STAGE_SLOTS, e = slot - cq * STAGE_SLOTS;
-            if (e < S.cnt[cq]) {
-                const int ray = V[c0 + cq].ray0 + S.k0[cq] + e;
-                const RayGeo g = rg[ray];
-                S.geo[cq][e] = make_float4(g.a_int, g.a_frac, g.s_hi, g.s_lo);
-                S.w[cq][e] = w[ray];
-            }
-        }
-        __syncthreads();
-        if (inside) {
-            for (int cq = 0; cq < cv; ++cq) {
-                const ViewRec v = V[c0 + cq];
-                const int k0 = S.k0[cq], cnt = S.cnt[cq];
-                const TileView tv = S.tv[cq];
-                const float kp = fmaf(tv.gx, dX, fmaf(tv.gy, dY, tv.kpc));
-                int x0, x1, y0, y1;
-                major_intervals(v, G.nch, x0, x1, y0, y1);
-                const LdsRead lds{S.geo[cq], S.w[cq], k0};
-                if (x0 < x1) {
-                    int lo, hi;
-                    candidate_range(kp, tv.hwx, x0, x1, lo, hi);
-                    if (lo <= hi) {
-                        if (lo >= k0 && hi < k0 + cnt)
-                            acc = add_window(acc, lo, hi, fi, fj, lds);
-                        else
-                            acc = add_window(acc, lo, hi, fi, fj, GlobalRead{rg + v.ray0, w + v.ray0, hi});
+        StagePrefetch P;
+        stage_load(S, rg, w, 0, min(STAGE_VIEWS, sn), P);
+        for (int t0 = 0, b = 0; t0 < sn; t0 += STAGE_VIEWS, b ^= 1) {
+            const int cv = min(STAGE_VIEWS, sn - t0);
+            // buffer b was last read by chunk t0 - 2, before the previous barrier
+            stage_store(S, b, t0, cv, P);
+            __syncthreads();
+            if (t0 + STAGE_VIEWS < sn) stage_load(S, rg, w, t0 + STAGE_VIEWS, min(STAGE_VIEWS, sn - t0 - STAGE_VIEWS), P);
+            if (inside) {
+                for (int cq = 0; cq < cv; ++cq) {
+                    const int t = t0 + cq;
+                    const ViewRec v = V[s0 + t];
+                    const int cnt = S.cnt[t];
+                    const TileView tv = S.tv[t];
+                    const float kp = fmaf(tv.gx, dX, fmaf(tv.gy, dY, tv.kpc));
+                    int x0, x1, y0, y1;
+                    major_intervals(v, G.nch, x0, x1, y0, y1);
+                    // slot bases: the part from k_split on sits behind the gap
+                    const int bx = x0 == v.k_split ? S.kb[t] : S.k0[t];
+                    const int by = y0 == v.k_split ? S.kb[t] : S.k0[t];
+                    if (x0 < x1) {
+                        int lo, hi;
+                        candidate_range(kp, tv.hwx, x0, x1, lo, hi);
+                        if (lo <= hi) {
+                            if (cnt > 0)  // every window lies in the staged range (stage_range)
+                                acc = add_window_padded(acc, lo, hi, fi, fj, LdsRead{S.geo[b][cq], S.w[b][cq], bx});
+                            else
+                                acc = add_window(acc, lo, hi, fi, fj, GlobalRead{rg + v.ray0, w + v.ray0, hi});
+                        }
+                    }
+                    if (y0 < y1) {
+                        int lo, hi;
+                        candidate_range(kp, tv.hwy, y0, y1, lo, hi);
+                        if (lo <= hi) {
+                            if (cnt > 0)
+                                acc = add_window_padded(acc, lo, hi, fj, fi, LdsRead{S.geo[b][cq], S.w[b][cq], by});
+                            else
+                                acc = add_window(acc, lo, hi, fj, fi, GlobalRead{rg + v.ray0, w + v.ray0, hi});
+                        }
                     }
                 }
-                if (y0 < y1) {
-                    int lo, hi;
-                    candidate_range(kp, tv.hwy, y0, y1, lo, hi);
-                    if (lo <= hi) {
-                        if (lo >= k0 && hi < k0 + cnt)
-                            acc = add_window(acc, lo, hi, fj, fi, lds);
-                        else
-                            acc = add_window(acc, lo, hi, fj, fi, GlobalRead{rg + v.ray0, w + v.ray0, hi});
-                    }
-                }
             }
         }
-        __syncthreads();
+        __syncthreads();  // the table and both buffers are rewritten by the next group of views
     }
     return acc;
 }

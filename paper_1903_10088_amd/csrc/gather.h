@@ -161,7 +161,26 @@ __host__ __device__ __forceinline__ float ray_offset(const RayGeo& g, float t, f
 
 // Joseph weight of a ray on a pixel: the hat function of the distance d, along
 // the ray's minor axis, between the ray's crossing of the pixel's sampling
-// line and the pixel centre.
-__host__ __device__ __forceinline__ float hat(float d) { return fmaxf(0.0f, 1.0f - fabsf(d)); }
+// line and the pixel centre.  max(0, 1 - |d|) written as a clamp to [0, 1]
+// (1 - |d| never exceeds 1), which the device does in the subtraction itself.
+__host__ __device__ __forceinline__ float hat(float d) { return fminf(fmaxf(1.0f - fabsf(d), 0.0f), 1.0f); }
+
+// Channels per view that the LDS-staged gather can stage for one tile.
+constexpr int STAGE_SLOTS = 64;
+
+// Channels of one view that the LDS-staged gather stages for a 16x16 tile:
+// [k0, k0 + cnt) covers the window of every pixel of the tile.  The windows
+// [ceil(kp - hw), floor(kp + hw)] have |kp - kpc| <= 7.5 (|gx| + |gy|) up to
+// the rounding of kp (below 1e-3 channel for any channel count under 2^16),
+// and hw <= max(hwx, hwy), so one channel of margin on each side contains
+// them.  cnt = 0 when the range exceeds `slots` (the view is then not staged).
+__host__ __device__ __forceinline__ void stage_range(const TileView& tv, int nch, int slots, int& k0, int& cnt)
+{
+    const float spread = (fabsf(tv.gx) + fabsf(tv.gy)) * 7.5f + fmaxf(tv.hwx, tv.hwy);
+    k0 = max(0, (int)floorf(tv.kpc - spread) - 1);
+    const int k1 = min(nch - 1, (int)ceilf(tv.kpc + spread) + 1);
+    cnt = k1 - k0 + 1;
+    if (cnt <= 0 || cnt > slots) cnt = 0;
+}
 
 }  // namespace recon
