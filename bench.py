@@ -286,10 +286,10 @@ def cnn_leg(batch: int, dev):
 
 
 def warm_leg(n_slices: int, weights: str, dev):
-    """Warm-start pipeline (10 sub-iterations, network, 40 refining, cold fallback) on full-study
-    slices (512^2, views U{600..900}, 738 channels, I0 log-uniform 1e3..1e4), against the plain
-    batched method run to the smallest sub-iteration count that reaches the same mean RMSE to each
-    slice's converged (500-sub-iteration) image."""
+    """Warm-start pipeline (10 sub-iterations, network, the record's refining count, a cold start of
+    the record's length above the record's limit) on full-study slices (512^2, views U{600..900}, 738 channels, I0
+    log-uniform 1e3..1e4), against the plain batched method run to the smallest sub-iteration count
+    (grid of 5) that reaches the same mean RMSE to each slice's converged (500-sub-iteration) image."""
     import json as _json
 
     import numpy as np
@@ -303,11 +303,13 @@ def warm_leg(n_slices: int, weights: str, dev):
         log(f"bench: no trained weights at {weights}; warm-start leg skipped")
         return None
     meta = os.path.join(os.path.dirname(weights), "train.json")
-    ratio = _json.load(open(meta))["residual_ratio_limit"] if os.path.exists(meta) else 1.05
+    rec = _json.load(open(meta)) if os.path.exists(meta) else {}
+    ratio = rec.get("residual_ratio_limit", 1.05)
+    n_pre, n_refine, n_cold = rec.get("n_pre", 10), rec.get("n_refine", 5), rec.get("n_cold", 500)
     items = ws.config4_items(range(30000, 30000 + n_slices))
     log(f"bench: warm-start leg: {n_slices} slices ...")
     counts = ws.make_counts(items, workers=8)
-    iters = [10, 20, 30, 40, 50, 60, 80, 100, 125, 150, 200, 250, 300, 400, 500]
+    iters = ws.EQUAL_RMSE_GRID
     runs = ws.plain_runs(items, counts, iters, chunk=n_slices, device=dev)
     conv = runs[500]
     curve = {k: float(np.mean(ws.disc_rmse(runs[k], conv, 512)) / ph.MU_WATER_PER_MM) for k in iters}
@@ -318,19 +320,19 @@ def warm_leg(n_slices: int, weights: str, dev):
     cts = [torch.from_numpy(c).to(dev) for c in counts]
     i0s = [i0 for _, _, i0 in items]
     imgs = [torch.empty((512, 512), dtype=torch.float32, device=dev) for _ in items]
-    B.warm_start(net, cts, i0s, imgs, 10, 40, 500, ratio)
-    (_, res, flo, fb), t_warm = ws.timed(lambda: B.warm_start(net, cts, i0s, imgs, 10, 40, 500, ratio))
+    B.warm_start(net, cts, i0s, imgs, n_pre, n_refine, n_cold, ratio)
+    (_, res, flo, fb), t_warm = ws.timed(lambda: B.warm_start(net, cts, i0s, imgs, n_pre, n_refine, n_cold, ratio))
     rmse_w = float(np.mean(ws.disc_rmse(torch.stack(imgs), conv, 512)) / ph.MU_WATER_PER_MM)
-    n_eq = next((k for k in iters if curve[k] <= rmse_w), 500)
+    n_eq = ws.equal_rmse_count(curve, rmse_w)
     pimgs = B.initial_images(dev)
     B.run(cts, i0s, pimgs, n_eq)
     pimgs = B.initial_images(dev)
     _, t_plain = ws.timed(lambda: B.run(cts, i0s, pimgs, n_eq))
-    out = {"slices": n_slices, "warm_slices_per_s": n_slices / t_warm, "warm_rmse_to_converged_over_muw": rmse_w,
-           "fallbacks": int(fb.sum()), "residual_ratio_limit": ratio,
+    out = {"slices": n_slices, "n_pre": n_pre, "n_refine": n_refine, "n_cold": n_cold,
+           "warm_slices_per_s": n_slices / t_warm,
+           "warm_rmse_to_converged_over_muw": rmse_w, "fallbacks": int(fb.sum()), "residual_ratio_limit": ratio,
            "plain_sub_iterations_at_equal_rmse": n_eq, "plain_rmse_to_converged_over_muw": curve[n_eq],
-           "plain_slices_per_s_at_equal_rmse": n_slices / t_plain, "speedup": t_plain / t_warm,
-           "plain_curve": curve}
+           "plain_slices_per_s_at_equal_rmse": n_slices / t_plain, "speedup": t_plain / t_warm}
     log(f"bench: warm start {out['warm_slices_per_s']:.1f} slices/s at RMSE {rmse_w:.4f} mu_w "
         f"({out['fallbacks']} fallbacks); plain needs {n_eq} sub-iterations: "
         f"{out['plain_slices_per_s_at_equal_rmse']:.1f} slices/s; speedup {out['speedup']:.2f}")

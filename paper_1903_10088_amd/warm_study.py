@@ -74,9 +74,11 @@ def cmd_train(args):
     os.makedirs(args.out, exist_ok=True)
     wpath = os.path.join(args.out, "warm_cnn.bin")
     net.save(wpath)
-    # fallback limit from the plain method's converged training images
-    cal = list(range(0, ntr, max(1, ntr // args.calibrate)))[:args.calibrate]
-    ratio, ratios = ws.calibrate_ratio([items[i] for i in cal], [counts[i] for i in cal], n_final=args.n_final)
+    # fallback limit and cold-start length: the plain method at the warm start's RMSE, on
+    # calibration slices drawn like the workload
+    citems = ws.calibration_items(args.calibrate)
+    calib = ws.calibrate_equal_rmse(citems, ws.make_counts(citems, workers=args.workers), net, args.n_pre,
+                                    args.n_refine, n_final=args.n_final, device=dev)
     # held-out RMSE to the converged image: network alone, and after refinement
     out = torch.empty_like(xva)
     net.forward(xva, out, project=True)
@@ -84,9 +86,8 @@ def cmd_train(args):
     r_net = ws.disc_rmse(out, yva, 512) / MU_W
     rec = dict(slices=len(items), held_out=n_hold, n_pre=args.n_pre, n_final=args.n_final, epochs=epochs,
                batch=args.batch, lr=args.lr, step_ms=step_s * 1e3, train_s=t_train, plain_pairs_s=t_plain,
-               loss_identity_val=base_val, history=hist, residual_ratio_limit=ratio,
-               residual_ratios=dict(min=float(ratios.min()), median=float(np.median(ratios)),
-                                    max=float(ratios.max())),
+               loss_identity_val=base_val, history=hist, n_refine=args.n_refine, n_cold=calib["n_cold"],
+               residual_ratio_limit=calib["limit"], calibration=calib,
                val_rmse_over_muw=dict(input=float(np.mean(r_in)), network=float(np.mean(r_net))),
                weights=os.path.basename(wpath))
     json.dump(rec, open(os.path.join(args.out, "train.json"), "w"), indent=1)
@@ -94,21 +95,27 @@ def cmd_train(args):
 
 
 def cmd_calibrate(args):
-    """Recomputes the fallback limit of a trained network's record from the plain method's
-    converged images of training slices (the first `calibrate` training seeds)."""
+    """Recomputes the fallback limit and the cold-start length of a trained network's record for the
+    pipeline (n_pre, network, n_refine) on calibration slices drawn like the workload."""
+    import torch
+
+    dev = torch.device("cuda:0")
     rec = json.load(open(args.train_json))
-    n_hold = rec["slices"] // 10
-    ntr = rec["slices"] - n_hold
-    seeds = [10000 + i for i in range(0, ntr, max(1, ntr // args.calibrate))][:args.calibrate]
-    items = ws.config3_items(seeds)
+    items = ws.calibration_items(args.calibrate)
     counts = ws.make_counts(items, workers=args.workers)
-    ratio, ratios = ws.calibrate_ratio(items, counts, n_final=rec["n_final"])
-    rec["residual_ratio_limit"] = ratio
-    rec["residual_ratios"] = dict(min=float(ratios.min()), median=float(np.median(ratios)), max=float(ratios.max()))
-    rec["residual_statistic"] = "full-data mean (l - p)^2 / mean 1/max(y,1) (recon_data_residual)"
+    net = recon.Cnn(None, max_batch=8, max_n=512, mu_scale=MU_W)
+    net.load(args.weights or os.path.join(os.path.dirname(os.path.abspath(args.train_json)), rec["weights"]))
+    calib = ws.calibrate_equal_rmse(items, counts, net, rec["n_pre"], args.n_refine, n_final=rec["n_final"],
+                                    device=dev)
+    for k in ("residual_ratios", "residual_statistic"):
+        rec.pop(k, None)
+    rec["n_refine"] = args.n_refine
+    rec["n_cold"] = calib["n_cold"]
+    rec["residual_ratio_limit"] = calib["limit"]
+    rec["calibration"] = calib
     os.makedirs(args.out, exist_ok=True)
     json.dump(rec, open(os.path.join(args.out, "train.json"), "w"), indent=1)
-    ws.log(json.dumps({k: rec[k] for k in ("residual_ratio_limit", "residual_ratios")}))
+    ws.log(json.dumps(calib))
 
 
 def cmd_eval(args):
@@ -118,7 +125,11 @@ def cmd_eval(args):
     items = ws.config4_items(range(20000, 20000 + args.slices))
     ws.log(f"eval: generating {len(items)} count sinograms ...")
     counts = ws.make_counts(items, workers=args.workers)
-    lim = json.load(open(args.train_json))["residual_ratio_limit"] if args.train_json else args.ratio
+    rec = json.load(open(args.train_json)) if args.train_json else {}
+    lim = rec.get("residual_ratio_limit", args.ratio)
+    if args.n_refine is None:
+        args.n_refine = rec.get("n_refine", 5)
+    n_cold = rec.get("n_cold", args.n_final)
     # converged images and the plain method's RMSE curve
     iters = sorted(set(args.curve + [args.n_final]))
     runs = ws.plain_runs(items, counts, iters, chunk=args.chunk, device=dev)
@@ -128,7 +139,8 @@ def cmd_eval(args):
     del runs
     net = recon.Cnn(None, max_batch=8, max_n=512, mu_scale=MU_W)
     net.load(args.weights)
-    res = dict(slices=len(items), residual_ratio_limit=lim, plain_curve=curve, batches=[])
+    res = dict(slices=len(items), n_pre=args.n_pre, n_refine=args.n_refine, n_cold=n_cold, residual_ratio_limit=lim,
+               plain_curve=curve, batches=[])
     warm_imgs = torch.empty_like(conv)
     lat, fb_all, r_all = [], [], []
     t_total = 0.0
@@ -138,9 +150,9 @@ def cmd_eval(args):
         cts = [torch.from_numpy(c).to(dev) for c in counts[c0:c0 + args.chunk]]
         i0s = [i0 for _, _, i0 in sub]
         imgs = [warm_imgs[c0 + i] for i in range(len(sub))]
-        B.warm_start(net, cts, i0s, imgs, args.n_pre, args.n_refine, args.n_final, lim)  # warm-up
+        B.warm_start(net, cts, i0s, imgs, args.n_pre, args.n_refine, n_cold, lim)  # warm-up
         (_, rr, fl, fb), dt = ws.timed(lambda: B.warm_start(net, cts, i0s, imgs, args.n_pre, args.n_refine,
-                                                            args.n_final, lim))
+                                                            n_cold, lim))
         t_total += dt
         lat += [dt] * len(sub)
         fb_all += list(map(int, fb))
@@ -150,7 +162,7 @@ def cmd_eval(args):
         ws.log(f"eval: warm batch {c0}: {dt:.3f} s, {int(fb.sum())} fallbacks")
     r_warm = ws.disc_rmse(warm_imgs, conv, 512) / MU_W
     rmse_w = float(np.mean(r_warm))
-    n_eq = next((k for k in iters if curve[k] <= rmse_w), args.n_final)
+    n_eq = ws.equal_rmse_count(curve, rmse_w, args.n_final)
     # plain batched throughput at n_eq sub-iterations (same batches, same timing)
     t_plain = 0.0
     for c0 in range(0, len(items), args.chunk):
@@ -188,14 +200,17 @@ def main():
     t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--train-seconds", type=float, default=300.0)
     t.add_argument("--max-epochs", type=int, default=60)
-    t.add_argument("--calibrate", type=int, default=64)
+    t.add_argument("--calibrate", type=int, default=128)
+    t.add_argument("--n-refine", type=int, default=5, help="refining sub-iterations the limit is calibrated for")
     t.add_argument("--chunk", type=int, default=64)
     t.add_argument("--workers", type=int, default=12)
     t.add_argument("--seed", type=int, default=0)
     c = sp.add_parser("calibrate")
     c.add_argument("--out", required=True)
     c.add_argument("--train-json", required=True)
-    c.add_argument("--calibrate", type=int, default=64)
+    c.add_argument("--calibrate", type=int, default=128)
+    c.add_argument("--n-refine", type=int, default=5)
+    c.add_argument("--weights", default=None, help="default: the record's weights file beside it")
     c.add_argument("--workers", type=int, default=12)
     e = sp.add_parser("eval")
     e.add_argument("--out", required=True)
@@ -204,10 +219,9 @@ def main():
     e.add_argument("--ratio", type=float, default=1.05)
     e.add_argument("--slices", type=int, default=256)
     e.add_argument("--n-pre", type=int, default=10)
-    e.add_argument("--n-refine", type=int, default=40)
+    e.add_argument("--n-refine", type=int, default=None, help="default: the record's, else 5")
     e.add_argument("--n-final", type=int, default=500)
-    e.add_argument("--curve", type=int, nargs="*",
-                   default=[10, 20, 30, 40, 50, 60, 80, 100, 125, 150, 200, 250, 300, 400])
+    e.add_argument("--curve", type=int, nargs="*", default=ws.EQUAL_RMSE_GRID)
     e.add_argument("--chunk", type=int, default=32)
     e.add_argument("--workers", type=int, default=12)
     args = ap.parse_args()

@@ -12,10 +12,15 @@ Workflow (the network is trained only on images the plain iteration produced):
   2. `train`: Adam on random minibatches of (input, target) pairs, with the
      eight symmetries of the square (rotations by 90 degrees and flips, which
      map the reconstruction disc onto itself) as augmentation;
-  3. `calibrate_ratio`: the largest ratio of full-data residual to noise level
-     (recon_data_residual) over the plain method's converged training images,
+  3. `calibrate_equal_rmse`: on training slices, the warm start's mean RMSE to
+     the converged image, the smallest sub-iteration count at which the plain
+     method reaches it, and the largest ratio of full-data residual to noise
+     level (recon_data_residual) of the plain method's images at that count,
      widened by a margin: the limit above which the warm start falls back to a
-     cold start;
+     cold start (its output must explain the data as well as the plain image it
+     stands in for), and that count as the cold start's length (a slice that
+     falls back gets the plain image of the quality the pipeline stands in
+     for);
   4. `disc_rmse` / `timed`: RMSE to each slice's converged image and
      throughput of the warm-start pipeline (recon_warm_start) and of the plain
      batched method (warm_study.py runs the comparison).
@@ -70,6 +75,12 @@ def config3_items(seeds):
     """The clinical-scale slice (512^2, 800 views, 738 channels, I0 2e3) for each seed."""
     g = ph.config1_geometry()
     return [(g, int(s), 2e3) for s in seeds]
+
+
+def calibration_items(n: int = 128):
+    """Slices drawn like the full-study workload (config4_items) with seeds of their own (40000+),
+    disjoint from the evaluation (20000+) and the benchmark (30000+)."""
+    return config4_items(range(40000, 40000 + n))
 
 
 def config4_items(seeds):
@@ -168,24 +179,53 @@ def evaluate_loss(net, inputs, targets, batch: int = 8):
     return tot / max(S, 1)
 
 
-def calibrate_ratio(items, counts, subsets: int = 20, beta: float = 1e-3, n_final: int = 500,
-                    margin: float = 0.02, device="cuda"):
-    """Largest (full-data residual / noise floor) (recon_data_residual) of the plain method's
-    converged images, times (1 + margin): the limit above which the warm start falls back to a cold
-    start."""
-    torch = _torch()
-    B = recon.Batch([g for g, _, _ in items], subsets, beta)
-    cts = [torch.from_numpy(c).to(device) for c in counts]
-    imgs, _ = B.run(cts, [i0 for _, _, i0 in items], None, n_final)
-    ratios = []
-    for (g, _, i0), c, img in zip(items, cts, imgs):
+EQUAL_RMSE_GRID = list(range(10, 200, 5)) + [200, 250, 300, 400, 500]
+
+
+def residual_ratios(items, counts, imgs, subsets: int = 20, beta: float = 1e-3):
+    """Full-data residual over its noise level (recon_data_residual) of each slice's image."""
+    out = []
+    for (g, _, i0), c, img in zip(items, counts, imgs):
         R = recon.Recon(g, subsets, beta)
-        r = R.data_residual(c, i0, img).cpu().numpy()
-        ratios.append(r[0] / r[1])
+        r = R.data_residual(c, i0, img.contiguous()).cpu().numpy()
+        out.append(r[0] / r[1])
         R.close()
+    return np.asarray(out)
+
+
+def equal_rmse_count(curve: dict, rmse: float, n_final: int = 500) -> int:
+    """Smallest sub-iteration count of the curve {count: mean RMSE} at or below rmse."""
+    return next((k for k in sorted(curve) if curve[k] <= rmse), n_final)
+
+
+def calibrate_equal_rmse(items, counts, net, n_pre: int, n_refine: int, n_final: int = 500, subsets: int = 20,
+                         beta: float = 1e-3, margin: float = 0.02, grid=None, device="cuda"):
+    """Fallback limit for the pipeline (n_pre, network, n_refine): the plain method's largest
+    residual ratio at the sub-iteration count where its mean RMSE to the converged image first
+    reaches the pipeline's (no fallback while measuring), times (1 + margin).  Returns a record."""
+    torch = _torch()
+    grid = sorted(set((grid or EQUAL_RMSE_GRID) + [n_final]))
+    cts = [torch.from_numpy(c).to(device) for c in counts]
+    i0s = [i0 for _, _, i0 in items]
+    runs = plain_runs(items, counts, grid, subsets=subsets, beta=beta, chunk=len(items), device=device)
+    conv = runs[n_final]
+    n = items[0][0].n
+    curve = {k: float(np.mean(disc_rmse(runs[k], conv, n))) / ph.MU_WATER_PER_MM for k in grid}
+    B = recon.Batch([g for g, _, _ in items], subsets, beta)
+    imgs = [torch.empty((n, n), dtype=torch.float32, device=device) for _ in items]
+    _, rr, fl, _ = B.warm_start(net, cts, i0s, imgs, n_pre, n_refine, n_final, 1e30)
     B.close()
-    ratios = np.asarray(ratios)
-    return float(ratios.max() * (1 + margin)), ratios
+    warm_rmse = float(np.mean(disc_rmse(torch.stack(imgs), conv, n))) / ph.MU_WATER_PER_MM
+    n_eq = equal_rmse_count(curve, warm_rmse, n_final)
+    plain_r = residual_ratios(items, cts, [runs[n_eq][i] for i in range(len(items))], subsets, beta)
+    warm_r = rr / fl
+    return dict(limit=float(plain_r.max() * (1 + margin)), n_pre=n_pre, n_refine=n_refine, n_cold=n_eq,
+                warm_rmse_over_muw=warm_rmse, plain_sub_iterations_at_equal_rmse=n_eq,
+                plain_ratio=dict(min=float(plain_r.min()), median=float(np.median(plain_r)),
+                                 max=float(plain_r.max())),
+                warm_ratio=dict(min=float(warm_r.min()), median=float(np.median(warm_r)),
+                                max=float(warm_r.max())),
+                slices=len(items))
 
 
 # ---------------------------------------------------------------------------
