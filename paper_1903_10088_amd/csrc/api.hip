@@ -716,6 +716,35 @@ recon_status recon_check_tables(const recon_geometry* geom, int32_t subsets, int
                                 (k < lo || k > hi))
                                 ++miss;
                     }
+                // the blocked gathers' windows (PX x PY pixels per thread): each holds the
+                // windows of its pixels and lies in the staged range
+                for (int shape = 0; shape < 3; ++shape) {
+                    const int PX = shape == 0 ? 1 : 2, PY = shape == 1 ? 1 : 2;
+                    const float spread = block_spread(tv, PX, PY);
+                    for (int j0 = tj0; j0 < std::min(N, tj0 + 16); j0 += PY)
+                        for (int i0 = ti0; i0 < std::min(N, ti0 + 16); i0 += PX) {
+                            const float dXb = (float)(i0 - ti0) + 0.5f * (PX - 1) - 7.5f;
+                            const float dYb = (float)(j0 - tj0) + 0.5f * (PY - 1) - 7.5f;
+                            const float kpb = fmaf(tv.gx, dXb, fmaf(tv.gy, dYb, tv.kpc));
+                            int bxl, bxh, byl, byh;
+                            candidate_range(kpb, tv.hwx + spread, x0, x1, bxl, bxh);
+                            candidate_range(kpb, tv.hwy + spread, y0, y1, byl, byh);
+                            if (x0 < x1 && outside_stage(bxl, bxh)) ++miss;
+                            if (y0 < y1 && outside_stage(byl, byh)) ++miss;
+                            for (int b = 0; b < PY; ++b)
+                                for (int a = 0; a < PX; ++a) {
+                                    const int i = i0 + a, j = j0 + b;
+                                    if (i >= N || j >= N) continue;
+                                    const float kp = fmaf(tv.gx, (float)(i - ti0) - 7.5f,
+                                                          fmaf(tv.gy, (float)(j - tj0) - 7.5f, tv.kpc));
+                                    int lo, hi;
+                                    candidate_range(kp, tv.hwx, x0, x1, lo, hi);
+                                    if (x0 < x1 && lo <= hi && (lo < bxl || hi > bxh)) ++miss;
+                                    candidate_range(kp, tv.hwy, y0, y1, lo, hi);
+                                    if (y0 < y1 && lo <= hi && (lo < byl || hi > byh)) ++miss;
+                                }
+                        }
+                }
             }
         for (int j = 0; j < N; ++j)
             for (int i = 0; i < N; ++i) {

@@ -301,28 +301,35 @@ __device__ __forceinline__ float gather_staged(StageLds& S, const Geo& G, const 
 // Blocked gather: each thread owns PX x PY pixels of a 16x16 tile
 // ----------------------------------------------------------------------------
 
-// One window of channels serves the whole pixel block: centred on the block's
-// centre and widened by its extent (the window half-width is linear in the
-// offset across and along the sampling line).  For every candidate the
-// lattice and residual parts of the crossing are formed once per sampling line
-// of the block and each pixel gets hat(...) x w exactly as in the one-pixel
-// gather, so every pixel's sum has the same terms in the same order (rays of
-// the window that miss a pixel add exactly zero).
+// One window of channels serves the whole pixel block: the tile's linear
+// channel model at the block's centre, widened by the model's spread over the
+// block.  For every candidate the lattice and residual parts of the crossing
+// are formed once per sampling line of the block and each pixel gets
+// hat(...) x w exactly as in the one-pixel gather, so every pixel's sum has
+// the same terms in the same order (rays of the window that miss a pixel add
+// exactly zero).  The rows are staged once per chunk (no double buffer: a
+// tile's LDS is shared by fewer waves here) with BLK_GAP zero-weight slots
+// after each major-axis part, so the unrolled candidates need no mask.
 constexpr int BLK_UNROLL = 6;
-constexpr int BLK_ROW = STAGE_SLOTS + BLK_UNROLL;
+constexpr int BLK_GAP = BLK_UNROLL - 1;
+constexpr int BLK_ROW = STAGE_SLOTS + 2 * BLK_GAP;
 
 struct StageLdsBlk {
     float4 geo[STAGE_VIEWS][BLK_ROW];
     float w[STAGE_VIEWS][BLK_ROW];
-    int k0[STAGE_VIEWS];
-    int cnt[STAGE_VIEWS];
+    TileView tv[STAGE_TABLE];
+    int k0[STAGE_TABLE];
+    int kb[STAGE_TABLE];
+    int cnt[STAGE_TABLE];
+    int ray0[STAGE_TABLE];
+    int ks[STAGE_TABLE];
 };
 
 // Adds channels [lo, hi] (lo <= hi) of one view to the block's accumulators.
 // MAJ_X: rays sampled per column (t = column, centre = row) or per row.
-// Reads of `read` for k in [lo, lo + BLK_UNROLL) must be in bounds; w is
-// replaced by 0 past hi, so those candidates add exactly zero.
-template <int PX, int PY, bool MAJ_X, class Read>
+// MASK: candidates past hi get w = 0 (global reads, clamped into [lo, hi]);
+// without it they must be zero-weight rays or slots (the padded LDS rows).
+template <int PX, int PY, bool MAJ_X, bool MASK, class Read>
 __device__ __forceinline__ void add_window_blk(float (&acc)[PY][PX], int lo, int hi, int i0, int j0, Read read)
 {
     constexpr int NT = MAJ_X ? PX : PY;  // sampling lines in the block
@@ -330,7 +337,7 @@ __device__ __forceinline__ void add_window_blk(float (&acc)[PY][PX], int lo, int
     auto body = [&](int k, bool valid) {
         float wk;
         const RayGeo g = read(k, wk);
-        wk = valid ? wk : 0.0f;
+        if constexpr (MASK) wk = valid ? wk : 0.0f;
 #pragma unroll
         for (int a = 0; a < NT; ++a) {
             const float t = (float)((MAJ_X ? i0 : j0) + a);
@@ -371,80 +378,97 @@ __device__ __forceinline__ void gather_block(StageLdsBlk& S, const Geo& G, const
 {
     const int tid = threadIdx.x;
     constexpr int NTH = 256 / (PX * PY);
-    const float Xc = (float)i0 + 0.5f * (PX - 1) - G.c, Yc = (float)j0 + 0.5f * (PY - 1) - G.c;
-    const int ti1 = min(ti0 + TILE - 1, G.n - 1), tj1 = min(tj0 + TILE - 1, G.n - 1);
-    for (int c0 = q0; c0 < q0 + nq; c0 += STAGE_VIEWS) {
-        const int cv = min(STAGE_VIEWS, q0 + nq - c0);
-        if (tid < cv) {
-            const ViewRec v = V[c0 + tid];
-            float kmin = 3.0e38f, kmax = -3.0e38f, hw = 0.0f;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const float cx = (float)((c & 1) ? ti1 : ti0) - G.c;
-                const float cy = (float)((c & 2) ? tj1 : tj0) - G.c;
-                const PixelView pv = pixel_view(G, v, cx, cy);
-                kmin = fminf(kmin, pv.kp);
-                kmax = fmaxf(kmax, pv.kp);
-                hw = fmaxf(hw, 1.5f * (pv.ax + pv.ay) + G.margin);
-            }
-            const int k0 = max(0, (int)floorf(kmin - 1.25f * hw) - 1);
-            const int k1 = min(G.nch - 1, (int)ceilf(kmax + 1.25f * hw) + 1);
-            const int cnt = k1 - k0 + 1;
+    static_assert(NTH >= STAGE_TABLE, "one thread per table view");
+    // the block centre's offsets from the tile centre, and the model's half-spread over the block
+    const float dXb = (float)(i0 - ti0) + 0.5f * (PX - 1) - 7.5f;
+    const float dYb = (float)(j0 - tj0) + 0.5f * (PY - 1) - 7.5f;
+    const float Xc = (float)ti0 + 7.5f - G.c, Yc = (float)tj0 + 7.5f - G.c;
+    for (int s0 = q0; s0 < q0 + nq; s0 += STAGE_TABLE) {
+        const int sn = min(STAGE_TABLE, q0 + nq - s0);
+        if (tid < sn) {
+            const ViewRec v = V[s0 + tid];
+            const TileView tv = tile_view(G, v, Xc, Yc);
+            int k0, cnt;
+            stage_range(tv, G.nch, STAGE_SLOTS, k0, cnt);
+            const bool gap = k0 < v.k_split && v.k_split < k0 + cnt;
+            S.tv[tid] = tv;
             S.k0[tid] = k0;
-            S.cnt[tid] = (cnt > 0 && cnt <= STAGE_SLOTS) ? cnt : 0;
+            S.kb[tid] = gap ? k0 - BLK_GAP : k0;
+            S.cnt[tid] = cnt;
+            S.ray0[tid] = v.ray0;
+            S.ks[tid] = v.k_split;
         }
         __syncthreads();
-        // fill every slot of the chunk's rows (zeros past the staged channels),
-        // so masked reads past a window see finite values
-        for (int slot = tid; slot < cv * BLK_ROW; slot += NTH) {
-            const int cq = slot / BLK_ROW, e = slot - cq * BLK_ROW;
-            float4 gg = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            float ww = 0.0f;
-            if (e < S.cnt[cq]) {
-                const int ray = V[c0 + cq].ray0 + S.k0[cq] + e;
-                const RayGeo g = rg[ray];
-                gg = make_float4(g.a_int, g.a_frac, g.s_hi, g.s_lo);
-                ww = w[ray];
-            }
-            S.geo[cq][e] = gg;
-            S.w[cq][e] = ww;
-        }
-        __syncthreads();
-        if (active) {
-            for (int cq = 0; cq < cv; ++cq) {
-                const ViewRec v = V[c0 + cq];
-                const int k0 = S.k0[cq], cnt = S.cnt[cq];
-                const PixelView pv = pixel_view(G, v, Xc, Yc);
-                int x0, x1, y0, y1;
-                major_intervals(v, G.nch, x0, x1, y0, y1);
-                const LdsRead lds{S.geo[cq], S.w[cq], k0};
-                if (x0 < x1) {
-                    const float hw = pv.ax * (1.0f + 0.5f * (PY - 1)) + pv.ay * (0.5f * (PX - 1)) + G.margin;
-                    int lo, hi;
-                    candidate_range(pv.kp, hw, x0, x1, lo, hi);
-                    if (lo <= hi) {
-                        if (lo >= k0 && hi < k0 + cnt)
-                            add_window_blk<PX, PY, true>(acc, lo, hi, i0, j0, lds);
-                        else
-                            add_window_blk<PX, PY, true>(acc, lo, hi, i0, j0,
-                                                         GlobalReadBlk{rg + v.ray0, w + v.ray0, hi});
-                    }
-                }
-                if (y0 < y1) {
-                    const float hw = pv.ay * (1.0f + 0.5f * (PX - 1)) + pv.ax * (0.5f * (PY - 1)) + G.margin;
-                    int lo, hi;
-                    candidate_range(pv.kp, hw, y0, y1, lo, hi);
-                    if (lo <= hi) {
-                        if (lo >= k0 && hi < k0 + cnt)
-                            add_window_blk<PX, PY, false>(acc, lo, hi, i0, j0, lds);
-                        else
-                            add_window_blk<PX, PY, false>(acc, lo, hi, i0, j0,
-                                                          GlobalReadBlk{rg + v.ray0, w + v.ray0, hi});
-                    }
+        for (int t0 = 0; t0 < sn; t0 += STAGE_VIEWS) {
+            const int cv = min(STAGE_VIEWS, sn - t0);
+            for (int sl = tid; sl < cv * STAGE_SLOTS; sl += NTH) {
+                const int cq = sl / STAGE_SLOTS, e = sl - cq * STAGE_SLOTS;
+                const int t = t0 + cq;
+                if (e < S.cnt[t]) {
+                    const int k = S.k0[t] + e;
+                    const RayGeo g = rg[S.ray0[t] + k];
+                    const int pos = k < S.ks[t] ? e : k - S.kb[t];
+                    S.geo[cq][pos] = make_float4(g.a_int, g.a_frac, g.s_hi, g.s_lo);
+                    S.w[cq][pos] = w[S.ray0[t] + k];
                 }
             }
+            for (int z = tid; z < cv * 2 * BLK_GAP; z += NTH) {
+                const int cq = z / (2 * BLK_GAP), m = z - cq * (2 * BLK_GAP);
+                const int t = t0 + cq;
+                const int k0 = S.k0[t], kb = S.kb[t], cnt = S.cnt[t];
+                int pos = -1;
+                if (cnt > 0) {
+                    if (m < BLK_GAP)
+                        pos = cnt + (k0 - kb) + m;
+                    else if (kb != k0)
+                        pos = S.ks[t] - k0 + (m - BLK_GAP);
+                }
+                if (pos >= 0) {
+                    S.geo[cq][pos] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    S.w[cq][pos] = 0.0f;
+                }
+            }
+            __syncthreads();
+            if (active) {
+                for (int cq = 0; cq < cv; ++cq) {
+                    const int t = t0 + cq;
+                    const ViewRec v = V[s0 + t];
+                    const int cnt = S.cnt[t];
+                    const TileView tv = S.tv[t];
+                    const float kp = fmaf(tv.gx, dXb, fmaf(tv.gy, dYb, tv.kpc));
+                    const float spread = block_spread(tv, PX, PY);
+                    int x0, x1, y0, y1;
+                    major_intervals(v, G.nch, x0, x1, y0, y1);
+                    const int bx = x0 == v.k_split ? S.kb[t] : S.k0[t];
+                    const int by = y0 == v.k_split ? S.kb[t] : S.k0[t];
+                    if (x0 < x1) {
+                        int lo, hi;
+                        candidate_range(kp, tv.hwx + spread, x0, x1, lo, hi);
+                        if (lo <= hi) {
+                            if (cnt > 0)  // every window lies in the staged range (stage_range)
+                                add_window_blk<PX, PY, true, false>(acc, lo, hi, i0, j0,
+                                                                    LdsRead{S.geo[cq], S.w[cq], bx});
+                            else
+                                add_window_blk<PX, PY, true, true>(acc, lo, hi, i0, j0,
+                                                                   GlobalReadBlk{rg + v.ray0, w + v.ray0, hi});
+                        }
+                    }
+                    if (y0 < y1) {
+                        int lo, hi;
+                        candidate_range(kp, tv.hwy + spread, y0, y1, lo, hi);
+                        if (lo <= hi) {
+                            if (cnt > 0)
+                                add_window_blk<PX, PY, false, false>(acc, lo, hi, i0, j0,
+                                                                     LdsRead{S.geo[cq], S.w[cq], by});
+                            else
+                                add_window_blk<PX, PY, false, true>(acc, lo, hi, i0, j0,
+                                                                    GlobalReadBlk{rg + v.ray0, w + v.ray0, hi});
+                        }
+                    }
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 

@@ -165,6 +165,16 @@ __host__ __device__ __forceinline__ float ray_offset(const RayGeo& g, float t, f
 // (1 - |d| never exceeds 1), which the device does in the subtraction itself.
 __host__ __device__ __forceinline__ float hat(float d) { return fminf(fmaxf(1.0f - fabsf(d), 0.0f), 1.0f); }
 
+// Widening of the per-tile window for a PX x PY block of pixels whose centre
+// is the model's point: the model's spread over the block, plus 1/64 channel
+// and two ulps of the centre channel so that the block's window, rounded
+// differently from its pixels' own, still holds every one of them.
+__host__ __device__ __forceinline__ float block_spread(const TileView& tv, int PX, int PY)
+{
+    return fabsf(tv.gx) * (0.5f * (PX - 1)) + fabsf(tv.gy) * (0.5f * (PY - 1)) + 0.015625f +
+           fabsf(tv.kpc) * 2.4e-7f;
+}
+
 // Channels per view that the LDS-staged gather can stage for one tile.
 constexpr int STAGE_SLOTS = 64;
 
