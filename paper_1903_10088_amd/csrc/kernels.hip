@@ -136,6 +136,7 @@ __device__ __forceinline__ float chunk_sum(const float* __restrict__ img, uint32
     float acc = 0.0f;
     int t = t0;
     float ft0 = (float)t0;  // exact: t < 2^24
+    const float fn = (float)n;
     uint32_t row = off0 + (uint32_t)(t0 * P);
     for (; t + 3 < t1; t += 4) {
         float v0[4], v1[4], f[4];
@@ -146,7 +147,8 @@ __device__ __forceinline__ float chunk_sum(const float* __restrict__ img, uint32
             const float res = fmaf(ft, g.s_lo, g.a_frac);
             const float fl = floorf(lat + res);
             f[u] = (lat - fl) + res;
-            const int j0 = min(max((int)fl, -PAD), n);
+            // clamp in float (fl is integral, so this equals clamping the integer)
+            const int j0 = (int)__builtin_amdgcn_fmed3f(fl, (float)-PAD, fn);
             const f32x2u v = pair_at(img, row + (uint32_t)(u * P) + (uint32_t)j0);
             v0[u] = v.x;
             v1[u] = v.y;
@@ -161,7 +163,7 @@ __device__ __forceinline__ float chunk_sum(const float* __restrict__ img, uint32
         const float res = fmaf(ft0, g.s_lo, g.a_frac);
         const float fl = floorf(lat + res);
         const float f = (lat - fl) + res;
-        const int j0 = min(max((int)fl, -PAD), n);
+        const int j0 = (int)__builtin_amdgcn_fmed3f(fl, (float)-PAD, fn);
         const f32x2u v = pair_at(img, row + (uint32_t)j0);
         const float v0 = v.x;
         const float v1 = v.y;
@@ -200,9 +202,8 @@ __device__ __forceinline__ void fp_body(const FpArgs& A, int rblock)
     const int nchunk = (A.n + ch - 1) / ch;  // <= 16
     const int cps = (nchunk + SEG - 1) / SEG;  // chunks per segment
     float total = 0.0f;
-    float part[(SEG == 1) ? 1 : 16];
-#pragma unroll
-    for (int c = 0; c < ((SEG == 1) ? 1 : 16); ++c) part[c] = 0.0f;
+    // SEG > 1: chunk sums go straight to their LDS slots (chunk, ray)
+    __shared__ float red[(SEG == 1) ? 1 : 16][RPB];
     float scale = 0.0f;
     if (r < A.nrays) {
         const int gr = A.ray0 + r;
@@ -223,15 +224,11 @@ __device__ __forceinline__ void fp_body(const FpArgs& A, int rblock)
             if constexpr (SEG == 1) {
                 total += acc;
             } else {
-                part[c - c_begin] = acc;
+                red[c][lr] = acc;
             }
         }
     }
     if constexpr (SEG > 1) {
-        constexpr int RPB_ = RPB;
-        __shared__ float red[16][RPB_];
-        for (int c = 0; c < cps; ++c)
-            if (seg * cps + c < nchunk) red[seg * cps + c][lr] = part[c];
         __syncthreads();
         if (seg == 0) {
             for (int c = 0; c < nchunk; ++c) total += red[c][lr];
