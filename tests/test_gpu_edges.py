@@ -1,0 +1,115 @@
+"""Edge cases of the GPU path against the FP64 oracle and against itself.
+
+* Tiles whose channel range does not fit the LDS-staged gather (more than 64 channels per
+  view): the staged update kernels then read those views from global memory.  A geometry
+  with ~11 channels per pixel makes every view unstaged; one with ~3 makes some views
+  staged and others not.  The iteration must meet the oracle bar and every update variant
+  must give the same bits.
+* Large images (1024^2 and 2048^2, up to 3200 views x 2400 channels): projection and
+  backprojection of one subset against the oracle on those views, and two sub-iterations
+  of the full iteration.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_10088_amd import phantom as ph
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RMSE_TOL = 1e-4 * ph.MU_WATER_PER_MM
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1903_10088_amd import recon
+    recon.lib()
+    return torch.device("cuda:0")
+
+
+def channels_per_pixel(g):
+    """Channels spanned by one pixel at the isocentre."""
+    dgamma = 2 * g.gamma_max / g.n_channels
+    return (g.pixel_mm / g.sad_mm) / dgamma
+
+
+STAGING = {
+    # ~11.5 channels per pixel: a 16-pixel tile spans far more than 64 channels in every view
+    "unstaged": (ph.Geometry(n=64, pixel_mm=6.25, n_views=90, n_channels=738), 5),
+    # ~3.1 channels per pixel: tiles span ~50-90 channels, some views staged, some not
+    "mixed": (ph.Geometry(n=128, pixel_mm=3.125, n_views=120, n_channels=400, start_angle_rad=0.2), 6),
+}
+
+
+@pytest.mark.parametrize("name", list(STAGING))
+def test_unstaged_views_iterate_to_the_oracle_and_agree_across_variants(dev, name):
+    from paper_1903_10088_amd import recon
+    g, M = STAGING[name]
+    cpp = channels_per_pixel(g)
+    assert (cpp * 16 > 64) if name == "unstaged" else (2.5 < cpp < 4.5)
+    print(f"staging edge {name}: n={g.n} channels={g.n_channels} ({cpp:.1f} per pixel) M={M}", flush=True)
+    sl = ph.make_slice(g, 31, 5e3, low_contrast=True, supersample=2)
+    counts = torch.from_numpy(sl.counts).to(dev)
+    R = recon.Recon(g, M, 1e-3)
+    ref = None
+    for bpv in (2, 1, 3, 4, 5):  # LDS-staged, global reads, blocked 1x2, 2x1, 2x2
+        R.set_launch(fp_segments=4, bp_variant=bpv)
+        img, tr = R.os_iterate(counts, sl.i0, None, 2 * M + 1, trace=True)
+        if ref is None:
+            ref = (img.clone(), tr.clone())
+        else:
+            assert torch.equal(img, ref[0]), bpv
+            assert torch.equal(tr, ref[1]), bpv
+    o_img, o_tr = oracle.os_iterate(g, M, 1e-3, sl.counts, sl.i0, None, 2 * M + 1)
+    disc = oracle.initial_image(g, 1.0) > 0
+    rmse = float(np.sqrt(np.mean((ref[0].cpu().numpy() - o_img)[disc] ** 2)))
+    print(f"  rmse {rmse:.2e}", flush=True)
+    assert np.array_equal(ref[1].cpu().numpy()[:, 1], o_tr[:, 1])
+    assert rmse <= RMSE_TOL
+
+
+LARGE = {
+    "n1024": (ph.Geometry(n=1024, pixel_mm=400 / 1024, n_views=1600, n_channels=1200), 40),
+    "n2048": (ph.Geometry(n=2048, pixel_mm=400 / 2048, n_views=3200, n_channels=2400), 80),
+}
+
+
+@pytest.mark.parametrize("name", list(LARGE))
+def test_large_image_subset_operators(dev, name):
+    from paper_1903_10088_amd import recon
+    g, M = LARGE[name]
+    print(f"large {name}: {g.n}^2, {g.n_views} views x {g.n_channels} channels, M={M}", flush=True)
+    R = recon.Recon(g, M, 1e-3)
+    rng = np.random.default_rng(7)
+    disc = oracle.initial_image(g, 1.0) > 0
+    img = np.where(disc, rng.uniform(0, 0.01, (g.n, g.n)), 0.0).astype(np.float32)
+    s = M // 3
+    views = oracle.subset_views(g.n_views, M, s)
+    ref = oracle.project(g, img.astype(np.float64), views)
+    out = R.project(torch.from_numpy(img).to(dev), s).cpu().numpy().astype(np.float64)
+    err = np.linalg.norm(out - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert err.max() <= 1e-5, err.max()
+    sino = rng.uniform(-1, 1, (len(views), g.n_channels)).astype(np.float32)
+    ref_b = oracle.backproject(g, sino.astype(np.float64), views)
+    out_b = R.backproject(torch.from_numpy(sino).to(dev), s).cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(out_b - ref_b) / np.linalg.norm(ref_b) <= 1e-5
+
+
+def test_large_image_iteration(dev):
+    """Two sub-iterations at 1024^2 / 1600 views (the staged update kernel on 4096 tiles)."""
+    from paper_1903_10088_amd import recon
+    g, M = LARGE["n1024"]
+    sl = ph.make_slice(g, 33, 2e3, low_contrast=True, supersample=1)
+    R = recon.Recon(g, M, 1e-3)
+    img, tr = R.os_iterate(torch.from_numpy(sl.counts).to(dev), sl.i0, None, 2, trace=True)
+    o_img, o_tr = oracle.os_iterate(g, M, 1e-3, sl.counts, sl.i0, None, 2)
+    disc = oracle.initial_image(g, 1.0) > 0
+    rmse = float(np.sqrt(np.mean((img.cpu().numpy() - o_img)[disc] ** 2)))
+    print(f"  1024^2 two sub-iterations: rmse {rmse:.2e}, f rel {abs(tr[1, 0].item() / o_tr[1, 0] - 1):.1e}",
+          flush=True)
+    assert rmse <= RMSE_TOL
+    assert np.allclose(tr.cpu().numpy(), o_tr, rtol=1e-4, atol=0)
+

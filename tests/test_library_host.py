@@ -94,6 +94,8 @@ def test_null_handle_calls_are_rejected():
     ("odd-rotated", ph.Geometry(n=37, pixel_mm=10.0, n_views=33, n_channels=51, start_angle_rad=0.3), 5, 1),
     ("tiny", ph.Geometry(n=8, pixel_mm=25.0, n_views=12, n_channels=10), 3, 1),
     ("wide-fan", ph.Geometry(n=64, pixel_mm=6.25, n_views=60, n_channels=90, sad_mm=300.0, sdd_mm=600.0), 6, 1),
+    ("unstaged", ph.Geometry(n=64, pixel_mm=6.25, n_views=90, n_channels=738), 5, 1),
+    ("mixed-staging", ph.Geometry(n=128, pixel_mm=3.125, n_views=120, n_channels=400, start_angle_rad=0.2), 6, 3),
 ])
 def test_gather_window_covers_every_weight(name, geom, M, stride):
     missed, cand, pairs = recon.check_tables(geom, M, stride)
