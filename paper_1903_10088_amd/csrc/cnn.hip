@@ -16,11 +16,11 @@
 // The weight gradient of a 32 -> 32 layer is a GEMM over pixels:
 //   dW_tap[out][in] = sum_p G[out][p] x A[in][p + tap]
 // also on the matrix cores, with K = 32 pixels per instruction.  Its operands
-// must hold 8 consecutive pixels of one channel per lane, so the tile is
-// transposed into channel-major LDS rows (the activation tile three times,
-// shifted by dx = -1, 0, 1, so every read is aligned).  Blocks loop over a
-// fixed set of tiles and write partial sums; a second kernel adds the
-// partials in a fixed order, so gradients are bitwise deterministic.
+// must hold 8 consecutive pixels of one channel per lane: the tiles stay
+// channels-last in LDS and the LDS transpose read (ds_read_b64_tr_b16) hands
+// each lane its channel of 4 pixels.  Blocks loop over a fixed set of tiles
+// and write partial sums; a second kernel adds the partials in a fixed order,
+// so gradients are bitwise deterministic.
 //
 // The 1 -> 32 and 32 -> 1 layers (0.6% of the work) run in float32 on the
 // vector ALUs.  None of the path uses atomics.
@@ -405,28 +405,52 @@ __global__ __launch_bounds__(256) void dgrad_out_kernel(const float* __restrict_
 //   dW[o][c][tap] = sum_p g[p][o] a[p + tap][c],  db[o] = sum_p g[p][o].
 // Block k handles tiles k, k + gridDim.x, ... in turn and writes its partial
 // sums (parameter layout, 9216 weights then 32 biases) to part[k].
-constexpr int GT_ROW = T * T + 8;       // bf16 per channel row of the transposed g tile (528 B)
-constexpr int AS_CH = HALO * T + 8;     // bf16 per channel of one shifted activation copy (592 B)
+//
+// The g tile and the activation halo stay channels-last in LDS, as loaded
+// (16-byte stores).  The operands of v_mfma_f32_16x16x32_bf16 need 8
+// consecutive pixels of one channel per lane; ds_read_b64_tr_b16 provides
+// them: within each 16-lane group, lane r points at 4 consecutive channels
+// (4 (r mod 4) ...) of pixel r / 4, and lane i receives channel i of those 4
+// pixels.  Each lane gives its own address, so the tap's pixel shift is an
+// address offset (no shifted copies).
+constexpr int WG_PSTR = 32;  // bf16 per staged pixel
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+// 4 consecutive pixels (pixel0 + 0..3, channels-last rows of WG_PSTR bf16,
+// row stride `pstride` bf16 between them) of channel `c16 + lane mod 16`.
+__device__ __forceinline__ u32x2 tr_read(const uint16_t* lds_row0, int pstride, int c16)
+{
+    const int r = threadIdx.x & 15;
+    const uint16_t* p = lds_row0 + (r >> 2) * pstride + c16 + 4 * (r & 3);
+    const s16x4 v = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) s16x4*)p);
+    return __builtin_bit_cast(u32x2, v);
+}
+
+__device__ __forceinline__ bf16x8 cat(u32x2 lo, u32x2 hi) { return as_bf8(u32x4{lo.x, lo.y, hi.x, hi.y}); }
 
 __global__ __launch_bounds__(256) void wgrad32_kernel(const uint16_t* __restrict__ g, const uint16_t* __restrict__ a,
                                                       float* __restrict__ part, int n, int tiles_x, int tiles_per_img,
                                                       int ntiles)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t gT[C][GT_ROW];
-    __shared__ __attribute__((aligned(16))) uint16_t aS[3][C][AS_CH];
+    // the g tile, then the activation halo; reused for the cross-wave sum at the end
+    __shared__ __attribute__((aligned(16))) uint16_t lds[(T * T + HALO * HALO) * WG_PSTR];
+    __shared__ float bpart[256];
+    uint16_t* gS = lds;
+    uint16_t* aS = lds + T * T * WG_PSTR;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = lane & 15, g4 = lane >> 4;
-    f32x4 acc[9][2][2];
+    // wave w: input channels 16 h2 ... 16 h2 + 15 (h2 = w mod 2), pixel blocks 4 (w / 2) ... + 3
+    const int h2 = wave & 1, kb0 = 4 * (wave >> 1);
+    f32x4 acc[9][2];
 #pragma unroll
-    for (int t = 0; t < 9; ++t)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) acc[t][h][0] = acc[t][h][1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int t = 0; t < 9; ++t) acc[t][0] = acc[t][1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // bias partial of channel tid mod 32 over pixels 32 (tid / 32) ... + 31 of every tile
     float bacc = 0.0f;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const Tile tl = tile_plain(t, tiles_x, tiles_per_img);
         __syncthreads();  // the previous tile's reads are done
         {
-            // g tile, transposed: gT[c][pixel]
             const int li = tid >> 4, lj = tid & 15;
             const int gi = tl.i0 + li, gj = tl.j0 + lj;
             u32x4 v[4] = {{0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}};
@@ -435,18 +459,12 @@ __global__ __launch_bounds__(256) void wgrad32_kernel(const uint16_t* __restrict
 #pragma unroll
                 for (int q = 0; q < 4; ++q) v[q] = src[q];
             }
+            u32x4* dst = (u32x4*)(gS + tid * WG_PSTR);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t w[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    gT[q * 8 + 2 * e][tid] = (uint16_t)(w[e] & 0xffffu);
-                    gT[q * 8 + 2 * e + 1][tid] = (uint16_t)(w[e] >> 16);
-                }
-            }
+            for (int q = 0; q < 4; ++q) dst[q] = v[q];
         }
         for (int e = tid; e < HALO * HALO; e += 256) {
-            // activation halo, transposed into three copies shifted by kx: aS[kx][c][row][col] = a[row - 1][col + kx - 1]
+            // activation halo: aS[row][col] = a[i0 + row - 1][j0 + col - 1], zero outside the image
             const int ly = e / HALO, lx = e - ly * HALO;
             const int gi = tl.i0 + ly - 1, gj = tl.j0 + lx - 1;
             u32x4 v[4] = {{0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}};
@@ -455,70 +473,67 @@ __global__ __launch_bounds__(256) void wgrad32_kernel(const uint16_t* __restrict
 #pragma unroll
                 for (int q = 0; q < 4; ++q) v[q] = src[q];
             }
+            u32x4* dst = (u32x4*)(aS + e * WG_PSTR);
 #pragma unroll
-            for (int kx = 0; kx < 3; ++kx) {
-                const int col = lx - kx;
-                if (col < 0 || col >= T) continue;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const uint32_t w[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
-#pragma unroll
-                    for (int e2 = 0; e2 < 4; ++e2) {
-                        aS[kx][q * 8 + 2 * e2][ly * T + col] = (uint16_t)(w[e2] & 0xffffu);
-                        aS[kx][q * 8 + 2 * e2 + 1][ly * T + col] = (uint16_t)(w[e2] >> 16);
-                    }
-                }
-            }
+            for (int q = 0; q < 4; ++q) dst[q] = v[q];
         }
         __syncthreads();
-        if (tid < C) {
+        {
+            const int c = tid & 31, p0 = 32 * (tid >> 5);
             float s = 0.0f;
-            for (int p = 0; p < T * T; ++p) s += bf2f(gT[tid][p]);
+            for (int p = p0; p < p0 + 32; ++p) s += bf2f(gS[p * WG_PSTR + c]);
             bacc += s;
         }
-        // this wave: pixel blocks kb = 2 wave, 2 wave + 1 (32 pixels = tile rows 2kb, 2kb + 1)
-#pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {
-            const int kb = 2 * wave + kk;
+        // pixel block kb = 32 pixels = tile rows 2 kb, 2 kb + 1; lane group g4 holds pixels
+        // 8 g4 ... 8 g4 + 7 of the block: row R, columns c0 ... c0 + 7
+        for (int kb = kb0; kb < kb0 + 4; ++kb) {
+            const int R = 2 * kb + (g4 >> 1), c0 = 8 * (g4 & 1);
+            const uint16_t* grow = gS + (R * T + c0) * WG_PSTR;
             bf16x8 Af[2];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) Af[h] = as_bf8(*(const u32x4*)(&gT[h * 16 + m][kb * 32 + g4 * 8]));
-            const int R = 2 * kb + (g4 >> 1), c0 = 8 * (g4 & 1);
+            for (int h = 0; h < 2; ++h)
+                Af[h] = cat(tr_read(grow, WG_PSTR, 16 * h), tr_read(grow + 4 * WG_PSTR, WG_PSTR, 16 * h));
 #pragma unroll
             for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
-                for (int kx = 0; kx < 3; ++kx)
-#pragma unroll
-                    for (int h2 = 0; h2 < 2; ++h2) {
-                        const bf16x8 Bf = as_bf8(*(const u32x4*)(&aS[kx][h2 * 16 + m][(R + ky) * T + c0]));
-                        acc[ky * 3 + kx][0][h2] = mfma(Af[0], Bf, acc[ky * 3 + kx][0][h2]);
-                        acc[ky * 3 + kx][1][h2] = mfma(Af[1], Bf, acc[ky * 3 + kx][1][h2]);
-                    }
+                for (int kx = 0; kx < 3; ++kx) {
+                    const uint16_t* arow = aS + ((R + ky) * HALO + c0 + kx) * WG_PSTR;
+                    const bf16x8 Bf =
+                        cat(tr_read(arow, WG_PSTR, 16 * h2), tr_read(arow + 4 * WG_PSTR, WG_PSTR, 16 * h2));
+                    acc[ky * 3 + kx][0] = mfma(Af[0], Bf, acc[ky * 3 + kx][0]);
+                    acc[ky * 3 + kx][1] = mfma(Af[1], Bf, acc[ky * 3 + kx][1]);
+                }
         }
     }
-    // add the four waves' sums in wave order, in LDS (reusing the activation copies)
+    // add the pixel halves' sums (waves h2 and h2 + 2, in that order), in LDS (reusing the tiles)
     __syncthreads();
-    float* red = (float*)&aS[0][0][0];
-    for (int w = 0; w < 4; ++w) {
-        if (wave == w) {
+    float* red = (float*)lds;
+    static_assert(W32 <= (T * T + HALO * HALO) * WG_PSTR / 2, "reduction fits the tile buffer");
+    for (int w = 0; w < 4; w += 2) {
+        if ((wave >> 1) == (w >> 1)) {
 #pragma unroll
             for (int tap = 0; tap < 9; ++tap)
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
 #pragma unroll
-                    for (int h2 = 0; h2 < 2; ++h2)
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int o = h * 16 + g4 * 4 + i, c = h2 * 16 + m;
-                            const int idx = (o * C + c) * 9 + tap;
-                            red[idx] = (w == 0 ? 0.0f : red[idx]) + acc[tap][h][h2][i];
-                        }
+                    for (int i = 0; i < 4; ++i) {
+                        const int o = h * 16 + g4 * 4 + i, c = h2 * 16 + m;
+                        const int idx = (o * C + c) * 9 + tap;
+                        red[idx] = (w == 0 ? 0.0f : red[idx]) + acc[tap][h][i];
+                    }
         }
         __syncthreads();
     }
+    bpart[tid] = bacc;
+    __syncthreads();
     float* dst = part + (size_t)blockIdx.x * P32;
     for (int k = tid; k < W32; k += 256) dst[k] = red[k];
-    if (tid < C) dst[W32 + tid] = bacc;
+    if (tid < C) {
+        // the 8 pixel groups' partials of channel tid, in group order
+        float b = 0.0f;
+        for (int q = 0; q < 8; ++q) b += bpart[32 * q + tid];
+        dst[W32 + tid] = b;
+    }
 }
 
 // Weight gradients of the first layer (g1 x a0; 288 weights + 32 biases) and
