@@ -65,6 +65,7 @@ def lib():
         d, i32, i64 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64
         L.oracle_project.argtypes = [P(_Geom), P(d), P(d), P(i32), i32]
         L.oracle_backproject.argtypes = [P(_Geom), P(d), P(d), P(i32), i32]
+        L.oracle_fbp.argtypes = [P(_Geom), P(d), P(d)]
         L.oracle_count_pairs.argtypes = [P(_Geom), P(i32), i32, P(i64)]
         L.oracle_ray_major.argtypes = [P(_Geom), P(i32)]
         L.oracle_tv.argtypes = [i32, d, P(d), P(d), P(d)]
@@ -120,6 +121,20 @@ def project(geom, img, views=None) -> np.ndarray:
     _check(lib().oracle_project(ctypes.byref(_g(geom)), _dp(img), _dp(out), None if v is None else _ip(v), nv),
            "project")
     return out
+
+
+def fbp(geom, sino) -> np.ndarray:
+    """Fan-beam filtered backprojection of line integrals [n_views][n_ch] over the full turn: [N][N] in
+    1/mm (oracle_fbp)."""
+    sino = np.ascontiguousarray(sino, dtype=np.float64).reshape(geom.n_views, geom.n_channels)
+    out = np.zeros((geom.n, geom.n), np.float64)
+    _check(lib().oracle_fbp(ctypes.byref(_g(geom)), _dp(sino), _dp(out)), "fbp")
+    return out
+
+
+def line_integrals(counts, i0: float) -> np.ndarray:
+    """p = ln(I0 / max(y, 1)), the measured line integrals the methods use (section 3.C.2)."""
+    return np.log(i0 / np.maximum(np.asarray(counts, np.float64), 1.0))
 
 
 def backproject(geom, sino, views=None) -> np.ndarray:

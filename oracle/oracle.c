@@ -370,6 +370,79 @@ double oracle_lambda_next(const og_params* p, int32_t first, double lambda_prev,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Filtered backprojection (the comparison baseline of sections 1 and 4)     */
+/* ------------------------------------------------------------------------ */
+
+/* Fan-beam filtered backprojection over the full turn for the equiangular
+ * arc geometry above (the paper compares with FBP but does not describe it;
+ * this is the textbook algorithm of Kak and Slaney, Principles of
+ * Computerized Tomographic Imaging, ch. 3, for equiangular rays):
+ *   R'(v, k) = R(v, k) D cos(gamma_k)                        (D = sad_mm)
+ *   Q(v, k)  = dgamma sum_k' R'(v, k') h(k - k'),   h(0) = 1 / (8 dgamma^2),
+ *              h(m) = 0 for even m, -1 / (2 pi^2 sin^2(m dgamma)) for odd m
+ *   f(x, y)  = dbeta sum_v Q(v, gamma') / L^2,   dbeta = 2 pi / n_views,
+ * with gamma' the fan angle and L the distance from view v's source to
+ * (x, y), Q linearly interpolated in gamma and zero outside the channels.
+ * sino: [n_views][n_ch] line integrals (natural view order); img: [n][n],
+ * 1/mm (no mask). */
+int oracle_fbp(const og_geometry* g, const double* sino, double* img)
+{
+    if (!geometry_ok(g) || !sino || !img) return OG_INVALID;
+    const int N = g->n, nv = g->n_views, nch = g->n_channels;
+    const double dgam = 2.0 * fan_half_angle(g) / (double)nch;
+    const double D = g->sad_mm;
+    double* h = (double*)malloc(sizeof(double) * (size_t)(2 * nch - 1));
+    double* q = (double*)malloc(sizeof(double) * (size_t)nv * nch);
+    for (int m = -(nch - 1); m <= nch - 1; ++m) {
+        double v;
+        if (m == 0)
+            v = 1.0 / (8.0 * dgam * dgam);
+        else if (m % 2 == 0)
+            v = 0.0;
+        else {
+            const double s = sin((double)m * dgam);
+            v = -1.0 / (2.0 * M_PI * M_PI * s * s);
+        }
+        h[m + nch - 1] = v;
+    }
+#pragma omp parallel for schedule(static)
+    for (int v = 0; v < nv; ++v)
+        for (int k = 0; k < nch; ++k) {
+            double acc = 0.0;
+            for (int kk = 0; kk < nch; ++kk) {
+                const double gam = ((double)kk - 0.5 * (double)(nch - 1)) * dgam;
+                acc += sino[(size_t)v * nch + kk] * D * cos(gam) * h[k - kk + nch - 1];
+            }
+            q[(size_t)v * nch + k] = dgam * acc;
+        }
+    const double c = 0.5 * (double)(N - 1), dbeta = 2.0 * M_PI / (double)nv;
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < N; ++j)
+        for (int i = 0; i < N; ++i) {
+            const double x = ((double)i - c) * g->pixel_mm, y = ((double)j - c) * g->pixel_mm;
+            double acc = 0.0;
+            for (int v = 0; v < nv; ++v) {
+                const double beta = g->start_angle_rad + 2.0 * M_PI * (double)v / (double)nv;
+                const double sx = D * cos(beta), sy = D * sin(beta);
+                const double ux = -cos(beta), uy = -sin(beta); /* towards the origin */
+                const double dx = x - sx, dy = y - sy;
+                const double gam = atan2(ux * dy - uy * dx, ux * dx + uy * dy);
+                const double kf = gam / dgam + 0.5 * (double)(nch - 1);
+                const double k0 = floor(kf), f = kf - k0;
+                const int ki = (int)k0;
+                double val = 0.0;
+                if (ki >= 0 && ki < nch) val += (1.0 - f) * q[(size_t)v * nch + ki];
+                if (ki + 1 >= 0 && ki + 1 < nch) val += f * q[(size_t)v * nch + ki + 1];
+                acc += val / (dx * dx + dy * dy);
+            }
+            img[(size_t)j * N + i] = dbeta * acc;
+        }
+    free(h);
+    free(q);
+    return OG_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Ordered-subset gradient iteration (Eq. 3, section 3.D)                    */
 /* ------------------------------------------------------------------------ */
 
