@@ -194,6 +194,21 @@ recon_status recon_os_iterate_ex(recon_handle* h, const float* d_counts, float i
  * reconstruction disc, 0 outside. */
 recon_status recon_initial_image(recon_handle* h, float* d_img, void* stream);
 
+/* Filtered backprojection, the baseline the paper compares the iterative
+ * method with (sections 1 and 4; the paper gives no details, so this is the
+ * textbook equiangular fan-beam algorithm over the full turn):
+ *   p = ln(I0 / max(y, 1)),  R' = p D cos(gamma_k)  (D = sad_mm),
+ *   Q = R' convolved per view with dgamma h,  h(0) = 1 / (8 dgamma^2),
+ *       h(m) = 0 for even m, -1 / (2 pi^2 sin^2(m dgamma)) for odd m,
+ *   f(x, y) = (2 pi / n_views) sum over views of Q(gamma') / L^2,
+ * gamma' being the fan angle and L the source distance of (x, y), with Q
+ * linearly interpolated in gamma and zero outside the channels.  d_counts:
+ * [n_views][n_channels] as for recon_os_iterate; d_img: [n][n] in 1/mm,
+ * overwritten, every pixel (no mask).  Deterministic (no atomics).  Uses the
+ * handle's workspace: do not overlap with other calls on the same handle.
+ * RECON_INVALID_ARG for more than 16384 channels. */
+recon_status recon_fbp(recon_handle* h, const float* d_counts, float i0, float* d_img, void* stream);
+
 /* Data consistency of an image against the counts of all views:
  *   d_out[0] = mean over every ray of (l_i - p_i)^2, l = A mu (d_img, 1/mm),
  *              p = ln(I0 / max(y, 1))  (the squared difference of section

@@ -299,7 +299,7 @@ void free_handle(recon_handle* h)
     drop_graphs(h);
     void* ptrs[] = {h->d_views, h->d_raygeo, h->d_raymeta, h->d_img[0], h->d_img[1],
                     h->d_yt,    h->d_p,      h->d_w,       h->d_part,   h->d_state,  h->d_part_all,
-                    h->d_fhist};
+                    h->d_fhist, h->d_fbp,     h->d_fbp_cs};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (h->h_state) (void)hipHostFree(h->h_state);
@@ -406,6 +406,21 @@ recon_status recon_create(const recon_geometry* geom, int32_t subsets, double be
     H_TRY(hipMalloc(&h->d_part_all, (nrays + SQ_GROUP - 1) / SQ_GROUP * sizeof(double)));
     H_TRY(hipMalloc(&h->d_state, 2 * sizeof(DevState)));
     H_TRY(hipMalloc(&h->d_fhist, (size_t)subsets * sizeof(double)));
+    // filtered-backprojection tables: D cos(gamma_k) (pixel units) and dgamma x the ramp taps
+    const std::vector<float> fbp_tab = fbp_tables(geom);
+    H_TRY(hipMalloc(&h->d_fbp, fbp_tab.size() * sizeof(float)));
+    H_TRY(hipMemcpy(h->d_fbp, fbp_tab.data(), fbp_tab.size() * sizeof(float), hipMemcpyHostToDevice));
+    // and cos / sin of every view's source angle in double, subset order
+    {
+        std::vector<double> cs(2 * (size_t)geom->n_views);
+        for (int q = 0; q < geom->n_views; ++q) {
+            const double beta = geom->start_angle_rad + 2.0 * kPi * (double)T.perm[q] / (double)geom->n_views;
+            cs[2 * (size_t)q] = std::cos(beta);
+            cs[2 * (size_t)q + 1] = std::sin(beta);
+        }
+        H_TRY(hipMalloc(&h->d_fbp_cs, cs.size() * sizeof(double)));
+        H_TRY(hipMemcpy(h->d_fbp_cs, cs.data(), cs.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     H_TRY(hipHostMalloc(&h->h_state, sizeof(DevState), hipHostMallocDefault));
     H_TRY(hipMemcpy(h->d_views, T.views.data(), T.views.size() * sizeof(ViewRec), hipMemcpyHostToDevice));
     H_TRY(hipMemcpy(h->d_raygeo, T.rg.data(), nrays * sizeof(RayGeo), hipMemcpyHostToDevice));

@@ -163,6 +163,8 @@ struct recon_handle {
     recon::DevState* d_state = nullptr;     // two copies: sub-iteration reads one, writes the other
     recon::DevState* h_state = nullptr;     // pinned read-back
     double* d_fhist = nullptr;              // [M] subset history of a fresh run with lambda_compare
+    float* d_fbp = nullptr;                 // [n_ch] D cos(gamma_k), then [2 n_ch - 1] dgamma h(m) (fbp.hip)
+    double* d_fbp_cs = nullptr;             // [n_views][2] cos / sin of the source angle, subset order (fbp.hip)
 
     int fp_segments = 8;
     int bp_variant = 1;      // 0: global candidate reads, 1: LDS-staged
@@ -247,6 +249,10 @@ hipError_t launch_fp_batch(int segments, const SliceDesc* slices, const FpWork* 
                            hipStream_t s);
 int fp_rays_per_block(int segments);
 hipError_t launch_tv_grad(const float* img, float* grad, int n, float eps, hipStream_t s);
+// fbp.hip: the filtered-backprojection tables of a geometry (host, double
+// precision, stored as float): D cos(gamma_k) in pixel units for every channel,
+// then dgamma h(m) for m = -(n_ch - 1) ... n_ch - 1.
+std::vector<float> fbp_tables(const recon_geometry* g);
 // kernels.hip: out[0] = (sum of part[0..ngroups)) / nrays, out[1] = mean of 1 / max(y, 1) over counts.
 hipError_t launch_residual_final(const double* part, int ngroups, const float* counts, long nrays, double* out,
                                  hipStream_t s);

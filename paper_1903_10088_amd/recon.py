@@ -54,7 +54,7 @@ EXPORTS = ["recon_default_params", "recon_status_string", "recon_last_error", "r
            "recon_cnn_param_count", "recon_cnn_create", "recon_cnn_destroy", "recon_cnn_get_state",
            "recon_cnn_set_state", "recon_cnn_save", "recon_cnn_load", "recon_cnn_forward", "recon_cnn_loss_grad",
            "recon_cnn_adam_step", "recon_cnn_train_step", "recon_cnn_tensor", "recon_cnn_time_kernels",
-           "recon_data_residual", "recon_warm_start"]
+           "recon_data_residual", "recon_warm_start", "recon_fbp"]
 
 _lib = None
 
@@ -81,6 +81,7 @@ def lib():
         L.recon_tv_grad.argtypes = [vp, vp, vp, vp]
         L.recon_os_iterate.argtypes = [vp, vp, f, vp, i32, P(State_c), vp, vp, vp]
         L.recon_os_iterate_ex.argtypes = [vp, vp, f, vp, i32, P(State_c), vp, vp, vp, vp, vp]
+        L.recon_fbp.argtypes = [vp, vp, f, vp, vp]
         L.recon_initial_image.argtypes = [vp, vp, vp]
         L.recon_subset_size.argtypes = [vp, i32, P(i32)]
         L.recon_set_launch.argtypes = [vp, i32, i32]
@@ -234,6 +235,16 @@ class Recon:
         _check(lib().recon_data_residual(self._h, _ptr(counts, torch.float32, (g.n_views, g.n_channels), "counts"),
                                          float(i0), _ptr(img, torch.float32, (g.n, g.n), "img"),
                                          _ptr(out, torch.float64, (2,), "out"), _stream()), "recon_data_residual")
+        return out
+
+    def fbp(self, counts, i0: float, out=None):
+        """recon_fbp: filtered backprojection of the counts, a float32 CUDA tensor [n][n] in 1/mm."""
+        torch = _torch()
+        g = self.geometry
+        if out is None:
+            out = torch.empty((g.n, g.n), dtype=torch.float32, device=counts.device)
+        _check(lib().recon_fbp(self._h, _ptr(counts, torch.float32, (g.n_views, g.n_channels), "counts"), float(i0),
+                               _ptr(out, torch.float32, (g.n, g.n), "img"), _stream()), "recon_fbp")
         return out
 
     def time_kernels(self, counts, i0: float, img, n_iter: int):
