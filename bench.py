@@ -169,6 +169,7 @@ def main():
                   "tolerance_per_mm": 1e-4 * ph.MU_WATER_PER_MM, "ok": rmse <= 1e-4 * ph.MU_WATER_PER_MM}
         log(f"bench: cpu {cpu['value']:.4f} slices/s; GPU vs oracle rmse after {n_cpu} sub-iterations {rmse:.2e}")
 
+    fbp = fbp_leg(R, counts, sl.i0)
     batch = batch_leg(args.batch_slices, args.iters, dev) if args.batch_slices > 0 else None
     cnn = cnn_leg(args.cnn_batch, dev) if args.cnn_batch > 0 else None
     warm = warm_leg(args.warm_slices, args.weights, dev) if args.warm_slices > 0 else None
@@ -200,6 +201,7 @@ def main():
         "kernel_us": {"fp": fp_ms * 1e3, "bp_update": bp_ms * 1e3,
                       "graph_sub_iteration": sub_ms * 1e3},
         "parity": parity,
+        "fbp_baseline": fbp,
         "batched_plain": batch,
         "cnn_kernels": cnn,
         "warm_start": warm,
@@ -207,6 +209,24 @@ def main():
                           "thinning": "1/20", "note": "context only; channel count and precision not stated"},
     }
     print(json.dumps(out), flush=True)
+
+
+def fbp_leg(R, counts, i0: float, reps: int = 20):
+    """The filtered-backprojection baseline (recon_fbp) on the same slice: time per slice over
+    `reps` back-to-back calls (HIP events on the library's stream)."""
+    import torch
+
+    R.fbp(counts, i0)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        R.fbp(counts, i0)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    log(f"bench: fbp baseline {ms:.3f} ms per slice")
+    return {"ms_per_slice": ms, "slices_per_s": 1e3 / ms}
 
 
 def batch_leg(n_slices: int, iters: int, dev):
