@@ -299,7 +299,7 @@ void free_handle(recon_handle* h)
     drop_graphs(h);
     void* ptrs[] = {h->d_views, h->d_raygeo, h->d_raymeta, h->d_img[0], h->d_img[1],
                     h->d_yt,    h->d_p,      h->d_w,       h->d_part,   h->d_state,  h->d_part_all,
-                    h->d_fhist, h->d_fbp,     h->d_fbp_cs};
+                    h->d_fhist, h->d_fbp,     h->d_fbp_cs, h->d_res_part};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (h->h_state) (void)hipHostFree(h->h_state);
@@ -405,6 +405,7 @@ recon_status recon_create(const recon_geometry* geom, int32_t subsets, double be
     H_TRY(hipMalloc(&h->d_part, ngroups * sizeof(double)));
     H_TRY(hipMalloc(&h->d_part_all, (nrays + SQ_GROUP - 1) / SQ_GROUP * sizeof(double)));
     H_TRY(hipMalloc(&h->d_state, 2 * sizeof(DevState)));
+    H_TRY(hipMalloc(&h->d_res_part, 2 * RES_BLOCKS * sizeof(double)));
     H_TRY(hipMalloc(&h->d_fhist, (size_t)subsets * sizeof(double)));
     // filtered-backprojection tables: D cos(gamma_k) (pixel units) and dgamma x the ramp taps
     const std::vector<float> fbp_tab = fbp_tables(geom);
@@ -606,7 +607,8 @@ recon_status recon_data_residual(recon_handle* h, const float* d_counts, float i
     // all views are one contiguous ray range in subset order
     HIP_TRY(launch_fp_os(G, h->fp_segments, h->d_img[0], h->d_imgT[0], h->d_raygeo, h->d_raymeta, 0, (int)nrays,
                          h->d_yt, h->d_p, h->d_w, h->d_part_all, s));
-    HIP_TRY(launch_residual_final(h->d_part_all, (int)((nrays + SQ_GROUP - 1) / SQ_GROUP), d_counts, nrays, d_out, s));
+    HIP_TRY(launch_residual_final(h->d_part_all, (int)((nrays + SQ_GROUP - 1) / SQ_GROUP), d_counts, nrays,
+                                  h->d_res_part, d_out, s));
     return RECON_OK;
 }
 

@@ -190,6 +190,7 @@ recon_status setup_batch(recon_batch_handle* b, int fp_segments)
         D.w = h->d_w;
         D.part = h->d_part;
         D.part_all = h->d_part_all;
+        D.res_part = h->d_res_part;
         D.state = h->d_state;
         D.subs = b->d_subs + (size_t)i * subsets;
         D.uc = update_const(h);

@@ -116,10 +116,16 @@ struct SliceDesc {
     float* w;
     double* part;
     double* part_all;  // squared-difference sums per SQ_GROUP rays over all views
+    double* res_part;  // [RES_BLOCKS][2] partial sums of the full-data residual
     DevState* state;   // two copies
     const int2* subs;  // per subset: (first subset-ordered view, number of views)
     UpdateConst uc;
 };
+
+// The full-data residual is reduced in RES_BLOCKS fixed ray ranges per slice,
+// whose sums are then added in range order (a fixed order, so the result does
+// not depend on batching).
+constexpr int RES_BLOCKS = 64;
 
 // Work items of the batched kernels: one per thread block.  slice < 0 = idle.
 struct FpWork {
@@ -160,6 +166,7 @@ struct recon_handle {
     float* d_w = nullptr;                   // weighted residual per ray, subset order
     double* d_part = nullptr;               // squared-difference sums per SQ_GROUP rays of a subset
     double* d_part_all = nullptr;           // the same over all views (full-data residual)
+    double* d_res_part = nullptr;           // [RES_BLOCKS][2] partial sums of the full-data residual
     recon::DevState* d_state = nullptr;     // two copies: sub-iteration reads one, writes the other
     recon::DevState* h_state = nullptr;     // pinned read-back
     double* d_fhist = nullptr;              // [M] subset history of a fresh run with lambda_compare
@@ -253,8 +260,10 @@ hipError_t launch_tv_grad(const float* img, float* grad, int n, float eps, hipSt
 // precision, stored as float): D cos(gamma_k) in pixel units for every channel,
 // then dgamma h(m) for m = -(n_ch - 1) ... n_ch - 1.
 std::vector<float> fbp_tables(const recon_geometry* g);
-// kernels.hip: out[0] = (sum of part[0..ngroups)) / nrays, out[1] = mean of 1 / max(y, 1) over counts.
-hipError_t launch_residual_final(const double* part, int ngroups, const float* counts, long nrays, double* out,
+// kernels.hip: out[0] = (sum of part[0..ngroups)) / nrays, out[1] = mean of 1 / max(y, 1) over counts
+// (partial sums of RES_BLOCKS ray ranges in res_part, then added in range order).
+hipError_t launch_residual_final(const double* part, int ngroups, const float* counts, long nrays, double* res_part,
+                                 double* out,
                                  hipStream_t s);
 // kernels.hip: the same for every slice of a batch (block i -> out[2i], out[2i + 1]).
 hipError_t launch_residual_final_batch(const SliceDesc* slices, const float* const* counts, int n_slices,

@@ -326,16 +326,21 @@ __global__ void flush_hist_kernel(const DevState* st, int M)
     if (v.fhist && v.n_global >= 1) v.fhist[(v.n_global - 1) % M] = v.f_prev;
 }
 
-// Full-data residual: one block, fixed summation order (thread-strided sums,
-// then a tree over the 256 threads).
-__global__ __launch_bounds__(256) void residual_final_kernel(const double* __restrict__ part, int ngroups,
-                                                             const float* __restrict__ counts, long nrays,
-                                                             double* __restrict__ out)
+// Full-data residual: block b of a slice reduces its share of the ray groups
+// and of the rays (range b of RES_BLOCKS equal ranges), thread-strided and
+// then by a fixed tree over the 256 threads; a second kernel adds the
+// RES_BLOCKS range sums in range order.  The order is fixed, so a slice gets
+// the same bits alone or in a batch.
+__device__ __forceinline__ void residual_range(const double* __restrict__ part, int ngroups,
+                                               const float* __restrict__ y, long nrays, int b,
+                                               double* __restrict__ dst)
 {
     __shared__ double r0[256], r1[256];
+    const long k0 = nrays * b / RES_BLOCKS, k1 = nrays * (b + 1) / RES_BLOCKS;
+    const int g0 = (int)((long)ngroups * b / RES_BLOCKS), g1 = (int)((long)ngroups * (b + 1) / RES_BLOCKS);
     double s0 = 0.0, s1 = 0.0;
-    for (int k = threadIdx.x; k < ngroups; k += 256) s0 += part[k];
-    for (long k = threadIdx.x; k < nrays; k += 256) s1 += 1.0 / (double)fmaxf(counts[k], 1.0f);
+    for (int k = g0 + (int)threadIdx.x; k < g1; k += 256) s0 += part[k];
+    for (long k = k0 + threadIdx.x; k < k1; k += 256) s1 += 1.0 / (double)fmaxf(y[k], 1.0f);
     r0[threadIdx.x] = s0;
     r1[threadIdx.x] = s1;
     __syncthreads();
@@ -347,39 +352,52 @@ __global__ __launch_bounds__(256) void residual_final_kernel(const double* __res
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        out[0] = r0[0] / (double)nrays;
-        out[1] = r1[0] / (double)nrays;
+        dst[0] = r0[0];
+        dst[1] = r1[0];
     }
 }
 
-// Batched full-data residual: block i reduces slice i.
-__global__ __launch_bounds__(256) void residual_final_batch_kernel(const SliceDesc* __restrict__ slices,
-                                                                   const float* const* __restrict__ counts,
-                                                                   double* __restrict__ out)
+__device__ __forceinline__ void residual_combine(const double* __restrict__ res_part, long nrays,
+                                                 double* __restrict__ out)
 {
-    __shared__ double r0[256], r1[256];
-    const SliceDesc* __restrict__ D = slices + blockIdx.x;
+    double s0 = 0.0, s1 = 0.0;
+    for (int b = 0; b < RES_BLOCKS; ++b) {
+        s0 += res_part[2 * b];
+        s1 += res_part[2 * b + 1];
+    }
+    out[0] = s0 / (double)nrays;
+    out[1] = s1 / (double)nrays;
+}
+
+__global__ __launch_bounds__(256) void residual_range_kernel(const double* __restrict__ part, int ngroups,
+                                                             const float* __restrict__ counts, long nrays,
+                                                             double* __restrict__ res_part)
+{
+    residual_range(part, ngroups, counts, nrays, blockIdx.x, res_part + 2 * blockIdx.x);
+}
+
+__global__ void residual_combine_kernel(const double* __restrict__ res_part, long nrays, double* __restrict__ out)
+{
+    if (threadIdx.x == 0) residual_combine(res_part, nrays, out);
+}
+
+// Batched: block (b, i) reduces range b of slice i; then thread i adds slice i's ranges.
+__global__ __launch_bounds__(256) void residual_range_batch_kernel(const SliceDesc* __restrict__ slices,
+                                                                   const float* const* __restrict__ counts)
+{
+    const SliceDesc* __restrict__ D = slices + blockIdx.y;
     const long nrays = (long)D->geo.nv * D->geo.nch;
     const int ngroups = (int)((nrays + SQ_GROUP - 1) / SQ_GROUP);
-    const double* __restrict__ part = D->part_all;
-    const float* __restrict__ y = counts[blockIdx.x];
-    double s0 = 0.0, s1 = 0.0;
-    for (int k = threadIdx.x; k < ngroups; k += 256) s0 += part[k];
-    for (long k = threadIdx.x; k < nrays; k += 256) s1 += 1.0 / (double)fmaxf(y[k], 1.0f);
-    r0[threadIdx.x] = s0;
-    r1[threadIdx.x] = s1;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            r0[threadIdx.x] += r0[threadIdx.x + w];
-            r1[threadIdx.x] += r1[threadIdx.x + w];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        out[2 * blockIdx.x] = r0[0] / (double)nrays;
-        out[2 * blockIdx.x + 1] = r1[0] / (double)nrays;
-    }
+    residual_range(D->part_all, ngroups, counts[blockIdx.y], nrays, blockIdx.x, D->res_part + 2 * blockIdx.x);
+}
+
+__global__ void residual_combine_batch_kernel(const SliceDesc* __restrict__ slices, int n_slices,
+                                              double* __restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_slices) return;
+    const SliceDesc* __restrict__ D = slices + i;
+    residual_combine(D->res_part, (long)D->geo.nv * D->geo.nch, out + 2 * i);
 }
 
 }  // namespace
@@ -499,18 +517,19 @@ hipError_t launch_flush_hist(const DevState* st, int M, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_residual_final(const double* part, int ngroups, const float* counts, long nrays, double* out,
-                                 hipStream_t s)
+hipError_t launch_residual_final(const double* part, int ngroups, const float* counts, long nrays, double* res_part,
+                                 double* out, hipStream_t s)
 {
-    residual_final_kernel<<<1, 256, 0, s>>>(part, ngroups, counts, nrays, out);
+    residual_range_kernel<<<RES_BLOCKS, 256, 0, s>>>(part, ngroups, counts, nrays, res_part);
+    residual_combine_kernel<<<1, 64, 0, s>>>(res_part, nrays, out);
     return hipGetLastError();
 }
 
 hipError_t launch_residual_final_batch(const SliceDesc* slices, const float* const* counts, int n_slices,
                                        double* out, hipStream_t s)
 {
-    if (n_slices <= 0) return hipSuccess;
-    residual_final_batch_kernel<<<n_slices, 256, 0, s>>>(slices, counts, out);
+    residual_range_batch_kernel<<<dim3(RES_BLOCKS, n_slices), 256, 0, s>>>(slices, counts);
+    residual_combine_batch_kernel<<<cdiv(n_slices, 64), 64, 0, s>>>(slices, n_slices, out);
     return hipGetLastError();
 }
 
