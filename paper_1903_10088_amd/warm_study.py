@@ -162,6 +162,21 @@ def cmd_eval(args):
         ws.log(f"eval: warm batch {c0}: {dt:.3f} s, {int(fb.sum())} fallbacks")
     r_warm = ws.disc_rmse(warm_imgs, conv, 512) / MU_W
     rmse_w = float(np.mean(r_warm))
+    # the network's evaluation setting (40 refining sub-iterations, no fallback): RMSE to converged
+    # and data residual against the plain method, every slice
+    r40 = []
+    for c0 in range(0, len(items), args.chunk):
+        sub = items[c0:c0 + args.chunk]
+        B = recon.Batch([g for g, _, _ in sub], 20, 1e-3)
+        cts = [torch.from_numpy(c).to(dev) for c in counts[c0:c0 + args.chunk]]
+        imgs = [warm_imgs[c0 + i] for i in range(len(sub))]
+        _, rr, fl, _ = B.warm_start(net, cts, [i0 for _, _, i0 in sub], imgs, args.n_pre, 40, args.n_final, 1e30)
+        r40 += list((rr / fl).tolist())
+        B.close()
+    rmse40 = float(np.mean(ws.disc_rmse(warm_imgs, conv, 512) / MU_W))
+    res_refine40 = dict(n_refine=40, rmse_to_converged_over_muw=rmse40,
+                        plain_sub_iterations_at_equal_rmse=ws.equal_rmse_count(curve, rmse40, args.n_final),
+                        residual_ratio=dict(median=float(np.median(r40)), max=float(np.max(r40))))
     n_eq = ws.equal_rmse_count(curve, rmse_w, args.n_final)
     # plain batched throughput at n_eq sub-iterations (same batches, same timing)
     t_plain = 0.0
@@ -182,7 +197,7 @@ def cmd_eval(args):
                                                                          max=float(np.max(r_all)))),
                plain_equal_rmse=dict(sub_iterations=n_eq, rmse_to_converged_over_muw=curve[n_eq],
                                      slices_per_s=len(items) / t_plain),
-               speedup=(len(items) / t_total) / (len(items) / t_plain))
+               speedup=(len(items) / t_total) / (len(items) / t_plain), refine40=res_refine40)
     os.makedirs(args.out, exist_ok=True)
     json.dump(res, open(os.path.join(args.out, "eval.json"), "w"), indent=1)
     ws.log(json.dumps({k: v for k, v in res.items() if k != "batches"}))

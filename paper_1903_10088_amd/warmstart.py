@@ -18,9 +18,8 @@ Workflow (the network is trained only on images the plain iteration produced):
      level (recon_data_residual) of the plain method's images at that count,
      widened by a margin: the limit above which the warm start falls back to a
      cold start (its output must explain the data as well as the plain image it
-     stands in for), and that count as the cold start's length (a slice that
-     falls back gets the plain image of the quality the pipeline stands in
-     for);
+     stands in for); a slice that falls back is reconstructed by a cold start
+     of the full n_final sub-iterations;
   4. `disc_rmse` / `timed`: RMSE to each slice's converged image and
      throughput of the warm-start pipeline (recon_warm_start) and of the plain
      batched method (warm_study.py runs the comparison).
@@ -219,7 +218,7 @@ def calibrate_equal_rmse(items, counts, net, n_pre: int, n_refine: int, n_final:
     n_eq = equal_rmse_count(curve, warm_rmse, n_final)
     plain_r = residual_ratios(items, cts, [runs[n_eq][i] for i in range(len(items))], subsets, beta)
     warm_r = rr / fl
-    return dict(limit=float(plain_r.max() * (1 + margin)), n_pre=n_pre, n_refine=n_refine, n_cold=n_eq,
+    return dict(limit=float(plain_r.max() * (1 + margin)), n_pre=n_pre, n_refine=n_refine, n_cold=n_final,
                 warm_rmse_over_muw=warm_rmse, plain_sub_iterations_at_equal_rmse=n_eq,
                 plain_ratio=dict(min=float(plain_r.min()), median=float(np.median(plain_r)),
                                  max=float(plain_r.max())),
