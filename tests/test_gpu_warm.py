@@ -89,6 +89,35 @@ def test_pipeline_falls_back_to_a_cold_start(dev):
         assert torch.equal(imgs[k], cold)
 
 
+@pytest.mark.parametrize("kind", ["noise", "nan"])
+def test_bad_network_falls_back_through_the_check(dev, kind):
+    """A broken network (a huge random last layer, or a NaN bias) with the calibrated limit, not a
+    forced one: the data-consistency check alone sends every slice to the cold start (a NaN residual
+    counts as failing)."""
+    import json
+    import os
+
+    from paper_1903_10088_amd import recon
+    rec = json.load(open(os.path.join(os.path.dirname(recon.__file__), "weights", "train.json")))
+    geoms, slices = small_batch()
+    M, beta = 5, 1e-3
+    B = recon.Batch(geoms, M, beta)
+    theta = ph.cnn_initial_params(4, zero_last=False, last_std=2.0)
+    if kind == "nan":
+        theta = ph.cnn_initial_params(4)
+        theta[-1] = np.nan
+    net = recon.Cnn(theta, max_batch=2, max_n=128, mu_scale=ph.MU_WATER_PER_MM)
+    counts = [torch.from_numpy(s.counts).to(dev) for s in slices]
+    imgs, res, flo, fb = B.warm_start(net, counts, [s.i0 for s in slices], None, rec["n_pre"], rec["n_refine"], 13,
+                                      rec["residual_ratio_limit"])
+    print(f"  {kind} network: residual ratios {res / flo}", flush=True)
+    assert fb.all()
+    for k, (g, sl) in enumerate(zip(geoms, slices)):
+        R = recon.Recon(g, M, beta)
+        cold, _ = R.os_iterate(counts[k], sl.i0, None, 13)
+        assert torch.equal(imgs[k], cold)
+
+
 def test_many_fallbacks_go_through_a_batch(dev):
     """Nine slices, all sent to the cold start (the batched cold-start path): each equals its own
     single-slice cold reconstruction."""
