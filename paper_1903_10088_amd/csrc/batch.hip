@@ -237,20 +237,66 @@ recon_status get_graph(recon_batch_handle* b, int parity, hipGraphExec_t* out)
     return RECON_OK;
 }
 
-// Per-slice preparation of a run: counts, start image, fresh step-rule state.
+// Groups of up to BATCH_ARGS consecutive slices for the batched layout kernels.
+template <class F>
+recon_status for_groups(const recon_batch_handle* b, F&& f)
+{
+    const int n = (int)b->h.size();
+    for (int first = 0; first < n; first += BATCH_ARGS) {
+        BatchRunArgs a{};
+        a.first = first;
+        a.count = std::min(BATCH_ARGS, n - first);
+        for (int k = 0; k < a.count; ++k) {
+            const Geo& G = b->h[first + k]->geo;
+            a.max_n = std::max(a.max_n, G.n);
+            a.max_rays = std::max(a.max_rays, (long)G.nv * G.nch);
+        }
+        recon_status st = f(a);
+        if (st != RECON_OK) return st;
+    }
+    return RECON_OK;
+}
+
+// Start of a run of every slice: counts, start image, fresh step-rule state
+// (one launch per group of slices).
 recon_status prepare(recon_batch_handle* b, const float* const* d_counts, const float* i0, float* const* d_imgs,
                      double* const* d_traces, hipStream_t s)
 {
-    for (size_t i = 0; i < b->h.size(); ++i) {
-        recon_handle* h = b->h[i];
-        const Geo& G = h->geo;
+    for (size_t i = 0; i < b->h.size(); ++i)
         if (!d_counts[i] || !d_imgs[i] || !(i0[i] > 0) || !std::isfinite(i0[i]))
             return fail(RECON_INVALID_ARG, "slice " + std::to_string(i) + ": NULL buffer or bad i0");
-        RECON_HIP_TRY(launch_prep_counts(d_counts[i], h->d_views, G.nv, G.nch, i0[i], h->d_yt, h->d_p, s));
-        RECON_HIP_TRY(launch_pad_image(d_imgs[i], h->d_img[0], h->d_imgT[0], G.n, G.P, s, true));
-        DevState v = fresh_state(h->p.lambda0);
-        v.trace = d_traces ? d_traces[i] : nullptr;
-        RECON_HIP_TRY(launch_set_state(h->d_state, v, s));
+    const DevState fresh = fresh_state(b->h[0]->p.lambda0);
+    return for_groups(b, [&](BatchRunArgs& a) -> recon_status {
+        for (int k = 0; k < a.count; ++k) {
+            a.counts[k] = d_counts[a.first + k];
+            a.img[k] = d_imgs[a.first + k];
+            a.trace[k] = d_traces ? d_traces[a.first + k] : nullptr;
+            a.i0[k] = i0[a.first + k];
+        }
+        RECON_HIP_TRY(launch_prepare_batch(b->d_slices, a, fresh, s));
+        return RECON_OK;
+    });
+}
+
+// Copies images of side sz between the slices' buffers and a contiguous stage
+// (to_stage: d_imgs[i] -> stage slot, else back), slices of that size in order.
+recon_status stage_copy(const recon_batch_handle* b, float* const* d_imgs, float* d_stage, int sz, bool to_stage,
+                        hipStream_t s)
+{
+    const size_t img = (size_t)sz * sz;
+    BatchCopyArgs c{};
+    int slot = 0;
+    for (size_t i = 0; i <= b->h.size(); ++i) {
+        if (c.count == BATCH_ARGS || (i == b->h.size() && c.count > 0)) {
+            RECON_HIP_TRY(launch_copy_batch(c, (long)img, s));
+            c.count = 0;
+        }
+        if (i == b->h.size()) break;
+        if (b->h[i]->geo.n != sz) continue;
+        float* st = d_stage + (size_t)(slot++) * img;
+        c.src[c.count] = to_stage ? d_imgs[i] : st;
+        c.dst[c.count] = to_stage ? st : d_imgs[i];
+        ++c.count;
     }
     return RECON_OK;
 }
@@ -296,11 +342,17 @@ recon_status recon_batch_create(const recon_geometry* geoms, int32_t n_slices, i
 recon_status recon_batch_initial_images(recon_batch_handle* b, float* const* d_imgs, void* stream)
 {
     if (!b || !d_imgs) return fail(RECON_INVALID_ARG, "NULL argument");
-    for (size_t i = 0; i < b->h.size(); ++i) {
-        recon_status st = recon_initial_image(b->h[i], d_imgs[i], stream);
-        if (st != RECON_OK) return st;
-    }
-    return RECON_OK;
+    for (size_t i = 0; i < b->h.size(); ++i)
+        if (!d_imgs[i]) return fail(RECON_INVALID_ARG, "slice " + std::to_string(i) + ": NULL image");
+    hipStream_t s = as_stream(stream);
+    return for_groups(b, [&](BatchRunArgs& a) -> recon_status {
+        for (int k = 0; k < a.count; ++k) {
+            a.img[k] = d_imgs[a.first + k];
+            a.mu0[k] = (float)b->h[a.first + k]->p.mu0_per_mm;
+        }
+        RECON_HIP_TRY(launch_initial_batch(b->d_slices, a, s));
+        return RECON_OK;
+    });
 }
 
 recon_status recon_batch_destroy(recon_batch_handle* b)
@@ -351,10 +403,12 @@ recon_status recon_batch_run(recon_batch_handle* b, const float* const* d_counts
         in = 1 - in;
         ++n;
     }
-    for (size_t i = 0; i < b->h.size(); ++i) {
-        const Geo& G = b->h[i]->geo;
-        RECON_HIP_TRY(launch_unpad_image(b->h[i]->d_img[in], d_imgs[i], G.n, G.P, s));
-    }
+    st = for_groups(b, [&](BatchRunArgs& a) -> recon_status {
+        for (int k = 0; k < a.count; ++k) a.img[k] = d_imgs[a.first + k];
+        RECON_HIP_TRY(launch_unpad_batch(b->d_slices, a, in, s));
+        return RECON_OK;
+    });
+    if (st != RECON_OK) return st;
     b->last_in = in;
     return RECON_OK;
 }
@@ -482,17 +536,11 @@ recon_status recon_warm_start(recon_batch_handle* b, recon_cnn* net, const float
     if (e == hipSuccess) e = hipMemcpyAsync(d_cptr, d_counts, sizeof(float*) * n, hipMemcpyHostToDevice, s);
     for (size_t k = 0; k < sizes.size() && e == hipSuccess && st == RECON_OK; ++k) {
         const int sz = sizes[k];
-        const size_t img = (size_t)sz * sz;
         int cnt = 0;
-        for (int i = 0; i < n && e == hipSuccess; ++i)
-            if (b->h[i]->geo.n == sz)
-                e = hipMemcpyAsync(d_stage + (cnt++) * img, d_imgs[i], img * sizeof(float), hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) break;
-        st = recon_cnn_forward(net, d_stage, d_stage, cnt, sz, 1, stream);
-        cnt = 0;
-        for (int i = 0; i < n && e == hipSuccess && st == RECON_OK; ++i)
-            if (b->h[i]->geo.n == sz)
-                e = hipMemcpyAsync(d_imgs[i], d_stage + (cnt++) * img, img * sizeof(float), hipMemcpyDeviceToDevice, s);
+        for (recon_handle* h : b->h) cnt += (h->geo.n == sz);
+        st = stage_copy(b, d_imgs, d_stage, sz, true, s);
+        if (st == RECON_OK) st = recon_cnn_forward(net, d_stage, d_stage, cnt, sz, 1, stream);
+        if (st == RECON_OK) st = stage_copy(b, d_imgs, d_stage, sz, false, s);
     }
     // 3. refinement by the plain iteration, fresh step-rule state
     if (e == hipSuccess && st == RECON_OK) st = recon_batch_run(b, d_counts, i0, d_imgs, n_refine, nullptr, stream);

@@ -111,8 +111,8 @@ struct SliceDesc {
     const RayMeta* rm;
     float* img[2];
     float* imgT[2];
-    const float* yt;
-    const float* p;
+    float* yt;  // written at the start of a run, read by the projector
+    float* p;
     float* w;
     double* part;
     double* part_all;  // squared-difference sums per SQ_GROUP rays over all views
@@ -213,6 +213,36 @@ hipError_t launch_prep_counts(const float* counts, const ViewRec* views, int nv,
                               float* p, hipStream_t s);
 hipError_t launch_scale_sino(const float* sino, const RayMeta* meta, int ray0, int nrays, int nch,
                              const ViewRec* views, int q0, int natural_rows, float* w, hipStream_t s);
+// Per-slice arguments of the batched layout kernels, passed by value (no
+// upload): one launch covers up to BATCH_ARGS slices [first, first + count) of
+// a slice table.  max_n / max_rays: the group's largest image side and
+// views x channels, which size the grid.
+constexpr int BATCH_ARGS = 64;
+struct BatchRunArgs {
+    const float* counts[BATCH_ARGS];
+    float* img[BATCH_ARGS];
+    double* trace[BATCH_ARGS];
+    float i0[BATCH_ARGS];
+    float mu0[BATCH_ARGS];
+    int first, count;
+    int max_n;
+    long max_rays;
+};
+struct BatchCopyArgs {
+    const float* src[BATCH_ARGS];
+    float* dst[BATCH_ARGS];
+    int count;
+};
+// Start of a batched run: counts -> yt, p; start image -> padded copies
+// (masked to the disc); state[0] = fresh with the slice's trace and it = 0.
+hipError_t launch_prepare_batch(const SliceDesc* slices, const BatchRunArgs& a, const DevState& fresh, hipStream_t s);
+// img[k] = the unpadded image buffer `in` of slice first + k.
+hipError_t launch_unpad_batch(const SliceDesc* slices, const BatchRunArgs& a, int in, hipStream_t s);
+// img[k] = the homogeneous start image (mu0[k] in the disc, 0 outside).
+hipError_t launch_initial_batch(const SliceDesc* slices, const BatchRunArgs& a, hipStream_t s);
+// dst[k][0, len) = src[k][0, len) for k < count.
+hipError_t launch_copy_batch(const BatchCopyArgs& a, long len, hipStream_t s);
+
 hipError_t launch_fp_plain(const Geo& geo, int segments, const float* img, const float* imgT, const RayGeo* rg,
                            const RayMeta* rm, const ViewRec* views, int q0, int nq, int natural_rows, float* out,
                            hipStream_t s);

@@ -29,12 +29,11 @@ inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 // ----------------------------------------------------------------------------
 
 // [n][n] image -> padded row-major and padded transposed copies (32x32 tiles
-// transposed through LDS so both writes are coalesced).
-__global__ __launch_bounds__(256) void pad_image_kernel(const float* __restrict__ src, float* __restrict__ dst,
-                                                        float* __restrict__ dstT, int n, int P, int mask_disc)
+// transposed through LDS so both writes are coalesced); tile (bx, by).
+__device__ __forceinline__ void pad_tile(const float* __restrict__ src, float* __restrict__ dst,
+                                         float* __restrict__ dstT, int n, int P, bool mask_disc, int bx, int by,
+                                         float (&tile)[32][33])
 {
-    __shared__ float tile[32][33];
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int r = ty; r < 32; r += 8) {
         const int j = by + r, i = bx + tx;
@@ -52,34 +51,111 @@ __global__ __launch_bounds__(256) void pad_image_kernel(const float* __restrict_
     }
 }
 
+// Counts in natural view order -> y / I0 and p = ln(I0 / max(y, 1)) in subset order; ray r.
+__device__ __forceinline__ void prep_count(const float* __restrict__ counts, const ViewRec* __restrict__ views,
+                                           int nch, float i0, float* __restrict__ yt, float* __restrict__ p, long r)
+{
+    const int q = (int)(r / nch), k = (int)(r - (long)q * nch);
+    const float y = counts[(size_t)views[q].nat_view * nch + k];
+    yt[r] = y / i0;
+    p[r] = (float)log((double)i0 / (double)fmaxf(y, 1.0f));
+}
+
+__device__ __forceinline__ float initial_value(long idx, int n, float mu0)
+{
+    const int j = (int)(idx / n), i = (int)(idx - (long)j * n);
+    return in_disc(i, j, n) ? mu0 : 0.0f;
+}
+
+__device__ __forceinline__ float unpadded_value(const float* __restrict__ src, long idx, int n, int P)
+{
+    const int j = (int)(idx / n), i = (int)(idx - (long)j * n);
+    return src[(size_t)j * P + i + PAD];
+}
+
+__global__ __launch_bounds__(256) void pad_image_kernel(const float* __restrict__ src, float* __restrict__ dst,
+                                                        float* __restrict__ dstT, int n, int P, int mask_disc)
+{
+    __shared__ float tile[32][33];
+    pad_tile(src, dst, dstT, n, P, mask_disc != 0, blockIdx.x * 32, blockIdx.y * 32, tile);
+}
+
 __global__ __launch_bounds__(256) void unpad_image_kernel(const float* __restrict__ src, float* __restrict__ dst,
                                                           int n, int P)
 {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)n * n) return;
-    const int j = (int)(idx / n), i = (int)(idx - (long)j * n);
-    dst[idx] = src[(size_t)j * P + i + PAD];
+    dst[idx] = unpadded_value(src, idx, n, P);
 }
 
 __global__ __launch_bounds__(256) void initial_image_kernel(float* __restrict__ dst, int n, float mu0)
 {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)n * n) return;
-    const int j = (int)(idx / n), i = (int)(idx - (long)j * n);
-    dst[idx] = in_disc(i, j, n) ? mu0 : 0.0f;
+    dst[idx] = initial_value(idx, n, mu0);
 }
 
-// Counts in natural view order -> y / I0 and p = ln(I0 / max(y, 1)) in subset order.
 __global__ __launch_bounds__(256) void prep_counts_kernel(const float* __restrict__ counts,
                                                           const ViewRec* __restrict__ views, int nv, int nch,
                                                           float i0, float* __restrict__ yt, float* __restrict__ p)
 {
     const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= (long)nv * nch) return;
-    const int q = (int)(r / nch), k = (int)(r - (long)q * nch);
-    const float y = counts[(size_t)views[q].nat_view * nch + k];
-    yt[r] = y / i0;
-    p[r] = (float)log((double)i0 / (double)fmaxf(y, 1.0f));
+    prep_count(counts, views, nch, i0, yt, p, r);
+}
+
+// Batched forms over a group of slices: blockIdx.y is the slice within the
+// group, blocks beyond a smaller slice's extent return at once.  Each element
+// is computed by the same device function as in the single-slice kernels.
+
+// Start of a run of every slice in the group: blocks [0, count_blocks) prepare
+// the counts (block 0 also writes the fresh step-rule state), the rest pad the
+// start image (masked to the disc) in 32x32 tiles.
+__global__ __launch_bounds__(256) void prepare_batch_kernel(const SliceDesc* __restrict__ slices, BatchRunArgs a,
+                                                            DevState fresh, int count_blocks)
+{
+    __shared__ float tile[32][33];
+    const int y = blockIdx.y;
+    const SliceDesc* __restrict__ D = slices + a.first + y;
+    const Geo G = D->geo;
+    if ((int)blockIdx.x < count_blocks) {
+        const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;
+        if (r < (long)G.nv * G.nch) prep_count(a.counts[y], D->views, G.nch, a.i0[y], D->yt, D->p, r);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            fresh.trace = a.trace[y];
+            fresh.it = 0;
+            D->state[0] = fresh;
+        }
+        return;
+    }
+    const int t = (int)blockIdx.x - count_blocks, tiles = (G.n + 31) / 32;
+    if (t >= tiles * tiles) return;
+    pad_tile(a.img[y], D->img[0], D->imgT[0], G.n, G.P, true, (t % tiles) * 32, (t / tiles) * 32, tile);
+}
+
+__global__ __launch_bounds__(256) void unpad_batch_kernel(const SliceDesc* __restrict__ slices, BatchRunArgs a, int in)
+{
+    const int y = blockIdx.y;
+    const SliceDesc* __restrict__ D = slices + a.first + y;
+    const int n = D->geo.n;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n * n) return;
+    a.img[y][idx] = unpadded_value(D->img[in], idx, n, D->geo.P);
+}
+
+__global__ __launch_bounds__(256) void initial_batch_kernel(const SliceDesc* __restrict__ slices, BatchRunArgs a)
+{
+    const int y = blockIdx.y;
+    const int n = slices[a.first + y].geo.n;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n * n) return;
+    a.img[y][idx] = initial_value(idx, n, a.mu0[y]);
+}
+
+__global__ __launch_bounds__(256) void copy_batch_kernel(BatchCopyArgs a, long len)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < len) a.dst[blockIdx.y][idx] = a.src[blockIdx.y][idx];
 }
 
 // Sinogram rows (natural or subset order) -> path-weighted values in subset order,
@@ -429,6 +505,37 @@ hipError_t launch_prep_counts(const float* counts, const ViewRec* views, int nv,
                               float* p, hipStream_t s)
 {
     prep_counts_kernel<<<cdiv((long)nv * nch, 256), 256, 0, s>>>(counts, views, nv, nch, i0, yt, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare_batch(const SliceDesc* slices, const BatchRunArgs& a, const DevState& fresh, hipStream_t s)
+{
+    if (a.count < 1 || a.count > BATCH_ARGS) return hipErrorInvalidValue;
+    const unsigned count_blocks = cdiv(a.max_rays, 256), tiles = cdiv(a.max_n, 32);
+    prepare_batch_kernel<<<dim3(count_blocks + tiles * tiles, a.count), 256, 0, s>>>(slices, a, fresh,
+                                                                                     (int)count_blocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpad_batch(const SliceDesc* slices, const BatchRunArgs& a, int in, hipStream_t s)
+{
+    if (a.count < 1 || a.count > BATCH_ARGS) return hipErrorInvalidValue;
+    unpad_batch_kernel<<<dim3(cdiv((long)a.max_n * a.max_n, 256), a.count), 256, 0, s>>>(slices, a, in);
+    return hipGetLastError();
+}
+
+hipError_t launch_initial_batch(const SliceDesc* slices, const BatchRunArgs& a, hipStream_t s)
+{
+    if (a.count < 1 || a.count > BATCH_ARGS) return hipErrorInvalidValue;
+    initial_batch_kernel<<<dim3(cdiv((long)a.max_n * a.max_n, 256), a.count), 256, 0, s>>>(slices, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_batch(const BatchCopyArgs& a, long len, hipStream_t s)
+{
+    if (a.count < 1 || a.count > BATCH_ARGS) return hipErrorInvalidValue;
+    if (len <= 0) return hipSuccess;
+    copy_batch_kernel<<<dim3(cdiv(len, 256), a.count), 256, 0, s>>>(a, len);
     return hipGetLastError();
 }
 

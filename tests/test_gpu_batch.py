@@ -147,3 +147,36 @@ def test_batch_rejects_bad_subsets(dev):
     with pytest.raises(recon.ReconError) as ei:
         recon.Batch(geoms, 40, 1e-3)  # more subsets than the second slice has views
     assert ei.value.status == recon.RECON_INVALID_ARG
+
+
+def test_batch_of_several_launch_groups(dev):
+    """70 slices, more than one group of the batched start / end kernels (64 slices a launch) and
+    more than 64 of one image size for the network's staging copies: start images, run results and
+    traces equal the single-slice ones, and the identity-network pipeline equals its steps."""
+    from paper_1903_10088_amd import recon
+    ga = ph.Geometry(n=37, pixel_mm=10.0, n_views=33, n_channels=51, start_angle_rad=0.3)
+    gb = ph.Geometry(n=32, pixel_mm=12.5, n_views=40, n_channels=48)
+    geoms = [gb if k in (10, 40, 64, 69) else ga for k in range(70)]
+    slices = [ph.make_slice(g, 700 + k, 10 ** (3 + 0.02 * k), low_contrast=True, supersample=1)
+              for k, g in enumerate(geoms)]
+    M, beta, n_iter = 3, 1e-3, 4
+    print(f"batch of {len(geoms)} slices, M={M}", flush=True)
+    B = recon.Batch(geoms, M, beta)
+    starts = B.initial_images(dev)
+    for k in (0, 10, 63, 64, 69):
+        assert torch.equal(starts[k], recon.Recon(geoms[k], M, beta).initial_image(dev)), k
+    counts = [torch.from_numpy(s.counts).to(dev) for s in slices]
+    i0s = [s.i0 for s in slices]
+    imgs, trs = B.run(counts, i0s, None, n_iter, trace=True)
+    imgs = [x.clone() for x in imgs]
+    torch.cuda.synchronize()
+    for k in (0, 10, 63, 64, 65, 69):
+        ref, rtr = run_single(dev, geoms[k], slices[k], M, beta, n_iter)
+        assert torch.equal(imgs[k], ref), k
+        assert torch.equal(trs[k], rtr), k
+    net = recon.Cnn(None, max_batch=8, max_n=64, mu_scale=ph.MU_WATER_PER_MM)
+    w, _, _, fb = B.warm_start(net, counts, i0s, None, n_iter, 2, 3, 1e6)
+    assert not fb.any()
+    ref, _ = B.run(counts, i0s, [x.clone() for x in imgs], 2)
+    for k, (a, b) in enumerate(zip(w, ref)):
+        assert torch.equal(a, b), k
