@@ -641,7 +641,10 @@ __device__ __forceinline__ void bp_update_tile(Geo G, const ViewRec* __restrict_
     __shared__ float s[TILE + 2][TILE + 3];
     __shared__ float t[TILE][TILE + 1];
     __shared__ double red[4];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    // each wave takes an 8x8 quadrant of the tile, whose pixels span fewer
+    // channels of a view than a 16x4 strip
+    const int lane = threadIdx.x & 63, wq = threadIdx.x >> 6;
+    const int tx = (lane & 7) + 8 * (wq & 1), ty = (lane >> 3) + 8 * (wq >> 1);
     const int i = ti0 + tx, j = tj0 + ty;
 
     for (int e = threadIdx.x; e < (TILE + 2) * (TILE + 2); e += 256) {
