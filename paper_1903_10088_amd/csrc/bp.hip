@@ -257,38 +257,46 @@ __device__ __forceinline__ float gather_staged(StageLds& S, const Geo& G, const 
             stage_store(S, b, t0, cv, P);
             __syncthreads();
             if (t0 + STAGE_VIEWS < sn) stage_load(S, rg, w, t0 + STAGE_VIEWS, min(STAGE_VIEWS, sn - t0 - STAGE_VIEWS), P);
+            // one view of the chunk (a full chunk is unrolled, so the table
+            // reads of later views can be issued ahead of earlier views' work)
+            auto view = [&](int cq) {
+                const int t = t0 + cq;
+                const ViewRec v = V[s0 + t];
+                const int cnt = S.cnt[t];
+                const TileView tv = S.tv[t];
+                const float kp = fmaf(tv.gx, dX, fmaf(tv.gy, dY, tv.kpc));
+                int x0, x1, y0, y1;
+                major_intervals(v, G.nch, x0, x1, y0, y1);
+                // slot bases: the part from k_split on sits behind the gap
+                const int bx = x0 == v.k_split ? S.kb[t] : S.k0[t];
+                const int by = y0 == v.k_split ? S.kb[t] : S.k0[t];
+                if (x0 < x1) {
+                    int lo, hi;
+                    candidate_range(kp, tv.hwx, x0, x1, lo, hi);
+                    if (lo <= hi) {
+                        if (cnt > 0)  // every window lies in the staged range (stage_range)
+                            acc = add_window_padded(acc, lo, hi, fi, fj, LdsRead{S.geo[b][cq], S.w[b][cq], bx});
+                        else
+                            acc = add_window(acc, lo, hi, fi, fj, GlobalRead{rg + v.ray0, w + v.ray0, hi});
+                    }
+                }
+                if (y0 < y1) {
+                    int lo, hi;
+                    candidate_range(kp, tv.hwy, y0, y1, lo, hi);
+                    if (lo <= hi) {
+                        if (cnt > 0)
+                            acc = add_window_padded(acc, lo, hi, fj, fi, LdsRead{S.geo[b][cq], S.w[b][cq], by});
+                        else
+                            acc = add_window(acc, lo, hi, fj, fi, GlobalRead{rg + v.ray0, w + v.ray0, hi});
+                    }
+                }
+            };
             if (inside) {
-                for (int cq = 0; cq < cv; ++cq) {
-                    const int t = t0 + cq;
-                    const ViewRec v = V[s0 + t];
-                    const int cnt = S.cnt[t];
-                    const TileView tv = S.tv[t];
-                    const float kp = fmaf(tv.gx, dX, fmaf(tv.gy, dY, tv.kpc));
-                    int x0, x1, y0, y1;
-                    major_intervals(v, G.nch, x0, x1, y0, y1);
-                    // slot bases: the part from k_split on sits behind the gap
-                    const int bx = x0 == v.k_split ? S.kb[t] : S.k0[t];
-                    const int by = y0 == v.k_split ? S.kb[t] : S.k0[t];
-                    if (x0 < x1) {
-                        int lo, hi;
-                        candidate_range(kp, tv.hwx, x0, x1, lo, hi);
-                        if (lo <= hi) {
-                            if (cnt > 0)  // every window lies in the staged range (stage_range)
-                                acc = add_window_padded(acc, lo, hi, fi, fj, LdsRead{S.geo[b][cq], S.w[b][cq], bx});
-                            else
-                                acc = add_window(acc, lo, hi, fi, fj, GlobalRead{rg + v.ray0, w + v.ray0, hi});
-                        }
-                    }
-                    if (y0 < y1) {
-                        int lo, hi;
-                        candidate_range(kp, tv.hwy, y0, y1, lo, hi);
-                        if (lo <= hi) {
-                            if (cnt > 0)
-                                acc = add_window_padded(acc, lo, hi, fj, fi, LdsRead{S.geo[b][cq], S.w[b][cq], by});
-                            else
-                                acc = add_window(acc, lo, hi, fj, fi, GlobalRead{rg + v.ray0, w + v.ray0, hi});
-                        }
-                    }
+                if (cv == STAGE_VIEWS) {
+#pragma unroll
+                    for (int cq = 0; cq < STAGE_VIEWS; ++cq) view(cq);
+                } else {
+                    for (int cq = 0; cq < cv; ++cq) view(cq);
                 }
             }
         }
