@@ -148,10 +148,16 @@ __device__ __forceinline__ float gather_global(const Geo& G, const ViewRec* __re
 constexpr int STAGE_TABLE = 64;  // views whose tile models are formed together, one per thread
 constexpr int STAGE_LOADS = STAGE_VIEWS * STAGE_SLOTS / 256;  // staged slots per thread and chunk
 
+// Per view, what every pixel reads, packed into three 16-byte records:
+// va = (kpc, gx, gy, hwx), vb = (hwy, x-part first and last channel, y-part
+// first channel), vc = (y-part last channel, staged count, x-part and y-part
+// slot bases); channels as floats for the window clamps.
 struct StageLds {
     float4 geo[2][STAGE_VIEWS][STAGE_ROW];
     float w[2][STAGE_VIEWS][STAGE_ROW];
-    TileView tv[STAGE_TABLE];
+    float4 va[STAGE_TABLE];
+    float4 vb[STAGE_TABLE];
+    int4 vc[STAGE_TABLE];
     int k0[STAGE_TABLE];
     int kb[STAGE_TABLE];
     int cnt[STAGE_TABLE];  // staged channels, 0 = view not staged
@@ -241,9 +247,16 @@ __device__ __forceinline__ float gather_staged(StageLds& S, const Geo& G, const 
             int k0, cnt;
             stage_range(tv, G.nch, STAGE_SLOTS, k0, cnt);
             const bool gap = k0 < v.k_split && v.k_split < k0 + cnt;
-            S.tv[tid] = tv;
+            const int kb = gap ? k0 - STAGE_GAP : k0;
+            int x0, x1, y0, y1;
+            major_intervals(v, G.nch, x0, x1, y0, y1);
+            // slot bases: the part from k_split on sits behind the gap
+            S.va[tid] = make_float4(tv.kpc, tv.gx, tv.gy, tv.hwx);
+            S.vb[tid] = make_float4(tv.hwy, (float)x0, (float)(x1 - 1), (float)y0);
+            S.vc[tid] = make_int4(__float_as_int((float)(y1 - 1)), cnt, x0 == v.k_split ? kb : k0,
+                                  y0 == v.k_split ? kb : k0);
             S.k0[tid] = k0;
-            S.kb[tid] = gap ? k0 - STAGE_GAP : k0;
+            S.kb[tid] = kb;
             S.cnt[tid] = cnt;
             S.ray0[tid] = v.ray0;
             S.ks[tid] = v.k_split;
@@ -262,17 +275,16 @@ __device__ __forceinline__ float gather_staged(StageLds& S, const Geo& G, const 
             auto view = [&](int cq) {
                 const int t = t0 + cq;
                 const ViewRec v = V[s0 + t];
-                const int cnt = S.cnt[t];
-                const TileView tv = S.tv[t];
-                const float kp = fmaf(tv.gx, dX, fmaf(tv.gy, dY, tv.kpc));
+                const float4 va = S.va[t], vb = S.vb[t];
+                const int4 vc = S.vc[t];
+                const int cnt = vc.y;
+                const float kp = fmaf(va.y, dX, fmaf(va.z, dY, va.x));
                 int x0, x1, y0, y1;
                 major_intervals(v, G.nch, x0, x1, y0, y1);
-                // slot bases: the part from k_split on sits behind the gap
-                const int bx = x0 == v.k_split ? S.kb[t] : S.k0[t];
-                const int by = y0 == v.k_split ? S.kb[t] : S.k0[t];
+                const int bx = vc.z, by = vc.w;
                 if (x0 < x1) {
                     int lo, hi;
-                    candidate_range(kp, tv.hwx, x0, x1, lo, hi);
+                    candidate_range_f(kp, va.w, vb.y, vb.z, lo, hi);
                     if (lo <= hi) {
                         if (cnt > 0)  // every window lies in the staged range (stage_range)
                             acc = add_window_padded(acc, lo, hi, fi, fj, LdsRead{S.geo[b][cq], S.w[b][cq], bx});
@@ -282,7 +294,7 @@ __device__ __forceinline__ float gather_staged(StageLds& S, const Geo& G, const 
                 }
                 if (y0 < y1) {
                     int lo, hi;
-                    candidate_range(kp, tv.hwy, y0, y1, lo, hi);
+                    candidate_range_f(kp, vb.x, vb.w, __int_as_float(vc.x), lo, hi);
                     if (lo <= hi) {
                         if (cnt > 0)
                             acc = add_window_padded(acc, lo, hi, fj, fi, LdsRead{S.geo[b][cq], S.w[b][cq], by});

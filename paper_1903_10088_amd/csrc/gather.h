@@ -135,6 +135,14 @@ __host__ __device__ __forceinline__ void candidate_range(float kp, float hw, int
     hi = (int)fhi;
 }
 
+// candidate_range with the channel interval given as floats [fa, fb] (a and
+// b - 1, exact for channel counts below 2^24): the same result.
+__host__ __device__ __forceinline__ void candidate_range_f(float kp, float hw, float fa, float fb, int& lo, int& hi)
+{
+    lo = (int)fmaxf(ceilf(kp - hw), fa);
+    hi = (int)fminf(floorf(kp + hw), fb);
+}
+
 // A pointer read from device memory is generic to the compiler (flat loads);
 // passing it through the global address space lets the loads be global ones.
 template <class T>
