@@ -56,6 +56,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=500,
                     help="sub-iterations of the oracle timed for the CPU baseline (0 = skip)")
     ap.add_argument("--time-iters", type=int, default=100, help="sub-iterations of the per-kernel timing pass")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="host threads of the oracle baseline (0 = all; 1 = the paper's single-CPU setting)")
     ap.add_argument("--fp-segments", type=int, default=0)
     ap.add_argument("--bp-variant", type=int, default=0, help="1 = global reads, 2 = LDS-staged (0 = default)")
     ap.add_argument("--cnn-batch", type=int, default=8,
@@ -154,6 +156,8 @@ def main():
         import oracle
 
         n_cpu = min(args.cpu_iters, args.iters)
+        if args.cpu_threads > 0:
+            oracle.set_threads(args.cpu_threads)
         log(f"bench: oracle on {oracle.num_threads()} host threads, {n_cpu} sub-iterations ...")
         t0 = time.perf_counter()
         ref, _ = oracle.os_iterate(g, M, args.beta, sl.counts, i0, None, n_cpu, want_trace=False)
