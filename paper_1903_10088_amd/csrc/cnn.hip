@@ -26,6 +26,7 @@
 // vector ALUs.  None of the path uses atomics.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -196,27 +197,14 @@ __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ 
     for (int q = 0; q < 4; ++q) dst[q] = u32x4{pk[4 * q], pk[4 * q + 1], pk[4 * q + 2], pk[4 * q + 3]};
 }
 
-// 32 -> 32 convolution on the matrix cores.  MODE 0 (forward): out =
-// bf(relu(conv(in, W) + bias)).  MODE 1 (dgrad): out = bf(conv(in, Wt) *
-// [mask > 0]) with Wt the flipped, transposed taps.  wts: [9][32 out][32 in]
-// bfloat16.
+// One 16x16 output tile of the 32 -> 32 convolution (stages its halo, then the MFMAs).
 template <int MODE>
-__global__ __launch_bounds__(256) void conv32_kernel(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wts,
-                                                     const float* __restrict__ bias, const uint16_t* __restrict__ mask,
-                                                     uint16_t* __restrict__ out, int n, int tiles_x,
-                                                     int tiles_per_img, int nblocks)
+__device__ __forceinline__ void conv32_tile(uint16_t (*s)[HALO][LDS_PIX], const bf16x8 (&A)[9][2],
+                                            const uint16_t* __restrict__ in, const float* __restrict__ bias,
+                                            const uint16_t* __restrict__ mask, uint16_t* __restrict__ out, int n,
+                                            Tile tl, int wave, int m, int g)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t s[HALO][HALO][LDS_PIX];
-    const Tile tl = tile_of(blockIdx.x, nblocks, tiles_x, tiles_per_img);
     load_halo(s, in, tl, n);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int m = lane & 15, g = lane >> 4;
-    // A operands: lane (m, g) holds W_tap[h*16 + m][8g .. 8g+7]
-    bf16x8 A[9][2];
-#pragma unroll
-    for (int tap = 0; tap < 9; ++tap)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) A[tap][h] = as_bf8(*(const u32x4*)(wts + ((tap * C) + h * 16 + m) * C + g * 8));
     __syncthreads();
     f32x4 acc[4][2];
 #pragma unroll
@@ -260,6 +248,45 @@ __global__ __launch_bounds__(256) void conv32_kernel(const uint16_t* __restrict_
             *(u32x2*)(out + base + o0) = u32x2{f2bf(v[0]) | (f2bf(v[1]) << 16), f2bf(v[2]) | (f2bf(v[3]) << 16)};
         }
     }
+}
+
+// 32 -> 32 convolution on the matrix cores.  MODE 0 (forward): out =
+// bf(relu(conv(in, W) + bias)).  MODE 1 (dgrad): out = bf(conv(in, Wt) *
+// [mask > 0]) with Wt the flipped, transposed taps.  wts: [9][32 out][32 in]
+// bfloat16.  Persistent: the weights are loaded into registers once per
+// block, which then takes tiles blockIdx.x, blockIdx.x + gridDim.x, ... of the
+// XCD-aware order (gridDim.x a multiple of 8 or equal to the tile count, so a
+// block's tiles stay on its own XCD).
+template <int MODE>
+__device__ __forceinline__ void conv32_body(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wts,
+                                            const float* __restrict__ bias, const uint16_t* __restrict__ mask,
+                                            uint16_t* __restrict__ out, int n, int tiles_x, int tiles_per_img,
+                                            int nblocks)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t s[HALO][HALO][LDS_PIX];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    // A operands: lane (m, g) holds W_tap[h*16 + m][8g .. 8g+7]
+    bf16x8 A[9][2];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) A[tap][h] = as_bf8(*(const u32x4*)(wts + ((tap * C) + h * 16 + m) * C + g * 8));
+    for (int v = blockIdx.x; v < nblocks; v += gridDim.x) {
+        if (v != (int)blockIdx.x) __syncthreads();  // the previous tile's reads of s are done
+        conv32_tile<MODE>(s, A, in, bias, mask, out, n, tile_of(v, nblocks, tiles_x, tiles_per_img), wave, m, g);
+    }
+}
+
+// Held to 4 waves per SIMD: with the weights in registers for the whole
+// persistent loop the compiler would otherwise settle on 3, and a whole
+// forward pass measured faster at 4 despite a few spilled registers.
+template <int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void conv32_kernel(
+    const uint16_t* __restrict__ in, const uint16_t* __restrict__ wts, const float* __restrict__ bias,
+    const uint16_t* __restrict__ mask, uint16_t* __restrict__ out, int n, int tiles_x, int tiles_per_img, int nblocks)
+{
+    conv32_body<MODE>(in, wts, bias, mask, out, n, tiles_x, tiles_per_img, nblocks);
 }
 
 // Layer 8 (32 -> 1): z = b8 + sum_tap sum_c w8 a7, y = x + z with x = mu / scale
@@ -768,13 +795,18 @@ hipError_t launch_prep(recon_cnn* c, hipStream_t s)
     return hipGetLastError();
 }
 
+// Blocks of the persistent 32 -> 32 convolution: as many as are resident at
+// once (256 CUs x 4), a multiple of 8.
+constexpr int CONV_GRID = 256 * 4;
+
 hipError_t launch_conv32(int mode, const uint16_t* in, const uint16_t* w, const float* bias, const uint16_t* mask,
                          uint16_t* out, const Shape& S, hipStream_t s)
 {
+    const int grid = std::min(S.ntiles, CONV_GRID);
     if (mode == 0)
-        conv32_kernel<0><<<S.ntiles, 256, 0, s>>>(in, w, bias, mask, out, S.n, S.tiles_x, S.tiles_per_img, S.ntiles);
+        conv32_kernel<0><<<grid, 256, 0, s>>>(in, w, bias, mask, out, S.n, S.tiles_x, S.tiles_per_img, S.ntiles);
     else
-        conv32_kernel<1><<<S.ntiles, 256, 0, s>>>(in, w, bias, mask, out, S.n, S.tiles_x, S.tiles_per_img, S.ntiles);
+        conv32_kernel<1><<<grid, 256, 0, s>>>(in, w, bias, mask, out, S.n, S.tiles_x, S.tiles_per_img, S.ntiles);
     return hipGetLastError();
 }
 
