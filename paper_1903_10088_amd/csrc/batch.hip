@@ -204,6 +204,7 @@ recon_status setup_batch(recon_batch_handle* b, int fp_segments)
 hipError_t enqueue_batch_subiter(recon_batch_handle* b, int s, int in, hipStream_t st)
 {
     hipError_t e = launch_fp_batch(b->fp_segments, b->d_slices, b->d_fp[s], b->n_fp[s], s, in, st);
+    if (e == hipSuccess) e = launch_step_batch(b->d_slices, (int)b->h.size(), s, in, rule_of(b->h[0]), st);
     if (e != hipSuccess) return e;
     return launch_bp_update_batch(b->bp_variant, b->d_slices, b->d_bp, b->n_bp, s, in, rule_of(b->h[0]), st);
 }

@@ -656,7 +656,8 @@ __device__ __forceinline__ void bp_update_tile(Geo G, const ViewRec* __restrict_
                                                const float* __restrict__ w, const double* __restrict__ part,
                                                const DevState* __restrict__ st_in, DevState* __restrict__ st_out,
                                                const float* __restrict__ img, float* __restrict__ img_out,
-                                               float* __restrict__ imgT_out, UpdateScalars sc, int ti0, int tj0)
+                                               float* __restrict__ imgT_out, UpdateScalars sc, int ti0, int tj0,
+                                               const DevState* __restrict__ st_pre)
 {
     __shared__ float s[TILE + 2][TILE + 3];
     __shared__ float t[TILE][TILE + 1];
@@ -683,11 +684,18 @@ __device__ __forceinline__ void bp_update_tile(Geo G, const ViewRec* __restrict_
         if (inside) gl = gather_global(G, V, rg, w, sc.q0, sc.nq, i, j);
     }
 
-    // step rule (needed only for the update, so its loads overlap other waves' gathers)
-    const double f = block_sum<256>(part, (sc.nrays + SQ_GROUP - 1) / SQ_GROUP, red) / (double)sc.nrays;
-    const DevState in = *st_in;
-    const StepDecision dec = step_rule(in, sc.rule, f);
-    if (ti0 == 0 && tj0 == 0 && threadIdx.x == 0) record_state(in, sc.rule, f, dec.lam, st_out);
+    // step rule (needed only for the update, so its loads overlap other waves' gathers),
+    // unless a step kernel has already taken it (st_pre: the new state)
+    StepDecision dec{0.0, false};
+    DevState in{};
+    if (st_pre) {
+        dec.lam = st_pre->lambda;
+    } else {
+        const double f = block_sum<256>(part, (sc.nrays + SQ_GROUP - 1) / SQ_GROUP, red) / (double)sc.nrays;
+        in = *st_in;
+        dec = step_rule(in, sc.rule, f);
+        if (ti0 == 0 && tj0 == 0 && threadIdx.x == 0) record_state(in, sc.rule, f, dec.lam, st_out);
+    }
     const float lam = (float)dec.lam;
 
     float mu_new = 0.0f;
@@ -712,7 +720,8 @@ __device__ __forceinline__ void bp_update_tile_blk(Geo G, const ViewRec* __restr
                                                    const double* __restrict__ part,
                                                    const DevState* __restrict__ st_in, DevState* __restrict__ st_out,
                                                    const float* __restrict__ img, float* __restrict__ img_out,
-                                                   float* __restrict__ imgT_out, UpdateScalars sc, int ti0, int tj0)
+                                                   float* __restrict__ imgT_out, UpdateScalars sc, int ti0, int tj0,
+                                                   const DevState* __restrict__ st_pre)
 {
     constexpr int NTH = 256 / (PX * PY);
     constexpr int BW = TILE / PX;  // pixel blocks per tile row
@@ -737,10 +746,16 @@ __device__ __forceinline__ void bp_update_tile_blk(Geo G, const ViewRec* __restr
     gather_block<PX, PY>(S, G, V, rg, w, sc.q0, sc.nq, i0, j0, i0 < G.n && j0 < G.n, acc, ti0,
                          tj0);  // has barriers
 
-    const double f = block_sum<NTH>(part, (sc.nrays + SQ_GROUP - 1) / SQ_GROUP, red) / (double)sc.nrays;
-    const DevState in = *st_in;
-    const StepDecision dec = step_rule(in, sc.rule, f);
-    if (ti0 == 0 && tj0 == 0 && tid == 0) record_state(in, sc.rule, f, dec.lam, st_out);
+    StepDecision dec{0.0, false};
+    DevState in{};
+    if (st_pre) {
+        dec.lam = st_pre->lambda;
+    } else {
+        const double f = block_sum<NTH>(part, (sc.nrays + SQ_GROUP - 1) / SQ_GROUP, red) / (double)sc.nrays;
+        in = *st_in;
+        dec = step_rule(in, sc.rule, f);
+        if (ti0 == 0 && tj0 == 0 && tid == 0) record_state(in, sc.rule, f, dec.lam, st_out);
+    }
     const float lam = (float)dec.lam;
 
 #pragma unroll
@@ -772,16 +787,16 @@ __device__ __forceinline__ void bp_update_any(Geo G, const ViewRec* __restrict__
                                               const float* __restrict__ w, const double* __restrict__ part,
                                               const DevState* __restrict__ st_in, DevState* __restrict__ st_out,
                                               const float* __restrict__ img, float* __restrict__ img_out,
-                                              float* __restrict__ imgT_out, UpdateScalars sc, int ti0, int tj0)
+                                              float* __restrict__ imgT_out, UpdateScalars sc, int ti0, int tj0,
+                                              const DevState* __restrict__ st_pre)
 {
-    if constexpr (VAR == 0) bp_update_tile<false>(G, V, rg, w, part, st_in, st_out, img, img_out, imgT_out, sc, ti0, tj0);
-    if constexpr (VAR == 1) bp_update_tile<true>(G, V, rg, w, part, st_in, st_out, img, img_out, imgT_out, sc, ti0, tj0);
-    if constexpr (VAR == 2)
-        bp_update_tile_blk<1, 2>(G, V, rg, w, part, st_in, st_out, img, img_out, imgT_out, sc, ti0, tj0);
-    if constexpr (VAR == 3)
-        bp_update_tile_blk<2, 1>(G, V, rg, w, part, st_in, st_out, img, img_out, imgT_out, sc, ti0, tj0);
-    if constexpr (VAR == 4)
-        bp_update_tile_blk<2, 2>(G, V, rg, w, part, st_in, st_out, img, img_out, imgT_out, sc, ti0, tj0);
+#define BP_TILE_ARGS G, V, rg, w, part, st_in, st_out, img, img_out, imgT_out, sc, ti0, tj0, st_pre
+    if constexpr (VAR == 0) bp_update_tile<false>(BP_TILE_ARGS);
+    if constexpr (VAR == 1) bp_update_tile<true>(BP_TILE_ARGS);
+    if constexpr (VAR == 2) bp_update_tile_blk<1, 2>(BP_TILE_ARGS);
+    if constexpr (VAR == 3) bp_update_tile_blk<2, 1>(BP_TILE_ARGS);
+    if constexpr (VAR == 4) bp_update_tile_blk<2, 2>(BP_TILE_ARGS);
+#undef BP_TILE_ARGS
 }
 
 constexpr int bp_threads(int var) { return var == 4 ? 64 : (var >= 2 ? 128 : 256); }
@@ -794,11 +809,27 @@ __global__ __launch_bounds__(bp_threads(VAR)) void bp_update_kernel(
     const float* __restrict__ img, float* __restrict__ img_out, float* __restrict__ imgT_out, UpdateScalars sc)
 {
     bp_update_any<VAR>(G, V, rg, w, part, st_in, st_out, img, img_out, imgT_out, sc, blockIdx.x * TILE,
-                       blockIdx.y * TILE);
+                       blockIdx.y * TILE, nullptr);
+}
+
+// The step rule of every slice of a batch, once per slice (block i: slice i):
+// the same fixed-order sum and rule as the update kernel's own, so the same
+// bits; writes the slice's state 1 - in, whose lambda the batched update reads.
+__global__ __launch_bounds__(256) void step_batch_kernel(const SliceDesc* __restrict__ slices, int s, int in,
+                                                         StepRule rule)
+{
+    __shared__ double red[4];
+    const SliceDesc* __restrict__ D = slices + blockIdx.x;
+    const int nrays = D->subs[s].y * D->geo.nch;
+    const double f = block_sum<256>(as_global(D->part), (nrays + SQ_GROUP - 1) / SQ_GROUP, red) / (double)nrays;
+    const DevState st = D->state[in];
+    const StepDecision dec = step_rule(st, rule, f);
+    if (threadIdx.x == 0) record_state(st, rule, f, dec.lam, D->state + (1 - in));
 }
 
 // A batch of slices: block b updates tile work[b] of slice work[b].slice with
-// that slice's subset s, reading image/state buffers `in` and writing 1 - in.
+// that slice's subset s and the step size step_batch_kernel left in state
+// 1 - in, reading image buffer `in` and writing 1 - in.
 template <int VAR>
 __global__ __launch_bounds__(bp_threads(VAR)) void bp_update_batch_kernel(const SliceDesc* __restrict__ slices,
                                                                           const BpWork* __restrict__ work, int s,
@@ -811,7 +842,8 @@ __global__ __launch_bounds__(bp_threads(VAR)) void bp_update_batch_kernel(const 
     const UpdateScalars sc{sq.x, sq.y, sq.y * D->geo.nch, rule, D->uc};
     bp_update_any<VAR>(D->geo, as_global(D->views), as_global(D->rg), as_global(D->w), as_global(D->part),
                        as_global(D->state + in), as_global(D->state + (1 - in)), as_global(D->img[in]),
-                       as_global(D->img[1 - in]), as_global(D->imgT[1 - in]), sc, wk.ti0, wk.tj0);
+                       as_global(D->img[1 - in]), as_global(D->imgT[1 - in]), sc, wk.ti0, wk.tj0,
+                       as_global(D->state + (1 - in)));
 }
 
 }  // namespace
@@ -853,6 +885,13 @@ hipError_t launch_bp_update_batch(int variant, const SliceDesc* slices, const Bp
     case 4: bp_update_batch_kernel<4><<<nblocks, bp_threads(4), 0, s>>>(slices, work, sub, in, rule); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_step_batch(const SliceDesc* slices, int n_slices, int sub, int in, StepRule rule, hipStream_t s)
+{
+    if (n_slices <= 0) return hipSuccess;
+    step_batch_kernel<<<n_slices, 256, 0, s>>>(slices, sub, in, rule);
     return hipGetLastError();
 }
 

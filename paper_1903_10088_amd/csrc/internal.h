@@ -277,6 +277,10 @@ struct UpdateArgs {
     UpdateConst uc;
 };
 hipError_t launch_bp_update(const Geo& geo, int variant, const UpdateArgs& a, hipStream_t s);
+// Batched sub-iteration after the projector: launch_step_batch takes every
+// slice's step rule once (state in -> state 1 - in), then the batched update
+// reads its step size from state 1 - in.
+hipError_t launch_step_batch(const SliceDesc* slices, int n_slices, int sub, int in, StepRule rule, hipStream_t s);
 hipError_t launch_bp_update_batch(int variant, const SliceDesc* slices, const BpWork* work, int nblocks, int sub,
                                   int in, StepRule rule, hipStream_t s);
 // kernels.hip, batched projector: block b projects rays [r0, r0 + 256/segments)
