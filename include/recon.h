@@ -238,8 +238,9 @@ recon_status recon_set_launch(recon_handle* h, int32_t fp_segments, int32_t bp_v
  * Batches of slices (the many slices of a helical scan, each with its own
  * image size, view count, channel count and I0).  All slices share the subset
  * count M, beta and params.  One sub-iteration of every slice runs as one
- * projector launch plus one update launch over a work table that covers all
- * slices; each subset epoch is replayed from a captured HIP graph.  Every
+ * projector launch, one step-rule launch (a block per slice) and one update
+ * launch over work tables that cover all slices; each subset epoch is
+ * replayed from a captured HIP graph.  Every
  * slice's result is bitwise equal to recon_os_iterate on that slice alone
  * (fresh state).
  * ------------------------------------------------------------------------ */

@@ -1,7 +1,7 @@
 // Batched reconstruction: many slices of different sizes (image size, views,
-// channels, I0) advance together, one projector launch and one update launch
-// per sub-iteration for the whole batch, each subset epoch replayed from a
-// captured HIP graph.
+// channels, I0) advance together, one projector launch, one step-rule launch
+// (a block per slice) and one update launch per sub-iteration for the whole
+// batch, each subset epoch replayed from a captured HIP graph.
 //
 // Work tables map thread blocks to (slice, ray block) for the projector and to
 // (slice, 16x16 tile) for the update.  Slices are placed on XCDs (the
