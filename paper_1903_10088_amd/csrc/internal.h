@@ -233,6 +233,9 @@ struct BatchCopyArgs {
     float* dst[BATCH_ARGS];
     int count;
 };
+// passed by value: keep well inside the 4 KB of kernel arguments
+static_assert(sizeof(BatchRunArgs) + sizeof(DevState) + 64 <= 4096, "batched layout arguments too large");
+static_assert(sizeof(BatchCopyArgs) + 64 <= 4096, "batched copy arguments too large");
 // Start of a batched run: counts -> yt, p; start image -> padded copies
 // (masked to the disc); state[0] = fresh with the slice's trace and it = 0.
 hipError_t launch_prepare_batch(const SliceDesc* slices, const BatchRunArgs& a, const DevState& fresh, hipStream_t s);
