@@ -46,6 +46,69 @@ def measured_traffic(kernel: str):
         return None
 
 
+TRAFFIC_SOURCES = {
+    # kernel record name: (name pattern in the counter files, sources it is built from)
+    "bp_update_kernel": ("bp_update_kernel<1>", ["paper_1903_10088_amd/csrc/bp.hip",
+                                                 "paper_1903_10088_amd/csrc/gather.h",
+                                                 "paper_1903_10088_amd/csrc/internal.h"]),
+    "fp_kernel<OS>": ("fp_kernel<16, true>", ["paper_1903_10088_amd/csrc/kernels.hip",
+                                              "paper_1903_10088_amd/csrc/gather.h",
+                                              "paper_1903_10088_amd/csrc/internal.h"]),
+}
+COUNTER_CMD = ("python3 <repo>/bench.py --steps 1 --warmup 0 --iters 40 --cpu-iters 0 --time-iters 0 "
+               "--cnn-batch 0 --warm-slices 0 --batch-slices 0")
+
+
+def summarize_counters(d: str, copy_mib: int = 256, out_path: str | None = None) -> dict:
+    """profiles/traffic_512x800.json from four rocprofv3 --pmc runs under d: pmc_FETCH_SIZE and
+    pmc_WRITE_SIZE of COUNTER_CMD, cal_FETCH_SIZE and cal_WRITE_SIZE of `--calibrate-copy
+    copy_mib` (each with its pmc_counter_collection.csv).  Each counter is averaged per dispatch
+    and scaled by bytes moved / counter reading of the plain copy."""
+    import collections
+    import csv
+    import hashlib
+
+    def agg(sub):
+        a = collections.defaultdict(list)
+        for r in csv.DictReader(open(os.path.join(d, sub, "pmc_counter_collection.csv"))):
+            a[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in a.items()}
+
+    def pick(a, pat):
+        ks = [k for k in a if pat in k]
+        if len(ks) != 1:
+            raise SystemExit(f"bench: {len(ks)} kernels match {pat!r} in the counter files")
+        return a[ks[0]]
+
+    f, w = agg("pmc_FETCH_SIZE"), agg("pmc_WRITE_SIZE")
+    cf = pick(agg("cal_FETCH_SIZE"), "copyBuffer")
+    cw = pick(agg("cal_WRITE_SIZE"), "copyBuffer")
+    copy_kib = copy_mib * 1024
+    ff, wf = copy_kib / cf, copy_kib / cw
+    kernels = {}
+    for name, (pat, src) in TRAFFIC_SOURCES.items():
+        h = hashlib.sha256()
+        for x in src:
+            h.update(open(os.path.join(ROOT, x), "rb").read())
+        kernels[name] = {"fetch_kib": pick(f, pat), "write_kib": pick(w, pat),
+                         "fetch_bytes": pick(f, pat) * 1024 * ff, "write_bytes": pick(w, pat) * 1024 * wf,
+                         "source_sha": h.hexdigest()[:16], "sources": src}
+    out = {"workload": "512x512, 800 views x 738 channels, 20 subsets (one subset per launch)",
+           "calibration": {"copy_mib": copy_mib, "fetch_kib_read": cf, "write_kib_read": cw,
+                           "fetch_factor": ff, "write_factor": wf},
+           "kernels": kernels,
+           "commands": [f"cd /tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o pmc -- {COUNTER_CMD}",
+                        f"cd /tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o pmc -- {COUNTER_CMD}",
+                        "cd /tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o pmc -- "
+                        f"python3 <repo>/bench.py --calibrate-copy {copy_mib}",
+                        "cd /tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o pmc -- "
+                        f"python3 <repo>/bench.py --calibrate-copy {copy_mib}",
+                        "python3 <repo>/bench.py --summarize-counters <dir>"]}
+    with open(out_path or os.path.join(ROOT, "profiles", "traffic_512x800.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,12 +130,18 @@ def main():
     ap.add_argument("--warm-slices", type=int, default=32,
                     help="full-study slices for the warm-start leg (0 = skip; needs trained weights)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1903_10088_amd", "weights", "warm_cnn.bin"))
+    ap.add_argument("--summarize-counters", default=None, metavar="DIR",
+                    help="write profiles/traffic_512x800.json from the counter runs under DIR (no GPU)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 10 plain device copies of MIB MiB (reference for HBM byte counters) and exit")
     args = ap.parse_args()
 
+    if args.summarize_counters:
+        rec = summarize_counters(args.summarize_counters)
+        print(json.dumps(rec["kernels"]))
+        return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (slices shard across GPUs with no "
+        print("bench.py measures one GPU: the library has no multi-GPU path (slices shard across GPUs with no "
               "exchange, so N GPUs would run N independent copies). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
