@@ -1,16 +1,17 @@
 // HIP kernels of the ordered-subset TV reconstruction for gfx950.
 //
-// Per sub-iteration the path is two launches:
+// Per sub-iteration of one slice the path is two launches:
 //   fp_kernel<OS>     Joseph forward projection of the subset (section 4.C
 //                     "reprojection") fused with the likelihood epilogue:
 //                     t = exp(-l), weighted residual w = (t - y/I0) * path,
 //                     squared difference e = (l - p)^2 (section 3.C.2);
 //                     (e summed in fixed groups of rays);
-//   bp_update_kernel  (bp.hip) fixed-order FP64 mean of e and the step rule of
-//                     Eqs. 4-5 in every block's prologue, gather backprojection
-//                     of w (the exact transpose of the projector, no atomics),
-//                     TV gradient from an LDS tile with a one-pixel halo, and
-//                     the update of Eq. 3.
+//   bp_update_kernel  (bp.hip) gather backprojection of w (the exact
+//                     transpose of the projector, no atomics), then in every
+//                     block the fixed-order FP64 mean of e and the step rule
+//                     of Eqs. 4-5, the TV gradient from an LDS tile with a
+//                     one-pixel halo, and the update of Eq. 3.
+// (Batches take the step rule once per slice in a launch of its own.)
 // None of these is a dense contraction: they are gather / stencil kernels
 // bound by the memory hierarchy and VALU, so no MFMA is used.
 #include <hip/hip_runtime.h>
@@ -258,8 +259,8 @@ __device__ __forceinline__ float chunk_sum(const float* __restrict__ img, uint32
 // OS mode: the epilogue writes the weighted residual of every ray and, for
 // every group of SQ_GROUP consecutive rays, the sum of their squared
 // differences (in ray order, FP64); blocks hold whole groups, so the sums do
-// not depend on SEG.  The step rule itself runs in the backprojector's
-// prologue.  (Finishing it in the projector's last block instead would need
+// not depend on SEG.  The step rule itself runs in the update kernel.
+// (Finishing it in the projector's last block instead would need
 // every block to write back its XCD's L2 before taking a ticket, which costs
 // more than it saves.)
 // rblock: first ray (within A's ray range) of this block's 256 / SEG rays.
