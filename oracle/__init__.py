@@ -137,6 +137,31 @@ def line_integrals(counts, i0: float) -> np.ndarray:
     return np.log(i0 / np.maximum(np.asarray(counts, np.float64), 1.0))
 
 
+def rebin_helical(geom, counts, i0: float, pitch_mm: float, z0_mm: float, z_slices) -> np.ndarray:
+    """Helical single-row fan data -> one full-turn fan sinogram per slice position, by 360-degree
+    linear interpolation along z (360LI, Kalender et al. 1990): for view v of a turn and slice z,
+    the two helical views at that angle whose source z brackets z are interpolated linearly in z.
+    Helical view h has angle start + 2 pi h / n_views and source z0 + pitch h / n_views.  The
+    interpolation runs on the measured line integrals ln(I0 / max(y, 1)); the result is returned
+    as counts I0 exp(-l), [n_slices][n_views][n_channels] float64, ready for the iterative method.
+    Raises ValueError when a slice lacks helical views on either side.  (The paper reconstructs
+    helical MVCT slices but does not state its rebinning; this is the textbook method.)"""
+    nv, nch = geom.n_views, geom.n_channels
+    ell = line_integrals(counts, i0).reshape(-1, nch)
+    nh = ell.shape[0]
+    v = np.arange(nv)
+    out = np.empty((len(z_slices), nv, nch))
+    for s, z in enumerate(z_slices):
+        q = (float(z) - z0_mm) / pitch_mm - v / nv  # turns since the first view at this angle
+        m = np.floor(q)
+        w = q - m  # (z - z_lower) / pitch
+        h = v + m.astype(np.int64) * nv
+        if h.min() < 0 or (h + nv).max() >= nh:
+            raise ValueError(f"slice z = {z} mm is not bracketed by the helical views")
+        out[s] = i0 * np.exp(-((1.0 - w)[:, None] * ell[h] + w[:, None] * ell[h + nv]))
+    return out
+
+
 def backproject(geom, sino, views=None) -> np.ndarray:
     """Exact transpose of project (weights in mm): [N][N]."""
     v, nv = _views(views)

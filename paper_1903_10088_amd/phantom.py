@@ -194,6 +194,65 @@ def analytic_sinogram(ellipses: list[Ellipse], g: Geometry) -> np.ndarray:
     return out
 
 
+# ---------------------------------------------------------------------------
+# Helical acquisition (single-row fan beam, as on a helical tomotherapy unit)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass(frozen=True)
+class Ellipsoid:
+    """An ellipse in the (x, y) plane extruded along z: semi-axis c in z (math.inf: a cylinder);
+    the cross-section at z has semi-axes a r and b r with r = sqrt(1 - ((z - cz) / c)^2), and the
+    value value + dvalue_dz (z - cz)."""
+    cx: float
+    cy: float
+    cz: float
+    a: float
+    b: float
+    c: float
+    phi: float
+    value: float
+    dvalue_dz: float = 0.0
+
+    def section(self, z: float) -> Ellipse | None:
+        t = 0.0 if math.isinf(self.c) else (z - self.cz) / self.c
+        if abs(t) >= 1.0:
+            return None
+        r = math.sqrt(1.0 - t * t)
+        return Ellipse(self.cx, self.cy, self.a * r, self.b * r, self.phi, self.value + self.dvalue_dz * (z - self.cz))
+
+
+def helical_view_z(g: Geometry, n_helical: int, pitch_mm: float, z0_mm: float) -> np.ndarray:
+    """Source z of helical view h: z0 + pitch h / n_views (the table advances `pitch` per turn)."""
+    return z0_mm + pitch_mm * np.arange(n_helical) / g.n_views
+
+
+def helical_line_integrals(ellipsoids: list[Ellipsoid], g: Geometry, n_helical: int, pitch_mm: float,
+                           z0_mm: float) -> np.ndarray:
+    """Exact line integrals of a helical scan, [n_helical][n_channels] (float64): view h is the
+    fan of geometry g at angle start + 2 pi h / n_views, in the plane z = helical_view_z(h), and
+    sees the cross-sections of the ellipsoids there."""
+    zs = helical_view_z(g, n_helical, pitch_mm, z0_mm)
+    out = np.zeros((n_helical, g.n_channels))
+    for h, z in enumerate(zs):
+        gv = dataclasses.replace(g, n_views=1, start_angle_rad=g.start_angle_rad + 2 * math.pi * h / g.n_views)
+        sec = [e for e in (q.section(float(z)) for q in ellipsoids) if e is not None]
+        if sec:
+            out[h] = analytic_sinogram(sec, gv)[0]
+    return out
+
+
+def random_helical_phantom(seed: int, *, scale: float = 1.0, length_mm: float = 60.0) -> list[Ellipsoid]:
+    """Seeded helical phantom: random_phantom's body as a cylinder, its inserts as ellipsoids
+    centred at U(-length/4, length/4) mm with z semi-axes U(10, length/2) mm."""
+    rng = np.random.default_rng([seed, 7])
+    ell = random_phantom(seed, low_contrast=True, scale=scale)
+    out = [Ellipsoid(ell[0].cx, ell[0].cy, 0.0, ell[0].a, ell[0].b, math.inf, ell[0].phi, ell[0].value)]
+    for e in ell[1:]:
+        out.append(Ellipsoid(e.cx, e.cy, rng.uniform(-0.25, 0.25) * length_mm, e.a, e.b,
+                             rng.uniform(10.0, 0.5 * length_mm), e.phi, e.value))
+    return out
+
+
 def poisson_counts(line_integrals: np.ndarray, i0: float, seed: int) -> np.ndarray:
     """Transmission counts y ~ Poisson(I0 exp(-l)), float32 (exact integers)."""
     rng = np.random.default_rng([seed, 1])
