@@ -130,6 +130,8 @@ def main():
     ap.add_argument("--warm-slices", type=int, default=32,
                     help="full-study slices for the warm-start leg (0 = skip; needs trained weights)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1903_10088_amd", "weights", "warm_cnn.bin"))
+    ap.add_argument("--rebin-slices", type=int, default=16,
+                    help="slices of the helical-rebinning leg (0 = skip)")
     ap.add_argument("--summarize-counters", default=None, metavar="DIR",
                     help="write profiles/traffic_512x800.json from the counter runs under DIR (no GPU)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -243,6 +245,7 @@ def main():
         log(f"bench: cpu {cpu['value']:.4f} slices/s; GPU vs oracle rmse after {n_cpu} sub-iterations {rmse:.2e}")
 
     fbp = fbp_leg(R, counts, sl.i0)
+    rebin = rebin_leg(args.rebin_slices, dev) if args.rebin_slices > 0 else None
     batch = batch_leg(args.batch_slices, args.iters, dev) if args.batch_slices > 0 else None
     cnn = cnn_leg(args.cnn_batch, dev) if args.cnn_batch > 0 else None
     warm = warm_leg(args.warm_slices, args.weights, dev) if args.warm_slices > 0 else None
@@ -275,6 +278,7 @@ def main():
                       "graph_sub_iteration": sub_ms * 1e3},
         "parity": parity,
         "fbp_baseline": fbp,
+        "helical_rebin": rebin,
         "batched_plain": batch,
         "cnn_kernels": cnn,
         "warm_start": warm,
@@ -339,6 +343,41 @@ def batch_leg(n_slices: int, iters: int, dev):
 
 
 PEAK_BF16_TFLOPS = 2500.0  # dense bf16 matrix-core peak
+
+
+def rebin_leg(n_slices: int, dev):
+    """Helical rebinning (recon_rebin_helical) of a 3-turn single-row scan of 800 views x 738
+    channels per turn (pitch 10 mm) to n_slices slices: HBM rate of the kernel from 8 bytes read
+    and 4 written per output element, mean over 20 calls (CUDA events on the library's stream)."""
+    import numpy as np
+    import torch
+
+    from paper_1903_10088_amd import phantom as ph
+    from paper_1903_10088_amd import recon
+
+    g = ph.config1_geometry()
+    nh, pitch, z0 = 3 * g.n_views, 10.0, -15.0
+    rng = np.random.default_rng(9)
+    counts = torch.from_numpy(rng.poisson(2000.0 * np.exp(-rng.uniform(0, 3, (nh, g.n_channels))))
+                              .astype(np.float32)).to(dev)
+    lo = z0 + pitch * (g.n_views - 1) / g.n_views + 1e-6
+    hi = z0 + pitch * (nh - g.n_views) / g.n_views - 1e-6
+    zs = list(np.linspace(lo, hi, n_slices))
+    out = recon.rebin_helical(g, counts, 2e3, pitch, z0, zs)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        recon.rebin_helical(g, counts, 2e3, pitch, z0, zs, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 20
+    nbytes = 12.0 * n_slices * g.n_views * g.n_channels
+    gbps = nbytes / (ms * 1e-3) / 1e9
+    log(f"bench: helical rebinning {ms * 1e3:.1f} us for {n_slices} slices ({gbps:.0f} GB/s, "
+        f"{gbps / PEAK_HBM_GBPS:.2f} of HBM peak)")
+    return {"slices": n_slices, "views": g.n_views, "channels": g.n_channels, "helical_views": nh,
+            "us": ms * 1e3, "gbps": gbps, "frac_of_hbm_peak": gbps / PEAK_HBM_GBPS,
+            "bytes_per_output": 12}
 
 
 def cnn_leg(batch: int, dev):

@@ -209,6 +209,30 @@ recon_status recon_initial_image(recon_handle* h, float* d_img, void* stream);
  * RECON_INVALID_ARG for more than 16384 channels. */
 recon_status recon_fbp(recon_handle* h, const float* d_counts, float i0, float* d_img, void* stream);
 
+/* Helical rebinning: single-row helical fan data (a helical tomotherapy MVCT
+ * scan, section 1) -> one full-turn fan sinogram per slice position, by
+ * 360-degree linear interpolation along z (the textbook 360LI method; the
+ * paper reconstructs helical MVCT slices but does not state its rebinning).
+ * g: the geometry of one turn (n_views views per turn, n_channels channels;
+ * the other fields are not used).  Helical view h (0 <= h < n_helical_views)
+ * has the angle of view h mod n_views and source z = z0_mm + pitch_mm h /
+ * n_views (pitch_mm: table feed per turn, > 0).  For slice z and view v the
+ * two helical views at that angle whose z bracket z (z_a <= z < z_b) are
+ * interpolated with weight w = (z - z_a) / pitch on the measured line
+ * integrals l = ln(I0 / max(y, 1)), and the result is written as counts
+ * I0 exp(-l), the input form of recon_os_iterate (I0 cancels: the value is
+ * y0^(1-w) y1^w with y0, y1 the bracketing counts floored at 1; i0 is
+ * validated only).  Bracket, weight and interpolation are in double precision.
+ * d_counts: device float [n_helical_views][n_channels]; z_slices: host
+ * double [n_slices] (mm); d_out: device float [n_slices][n_views][n_channels],
+ * overwritten.  RECON_INVALID_ARG for NULL buffers, non-positive sizes, pitch
+ * or I0, or a slice outside [z0 + pitch (n_views - 1) / n_views,
+ * z0 + pitch (n_helical_views - n_views) / n_views) (no helical view on one
+ * side); nothing is launched then.  n_slices = 0 does nothing. */
+recon_status recon_rebin_helical(const recon_geometry* g, int32_t n_helical_views, double pitch_mm, double z0_mm,
+                                 const float* d_counts, float i0, const double* z_slices, int32_t n_slices,
+                                 float* d_out, void* stream);
+
 /* Data consistency of an image against the counts of all views:
  *   d_out[0] = mean over every ray of (l_i - p_i)^2, l = A mu (d_img, 1/mm),
  *              p = ln(I0 / max(y, 1))  (the squared difference of section

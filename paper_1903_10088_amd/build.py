@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB_PATH = os.path.join(HERE, "librecon.so")
-SOURCES = ["kernels.hip", "bp.hip", "api.hip", "batch.hip", "cnn.hip", "fbp.hip"]
+SOURCES = ["kernels.hip", "bp.hip", "api.hip", "batch.hip", "cnn.hip", "fbp.hip", "rebin.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -54,7 +54,7 @@ EXPORTS = ["recon_default_params", "recon_status_string", "recon_last_error", "r
            "recon_cnn_param_count", "recon_cnn_create", "recon_cnn_destroy", "recon_cnn_get_state",
            "recon_cnn_set_state", "recon_cnn_save", "recon_cnn_load", "recon_cnn_forward", "recon_cnn_loss_grad",
            "recon_cnn_adam_step", "recon_cnn_train_step", "recon_cnn_tensor", "recon_cnn_time_kernels",
-           "recon_data_residual", "recon_warm_start", "recon_fbp"]
+           "recon_data_residual", "recon_warm_start", "recon_fbp", "recon_rebin_helical"]
 
 _lib = None
 
@@ -82,6 +82,7 @@ def lib():
         L.recon_os_iterate.argtypes = [vp, vp, f, vp, i32, P(State_c), vp, vp, vp]
         L.recon_os_iterate_ex.argtypes = [vp, vp, f, vp, i32, P(State_c), vp, vp, vp, vp, vp]
         L.recon_fbp.argtypes = [vp, vp, f, vp, vp]
+        L.recon_rebin_helical.argtypes = [P(Geometry_c), i32, d, d, vp, f, P(d), i32, vp, vp]
         L.recon_initial_image.argtypes = [vp, vp, vp]
         L.recon_subset_size.argtypes = [vp, i32, P(i32)]
         L.recon_set_launch.argtypes = [vp, i32, i32]
@@ -332,6 +333,26 @@ class Recon:
                                          _ptr(best, torch.float32, (g.n, g.n), "best"), _stream()),
                "recon_os_iterate_ex")
         return img, tr
+
+
+def rebin_helical(geometry, counts, i0: float, pitch_mm: float, z0_mm: float, z_slices, out=None):
+    """recon_rebin_helical: helical single-row counts [n_helical][n_channels] (float32 CUDA tensor;
+    view h at the angle of view h mod n_views of `geometry`, source z0 + pitch h / n_views) ->
+    per-slice full-turn counts [len(z_slices)][n_views][n_channels] by 360-degree linear
+    interpolation along z."""
+    torch = _torch()
+    g = geometry
+    nh = int(counts.shape[0])
+    zs = [float(z) for z in z_slices]
+    if out is None:
+        out = torch.empty((len(zs), g.n_views, g.n_channels), dtype=torch.float32, device=counts.device)
+    za = (ctypes.c_double * max(1, len(zs)))(*zs)
+    gc = geometry_c(g)
+    _check(lib().recon_rebin_helical(ctypes.byref(gc), nh, float(pitch_mm), float(z0_mm),
+                                     _ptr(counts, torch.float32, (nh, g.n_channels), "counts"), float(i0), za, len(zs),
+                                     _ptr(out, torch.float32, (len(zs), g.n_views, g.n_channels), "out"), _stream()),
+           "recon_rebin_helical")
+    return out
 
 
 def _ptr_array(tensors, dtype, shapes, name):

@@ -157,3 +157,31 @@ def test_abi_struct_sizes():
     assert ctypes.sizeof(recon.Params_c) == 56
     assert ctypes.sizeof(recon.State_c) == 48
     assert recon.State_c.best_n.offset == 40
+
+
+def test_rebin_validates_before_the_device():
+    """recon_rebin_helical refuses bad sizes, pitch, I0 and unbracketed slices before any launch
+    (the buffer addresses below are never touched)."""
+    L = recon.lib()
+    g = recon.geometry_c(ph.Geometry(n=64, pixel_mm=6.25, n_views=36, n_channels=48))
+    fake = ctypes.c_void_p(0x1000)
+
+    def call(nh=108, pitch=20.0, z0=-30.0, i0=1e4, zs=(0.0,), counts=fake, out=fake, n=None):
+        za = (ctypes.c_double * max(1, len(zs)))(*zs)
+        return L.recon_rebin_helical(ctypes.byref(g), nh, pitch, z0, counts, i0, za, len(zs) if n is None else n,
+                                     out, None)
+
+    bad = recon.RECON_INVALID_ARG
+    assert call(nh=36) == bad  # one turn only
+    assert call(pitch=0.0) == bad
+    assert call(pitch=float("nan")) == bad
+    assert call(i0=0.0) == bad
+    assert call(counts=None) == bad
+    assert call(out=None) == bad
+    assert call(n=-1) == bad
+    assert call(zs=(), n=0) == recon.RECON_OK  # nothing to do
+    lo = -30.0 + 20.0 * 35 / 36
+    hi = -30.0 + 20.0 * (108 - 36) / 36  # exclusive
+    assert call(zs=(lo - 1e-6,)) == bad
+    assert call(zs=(0.0, hi + 1e-6)) == bad
+    assert call(zs=(float("inf"),)) == bad
