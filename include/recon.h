@@ -298,7 +298,9 @@ recon_status recon_batch_run(recon_batch_handle* b, const float* const* d_counts
 recon_status recon_batch_tune(recon_batch_handle* b, const float* const* d_counts, const float* i0, float* const* d_imgs,
                               int32_t reps, int32_t* fp_segments_out, int32_t* bp_variant_out, void* stream);
 
-/* Pins the batch's launch shapes (as recon_set_launch; 0 keeps). */
+/* Pins the batch's launch shapes (as recon_set_launch; 0 keeps).  A new batch
+ * starts with 4 threads per projector ray and bp_variant 3 (1x2 pixels per
+ * thread), the tuner's choice for batches of 512^2 slices. */
 recon_status recon_batch_set_launch(recon_batch_handle* b, int32_t fp_segments, int32_t bp_variant);
 
 /* One-shot form: create, run n_iter sub-iterations, wait, destroy. */

@@ -26,13 +26,18 @@
 
 using namespace recon;
 
+constexpr int BATCH_FP_SEGMENTS = 4;
+
 struct recon_batch_handle {
     std::vector<recon_handle*> h;  // one handle (tables + workspace) per slice
     bool owns = true;              // destroy the handles with the batch
     int M = 1;
     int last_in = 0;               // image / state buffer holding the last run's result
-    int fp_segments = 8;
-    int bp_variant = 1;
+    // launch shapes until recon_batch_tune or recon_batch_set_launch: what the
+    // tuner picks for batches of 512^2 slices (4 threads per projector ray, the
+    // 1x2-pixel staged update); results are identical for every choice
+    int fp_segments = BATCH_FP_SEGMENTS;
+    int bp_variant = 2;
     std::vector<int> xcd;  // XCD of each slice
 
     SliceDesc* d_slices = nullptr;
@@ -160,11 +165,11 @@ recon_status upload_work(recon_batch_handle* b)
 }
 
 // Slice descriptors, subset tables, XCD placement and work tables of a batch
-// whose handles are in b->h; fp_segments 0 takes the first handle's default.
+// whose handles are in b->h; fp_segments 0 takes the batch default.
 recon_status setup_batch(recon_batch_handle* b, int fp_segments)
 {
     const int n_slices = (int)b->h.size(), subsets = b->M;
-    b->fp_segments = fp_segments > 0 ? fp_segments : b->h[0]->fp_segments;
+    b->fp_segments = fp_segments > 0 ? fp_segments : BATCH_FP_SEGMENTS;
     assign_xcds(b);
     std::vector<int2> subs((size_t)n_slices * subsets);
     for (int i = 0; i < n_slices; ++i)
