@@ -9,10 +9,11 @@
 //
 // One thread per output element, consecutive threads on consecutive channels
 // (coalesced reads of the two bracketing rows and the write), up to 64 slices
-// per launch.  Bound by HBM traffic: 12 bytes per output element.  The
-// bracket, weight and the interpolation, written as y0 exp(w ln(y1 / y0)) (the
-// same value as the line-integral form, one logarithm instead of two), are in
-// double precision.
+// per launch; 12 bytes of HBM traffic per output element.  The bracket,
+// weight and the interpolation, written as y0 exp(w ln(y1 / y0)) (the same
+// value as the line-integral form, one logarithm instead of two), are in
+// double precision, whose logarithm, exponential and divisions make the
+// kernel ALU-bound rather than HBM-bound.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,10 +36,10 @@ struct RebinSlices {
 __global__ __launch_bounds__(256) void rebin_kernel(const float* __restrict__ counts, int nv, int nch, int nh,
                                                     RebinSlices sl, float* __restrict__ out)
 {
-    const long per = (long)nv * nch;
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int per = nv * nch;  // < 2^31 (checked on the host)
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= per) return;
-    const int v = (int)(idx / nch), k = (int)(idx - (long)v * nch);
+    const int v = idx / nch, k = idx - v * nch;
     const double q = sl.q0[blockIdx.y] - (double)v / nv;  // turns since the first helical view at this angle
     const double m = floor(q);
     const double w = q - m;  // (z - z_lower) / pitch
