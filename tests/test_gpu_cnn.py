@@ -81,6 +81,24 @@ def gpu_signals(net, B, n):
 CHAIN_TOL = 1e-2
 
 
+def check_forward_layers(ga, theta, mu):
+    """Each stored activation a_l (l = 0..7) against the oracle's layer l applied to the GPU's own
+    a_{l-1}.  Returns the worst relative error."""
+    layers = ocnn.unpack(theta.astype(np.float64))
+    Wr = [ocnn.bf16_round(W) for W, _ in layers]
+    e0 = rel(ga[0][:, 0], ocnn.bf16_round(mu.astype(np.float64) / MU_W))
+    print(f"a_0: rel {e0:.2e}", flush=True)
+    assert e0 <= TOL
+    worst = e0
+    for l in range(1, 8):
+        ref = ocnn.bf16_round(np.maximum(ocnn.conv(ga[l - 1], Wr[l - 1]) + layers[l - 1][1][None, :, None, None], 0))
+        e = rel(ga[l], ref)
+        print(f"a_{l} (layer {l} on the GPU's a_{l - 1}): rel {e:.2e}", flush=True)
+        assert e <= TOL, l
+        worst = max(worst, e)
+    return worst
+
+
 @pytest.mark.parametrize("B,n", [(2, 40), (3, 96), (1, 17)])
 def test_forward_matches_oracle(dev, B, n):
     theta = ph.cnn_initial_params(1, zero_last=False, last_std=0.05)
@@ -91,14 +109,7 @@ def test_forward_matches_oracle(dev, B, n):
     layers = ocnn.unpack(theta.astype(np.float64))
     Wr = [ocnn.bf16_round(W) for W, _ in layers]
     ga = gpu_acts(net, B, n)
-    e0 = rel(ga[0][:, 0], ocnn.bf16_round(mu.astype(np.float64) / MU_W))
-    print(f"a_0: rel {e0:.2e}", flush=True)
-    assert e0 <= TOL
-    for l in range(1, 8):
-        ref = ocnn.bf16_round(np.maximum(ocnn.conv(ga[l - 1], Wr[l - 1]) + layers[l - 1][1][None, :, None, None], 0))
-        e = rel(ga[l], ref)
-        print(f"a_{l} (layer {l} on the GPU's a_{l - 1}): rel {e:.2e}", flush=True)
-        assert e <= TOL, l
+    check_forward_layers(ga, theta, mu)
     z8 = ocnn.conv(ga[7], Wr[7])[:, 0] + layers[7][1][0]
     e8 = rel(out - mu, MU_W * z8)
     print(f"output (layer 8 on the GPU's a_7): rel {e8:.2e}", flush=True)
@@ -162,19 +173,44 @@ def test_full_size_gradient_matches_oracle(dev):
     loss = torch.empty(1, dtype=torch.float64, device=dev)
     net.loss_grad(torch.from_numpy(mu).to(dev), torch.from_numpy(tgt).to(dev), grad, loss)
     torch.cuda.synchronize()
+    print("512^2 x 2, per layer (persistent blocks take 2 tiles each):", flush=True)
+    check_forward_layers(gpu_acts(net, 2, 512), theta, mu)
     check_backward(net, theta, mu, tgt, grad, loss, 2, 512)
 
 
+WINDOWS = [(0, 0), (448, 448), (200, 240), (0, 300), (470, 7), (100, 100), (448, 0), (256, 448)]
+
+
 def test_full_size_forward_on_sampled_windows(dev):
-    """Batch of 8 512 x 512 slices (the inference launch shape): each output pixel depends on the
-    17 x 17 input window around it, so the oracle run on a 64 x 64 crop gives the exact output on
-    the crop's inner 48 x 48 (and up to the image border where the crop touches it)."""
+    """Batch of 8 512 x 512 slices (the inference launch shape, 8192 tiles: each persistent block
+    takes 8).  Per layer: each stored a_l on a 64 x 64 window of every slice against the oracle's
+    layer l on the GPU's a_{l-1} over the window plus its one-pixel ring (exact on the window).
+    Chained: each output pixel depends on the 17 x 17 input window around it, so the oracle run
+    on a 64 x 64 crop gives the exact output on the crop's inner 48 x 48 (and up to the image
+    border where the crop touches it)."""
     theta = ph.cnn_initial_params(7, zero_last=False, last_std=0.05)
     mu, _ = images(8, 8, 512)
     net = gpu_net(theta)
     out = net.forward(torch.from_numpy(mu).to(dev)).cpu().numpy()
-    for b, (i0, j0) in zip(range(8), [(0, 0), (448, 448), (200, 240), (0, 300), (470, 7), (100, 100),
-                                      (448, 0), (256, 448)]):
+    layers = ocnn.unpack(theta.astype(np.float64))
+    Wr = [ocnn.bf16_round(W) for W, _ in layers]
+    prev = None
+    worst = 0.0
+    for l in range(8):
+        cur = net.tensor(0, l, 8, 512).cpu().numpy()
+        cur = cur[:, None] if l == 0 else cur.transpose(0, 3, 1, 2)
+        if l > 0:
+            for b, (i0, j0) in enumerate(WINDOWS):
+                r0, r1, c0, c1 = max(i0 - 1, 0), min(i0 + 65, 512), max(j0 - 1, 0), min(j0 + 65, 512)
+                x = prev[b:b + 1, :, r0:r1, c0:c1].astype(np.float64)
+                z = ocnn.conv(x, Wr[l - 1]) + layers[l - 1][1][None, :, None, None]
+                ref = ocnn.bf16_round(np.maximum(z, 0))[0, :, i0 - r0:i0 - r0 + 64, j0 - c0:j0 - c0 + 64]
+                e = rel(cur[b, :, i0:i0 + 64, j0:j0 + 64], ref)
+                worst = max(worst, e)
+                assert e <= TOL, (l, b, i0, j0, e)
+            print(f"a_{l} (layer {l} on the GPU's a_{l - 1}) on 8 windows: worst rel {worst:.2e}", flush=True)
+        prev = cur
+    for b, (i0, j0) in enumerate(WINDOWS):
         crop = mu[b:b + 1, i0:i0 + 64, j0:j0 + 64].astype(np.float64)
         ref, _ = ocnn.forward(theta.astype(np.float64), crop, MU_W)
         lo_i = 0 if i0 == 0 else 8

@@ -2,9 +2,9 @@
 
 Bar: image RMSE over the reconstruction disc <= 1e-4 * mu_water (4.9e-7 / mm)
 after the full iteration count, the GPU taking its own step-rule decisions; the
-lambda trace is compared too.  Should a decision differ, the same comparison is
-repeated on a replay of the oracle's lambda schedule and the difference is
-reported.
+lambda traces must be equal (a differing decision is tolerated only at a
+near-tie of the oracle's own comparison, and then judged on a replay of the
+oracle's schedule).
 """
 import numpy as np
 import pytest
@@ -45,16 +45,26 @@ def disc_rmse(g, a, b):
 
 
 def check_parity(dev, g, M, beta, sl, n_iter, label):
+    """GPU run (own step-rule decisions) against the oracle.  The lambda traces must be equal; a
+    differing decision is accepted only where the oracle's own comparison was a near-tie, i.e.
+    its relative margin |f_n - f_ref| / f_n at the first differing sub-iteration is below the
+    GPU-vs-oracle agreement of f (FP32 line integrals), and the run is then judged on a replay of
+    the oracle's schedule, as the tolerances allow.  Anything else fails and names the first
+    differing sub-iteration."""
     print(f"os_iterate parity {label}: n={g.n} views={g.n_views} M={M} beta={beta} iters={n_iter}", flush=True)
     img, tr, ref, rtr = run_both(dev, g, M, beta, sl, n_iter)
     same = np.array_equal(tr[:, 1], rtr[:, 1])
     if not same:
         first = int(np.argmax(tr[:, 1] != rtr[:, 1]))
-        print(f"  lambda decision differs first at sub-iteration {first}; replaying the oracle's schedule")
+        margin = abs(rtr[first, 0] - rtr[first - 1, 0]) / rtr[first, 0] if first > 0 else np.inf
+        fdiff = np.max(np.abs(tr[:first + 1, 0] - rtr[:first + 1, 0]) / rtr[:first + 1, 0])
+        print(f"  lambda decision differs first at sub-iteration {first}: oracle margin {margin:.2e}, "
+              f"f agreement up to there {fdiff:.2e}", flush=True)
+        assert margin <= max(10 * fdiff, 1e-6), f"lambda schedule diverges at sub-iteration {first}"
         img, tr, ref, rtr = run_both(dev, g, M, beta, sl, n_iter, schedule=rtr[:, 1].copy())
     rmse = disc_rmse(g, img, ref)
     frel = np.max(np.abs(tr[:, 0] - rtr[:, 0]) / rtr[:, 0])
-    print(f"  rmse {rmse:.3e} (tol {RMSE_TOL:.2e}), max rel f diff {frel:.2e}, same lambda: {same}")
+    print(f"  rmse {rmse:.3e} (tol {RMSE_TOL:.2e}), max rel f diff {frel:.2e}, same lambda: {same}", flush=True)
     assert rmse <= RMSE_TOL
     assert frel <= 1e-4
     return same
@@ -81,18 +91,14 @@ def test_degenerate_subsets(dev, M, n_iter):
     check_parity(dev, g, M, 1e-3, sl, n_iter, f"odd geometry M={M}")
 
 
-@pytest.mark.parametrize("beta", [3e-4, 1e-3, 3e-3])
-def test_config1_beta_sweep_three_epochs(dev, beta):
-    g = ph.config1_geometry()
-    sl = ph.make_slice(g, 100, 2e3, low_contrast=True)
-    check_parity(dev, g, 20, beta, sl, 60, "config1 3 epochs")
-
-
 @pytest.mark.timeout(900)
-def test_config1_full_500(dev):
+@pytest.mark.parametrize("beta", [3e-4, 1e-3, 3e-3])
+def test_config1_full_500(dev, beta):
+    """The clinical-scale slice over its full 500 sub-iterations for every TV weight of the sweep
+    (the weight sets the TV curvature 8 beta / (M eps), where step-rule branches would part)."""
     g = ph.config1_geometry()
     sl = ph.make_slice(g, 100, 2e3, low_contrast=True)
-    check_parity(dev, g, 20, 1e-3, sl, 500, "config1 full")
+    check_parity(dev, g, 20, beta, sl, 500, f"config1 full beta={beta}")
 
 
 def test_resume_is_bitwise_and_deterministic(dev):
@@ -129,15 +135,14 @@ def test_launch_shapes_give_identical_bits(dev, name):
     ref = None
     shapes = [(seg, 2) for seg in (1, 2, 4, 8, 16)] + [(8, bpv) for bpv in (1, 3, 4, 5)]
     for seg, bpv in shapes:
-        if True:
-            print(f"{name}: fp_segments={seg} bp_variant={bpv}", flush=True)
-            R.set_launch(fp_segments=seg, bp_variant=bpv)
-            img, tr = R.os_iterate(counts, sl.i0, None, n, trace=True)
-            if ref is None:
-                ref = (img.clone(), tr.clone())
-            else:
-                assert torch.equal(img, ref[0]), (seg, bpv)
-                assert torch.equal(tr, ref[1]), (seg, bpv)
+        print(f"{name}: fp_segments={seg} bp_variant={bpv}", flush=True)
+        R.set_launch(fp_segments=seg, bp_variant=bpv)
+        img, tr = R.os_iterate(counts, sl.i0, None, n, trace=True)
+        if ref is None:
+            ref = (img.clone(), tr.clone())
+        else:
+            assert torch.equal(img, ref[0]), (seg, bpv)
+            assert torch.equal(tr, ref[1]), (seg, bpv)
 
 
 def test_start_image_is_held_at_zero_outside_the_disc(dev):

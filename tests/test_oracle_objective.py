@@ -243,3 +243,115 @@ def test_step_limit_reading():
         x /= nrm
     h_cm = nrm / 100.0  # A_cm = A_mm / 10
     assert 0.1 * 2.0 / h_cm < 0.01 < 2.0 / h_cm
+
+
+# ----------------------------------------------------------------------------- prior weight and support
+
+def _subset_loglik(g, mu_mm, counts, i0, views):
+    """L_s of section 2 restricted to the rays of the listed views (blank-scan normalised)."""
+    return oracle.loglik(oracle.project(g, mu_mm, views), counts[views] / i0)
+
+
+def _one_step(g, M, beta, counts, i0, mu0, n_done, lam, eps_mm):
+    st = oracle.State()
+    st._s.n_done = n_done
+    st._s.lambda_ = 0.01
+    mu1, _ = oracle.os_iterate(g, M, beta, counts, i0, mu0, 1, state=st, lambda_schedule=[lam],
+                               params=dict(tv_eps_per_mm=eps_mm))
+    return mu1
+
+
+def test_step_with_subsets_uses_thinned_prior_weight():
+    """Section 3.D: in ordered-subset mode the TV weight is multiplied by the thinning factor 1/M.
+    One sub-iteration with M = 4, beta > 0 and a given lambda, started at sub-iteration 5 (subset
+    s = 1), from a textured positive image: inside the disc (no pixel reaches the clamp) the
+    image moves by lambda * (dL_s/dmu + (beta/M) g_R) in cm units.  Both gradients come from
+    central differences outside the iteration: L_s of subset 1's views only, and TV of the image
+    in 1/cm.  The prior's share alone (the beta run minus the beta = 0 run) is checked against
+    -(beta/M) dTV/dmu on its own, so a weight of beta (or beta/M^2) fails by a factor M."""
+    g = _geom16()
+    sl = ph.make_slice(g, 11, 5e3)
+    i0, M, beta, eps_mm, lam, n_done = 5e3, 4, 2e-2, 1e-4, 2e-4, 5
+    rng = np.random.default_rng(12)
+    disc = oracle.initial_image(g, 1.0) > 0
+    mu0 = np.where(disc, 0.005 * (1.0 + 0.2 * rng.uniform(-1, 1, (g.n, g.n))), 0.0)
+    views = oracle.subset_views(g.n_views, M, n_done % M)
+
+    mu_b = _one_step(g, M, beta, sl.counts, i0, mu0, n_done, lam, eps_mm)
+    mu_0 = _one_step(g, M, 0.0, sl.counts, i0, mu0, n_done, lam, eps_mm)
+    assert np.all(mu_b[disc] > 0) and np.all(mu_0[disc] > 0)  # away from the clamp
+    step_b = 10 * (mu_b - mu0) / lam  # per 1/cm of image, as Eq. 3 is written
+    step_prior = 10 * (mu_b - mu_0) / lam
+
+    h = 1e-6
+    for _ in range(4):
+        d = rng.standard_normal((g.n, g.n)) * disc  # direction in 1/cm
+        fd_l = (_subset_loglik(g, mu0 + h * d / 10, sl.counts, i0, views)
+                - _subset_loglik(g, mu0 - h * d / 10, sl.counts, i0, views)) / (2 * h)
+        tv_p = oracle.tv(10 * mu0 + h * d, 10 * eps_mm)[0]
+        tv_m = oracle.tv(10 * mu0 - h * d, 10 * eps_mm)[0]
+        fd_r = -(tv_p - tv_m) / (2 * h)  # directional derivative of R = -TV
+        full = fd_l + (beta / M) * fd_r
+        assert np.sum(step_b * d) == pytest.approx(full, rel=1e-6)
+        assert np.sum(step_prior * d) == pytest.approx((beta / M) * fd_r, rel=1e-5)
+        # the prior's share is far above the 1e-6 tolerance: a weight off by M would show in both
+        assert abs((beta / M) * fd_r) > 1e-4 * abs(full)
+
+
+def _integer_disc(n):
+    """Pixel centres inside the reconstruction circle of radius N*pixel/2, decided in integers:
+    with centre offsets (i - (N-1)/2, j - (N-1)/2) in pixels, the test doubled is
+    (2i - N + 1)^2 + (2j - N + 1)^2 <= N^2 (no centre lies exactly on the circle: the two
+    squares are both even for odd N and both odd for even N, while N^2 is odd or 0 mod 4)."""
+    a = 2 * np.arange(n, dtype=np.int64) - n + 1
+    return a[None, :] ** 2 + a[:, None] ** 2 <= n * n
+
+
+def _integer_disc_count(n):
+    """Number of pixel centres in the circle, counted row by row with integer square roots."""
+    import math as _m
+    total = 0
+    for j in range(n):
+        b = 2 * j - n + 1
+        rem = n * n - b * b
+        if rem < 0:
+            continue
+        r = _m.isqrt(rem)  # largest |a| with a^2 <= rem
+        # a = 2i - n + 1 runs over values of the parity of n - 1 in [-(n-1), n-1]
+        lo = -min(r, n - 1)
+        hi = min(r, n - 1)
+        par = (n - 1) % 2
+        if (lo - par) % 2:
+            lo += 1
+        if (hi - par) % 2:
+            hi -= 1
+        if hi >= lo:
+            total += (hi - lo) // 2 + 1
+    return total
+
+
+@pytest.mark.parametrize("n,px", [(5, 25.0), (16, 25.0), (17, 400 / 17), (128, 3.125), (200, 2.0), (512, 0.78125)])
+def test_initial_image_support_is_the_reconstruction_disc(n, px):
+    """Section 3.C.2: the homogeneous start image fills the reconstruction circle x^2 + y^2 <=
+    (N*pixel/2)^2 and is zero outside; the pixel set equals the integer-arithmetic disc and its
+    size equals an independent row-by-row isqrt count.  A radius of (N-1)*pixel/2 drops
+    a ring of boundary pixels and fails."""
+    g = ph.Geometry(n=n, pixel_mm=px, n_views=8, n_channels=8)
+    img = oracle.initial_image(g, 0.005)
+    disc = _integer_disc(n)
+    assert np.array_equal(img > 0, disc)
+    assert np.all(img[disc] == 0.005) and np.all(img[~disc] == 0.0)
+    assert int(disc.sum()) == _integer_disc_count(n)
+
+
+def test_iteration_holds_the_image_at_zero_outside_the_disc():
+    """The iterate is zero outside the reconstruction circle and the start image is taken as zero
+    there too: a start image positive everywhere (corners included) gives, after one small step,
+    exactly zero on the pixels outside the integer-arithmetic disc and positive values inside."""
+    g = ph.Geometry(n=17, pixel_mm=400 / 17, n_views=24, n_channels=24)
+    sl = ph.make_slice(g, 13, 5e3)
+    mu0 = np.full((g.n, g.n), 0.005)
+    mu1, _ = oracle.os_iterate(g, 3, 1e-3, sl.counts, 5e3, mu0, 1, lambda_schedule=[1e-4])
+    disc = _integer_disc(g.n)
+    assert np.all(mu1[~disc] == 0.0)
+    assert np.all(mu1[disc] > 0.0)
