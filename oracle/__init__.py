@@ -32,7 +32,8 @@ class _Geom(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("pad0", ctypes.c_int32), ("pixel_mm", ctypes.c_double),
                 ("n_views", ctypes.c_int32), ("n_channels", ctypes.c_int32),
                 ("sad_mm", ctypes.c_double), ("sdd_mm", ctypes.c_double),
-                ("fan_half_angle_rad", ctypes.c_double), ("start_angle_rad", ctypes.c_double)]
+                ("fan_half_angle_rad", ctypes.c_double), ("start_angle_rad", ctypes.c_double),
+                ("scan_arc_rad", ctypes.c_double)]
 
 
 class _Params(ctypes.Structure):
@@ -83,8 +84,8 @@ def lib():
 
 
 def _g(geom) -> _Geom:
-    n, px, nv, nc, sad, sdd, fan, start = geom.as_tuple()
-    return _Geom(n, 0, px, nv, nc, sad, sdd, fan, start)
+    n, px, nv, nc, sad, sdd, fan, start, arc = geom.as_tuple()
+    return _Geom(n, 0, px, nv, nc, sad, sdd, fan, start, arc)
 
 
 def _dp(a):

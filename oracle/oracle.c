@@ -38,6 +38,7 @@ typedef struct {
     double sad_mm, sdd_mm;
     double fan_half_angle_rad;  /* 0: asin(R/SAD), R = n*pixel/2 */
     double start_angle_rad;
+    double scan_arc_rad;        /* angular range swept by the views; 0: a full turn (2 pi) */
 } og_geometry;
 
 /* Step-rule and prior parameters. */
@@ -78,7 +79,20 @@ static int geometry_ok(const og_geometry* g)
     double half = 0.5 * g->n * g->pixel_mm;
     /* every pixel must lie between source and detector */
     if (g->sad_mm <= sqrt(2.0) * half) return 0;
+    /* a partial arc (limited-angle data) lies in (0, 2 pi]; 0 selects the full turn */
+    if (!(g->scan_arc_rad >= 0.0) || g->scan_arc_rad > 2.0 * M_PI) return 0;
     return 1;
+}
+
+/* Source angle of view v: the views step counter-clockwise from start_angle by
+ * arc / n_views, arc = scan_arc_rad, or 2 pi for a full turn.  A partial arc
+ * is the limited-data case (section 4, reconstructed images: fewer projection
+ * data); its n_views views cover [start, start + arc) at the same spacing a
+ * full turn of 2 pi n_views / arc views would have. */
+static double view_angle(const og_geometry* g, int v)
+{
+    const double arc = g->scan_arc_rad > 0.0 ? g->scan_arc_rad : 2.0 * M_PI;
+    return g->start_angle_rad + arc * (double)v / (double)g->n_views;
 }
 
 static double fan_half_angle(const og_geometry* g)
@@ -88,13 +102,13 @@ static double fan_half_angle(const og_geometry* g)
 }
 
 /* Source position and unit direction of ray (view v, channel k): the source
- * turns counter-clockwise from start_angle in n_views equal steps over 2 pi;
+ * sits at angle view_angle(v);
  * channel k sits at fan angle (k - (n_ch-1)/2) * dgamma on an arc centred on
  * the source, dgamma = 2 gamma_max / n_ch; the ray leaves the source towards
  * angle beta + pi + gamma. */
 static void ray_of(const og_geometry* g, int v, int k, double* sx, double* sy, double* dx, double* dy)
 {
-    double beta = g->start_angle_rad + 2.0 * M_PI * (double)v / (double)g->n_views;
+    double beta = view_angle(g, v);
     double dgam = 2.0 * fan_half_angle(g) / (double)g->n_channels;
     double gam = ((double)k - 0.5 * (double)(g->n_channels - 1)) * dgam;
     *sx = g->sad_mm * cos(beta);
@@ -384,10 +398,12 @@ double oracle_lambda_next(const og_params* p, int32_t first, double lambda_prev,
  * with gamma' the fan angle and L the distance from view v's source to
  * (x, y), Q linearly interpolated in gamma and zero outside the channels.
  * sino: [n_views][n_ch] line integrals (natural view order); img: [n][n],
- * 1/mm (no mask). */
+ * 1/mm (no mask).  Full turns only: a partial arc would need redundancy
+ * weights, which the comparison method is not stated to use. */
 int oracle_fbp(const og_geometry* g, const double* sino, double* img)
 {
     if (!geometry_ok(g) || !sino || !img) return OG_INVALID;
+    if (g->scan_arc_rad != 0.0 && g->scan_arc_rad != 2.0 * M_PI) return OG_INVALID;
     const int N = g->n, nv = g->n_views, nch = g->n_channels;
     const double dgam = 2.0 * fan_half_angle(g) / (double)nch;
     const double D = g->sad_mm;

@@ -15,8 +15,8 @@ discrete projector that reconstructs them.
 Geometry convention (shared by every consumer, each re-implementing it):
   * pixel (i, j) centre: x = (i - (N-1)/2) * pixel, y = (j - (N-1)/2) * pixel,
     stored at index j * N + i;
-  * view v: source angle beta = start + 2*pi*v / n_views, source at
-    SAD * (cos beta, sin beta);
+  * view v: source angle beta = start + arc*v / n_views (arc = 2*pi for a full
+    turn, less for limited-angle data), source at SAD * (cos beta, sin beta);
   * channel k on an arc centred on the source: fan angle
     gamma = (k - (n_ch-1)/2) * dgamma with dgamma = 2 * gamma_max / n_ch and
     gamma_max = asin(R / SAD) (R = N * pixel / 2), unless given;
@@ -45,6 +45,11 @@ class Geometry:
     sdd_mm: float = 1450.0
     fan_half_angle_rad: float = 0.0  # 0 means asin(R / SAD): the fan just covers the FOV circle
     start_angle_rad: float = 0.0
+    scan_arc_rad: float = 0.0  # angular range of the views; 0 means a full turn (2 pi)
+
+    @property
+    def arc_rad(self) -> float:
+        return self.scan_arc_rad if self.scan_arc_rad > 0 else 2 * math.pi
 
     @property
     def fov_radius_mm(self) -> float:
@@ -58,7 +63,7 @@ class Geometry:
 
     def as_tuple(self):
         return (self.n, self.pixel_mm, self.n_views, self.n_channels, self.sad_mm, self.sdd_mm,
-                self.fan_half_angle_rad, self.start_angle_rad)
+                self.fan_half_angle_rad, self.start_angle_rad, self.scan_arc_rad)
 
 
 @dataclasses.dataclass(frozen=True)
@@ -162,7 +167,7 @@ def rasterize(ellipses: list[Ellipse], n: int, pixel_mm: float, supersample: int
 
 def ray_table(g: Geometry):
     """Source positions and unit directions of every ray: arrays [n_views][n_channels]."""
-    beta = g.start_angle_rad + 2 * math.pi * np.arange(g.n_views) / g.n_views
+    beta = g.start_angle_rad + g.arc_rad * np.arange(g.n_views) / g.n_views
     dgam = 2 * g.gamma_max / g.n_channels
     gam = (np.arange(g.n_channels) - 0.5 * (g.n_channels - 1)) * dgam
     sx = g.sad_mm * np.cos(beta)[:, None] * np.ones((1, g.n_channels))

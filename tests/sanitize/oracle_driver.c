@@ -9,7 +9,7 @@ typedef struct {
     int32_t n, pad0;
     double pixel_mm;
     int32_t n_views, n_channels;
-    double sad_mm, sdd_mm, fan_half_angle_rad, start_angle_rad;
+    double sad_mm, sdd_mm, fan_half_angle_rad, start_angle_rad, scan_arc_rad;
 } og_geometry;
 typedef struct {
     double lambda0, lambda_inc, lambda_dec, lambda_min, mu0_per_mm, tv_eps_per_mm;
@@ -31,7 +31,7 @@ int oracle_fbp(const og_geometry*, const double*, double*);
 
 int main(void)
 {
-    og_geometry g = {13, 0, 20.0, 17, 23, 850.0, 1450.0, 0.0, 0.4};
+    og_geometry g = {13, 0, 20.0, 17, 23, 850.0, 1450.0, 0.0, 0.4, 0.0};
     const int N = g.n, nv = g.n_views, nch = g.n_channels, M = 4;
     double* img = calloc((size_t)N * N, sizeof(double));
     double* img2 = calloc((size_t)N * N, sizeof(double));
@@ -54,6 +54,13 @@ int main(void)
     rc |= oracle_initial_image(&g, 0.005, img);
     rc |= oracle_os_iterate(&g, M, 1e-3, &p, counts, 2000.0, img, 9, &st, trace, NULL, hist, img2);
     rc |= oracle_fbp(&g, sino, img);
+    /* a partial arc: the iteration runs, the filtered backprojection refuses it */
+    og_geometry gs = g;
+    gs.scan_arc_rad = 2.0;
+    og_state st2 = {0};
+    rc |= oracle_project(&gs, img, sino, NULL, nv);
+    rc |= oracle_os_iterate(&gs, M, 1e-3, &p, counts, 2000.0, img, 5, &st2, NULL, NULL, hist, img2);
+    rc |= oracle_fbp(&gs, sino, img) == 0;
     printf("rc %d f %.6e best_n %d\n", rc, trace[16], st.best_n);
     free(img); free(img2); free(sino); free(counts); free(trace); free(hist);
     return rc != 0;
