@@ -17,7 +17,8 @@
  *    reconstruction disc is x^2 + y^2 <= (n * pixel_mm / 2)^2; outside it the
  *    iterate is held at zero.
  *  - Fan beam: view v has its source at SAD * (cos b, sin b),
- *    b = start_angle + 2 pi v / n_views (counter-clockwise); channel k lies on
+ *    b = start_angle + arc v / n_views (counter-clockwise), arc = scan_arc_rad
+ *    or 2 pi when that is 0; channel k lies on
  *    an arc centred on the source at fan angle g = (k - (n_channels-1)/2) * dg,
  *    dg = 2 * gamma_max / n_channels, gamma_max = fan_half_angle_rad or, when
  *    that is 0, asin(R / SAD) with R = n * pixel_mm / 2; the ray leaves the
@@ -54,8 +55,14 @@ typedef enum {
 /* Fan-beam geometry.  Requirements: n >= 2, pixel_mm > 0, n_views >= 1,
  * 1 <= n_channels <= 65535, sad_mm > sqrt(2) * n * pixel_mm / 2 (the whole
  * pixel grid lies on the detector side of the source), full fan angle below
- * 90 degrees.  sdd_mm is carried for completeness: on an arc detector centred
- * on the source it does not change any line integral. */
+ * 90 degrees, 0 <= scan_arc_rad <= 2 pi.  sdd_mm is carried for completeness:
+ * on an arc detector centred on the source it does not change any line
+ * integral.  scan_arc_rad is the angular range the views sweep: 0 (or 2 pi)
+ * is a full turn; a smaller value is limited-angle data (section 4,
+ * reconstructed images: fewer projection data), its n_views views spaced
+ * arc / n_views apart over [start, start + arc).  The iteration, projector and
+ * backprojector take any arc; recon_fbp and recon_rebin_helical need a full
+ * turn. */
 typedef struct {
     int32_t n;
     int32_t reserved0;
@@ -66,6 +73,7 @@ typedef struct {
     double sdd_mm;
     double fan_half_angle_rad;
     double start_angle_rad;
+    double scan_arc_rad;
 } recon_geometry;
 
 /* Step rule and prior parameters (section 3.C).  Defaults (recon_default_params):
@@ -206,7 +214,9 @@ recon_status recon_initial_image(recon_handle* h, float* d_img, void* stream);
  * [n_views][n_channels] as for recon_os_iterate; d_img: [n][n] in 1/mm,
  * overwritten, every pixel (no mask).  Deterministic (no atomics).  Uses the
  * handle's workspace: do not overlap with other calls on the same handle.
- * RECON_INVALID_ARG for more than 16384 channels. */
+ * RECON_INVALID_ARG for more than 16384 channels, or for a handle whose views
+ * cover less than a full turn (a partial arc would need redundancy weights,
+ * which the comparison method is not stated to use). */
 recon_status recon_fbp(recon_handle* h, const float* d_counts, float i0, float* d_img, void* stream);
 
 /* Helical rebinning: single-row helical fan data (a helical tomotherapy MVCT
@@ -214,7 +224,7 @@ recon_status recon_fbp(recon_handle* h, const float* d_counts, float i0, float* 
  * 360-degree linear interpolation along z (the textbook 360LI method; the
  * paper reconstructs helical MVCT slices but does not state its rebinning).
  * g: the geometry of one turn (n_views views per turn, n_channels channels;
- * the other fields are not used).  Helical view h (0 <= h < n_helical_views)
+ * scan_arc_rad must be 0 or 2 pi; the other fields are not used).  Helical view h (0 <= h < n_helical_views)
  * has the angle of view h mod n_views and source z = z0_mm + pitch_mm h /
  * n_views (pitch_mm: table feed per turn, > 0).  For slice z and view v the
  * two helical views at that angle whose z bracket z (z_a <= z < z_b) are

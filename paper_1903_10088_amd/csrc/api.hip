@@ -56,6 +56,8 @@ recon_status check_geometry(const recon_geometry* g, int M)
         return fail(RECON_INVALID_ARG, "sad_mm must exceed the half-diagonal of the pixel grid");
     const double gmax = g->fan_half_angle_rad > 0 ? g->fan_half_angle_rad : std::asin(half / g->sad_mm);
     if (!(gmax < kPi / 4)) return fail(RECON_INVALID_ARG, "full fan angle must be below 90 degrees");
+    if (!(g->scan_arc_rad >= 0.0) || g->scan_arc_rad > 2.0 * kPi)
+        return fail(RECON_INVALID_ARG, "scan_arc_rad must be in [0, 2 pi] (0: a full turn)");
     if (M < 1 || M > g->n_views) return fail(RECON_INVALID_ARG, "subsets must be in [1, n_views]");
     return RECON_OK;
 }
@@ -85,7 +87,7 @@ recon_status build_tables(const recon_geometry* g, int M, Tables& T)
     std::vector<double> a_tab((size_t)nv * nch), s_tab((size_t)nv * nch);
     for (int q = 0; q < nv; ++q) {
         const int v = T.perm[q];
-        const double beta = g->start_angle_rad + 2.0 * kPi * (double)v / (double)nv;
+        const double beta = view_angle(g, v);
         const double sx = g->sad_mm * std::cos(beta) / dpx, sy = g->sad_mm * std::sin(beta) / dpx;
         for (int k = 0; k < nch; ++k) {
             const double gam = ((double)k - 0.5 * (double)(nch - 1)) * dg;
@@ -310,6 +312,7 @@ void free_handle(recon_handle* h)
 }  // namespace
 
 // ABI layout of the public structs (mirrored by the Python binding)
+static_assert(sizeof(recon_geometry) == 64 && offsetof(recon_geometry, scan_arc_rad) == 56, "recon_geometry layout");
 static_assert(sizeof(recon_params) == 56 && offsetof(recon_params, keep_best) == 52, "recon_params layout");
 static_assert(sizeof(recon_state) == 48 && offsetof(recon_state, best_n) == 40, "recon_state layout");
 
@@ -415,7 +418,7 @@ recon_status recon_create(const recon_geometry* geom, int32_t subsets, double be
     {
         std::vector<double> cs(2 * (size_t)geom->n_views);
         for (int q = 0; q < geom->n_views; ++q) {
-            const double beta = geom->start_angle_rad + 2.0 * kPi * (double)T.perm[q] / (double)geom->n_views;
+            const double beta = view_angle(geom, T.perm[q]);
             cs[2 * (size_t)q] = std::cos(beta);
             cs[2 * (size_t)q + 1] = std::sin(beta);
         }

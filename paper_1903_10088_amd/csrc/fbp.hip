@@ -114,6 +114,7 @@ extern "C" recon_status recon_fbp(recon_handle* h, const float* d_counts, float 
     if (!(i0 > 0) || !std::isfinite(i0)) return fail(RECON_INVALID_ARG, "i0 must be finite and > 0");
     const Geo& G = h->geo;
     if (G.nch > FBP_MAX_CH) return fail(RECON_INVALID_ARG, "recon_fbp supports up to 16384 channels");
+    if (!full_turn(&h->g)) return fail(RECON_INVALID_ARG, "recon_fbp needs views over a full turn");
     hipStream_t s = as_stream(stream);
     RECON_HIP_TRY(launch_prep_counts(d_counts, h->d_views, G.nv, G.nch, i0, h->d_yt, h->d_p, s));
     const float* wcos = h->d_fbp;

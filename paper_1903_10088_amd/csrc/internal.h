@@ -187,6 +187,20 @@ struct recon_handle {
 
 namespace recon {
 
+// Source angle of view v (natural order): start + arc v / n_views, arc the
+// geometry's scan arc or a full turn when that is 0.
+inline double view_angle(const recon_geometry* g, int v)
+{
+    const double arc = g->scan_arc_rad > 0.0 ? g->scan_arc_rad : 2.0 * 3.14159265358979323846;
+    return g->start_angle_rad + arc * (double)v / (double)g->n_views;
+}
+
+// Whether the views cover a full turn (scan arc 0 or exactly 2 pi).
+inline bool full_turn(const recon_geometry* g)
+{
+    return g->scan_arc_rad == 0.0 || g->scan_arc_rad == 2.0 * 3.14159265358979323846;
+}
+
 // api.hip: error reporting and per-handle constants shared with batch.hip
 recon_status fail(recon_status s, const std::string& msg);
 hipStream_t as_stream(void* s);

@@ -70,6 +70,7 @@ extern "C" recon_status recon_rebin_helical(const recon_geometry* g, int32_t n_h
     const int nv = g->n_views, nch = g->n_channels, nh = n_helical_views;
     if (nv < 1 || nch < 1) return fail(RECON_INVALID_ARG, "n_views and n_channels must be >= 1");
     if (nh <= nv) return fail(RECON_INVALID_ARG, "n_helical_views must exceed n_views (more than one turn)");
+    if (!full_turn(g)) return fail(RECON_INVALID_ARG, "the rebinned views must cover a full turn");
     if ((long)nh * nch >= (1L << 40) || (long)nv * nch >= (1L << 31))
         return fail(RECON_INVALID_ARG, "helical data too large");
     if (!(pitch_mm > 0) || !std::isfinite(pitch_mm) || !std::isfinite(z0_mm))

@@ -29,7 +29,8 @@ class Geometry_c(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("pixel_mm", ctypes.c_double),
                 ("n_views", ctypes.c_int32), ("n_channels", ctypes.c_int32),
                 ("sad_mm", ctypes.c_double), ("sdd_mm", ctypes.c_double),
-                ("fan_half_angle_rad", ctypes.c_double), ("start_angle_rad", ctypes.c_double)]
+                ("fan_half_angle_rad", ctypes.c_double), ("start_angle_rad", ctypes.c_double),
+                ("scan_arc_rad", ctypes.c_double)]
 
 
 class Params_c(ctypes.Structure):
@@ -128,7 +129,8 @@ def _check(rc: int, where: str):
 def geometry_c(g) -> Geometry_c:
     """From a phantom.Geometry-like object (n, pixel_mm, n_views, n_channels, sad_mm, sdd_mm, ...)."""
     return Geometry_c(int(g.n), 0, float(g.pixel_mm), int(g.n_views), int(g.n_channels), float(g.sad_mm),
-                      float(g.sdd_mm), float(g.fan_half_angle_rad), float(g.start_angle_rad))
+                      float(g.sdd_mm), float(g.fan_half_angle_rad), float(g.start_angle_rad),
+                      float(getattr(g, "scan_arc_rad", 0.0)))
 
 
 def default_params() -> dict:

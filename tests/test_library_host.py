@@ -43,6 +43,8 @@ def test_default_params_are_the_paper_constants():
     dict(n=1), dict(pixel_mm=0.0), dict(n_views=0), dict(n_channels=0),
     dict(sad_mm=250.0),                      # source inside the pixel grid's circumcircle
     dict(fan_half_angle_rad=0.9),            # fan wider than 90 degrees
+    dict(scan_arc_rad=-0.1),                 # negative scan arc
+    dict(scan_arc_rad=6.3),                  # more than a full turn
 ])
 def test_create_rejects_bad_geometry(bad):
     base = dict(n=128, pixel_mm=3.125, n_views=180, n_channels=192)
@@ -185,3 +187,22 @@ def test_rebin_validates_before_the_device():
     assert call(zs=(lo - 1e-6,)) == bad
     assert call(zs=(0.0, hi + 1e-6)) == bad
     assert call(zs=(float("inf"),)) == bad
+
+
+def test_geometry_struct_layout():
+    """The binding's geometry record has the C layout (the library asserts 64 bytes with the scan
+    arc at offset 56)."""
+    assert ctypes.sizeof(recon.Geometry_c) == 64
+    assert recon.Geometry_c.scan_arc_rad.offset == 56
+
+
+def test_partial_arc_tables_hold_every_ray():
+    """Limited-angle views (half a turn plus the fan, and an odd start) get the same window
+    guarantee as full turns: every ray with a nonzero weight on a pixel lies in the gather's
+    candidate window."""
+    import math
+    g0 = ph.Geometry(n=64, pixel_mm=6.25, n_views=36, n_channels=48)
+    g = ph.Geometry(n=64, pixel_mm=6.25, n_views=36, n_channels=48, start_angle_rad=0.37,
+                    scan_arc_rad=math.pi + 2 * g0.gamma_max)
+    missed, cand, pairs = recon.check_tables(g, 4)
+    assert missed == 0 and pairs > 0 and cand >= pairs
