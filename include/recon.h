@@ -342,6 +342,28 @@ recon_status recon_warm_start(recon_batch_handle* b, struct recon_cnn* net, cons
                               double residual_ratio, double* h_residual, double* h_floor, int32_t* h_fallback,
                               void* stream);
 
+/* recon_warm_start for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments and the same results, bit for bit, with no hipMalloc,
+ * hipFree or graph instantiation during the call.  Its staging buffers live
+ * in a fixed scratch array of 16.1 MiB per GPU, reserved in device memory by
+ * the library (each GPU it runs on holds it until the process ends): the
+ * images pass through the network in chunks of at most 16 MiB, epoch graphs
+ * are replayed only if an earlier call on the same batch built them (else the
+ * sub-iterations are launched directly), and fallback slices run one by one
+ * on their own handles.  Limits: at most 4096 slices per call and images of
+ * at most 2048 x 2048; beyond them RECON_INVALID_ARG, with nothing launched.
+ * The batch's device must be the current device.  Every call on one GPU
+ * shares that GPU's scratch: calls that overlap in time on one GPU (from
+ * several threads or on several streams) race and must be serialised by the
+ * caller.  No part of the scratch needs to start at zero; each region is
+ * written before it is read within a call.  Blocks until done, as
+ * recon_warm_start. */
+recon_status recon_warm_start_noalloc(recon_batch_handle* b, struct recon_cnn* net, const float* const* d_counts,
+                                      const float* i0, float* const* d_imgs, int32_t n_pre, int32_t n_refine,
+                                      int32_t n_cold, double residual_ratio, double* h_residual, double* h_floor,
+                                      int32_t* h_fallback, void* stream);
+
 /* Number of (ray, in-image pixel) interpolation pairs of `subset` (-1 = all
  * views): the pixel reads of the projector and the sinogram reads of the
  * backprojector, from the handle's own ray tables.  disc_only = 1 counts only

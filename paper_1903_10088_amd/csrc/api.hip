@@ -529,6 +529,18 @@ recon_status recon_os_iterate_ex(recon_handle* h, const float* d_counts, float i
                                  recon_state* state, double* d_trace, const double* d_lambda_schedule,
                                  double* d_f_hist, float* d_best, void* stream)
 {
+    return os_iterate_run(h, d_counts, i0, d_img, n_iter, state, d_trace, d_lambda_schedule, d_f_hist, d_best,
+                          as_stream(stream), true);
+}
+
+}  // extern "C"
+
+namespace recon {
+
+recon_status os_iterate_run(recon_handle* h, const float* d_counts, float i0, float* d_img, int n_iter,
+                            recon_state* state, double* d_trace, const double* d_lambda_schedule, double* d_f_hist,
+                            float* d_best, hipStream_t s, bool new_graphs)
+{
     if (!h || !d_counts || !d_img) return fail(RECON_INVALID_ARG, "NULL argument");
     if (!(i0 > 0) || !std::isfinite(i0)) return fail(RECON_INVALID_ARG, "i0 must be finite and > 0");
     if (n_iter < 0) return fail(RECON_INVALID_ARG, "n_iter must be >= 0");
@@ -538,7 +550,6 @@ recon_status recon_os_iterate_ex(recon_handle* h, const float* d_counts, float i
     const int n_done = state ? state->n_done : 0;
     if (h->p.lambda_compare && h->M > 1 && n_done > 0 && !d_f_hist)
         return fail(RECON_INVALID_ARG, "a resumed run with lambda_compare needs the subset history d_f_hist");
-    hipStream_t s = as_stream(stream);
     const Geo& G = h->geo;
 
     DevState v = fresh_state(h->p.lambda0);
@@ -564,7 +575,7 @@ recon_status recon_os_iterate_ex(recon_handle* h, const float* d_counts, float i
     int n = 0;
     while (n < n_iter) {
         const int sub = (n_done + n) % h->M;
-        if (sub == 0 && n_iter - n >= h->M && !h->graph_bad) {
+        if (sub == 0 && n_iter - n >= h->M && !h->graph_bad && (new_graphs || h->graph[in])) {
             hipGraphExec_t exec = nullptr;
             if (get_graph(h, in, &exec) == RECON_OK) {
                 HIP_TRY(hipGraphLaunch(exec, s));
@@ -596,6 +607,10 @@ recon_status recon_os_iterate_ex(recon_handle* h, const float* d_counts, float i
     }
     return RECON_OK;
 }
+
+}  // namespace recon
+
+extern "C" {
 
 recon_status recon_data_residual(recon_handle* h, const float* d_counts, float i0, const float* d_img, double* d_out,
                                  void* stream)

@@ -15,7 +15,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -285,13 +287,14 @@ recon_status prepare(recon_batch_handle* b, const float* const* d_counts, const 
 }
 
 // Copies images of side sz between the slices' buffers and a contiguous stage
-// (to_stage: d_imgs[i] -> stage slot, else back), slices of that size in order.
+// (to_stage: d_imgs[i] -> stage slot, else back): the slices of that size
+// numbered [skip, skip + take) in batch order, to slots 0, 1, ...
 recon_status stage_copy(const recon_batch_handle* b, float* const* d_imgs, float* d_stage, int sz, bool to_stage,
-                        hipStream_t s)
+                        hipStream_t s, int skip = 0, int take = INT_MAX)
 {
     const size_t img = (size_t)sz * sz;
     BatchCopyArgs c{};
-    int slot = 0;
+    int slot = 0, seen = 0;
     for (size_t i = 0; i <= b->h.size(); ++i) {
         if (c.count == BATCH_ARGS || (i == b->h.size() && c.count > 0)) {
             RECON_HIP_TRY(launch_copy_batch(c, (long)img, s));
@@ -299,6 +302,8 @@ recon_status stage_copy(const recon_batch_handle* b, float* const* d_imgs, float
         }
         if (i == b->h.size()) break;
         if (b->h[i]->geo.n != sz) continue;
+        const int k = seen++;
+        if (k < skip || k - skip >= take) continue;
         float* st = d_stage + (size_t)(slot++) * img;
         c.src[c.count] = to_stage ? d_imgs[i] : st;
         c.dst[c.count] = to_stage ? st : d_imgs[i];
@@ -306,6 +311,9 @@ recon_status stage_copy(const recon_batch_handle* b, float* const* d_imgs, float
     }
     return RECON_OK;
 }
+
+recon_status batch_run(recon_batch_handle* b, const float* const* d_counts, const float* i0, float* const* d_imgs,
+                       int n_iter, double* const* d_traces, hipStream_t s, bool new_graphs);
 
 }  // namespace
 
@@ -387,15 +395,27 @@ recon_status recon_batch_set_launch(recon_batch_handle* b, int32_t fp_segments, 
 recon_status recon_batch_run(recon_batch_handle* b, const float* const* d_counts, const float* i0, float* const* d_imgs,
                              int32_t n_iter, double* const* d_traces, void* stream)
 {
+    return batch_run(b, d_counts, i0, d_imgs, n_iter, d_traces, as_stream(stream), true);
+}
+
+}  // extern "C"
+
+namespace {
+
+// recon_batch_run on a HIP stream; new_graphs = false replays only the epoch
+// graphs the batch has already instantiated and launches the rest directly
+// (same kernels, same bits).
+recon_status batch_run(recon_batch_handle* b, const float* const* d_counts, const float* i0, float* const* d_imgs,
+                       int n_iter, double* const* d_traces, hipStream_t s, bool new_graphs)
+{
     if (!b || !d_counts || !i0 || !d_imgs) return fail(RECON_INVALID_ARG, "NULL argument");
     if (n_iter < 0) return fail(RECON_INVALID_ARG, "n_iter must be >= 0");
-    hipStream_t s = as_stream(stream);
     recon_status st = prepare(b, d_counts, i0, d_imgs, d_traces, s);
     if (st != RECON_OK) return st;
     int in = 0, n = 0;
     while (n < n_iter) {
         const int sub = n % b->M;
-        if (sub == 0 && n_iter - n >= b->M && !b->graph_bad) {
+        if (sub == 0 && n_iter - n >= b->M && !b->graph_bad && (new_graphs || b->graph[in])) {
             hipGraphExec_t exec = nullptr;
             if (get_graph(b, in, &exec) == RECON_OK) {
                 RECON_HIP_TRY(hipGraphLaunch(exec, s));
@@ -418,6 +438,10 @@ recon_status recon_batch_run(recon_batch_handle* b, const float* const* d_counts
     b->last_in = in;
     return RECON_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 recon_status recon_batch_tune(recon_batch_handle* b, const float* const* d_counts, const float* i0, float* const* d_imgs,
                               int32_t reps, int32_t* fp_segments_out, int32_t* bp_variant_out, void* stream)
@@ -503,53 +527,88 @@ recon_status recon_batch(const recon_geometry* geoms, int32_t n_slices, int32_t 
     return st;
 }
 
-recon_status recon_warm_start(recon_batch_handle* b, recon_cnn* net, const float* const* d_counts, const float* i0,
-                              float* const* d_imgs, int32_t n_pre, int32_t n_refine, int32_t n_cold,
-                              double residual_ratio, double* h_residual, double* h_floor, int32_t* h_fallback,
-                              void* stream)
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Learned warm start.  With a null scratch the stage, the residuals and the
+// device copy of the count pointers are allocated for the call, the epoch
+// graphs are built on first use and many fallback slices run as a sub-batch.
+// With a scratch buffer (the allocation-free entry point) the images pass
+// through the network in chunks that fit the scratch stage, only graphs that
+// already exist are replayed, and fallback slices run one by one on their own
+// handles: the same kernels in the same order, so the same bits.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Allocation-free warm start: the scratch holds a stage of NOALLOC_STAGE_FLOATS
+// floats (16 MiB: 16 slices of 512^2, one of 2048^2), then per slice two
+// doubles (residual, noise level) and one count pointer.
+constexpr size_t NOALLOC_STAGE_FLOATS = (size_t)4 << 20;
+constexpr int NOALLOC_MAX_SLICES = 4096;
+constexpr size_t NOALLOC_RES_OFFSET = NOALLOC_STAGE_FLOATS * sizeof(float);
+constexpr size_t NOALLOC_CPTR_OFFSET = NOALLOC_RES_OFFSET + 2 * sizeof(double) * NOALLOC_MAX_SLICES;
+constexpr size_t NOALLOC_BYTES = NOALLOC_CPTR_OFFSET + sizeof(float*) * NOALLOC_MAX_SLICES;
+
+recon_status warm_start_impl(recon_batch_handle* b, recon_cnn* net, const float* const* d_counts, const float* i0,
+                             float* const* d_imgs, int n_pre, int n_refine, int n_cold, double residual_ratio,
+                             double* h_residual, double* h_floor, int32_t* h_fallback, hipStream_t s,
+                             unsigned char* ws)
 {
-    if (!b || !net || !d_counts || !i0 || !d_imgs) return fail(RECON_INVALID_ARG, "NULL argument");
-    if (n_pre < 0 || n_refine < 0 || n_cold < 0) return fail(RECON_INVALID_ARG, "iteration counts must be >= 0");
-    if (!(residual_ratio > 0)) return fail(RECON_INVALID_ARG, "residual_ratio must be > 0");
-    hipStream_t s = as_stream(stream);
+    const bool noalloc = ws != nullptr;
     const int n = (int)b->h.size();
     // 1. early iterate of every slice from the homogeneous start
-    recon_status st = recon_batch_initial_images(b, d_imgs, stream);
-    if (st == RECON_OK) st = recon_batch_run(b, d_counts, i0, d_imgs, n_pre, nullptr, stream);
+    recon_status st = recon_batch_initial_images(b, d_imgs, s);
+    if (st == RECON_OK) st = batch_run(b, d_counts, i0, d_imgs, n_pre, nullptr, s, !noalloc);
     if (st != RECON_OK) return st;
     // 2. network estimate of the converged image, projected onto the constraints:
     //    slices of one size go through the network together (staged contiguously)
-    std::vector<int> sizes;
-    for (recon_handle* h : b->h)
-        if (std::find(sizes.begin(), sizes.end(), h->geo.n) == sizes.end()) sizes.push_back(h->geo.n);
-    size_t stage_floats = 0;
-    for (int sz : sizes) {
-        size_t cnt = 0;
-        for (recon_handle* h : b->h) cnt += (h->geo.n == sz);
-        stage_floats = std::max(stage_floats, cnt * (size_t)sz * sz);
+    std::vector<int> sizes, per_size;
+    for (recon_handle* h : b->h) {
+        auto it = std::find(sizes.begin(), sizes.end(), h->geo.n);
+        if (it == sizes.end()) {
+            sizes.push_back(h->geo.n);
+            per_size.push_back(1);
+        } else {
+            ++per_size[it - sizes.begin()];
+        }
     }
     float* d_stage = nullptr;
     double* d_res = nullptr;
     const float** d_cptr = nullptr;
+    hipError_t e = hipSuccess;
+    if (noalloc) {
+        d_stage = reinterpret_cast<float*>(ws);
+        d_res = reinterpret_cast<double*>(ws + NOALLOC_RES_OFFSET);
+        d_cptr = reinterpret_cast<const float**>(ws + NOALLOC_CPTR_OFFSET);
+    } else {
+        size_t stage_floats = 0;
+        for (size_t k = 0; k < sizes.size(); ++k)
+            stage_floats = std::max(stage_floats, (size_t)per_size[k] * sizes[k] * sizes[k]);
+        e = hipMalloc(&d_stage, stage_floats * sizeof(float));
+        if (e == hipSuccess) e = hipMalloc(&d_res, 2 * sizeof(double) * n);
+        if (e == hipSuccess) e = hipMalloc((void**)&d_cptr, sizeof(float*) * n);
+    }
     auto cleanup = [&]() {
+        if (noalloc) return;
         if (d_stage) (void)hipFree(d_stage);
         if (d_res) (void)hipFree(d_res);
         if (d_cptr) (void)hipFree(d_cptr);
     };
-    hipError_t e = hipMalloc(&d_stage, stage_floats * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc(&d_res, 2 * sizeof(double) * n);
-    if (e == hipSuccess) e = hipMalloc((void**)&d_cptr, sizeof(float*) * n);
     if (e == hipSuccess) e = hipMemcpyAsync(d_cptr, d_counts, sizeof(float*) * n, hipMemcpyHostToDevice, s);
     for (size_t k = 0; k < sizes.size() && e == hipSuccess && st == RECON_OK; ++k) {
         const int sz = sizes[k];
-        int cnt = 0;
-        for (recon_handle* h : b->h) cnt += (h->geo.n == sz);
-        st = stage_copy(b, d_imgs, d_stage, sz, true, s);
-        if (st == RECON_OK) st = recon_cnn_forward(net, d_stage, d_stage, cnt, sz, 1, stream);
-        if (st == RECON_OK) st = stage_copy(b, d_imgs, d_stage, sz, false, s);
+        const int chunk = noalloc ? (int)std::min<size_t>(per_size[k], NOALLOC_STAGE_FLOATS / ((size_t)sz * sz))
+                                  : per_size[k];
+        for (int first = 0; first < per_size[k] && st == RECON_OK; first += chunk) {
+            const int cnt = std::min(chunk, per_size[k] - first);
+            st = stage_copy(b, d_imgs, d_stage, sz, true, s, first, cnt);
+            if (st == RECON_OK) st = recon_cnn_forward(net, d_stage, d_stage, cnt, sz, 1, s);
+            if (st == RECON_OK) st = stage_copy(b, d_imgs, d_stage, sz, false, s, first, cnt);
+        }
     }
     // 3. refinement by the plain iteration, fresh step-rule state
-    if (e == hipSuccess && st == RECON_OK) st = recon_batch_run(b, d_counts, i0, d_imgs, n_refine, nullptr, stream);
+    if (e == hipSuccess && st == RECON_OK) st = batch_run(b, d_counts, i0, d_imgs, n_refine, nullptr, s, !noalloc);
     // 4. full-data residual and its noise level, every slice at once from the final iterate
     //    (one projection of every view; the last refining epoch's own squared differences lag
     //    the still-moving iterate and would not be comparable with converged images)
@@ -563,7 +622,7 @@ recon_status recon_warm_start(recon_batch_handle* b, recon_cnn* net, const float
     cleanup();
     if (st != RECON_OK) return st;
     if (e != hipSuccess) return fail(RECON_DEVICE, std::string("warm start: ") + hipGetErrorString(e));
-    // 5. cold start, batched, for every slice whose data residual exceeds the limit
+    // 5. cold start for every slice whose data residual exceeds the limit
     std::vector<int> fb;
     for (int i = 0; i < n; ++i) {
         const bool bad = !(res[2 * i] <= residual_ratio * res[2 * i + 1]);
@@ -573,15 +632,15 @@ recon_status recon_warm_start(recon_batch_handle* b, recon_cnn* net, const float
         if (bad) fb.push_back(i);
     }
     if (fb.empty()) return RECON_OK;
-    // A few slices run alone on their own handles (cached graphs, no set-up);
-    // many go through a batch over their handles.  Both give the same bits.
+    // A few slices (or any number, without allocation) run alone on their own
+    // handles; many go through a batch over their handles.  Both give the same bits.
     constexpr size_t kSubBatchMin = 8;
-    if (fb.size() < kSubBatchMin) {
+    if (noalloc || fb.size() < kSubBatchMin) {
         for (int i : fb) {
-            st = recon_initial_image(b->h[i], d_imgs[i], stream);
+            st = recon_initial_image(b->h[i], d_imgs[i], s);
             if (st == RECON_OK)
-                st = recon_os_iterate(b->h[i], d_counts[i], i0[i], d_imgs[i], n_cold, nullptr, nullptr, nullptr,
-                                      stream);
+                st = os_iterate_run(b->h[i], d_counts[i], i0[i], d_imgs[i], n_cold, nullptr, nullptr, nullptr, nullptr,
+                                    nullptr, s, !noalloc);
             if (st != RECON_OK) return st;
         }
         RECON_HIP_TRY(hipStreamSynchronize(s));
@@ -602,13 +661,92 @@ recon_status recon_warm_start(recon_batch_handle* b, recon_cnn* net, const float
         img_sub.push_back(d_imgs[i]);
     }
     st = setup_batch(sub, b->fp_segments);
-    if (st == RECON_OK) st = recon_batch_initial_images(sub, img_sub.data(), stream);
-    if (st == RECON_OK) st = recon_batch_run(sub, c_sub.data(), i0_sub.data(), img_sub.data(), n_cold, nullptr, stream);
+    if (st == RECON_OK) st = recon_batch_initial_images(sub, img_sub.data(), s);
+    if (st == RECON_OK) st = recon_batch_run(sub, c_sub.data(), i0_sub.data(), img_sub.data(), n_cold, nullptr, s);
     hipError_t se = hipStreamSynchronize(s);
     free_batch(sub);
     if (st != RECON_OK) return st;
     if (se != hipSuccess) return fail(RECON_DEVICE, std::string("cold start: ") + hipGetErrorString(se));
     return RECON_OK;
+}
+
+recon_status check_warm_args(recon_batch_handle* b, recon_cnn* net, const float* const* d_counts, const float* i0,
+                             float* const* d_imgs, int n_pre, int n_refine, int n_cold, double residual_ratio)
+{
+    if (!b || !net || !d_counts || !i0 || !d_imgs) return fail(RECON_INVALID_ARG, "NULL argument");
+    if (n_pre < 0 || n_refine < 0 || n_cold < 0) return fail(RECON_INVALID_ARG, "iteration counts must be >= 0");
+    if (!(residual_ratio > 0)) return fail(RECON_INVALID_ARG, "residual_ratio must be > 0");
+    return RECON_OK;
+}
+
+}  // namespace
+
+// The allocation-free warm start's scratch: one copy per GPU, held until the
+// process ends.  Host code never passes this name to a kernel or a copy (on
+// the host it is only a stand-in for the symbol); it uses the device address
+// that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch, looked up once per device.
+recon_status scratch_of_current_device(unsigned char** out)
+{
+    int dev = -1;
+    RECON_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(RECON_INVALID_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(RECON_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<unsigned char*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return RECON_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+recon_status recon_warm_start(recon_batch_handle* b, recon_cnn* net, const float* const* d_counts, const float* i0,
+                              float* const* d_imgs, int32_t n_pre, int32_t n_refine, int32_t n_cold,
+                              double residual_ratio, double* h_residual, double* h_floor, int32_t* h_fallback,
+                              void* stream)
+{
+    recon_status st = check_warm_args(b, net, d_counts, i0, d_imgs, n_pre, n_refine, n_cold, residual_ratio);
+    if (st != RECON_OK) return st;
+    return warm_start_impl(b, net, d_counts, i0, d_imgs, n_pre, n_refine, n_cold, residual_ratio, h_residual,
+                           h_floor, h_fallback, as_stream(stream), nullptr);
+}
+
+recon_status recon_warm_start_noalloc(recon_batch_handle* b, recon_cnn* net, const float* const* d_counts,
+                                      const float* i0, float* const* d_imgs, int32_t n_pre, int32_t n_refine,
+                                      int32_t n_cold, double residual_ratio, double* h_residual, double* h_floor,
+                                      int32_t* h_fallback, void* stream)
+{
+    recon_status st = check_warm_args(b, net, d_counts, i0, d_imgs, n_pre, n_refine, n_cold, residual_ratio);
+    if (st != RECON_OK) return st;
+    if ((int)b->h.size() > NOALLOC_MAX_SLICES)
+        return fail(RECON_INVALID_ARG, "recon_warm_start_noalloc takes at most 4096 slices per call");
+    for (recon_handle* h : b->h)
+        if ((size_t)h->geo.n * h->geo.n > NOALLOC_STAGE_FLOATS)
+            return fail(RECON_INVALID_ARG, "recon_warm_start_noalloc takes images of at most 2048 x 2048");
+    int dev = -1;
+    RECON_HIP_TRY(hipGetDevice(&dev));
+    if (dev != b->h[0]->device)
+        return fail(RECON_INVALID_ARG, "the batch's device must be the current device");
+    unsigned char* sp = nullptr;
+    st = scratch_of_current_device(&sp);
+    if (st != RECON_OK) return st;
+    return warm_start_impl(b, net, d_counts, i0, d_imgs, n_pre, n_refine, n_cold, residual_ratio, h_residual,
+                           h_floor, h_fallback, as_stream(stream), sp);
 }
 
 }  // extern "C"

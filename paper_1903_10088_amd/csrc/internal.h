@@ -208,6 +208,12 @@ hipStream_t as_stream(void* s);
 recon_status validate_create(const recon_geometry* geom, int subsets, double beta, const recon_params* params);
 StepRule rule_of(const recon_handle* h);
 UpdateConst update_const(const recon_handle* h);
+// recon_os_iterate_ex on a HIP stream; new_graphs = false replays only epoch
+// graphs the handle has already instantiated and launches the rest directly
+// (same kernels, same bits), so the call creates no graph.
+recon_status os_iterate_run(recon_handle* h, const float* d_counts, float i0, float* d_img, int n_iter,
+                            recon_state* state, double* d_trace, const double* d_lambda_schedule, double* d_f_hist,
+                            float* d_best, hipStream_t s, bool new_graphs);
 
 #define RECON_HIP_TRY(expr)                                                                              \
     do {                                                                                                 \

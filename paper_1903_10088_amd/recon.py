@@ -55,7 +55,8 @@ EXPORTS = ["recon_default_params", "recon_status_string", "recon_last_error", "r
            "recon_cnn_param_count", "recon_cnn_create", "recon_cnn_destroy", "recon_cnn_get_state",
            "recon_cnn_set_state", "recon_cnn_save", "recon_cnn_load", "recon_cnn_forward", "recon_cnn_loss_grad",
            "recon_cnn_adam_step", "recon_cnn_train_step", "recon_cnn_tensor", "recon_cnn_time_kernels",
-           "recon_data_residual", "recon_warm_start", "recon_fbp", "recon_rebin_helical"]
+           "recon_data_residual", "recon_warm_start", "recon_warm_start_noalloc", "recon_fbp",
+           "recon_rebin_helical"]
 
 _lib = None
 
@@ -100,6 +101,7 @@ def lib():
         L.recon_batch.argtypes = [P(Geometry_c), i32, i32, d, P(Params_c), PP, P(f), PP, i32, vp]
         L.recon_data_residual.argtypes = [vp, vp, f, vp, vp, vp]
         L.recon_warm_start.argtypes = [vp, vp, PP, P(f), PP, i32, i32, i32, d, P(d), P(d), P(i32), vp]
+        L.recon_warm_start_noalloc.argtypes = [vp, vp, PP, P(f), PP, i32, i32, i32, d, P(d), P(d), P(i32), vp]
         L.recon_cnn_param_count.argtypes = []
         L.recon_cnn_param_count.restype = i64
         L.recon_cnn_create.argtypes = [P(f), i32, i32, f, P(vp)]
@@ -448,8 +450,9 @@ class Batch:
         _check(lib().recon_batch_set_launch(self._h, fp_segments, bp_variant), "recon_batch_set_launch")
 
     def warm_start(self, net, counts, i0s, imgs=None, n_pre: int = 10, n_refine: int = 40, n_cold: int = 500,
-                   residual_ratio: float = 1.0):
-        """recon_warm_start: returns (imgs, residual, floor, fallback) with numpy per-slice arrays."""
+                   residual_ratio: float = 1.0, noalloc: bool = False):
+        """recon_warm_start (noalloc: recon_warm_start_noalloc, the entry point that allocates no device
+        memory): returns (imgs, residual, floor, fallback) with numpy per-slice arrays."""
         torch = _torch()
         n = len(self.geometries)
         if imgs is None:
@@ -457,13 +460,13 @@ class Batch:
         i0 = (ctypes.c_float * n)(*[float(x) for x in i0s])
         res, flo = np.zeros(n), np.zeros(n)
         fb = np.zeros(n, dtype=np.int32)
-        _check(lib().recon_warm_start(self._h, net._h, _ptr_array(counts, torch.float32, self._count_shapes(), "counts"),
-                                      i0, _ptr_array(imgs, torch.float32, self._img_shapes(), "img"), int(n_pre),
-                                      int(n_refine), int(n_cold), float(residual_ratio),
-                                      res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                      flo.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                      fb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _stream()),
-               "recon_warm_start")
+        name = "recon_warm_start_noalloc" if noalloc else "recon_warm_start"
+        _check(getattr(lib(), name)(self._h, net._h, _ptr_array(counts, torch.float32, self._count_shapes(), "counts"),
+                                    i0, _ptr_array(imgs, torch.float32, self._img_shapes(), "img"), int(n_pre),
+                                    int(n_refine), int(n_cold), float(residual_ratio),
+                                    res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    flo.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    fb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _stream()), name)
         return imgs, res, flo, fb
 
 
