@@ -122,7 +122,8 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="host threads of the oracle baseline (0 = all; 1 = the paper's single-CPU setting)")
     ap.add_argument("--fp-segments", type=int, default=0)
-    ap.add_argument("--bp-variant", type=int, default=0, help="1 = global reads, 2 = LDS-staged (0 = default)")
+    ap.add_argument("--bp-variant", type=int, default=0,
+                    help="update variant as recon_set_launch numbers them (1-6; 0 = the library's default, 6)")
     ap.add_argument("--cnn-batch", type=int, default=8,
                     help="slices per timed CNN kernel launch (512 x 512; 0 = skip the CNN leg)")
     ap.add_argument("--batch-slices", type=int, default=64,

@@ -258,12 +258,16 @@ recon_status recon_data_residual(recon_handle* h, const float* d_counts, float i
 /* Geometry queries (host, synchronous). */
 recon_status recon_subset_size(recon_handle* h, int32_t subset, int32_t* n_views_out);
 
-/* Launch shapes are chosen by the library; this pins them for tuning and
- * tests.  fp_segments: threads sharing one ray in the projector, in
+/* Launch shapes are chosen by the library (a new handle uses 16 threads per
+ * projector ray from 384^2 images up, 8 from 192^2, else 4, and bp_variant 6);
+ * this pins them for tuning and tests.  fp_segments: threads sharing one ray in the projector, in
  * {1, 2, 4, 8, 16}.  bp_variant: 1 = one pixel per thread, candidates read
  * from global memory; 2 = one pixel per thread, candidates staged per 16x16
- * tile in LDS; 3, 4, 5 = LDS-staged with 1x2, 2x1, 2x2 pixels per thread.  0
- * keeps the current value.  Every choice gives bitwise identical results.
+ * tile in LDS; 3, 4, 5 = LDS-staged with 1x2, 2x1, 2x2 pixels per thread;
+ * 6 = LDS-staged with 2x2 pixels per thread and the views split over the four
+ * waves of a tile.  0 keeps the current value.  Every choice gives bitwise
+ * identical results (each pixel sums its views in four interleaved groups,
+ * added in a fixed order).
  * Cached graphs are dropped. */
 recon_status recon_set_launch(recon_handle* h, int32_t fp_segments, int32_t bp_variant);
 
@@ -309,8 +313,9 @@ recon_status recon_batch_tune(recon_batch_handle* b, const float* const* d_count
                               int32_t reps, int32_t* fp_segments_out, int32_t* bp_variant_out, void* stream);
 
 /* Pins the batch's launch shapes (as recon_set_launch; 0 keeps).  A new batch
- * starts with 4 threads per projector ray and bp_variant 3 (1x2 pixels per
- * thread), the tuner's choice for batches of 512^2 slices. */
+ * starts with 4 threads per projector ray and bp_variant 6 (2x2 pixels per
+ * thread, views split over a tile's waves), the tuner's choice for batches of
+ * 512^2 slices. */
 recon_status recon_batch_set_launch(recon_batch_handle* b, int32_t fp_segments, int32_t bp_variant);
 
 /* One-shot form: create, run n_iter sub-iterations, wait, destroy. */

@@ -469,7 +469,7 @@ recon_status recon_set_launch(recon_handle* h, int32_t fp_segments, int32_t bp_v
         h->fp_segments = fp_segments;
     }
     if (bp_variant != 0) {
-        if (bp_variant < 1 || bp_variant > 5) return fail(RECON_INVALID_ARG, "bp_variant must be in [0, 5]");
+        if (bp_variant < 1 || bp_variant > 6) return fail(RECON_INVALID_ARG, "bp_variant must be in [0, 6]");
         h->bp_variant = bp_variant - 1;
     }
     drop_graphs(h);

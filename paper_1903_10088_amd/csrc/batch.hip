@@ -37,9 +37,10 @@ struct recon_batch_handle {
     int last_in = 0;               // image / state buffer holding the last run's result
     // launch shapes until recon_batch_tune or recon_batch_set_launch: what the
     // tuner picks for batches of 512^2 slices (4 threads per projector ray, the
-    // 1x2-pixel staged update); results are identical for every choice
+    // 2x2-pixel update with the views split over a tile's waves); results are
+    // identical for every choice
     int fp_segments = BATCH_FP_SEGMENTS;
-    int bp_variant = 2;
+    int bp_variant = 5;
     std::vector<int> xcd;  // XCD of each slice
 
     SliceDesc* d_slices = nullptr;
@@ -386,7 +387,7 @@ recon_status recon_batch_set_launch(recon_batch_handle* b, int32_t fp_segments, 
         b->fp_segments = fp_segments;
     }
     if (bp_variant != 0) {
-        if (bp_variant < 1 || bp_variant > 5) return fail(RECON_INVALID_ARG, "bp_variant must be in [0, 5]");
+        if (bp_variant < 1 || bp_variant > 6) return fail(RECON_INVALID_ARG, "bp_variant must be in [0, 6]");
         b->bp_variant = bp_variant - 1;
     }
     return upload_work(b);
@@ -484,7 +485,7 @@ recon_status recon_batch_tune(recon_batch_handle* b, const float* const* d_count
     int best_var = b->bp_variant;
     if (st == RECON_OK && err == hipSuccess) {
         best_ms = 3.0e38f;
-        for (int var = 0; var < 5; ++var) {
+        for (int var = 0; var < 6; ++var) {
             float ms = 0.0f;
             err = timed(
                 [&](int sub) {

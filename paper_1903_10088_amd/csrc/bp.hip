@@ -31,9 +31,23 @@ inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
 constexpr int TILE = 16;
 constexpr int STAGE_VIEWS = 8;   // views per LDS chunk
-constexpr int UNROLL = 4;        // candidates evaluated without a loop
-constexpr int STAGE_GAP = UNROLL - 1;  // zero-weight slots after each major-axis part of a staged row
+constexpr int UNROLL = 4;        // candidates evaluated without a loop (one pixel per thread)
+constexpr int QUAD_UNROLL = 5;   // the same for 2x2 pixels per thread
+constexpr int STAGE_GAP = QUAD_UNROLL - 1;  // zero-weight slots after each major-axis part of a staged row
 constexpr int STAGE_ROW = STAGE_SLOTS + 2 * STAGE_GAP;
+static_assert(STAGE_GAP >= UNROLL - 1, "the padded rows must cover every unrolled candidate");
+
+// Summation order of a pixel's backprojection, shared by every variant: view q
+// of the subset belongs to group (q - q0) mod VIEW_GROUPS, each group sums its
+// views in increasing order (in a view, the x-major channels and then the
+// y-major ones, channels in increasing order), and the groups are added as
+// (g0 + g1) + (g2 + g3).  Launch shapes that split the views differently
+// therefore give the same bits.  Chunks of staged views start at multiples of
+// 4 within the subset, so within a chunk the group of view cq is cq mod 4.
+constexpr int VIEW_GROUPS = 4;
+static_assert(STAGE_VIEWS % VIEW_GROUPS == 0, "chunks must start at a group boundary");
+
+__device__ __forceinline__ float combine_groups(float a0, float a1, float a2, float a3) { return (a0 + a1) + (a2 + a3); }
 
 // Adds the contributions of channels [lo, hi] (lo <= hi) of one view to acc,
 // in increasing channel order.  `t` is the pixel's coordinate along the rays'
@@ -118,8 +132,7 @@ __device__ __forceinline__ float gather_global(const Geo& G, const ViewRec* __re
 {
     const float X = (float)i - G.c, Y = (float)j - G.c;
     const float fi = (float)i, fj = (float)j;
-    float acc = 0.0f;
-    for (int q = q0; q < q0 + nq; ++q) {
+    auto one_view = [&](int q, float acc) {
         const ViewRec v = V[q];
         const PixelView pv = pixel_view(G, v, X, Y);
         int x0, x1, y0, y1;
@@ -134,8 +147,15 @@ __device__ __forceinline__ float gather_global(const Geo& G, const ViewRec* __re
             candidate_range(pv.kp, pv.hwy, y0, y1, lo, hi);
             if (lo <= hi) acc = add_window(acc, lo, hi, fj, fi, GlobalRead{rg + v.ray0, w + v.ray0, hi});
         }
+        return acc;
+    };
+    float acc[VIEW_GROUPS] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int q = q0; q < q0 + nq; q += VIEW_GROUPS) {
+#pragma unroll
+        for (int g = 0; g < VIEW_GROUPS; ++g)
+            if (q + g < q0 + nq) acc[g] = one_view(q + g, acc[g]);
     }
-    return acc;
+    return combine_groups(acc[0], acc[1], acc[2], acc[3]);
 }
 
 // A staged row holds channels [k0, k0 + cnt) in order, with STAGE_GAP
@@ -225,42 +245,56 @@ __device__ __forceinline__ void stage_store(StageLds& S, int b, int t0, int cv, 
     }
 }
 
+// Table of views [s0, s0 + sn) for the tile centred at (Xc, Yc), one view per
+// thread: each view's linear channel model over the tile, the channel range
+// that holds every pixel's window, and the window half-widths, widened by the
+// model's spread over a PX x PY block of pixels when a thread owns such a
+// block.  The slot bases put the part from k_split on behind the gap.
+__device__ __forceinline__ void stage_table(StageLds& S, const Geo& G, const ViewRec* __restrict__ V, int s0, int sn,
+                                            float Xc, float Yc, int PX, int PY)
+{
+    const int tid = threadIdx.x;
+    if (tid < sn) {
+        const ViewRec v = V[s0 + tid];
+        const TileView tv = tile_view(G, v, Xc, Yc);
+        int k0, cnt;
+        stage_range(tv, G.nch, STAGE_SLOTS, k0, cnt);
+        const bool gap = k0 < v.k_split && v.k_split < k0 + cnt;
+        const int kb = gap ? k0 - STAGE_GAP : k0;
+        int x0, x1, y0, y1;
+        major_intervals(v, G.nch, x0, x1, y0, y1);
+        float hwx = tv.hwx, hwy = tv.hwy;
+        if (PX * PY > 1) {
+            const float spread = block_spread(tv, PX, PY);
+            hwx = tv.hwx + spread;
+            hwy = tv.hwy + spread;
+        }
+        S.va[tid] = make_float4(tv.kpc, tv.gx, tv.gy, hwx);
+        S.vb[tid] = make_float4(hwy, (float)x0, (float)(x1 - 1), (float)y0);
+        S.vc[tid] = make_int4(__float_as_int((float)(y1 - 1)), cnt, x0 == v.k_split ? kb : k0,
+                              y0 == v.k_split ? kb : k0);
+        S.k0[tid] = k0;
+        S.kb[tid] = kb;
+        S.cnt[tid] = cnt;
+        S.ray0[tid] = v.ray0;
+        S.ks[tid] = v.k_split;
+    }
+}
+
 // g_L at pixel (i, j) of a 16x16 tile with LDS staging.  Must be called by all
 // 256 threads of the block (it has barriers); `inside` marks real pixels.
 __device__ __forceinline__ float gather_staged(StageLds& S, const Geo& G, const ViewRec* __restrict__ V,
                                                const RayGeo* __restrict__ rg, const float* __restrict__ w, int q0,
                                                int nq, int i, int j, bool inside, int ti0, int tj0)
 {
-    const int tid = threadIdx.x;
     const float fi = (float)i, fj = (float)j;
     // offsets from the tile centre (exact in float32)
     const float dX = (float)(i - ti0) - 7.5f, dY = (float)(j - tj0) - 7.5f;
     const float Xc = (float)ti0 + 7.5f - G.c, Yc = (float)tj0 + 7.5f - G.c;
-    float acc = 0.0f;
+    float acc[VIEW_GROUPS] = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int s0 = q0; s0 < q0 + nq; s0 += STAGE_TABLE) {
         const int sn = min(STAGE_TABLE, q0 + nq - s0);
-        if (tid < sn) {
-            // each view's linear channel model over the tile and the channel
-            // range that holds every pixel's window
-            const ViewRec v = V[s0 + tid];
-            const TileView tv = tile_view(G, v, Xc, Yc);
-            int k0, cnt;
-            stage_range(tv, G.nch, STAGE_SLOTS, k0, cnt);
-            const bool gap = k0 < v.k_split && v.k_split < k0 + cnt;
-            const int kb = gap ? k0 - STAGE_GAP : k0;
-            int x0, x1, y0, y1;
-            major_intervals(v, G.nch, x0, x1, y0, y1);
-            // slot bases: the part from k_split on sits behind the gap
-            S.va[tid] = make_float4(tv.kpc, tv.gx, tv.gy, tv.hwx);
-            S.vb[tid] = make_float4(tv.hwy, (float)x0, (float)(x1 - 1), (float)y0);
-            S.vc[tid] = make_int4(__float_as_int((float)(y1 - 1)), cnt, x0 == v.k_split ? kb : k0,
-                                  y0 == v.k_split ? kb : k0);
-            S.k0[tid] = k0;
-            S.kb[tid] = kb;
-            S.cnt[tid] = cnt;
-            S.ray0[tid] = v.ray0;
-            S.ks[tid] = v.k_split;
-        }
+        stage_table(S, G, V, s0, sn, Xc, Yc, 1, 1);
         __syncthreads();
         StagePrefetch P;
         stage_load(S, rg, w, 0, min(STAGE_VIEWS, sn), P);
@@ -272,7 +306,7 @@ __device__ __forceinline__ float gather_staged(StageLds& S, const Geo& G, const 
             if (t0 + STAGE_VIEWS < sn) stage_load(S, rg, w, t0 + STAGE_VIEWS, min(STAGE_VIEWS, sn - t0 - STAGE_VIEWS), P);
             // one view of the chunk (a full chunk is unrolled, so the table
             // reads of later views can be issued ahead of earlier views' work)
-            auto view = [&](int cq) {
+            auto view = [&](int cq, float& acc) {
                 const int t = t0 + cq;
                 const ViewRec v = V[s0 + t];
                 const float4 va = S.va[t], vb = S.vb[t];
@@ -306,15 +340,17 @@ __device__ __forceinline__ float gather_staged(StageLds& S, const Geo& G, const 
             if (inside) {
                 if (cv == STAGE_VIEWS) {
 #pragma unroll
-                    for (int cq = 0; cq < STAGE_VIEWS; ++cq) view(cq);
+                    for (int cq = 0; cq < STAGE_VIEWS; ++cq) view(cq, acc[cq % VIEW_GROUPS]);
                 } else {
-                    for (int cq = 0; cq < cv; ++cq) view(cq);
+#pragma unroll
+                    for (int cq = 0; cq < STAGE_VIEWS; ++cq)
+                        if (cq < cv) view(cq, acc[cq % VIEW_GROUPS]);
                 }
             }
         }
         __syncthreads();  // the table and both buffers are rewritten by the next group of views
     }
-    return acc;
+    return combine_groups(acc[0], acc[1], acc[2], acc[3]);
 }
 
 // ----------------------------------------------------------------------------
@@ -349,7 +385,7 @@ struct StageLdsBlk {
 // MAJ_X: rays sampled per column (t = column, centre = row) or per row.
 // MASK: candidates past hi get w = 0 (global reads, clamped into [lo, hi]);
 // without it they must be zero-weight rays or slots (the padded LDS rows).
-template <int PX, int PY, bool MAJ_X, bool MASK, class Read>
+template <int PX, int PY, bool MAJ_X, bool MASK, int NU = BLK_UNROLL, class Read>
 __device__ __forceinline__ void add_window_blk(float (&acc)[PY][PX], int lo, int hi, int i0, int j0, Read read)
 {
     constexpr int NT = MAJ_X ? PX : PY;  // sampling lines in the block
@@ -373,8 +409,8 @@ __device__ __forceinline__ void add_window_blk(float (&acc)[PY][PX], int lo, int
         }
     };
 #pragma unroll
-    for (int u = 0; u < BLK_UNROLL; ++u) body(lo + u, lo + u <= hi);
-    for (int k = lo + BLK_UNROLL; k <= hi; ++k) body(k, true);
+    for (int u = 0; u < NU; ++u) body(lo + u, lo + u <= hi);
+    for (int k = lo + NU; k <= hi; ++k) body(k, true);
 }
 
 // Global reads for the blocked gather, clamped into [lo, hi].
@@ -393,8 +429,8 @@ struct GlobalReadBlk {
 template <int PX, int PY>
 __device__ __forceinline__ void gather_block(StageLdsBlk& S, const Geo& G, const ViewRec* __restrict__ V,
                                              const RayGeo* __restrict__ rg, const float* __restrict__ w, int q0,
-                                             int nq, int i0, int j0, bool active, float (&acc)[PY][PX], int ti0,
-                                             int tj0)
+                                             int nq, int i0, int j0, bool active,
+                                             float (&acc)[VIEW_GROUPS][PY][PX], int ti0, int tj0)
 {
     const int tid = threadIdx.x;
     constexpr int NTH = 256 / (PX * PY);
@@ -449,8 +485,8 @@ __device__ __forceinline__ void gather_block(StageLdsBlk& S, const Geo& G, const
                 }
             }
             __syncthreads();
-            if (active) {
-                for (int cq = 0; cq < cv; ++cq) {
+            // views of the chunk in groups of VIEW_GROUPS, each into its group's accumulators
+            auto view = [&](int cq, float (&a)[PY][PX]) {
                     const int t = t0 + cq;
                     const ViewRec v = V[s0 + t];
                     const int cnt = S.cnt[t];
@@ -466,10 +502,10 @@ __device__ __forceinline__ void gather_block(StageLdsBlk& S, const Geo& G, const
                         candidate_range(kp, tv.hwx + spread, x0, x1, lo, hi);
                         if (lo <= hi) {
                             if (cnt > 0)  // every window lies in the staged range (stage_range)
-                                add_window_blk<PX, PY, true, false>(acc, lo, hi, i0, j0,
+                                add_window_blk<PX, PY, true, false>(a, lo, hi, i0, j0,
                                                                     LdsRead{S.geo[cq], S.w[cq], bx});
                             else
-                                add_window_blk<PX, PY, true, true>(acc, lo, hi, i0, j0,
+                                add_window_blk<PX, PY, true, true>(a, lo, hi, i0, j0,
                                                                    GlobalReadBlk{rg + v.ray0, w + v.ray0, hi});
                         }
                     }
@@ -478,17 +514,103 @@ __device__ __forceinline__ void gather_block(StageLdsBlk& S, const Geo& G, const
                         candidate_range(kp, tv.hwy + spread, y0, y1, lo, hi);
                         if (lo <= hi) {
                             if (cnt > 0)
-                                add_window_blk<PX, PY, false, false>(acc, lo, hi, i0, j0,
+                                add_window_blk<PX, PY, false, false>(a, lo, hi, i0, j0,
                                                                      LdsRead{S.geo[cq], S.w[cq], by});
                             else
-                                add_window_blk<PX, PY, false, true>(acc, lo, hi, i0, j0,
+                                add_window_blk<PX, PY, false, true>(a, lo, hi, i0, j0,
                                                                     GlobalReadBlk{rg + v.ray0, w + v.ray0, hi});
                         }
                     }
+            };
+            if (active) {
+                for (int c0 = 0; c0 < cv; c0 += VIEW_GROUPS) {
+#pragma unroll
+                    for (int g = 0; g < VIEW_GROUPS; ++g)
+                        if (c0 + g < cv) view(c0 + g, acc[g]);
                 }
             }
             __syncthreads();
         }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// 2x2 pixels per lane, one view group per wave
+// ----------------------------------------------------------------------------
+
+// The four waves of a block share a 16x16 tile and its staged rows; lane l
+// owns the 2x2 block of pixels at (2 (l mod 8), 2 (l / 8)) of the tile and wave
+// g sums the views of group g (views g and g + 4 of every chunk).  Per view and
+// major axis one window of channels serves the lane's four pixels (the tile
+// model at the block centre, widened by its spread over the block), and per
+// candidate the lattice and residual parts of the crossing are formed once per
+// sampling line of the block: a quarter of the window set-ups and half of the
+// crossing arithmetic of one pixel per thread, with as many waves per tile.
+// acc[b][a] receives group g's sum for pixel (2 (l mod 8) + a, 2 (l / 8) + b).
+__device__ __forceinline__ void gather_quad(StageLds& S, const Geo& G, const ViewRec* __restrict__ V,
+                                            const RayGeo* __restrict__ rg, const float* __restrict__ w, int q0,
+                                            int nq, int ti0, int tj0, float (&acc)[2][2])
+{
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int bxl = 2 * (lane & 7), byl = 2 * (lane >> 3);
+    const int i0 = ti0 + bxl, j0 = tj0 + byl;
+    const bool active = i0 < G.n && j0 < G.n;
+    // the block centre's offsets from the tile centre (exact in float32)
+    const float dXb = (float)bxl + 0.5f - 7.5f, dYb = (float)byl + 0.5f - 7.5f;
+    const float Xc = (float)ti0 + 7.5f - G.c, Yc = (float)tj0 + 7.5f - G.c;
+    for (int s0 = q0; s0 < q0 + nq; s0 += STAGE_TABLE) {
+        const int sn = min(STAGE_TABLE, q0 + nq - s0);
+        stage_table(S, G, V, s0, sn, Xc, Yc, 2, 2);
+        __syncthreads();
+        StagePrefetch P;
+        stage_load(S, rg, w, 0, min(STAGE_VIEWS, sn), P);
+        for (int t0 = 0, b = 0; t0 < sn; t0 += STAGE_VIEWS, b ^= 1) {
+            const int cv = min(STAGE_VIEWS, sn - t0);
+            // buffer b was last read by chunk t0 - 2, before the previous barrier
+            stage_store(S, b, t0, cv, P);
+            __syncthreads();
+            if (t0 + STAGE_VIEWS < sn) stage_load(S, rg, w, t0 + STAGE_VIEWS, min(STAGE_VIEWS, sn - t0 - STAGE_VIEWS), P);
+            // view cq of the chunk (wave-uniform)
+            auto view = [&](int cq) {
+                const int t = t0 + cq;
+                const ViewRec v = V[s0 + t];
+                const float4 va = S.va[t], vb = S.vb[t];
+                const int4 vc = S.vc[t];
+                const int cnt = vc.y;
+                const float kp = fmaf(va.y, dXb, fmaf(va.z, dYb, va.x));
+                int x0, x1, y0, y1;
+                major_intervals(v, G.nch, x0, x1, y0, y1);
+                if (x0 < x1) {
+                    int lo, hi;
+                    candidate_range_f(kp, va.w, vb.y, vb.z, lo, hi);
+                    if (lo <= hi) {
+                        if (cnt > 0)  // every window lies in the staged range (stage_range)
+                            add_window_blk<2, 2, true, false, QUAD_UNROLL>(acc, lo, hi, i0, j0,
+                                                                           LdsRead{S.geo[b][cq], S.w[b][cq], vc.z});
+                        else
+                            add_window_blk<2, 2, true, true, QUAD_UNROLL>(acc, lo, hi, i0, j0,
+                                                                          GlobalReadBlk{rg + v.ray0, w + v.ray0, hi});
+                    }
+                }
+                if (y0 < y1) {
+                    int lo, hi;
+                    candidate_range_f(kp, vb.x, vb.w, __int_as_float(vc.x), lo, hi);
+                    if (lo <= hi) {
+                        if (cnt > 0)
+                            add_window_blk<2, 2, false, false, QUAD_UNROLL>(acc, lo, hi, i0, j0,
+                                                                            LdsRead{S.geo[b][cq], S.w[b][cq], vc.w});
+                        else
+                            add_window_blk<2, 2, false, true, QUAD_UNROLL>(acc, lo, hi, i0, j0,
+                                                                           GlobalReadBlk{rg + v.ray0, w + v.ray0, hi});
+                    }
+                }
+            };
+            if (active) {
+                if (grp < cv) view(grp);
+                if (grp + VIEW_GROUPS < cv) view(grp + VIEW_GROUPS);
+            }
+        }
+        __syncthreads();  // the table and both buffers are rewritten by the next group of views
     }
 }
 
@@ -738,13 +860,20 @@ __device__ __forceinline__ void bp_update_tile_blk(Geo G, const ViewRec* __restr
         const int gj = tj0 + ly - 1, gi = ti0 + lx - 1;
         s[ly][lx] = (gj >= 0 && gj < G.n && gi < G.n + PAD) ? img[(size_t)gj * G.P + gi + PAD] : 0.0f;
     }
+    float accg[VIEW_GROUPS][PY][PX];
+#pragma unroll
+    for (int g = 0; g < VIEW_GROUPS; ++g)
+#pragma unroll
+        for (int b = 0; b < PY; ++b)
+#pragma unroll
+            for (int a = 0; a < PX; ++a) accg[g][b][a] = 0.0f;
+    gather_block<PX, PY>(S, G, V, rg, w, sc.q0, sc.nq, i0, j0, i0 < G.n && j0 < G.n, accg, ti0,
+                         tj0);  // has barriers
     float acc[PY][PX];
 #pragma unroll
     for (int b = 0; b < PY; ++b)
 #pragma unroll
-        for (int a = 0; a < PX; ++a) acc[b][a] = 0.0f;
-    gather_block<PX, PY>(S, G, V, rg, w, sc.q0, sc.nq, i0, j0, i0 < G.n && j0 < G.n, acc, ti0,
-                         tj0);  // has barriers
+        for (int a = 0; a < PX; ++a) acc[b][a] = combine_groups(accg[0][b][a], accg[1][b][a], accg[2][b][a], accg[3][b][a]);
 
     StepDecision dec{0.0, false};
     DevState in{};
@@ -781,7 +910,70 @@ __device__ __forceinline__ void bp_update_tile_blk(Geo G, const ViewRec* __restr
     }
 }
 
-// Update body for variant VAR (0 global, 1 LDS-staged, 2 1x2, 3 2x1, 4 2x2).
+// 2x2-pixel, view-group form of bp_update_tile (256 threads per 16x16 tile):
+// the four groups' sums meet in LDS and each thread then finishes one pixel.
+// Same arithmetic per pixel, same bits.
+__device__ __forceinline__ void bp_update_tile_quad(Geo G, const ViewRec* __restrict__ V,
+                                                    const RayGeo* __restrict__ rg, const float* __restrict__ w,
+                                                    const double* __restrict__ part,
+                                                    const DevState* __restrict__ st_in, DevState* __restrict__ st_out,
+                                                    const float* __restrict__ img, float* __restrict__ img_out,
+                                                    float* __restrict__ imgT_out, UpdateScalars sc, int ti0, int tj0,
+                                                    const DevState* __restrict__ st_pre)
+{
+    __shared__ float s[TILE + 2][TILE + 3];
+    __shared__ float t[TILE][TILE + 1];
+    __shared__ double red[4];
+    __shared__ StageLds S;
+    __shared__ float gsum[VIEW_GROUPS][TILE * TILE];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < (TILE + 2) * (TILE + 2); e += 256) {
+        const int ly = e / (TILE + 2), lx = e - ly * (TILE + 2);
+        const int gj = tj0 + ly - 1, gi = ti0 + lx - 1;
+        s[ly][lx] = (gj >= 0 && gj < G.n && gi < G.n + PAD) ? img[(size_t)gj * G.P + gi + PAD] : 0.0f;
+    }
+    float acc[2][2] = {{0.0f, 0.0f}, {0.0f, 0.0f}};
+    gather_quad(S, G, V, rg, w, sc.q0, sc.nq, ti0, tj0, acc);  // has barriers
+    {
+        const int lane = tid & 63, grp = tid >> 6;
+        const int bxl = 2 * (lane & 7), byl = 2 * (lane >> 3);
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) gsum[grp][(byl + b) * TILE + bxl + a] = acc[b][a];
+    }
+
+    StepDecision dec{0.0, false};
+    DevState in{};
+    if (st_pre) {
+        dec.lam = st_pre->lambda;
+    } else {
+        const double f = block_sum<256>(part, (sc.nrays + SQ_GROUP - 1) / SQ_GROUP, red) / (double)sc.nrays;
+        in = *st_in;
+        dec = step_rule(in, sc.rule, f);
+        if (ti0 == 0 && tj0 == 0 && tid == 0) record_state(in, sc.rule, f, dec.lam, st_out);
+    }
+    __syncthreads();  // (block_sum has one too; this covers st_pre) the group sums are in LDS
+    const float lam = (float)dec.lam;
+    const int tx = tid & 15, ty = tid >> 4;
+    const int i = ti0 + tx, j = tj0 + ty;
+    float mu_new = 0.0f;
+    if (i < G.n && j < G.n) {
+        const float gl = combine_groups(gsum[0][tid], gsum[1][tid], gsum[2][tid], gsum[3][tid]);
+        const float gr = tv_neg_grad<TILE + 3>(s, tx + 1, ty + 1, i, j, G.n, sc.uc.eps);
+        const float v = s[ty + 1][tx + 1] + lam * fmaf(sc.uc.c_l, gl, sc.uc.c_r * gr);
+        mu_new = in_disc(i, j, G.n) ? fmaxf(v, 0.0f) : 0.0f;
+        img_out[(size_t)j * G.P + i + PAD] = mu_new;
+        if (dec.keep) in.best[(size_t)j * G.n + i] = mu_new;
+    }
+    t[ty][tx] = mu_new;
+    __syncthreads();
+    const int ii = ti0 + ty, jj = tj0 + tx;
+    if (ii < G.n && jj < G.n) imgT_out[(size_t)ii * G.P + jj + PAD] = t[tx][ty];
+}
+
+// Update body for variant VAR (0 global, 1 LDS-staged, 2 1x2, 3 2x1, 4 2x2, 5 2x2 per
+// lane with one view group per wave).
 template <int VAR>
 __device__ __forceinline__ void bp_update_any(Geo G, const ViewRec* __restrict__ V, const RayGeo* __restrict__ rg,
                                               const float* __restrict__ w, const double* __restrict__ part,
@@ -796,10 +988,11 @@ __device__ __forceinline__ void bp_update_any(Geo G, const ViewRec* __restrict__
     if constexpr (VAR == 2) bp_update_tile_blk<1, 2>(BP_TILE_ARGS);
     if constexpr (VAR == 3) bp_update_tile_blk<2, 1>(BP_TILE_ARGS);
     if constexpr (VAR == 4) bp_update_tile_blk<2, 2>(BP_TILE_ARGS);
+    if constexpr (VAR == 5) bp_update_tile_quad(BP_TILE_ARGS);
 #undef BP_TILE_ARGS
 }
 
-constexpr int bp_threads(int var) { return var == 4 ? 64 : (var >= 2 ? 128 : 256); }
+constexpr int bp_threads(int var) { return var == 4 ? 64 : (var == 2 || var == 3 ? 128 : 256); }
 
 // One slice: the grid covers its tiles.
 template <int VAR>
@@ -867,6 +1060,7 @@ hipError_t launch_bp_update(const Geo& geo, int variant, const UpdateArgs& a, hi
     case 2: bp_update_kernel<2><<<grid, bp_threads(2), 0, s>>>(BP_ARGS); break;
     case 3: bp_update_kernel<3><<<grid, bp_threads(3), 0, s>>>(BP_ARGS); break;
     case 4: bp_update_kernel<4><<<grid, bp_threads(4), 0, s>>>(BP_ARGS); break;
+    case 5: bp_update_kernel<5><<<grid, bp_threads(5), 0, s>>>(BP_ARGS); break;
     default: return hipErrorInvalidValue;
     }
 #undef BP_ARGS
@@ -883,6 +1077,7 @@ hipError_t launch_bp_update_batch(int variant, const SliceDesc* slices, const Bp
     case 2: bp_update_batch_kernel<2><<<nblocks, bp_threads(2), 0, s>>>(slices, work, sub, in, rule); break;
     case 3: bp_update_batch_kernel<3><<<nblocks, bp_threads(3), 0, s>>>(slices, work, sub, in, rule); break;
     case 4: bp_update_batch_kernel<4><<<nblocks, bp_threads(4), 0, s>>>(slices, work, sub, in, rule); break;
+    case 5: bp_update_batch_kernel<5><<<nblocks, bp_threads(5), 0, s>>>(slices, work, sub, in, rule); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -174,7 +174,7 @@ struct recon_handle {
     double* d_fbp_cs = nullptr;             // [n_views][2] cos / sin of the source angle, subset order (fbp.hip)
 
     int fp_segments = 8;
-    int bp_variant = 1;      // 0: global candidate reads, 1: LDS-staged
+    int bp_variant = 5;      // update variant (launch_bp_update): 5 = 2x2 pixels per lane, views split over the waves
 
     // host copies of the ray tables (pair counts, checks)
     std::vector<recon::RayGeo> h_raygeo;

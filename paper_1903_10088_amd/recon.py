@@ -263,7 +263,7 @@ class Recon:
         return tuple(out)
 
     def set_launch(self, fp_segments: int = 0, bp_variant: int = 0):
-        """fp_segments in {1,2,4,8,16}; bp_variant 1 = global reads, 2 = LDS-staged; 0 keeps."""
+        """fp_segments in {1,2,4,8,16}; bp_variant 1-6 as recon_set_launch numbers them; 0 keeps."""
         _check(lib().recon_set_launch(self._h, fp_segments, bp_variant), "recon_set_launch")
 
     # -- operators ---------------------------------------------------------

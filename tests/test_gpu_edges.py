@@ -55,7 +55,7 @@ def test_unstaged_views_iterate_to_the_oracle_and_agree_across_variants(dev, nam
     counts = torch.from_numpy(sl.counts).to(dev)
     R = recon.Recon(g, M, 1e-3)
     ref = None
-    for bpv in (2, 1, 3, 4, 5):  # LDS-staged, global reads, blocked 1x2, 2x1, 2x2
+    for bpv in (2, 1, 3, 4, 5, 6):  # LDS-staged, global reads, blocked 1x2, 2x1, 2x2, 2x2 with view groups
         R.set_launch(fp_segments=4, bp_variant=bpv)
         img, tr = R.os_iterate(counts, sl.i0, None, 2 * M + 1, trace=True)
         if ref is None:

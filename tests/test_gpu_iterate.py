@@ -133,7 +133,7 @@ def test_launch_shapes_give_identical_bits(dev, name):
     counts = torch.from_numpy(sl.counts).to(dev)
     R = recon.Recon(g, M, 1e-3)
     ref = None
-    shapes = [(seg, 2) for seg in (1, 2, 4, 8, 16)] + [(8, bpv) for bpv in (1, 3, 4, 5)]
+    shapes = [(seg, 2) for seg in (1, 2, 4, 8, 16)] + [(8, bpv) for bpv in (1, 3, 4, 5, 6)]
     for seg, bpv in shapes:
         print(f"{name}: fp_segments={seg} bp_variant={bpv}", flush=True)
         R.set_launch(fp_segments=seg, bp_variant=bpv)
