@@ -28,83 +28,142 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE) recorded in profiles/, or None when
-    the kernel's sources have changed since the counters were taken."""
-    import hashlib
-
-    path = os.path.join(ROOT, "profiles", "traffic_512x800.json")
-    try:
-        rec = json.load(open(path))["kernels"][kernel]
-        h = hashlib.sha256()
-        for f in rec["sources"]:
-            h.update(open(os.path.join(ROOT, f), "rb").read())
-        if h.hexdigest()[:16] != rec["source_sha"]:
-            return None
-        return rec["fetch_bytes"] + rec["write_bytes"]
-    except (OSError, KeyError, ValueError):
-        return None
-
-
-TRAFFIC_SOURCES = {
-    # kernel record name: (name pattern in the counter files, sources it is built from)
-    "bp_update_kernel": ("bp_update_kernel<1>", ["paper_1903_10088_amd/csrc/bp.hip",
+SOURCES_DIRS = ["paper_1903_10088_amd/csrc", "include"]
+COUNTER_RECORD = os.path.join(ROOT, "profiles", "counters_512x800.json")
+# kernel record name: (name pattern in the counter files, the sources it is built from)
+COUNTER_KERNELS = {
+    "bp_update_kernel": ("bp_update_kernel<5>", ["paper_1903_10088_amd/csrc/bp.hip",
                                                  "paper_1903_10088_amd/csrc/gather.h",
                                                  "paper_1903_10088_amd/csrc/internal.h"]),
     "fp_kernel<OS>": ("fp_kernel<16, true>", ["paper_1903_10088_amd/csrc/kernels.hip",
                                               "paper_1903_10088_amd/csrc/gather.h",
                                               "paper_1903_10088_amd/csrc/internal.h"]),
 }
-COUNTER_CMD = ("python3 <repo>/bench.py --steps 1 --warmup 0 --iters 40 --cpu-iters 0 --time-iters 0 "
-               "--cnn-batch 0 --warm-slices 0 --batch-slices 0")
+# counter runs of COUNTER_ARGS (one rocprofv3 --pmc run each, within the per-block limits) and of
+# the plain-copy calibration
+COUNTER_RUNS = {
+    "hbm_fetch": ["FETCH_SIZE"],
+    "hbm_write": ["WRITE_SIZE"],
+    "sq_issue": ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES",
+                 "SQ_ACTIVE_INST_LDS", "SQ_LDS_BANK_CONFLICT"],
+    "sq_wait": ["SQ_WAIT_INST_ANY", "SQ_WAIT_ANY", "SQ_ACTIVE_INST_VALU", "SQ_THREAD_CYCLES_VALU",
+                "SQ_WAIT_INST_LDS", "SQ_INST_LEVEL_LDS"],
+    "l2": ["TCC_HIT_sum", "TCC_MISS_sum"],
+}
+CAL_RUNS = {"cal_fetch": ["FETCH_SIZE"], "cal_write": ["WRITE_SIZE"]}
+COUNTER_ARGS = ("--steps 1 --warmup 0 --iters 40 --cpu-iters 0 --time-iters 0 --cnn-batch 0 --warm-slices 0 "
+                "--batch-slices 0 --rebin-slices 0")
+CAL_MIB = 256
+SIMDS = 1024              # 256 compute units x 4 SIMDs
+CLOCK_HZ = 2.4e9          # peak engine clock
+VALU_PEAK_TOPS = SIMDS * 16 * CLOCK_HZ / 1e12  # non-packed wave64 issue: 16 lanes per SIMD per cycle
 
 
-def summarize_counters(d: str, copy_mib: int = 256, out_path: str | None = None) -> dict:
-    """profiles/traffic_512x800.json from four rocprofv3 --pmc runs under d: pmc_FETCH_SIZE and
-    pmc_WRITE_SIZE of COUNTER_CMD, cal_FETCH_SIZE and cal_WRITE_SIZE of `--calibrate-copy
-    copy_mib` (each with its pmc_counter_collection.csv).  Each counter is averaged per dispatch
-    and scaled by bytes moved / counter reading of the plain copy."""
-    import collections
-    import csv
+def source_hashes(paths=None) -> dict:
+    """sha256 (first 16 hex digits) of the given repo files, or of every library source."""
     import hashlib
 
-    def agg(sub):
-        a = collections.defaultdict(list)
-        for r in csv.DictReader(open(os.path.join(d, sub, "pmc_counter_collection.csv"))):
-            a[r["Kernel_Name"]].append(float(r["Counter_Value"]))
-        return {k: sum(v) / len(v) for k, v in a.items()}
+    if paths is None:
+        paths = sorted(os.path.join(d, f) for d in SOURCES_DIRS for f in os.listdir(os.path.join(ROOT, d)))
+    return {p: hashlib.sha256(open(os.path.join(ROOT, p), "rb").read()).hexdigest()[:16] for p in paths}
 
-    def pick(a, pat):
-        ks = [k for k in a if pat in k]
+
+def combined_sha(hashes: dict, paths) -> str:
+    import hashlib
+
+    return hashlib.sha256("".join(hashes[p] for p in paths).encode()).hexdigest()[:16]
+
+
+def write_stamp(d: str):
+    """Records, at collection time, the hashes of the library sources a counter run is taken from."""
+    import hashlib
+
+    os.makedirs(d, exist_ok=True)
+    so = os.path.join(ROOT, "paper_1903_10088_amd", "librecon.so")
+    rec = {"sources": source_hashes(),
+           "librecon_so": hashlib.sha256(open(so, "rb").read()).hexdigest()[:16] if os.path.exists(so) else None,
+           "time": time.time()}
+    with open(os.path.join(d, "source_stamp.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+
+
+def measured_counters(kernel: str):
+    """The committed counter record of one kernel (HBM bytes per launch from calibrated FETCH_SIZE +
+    WRITE_SIZE, SQ instruction counts per launch), or None when the kernel's sources differ from
+    those the counters were taken from."""
+    try:
+        rec = json.load(open(COUNTER_RECORD))["kernels"][kernel]
+        if combined_sha(source_hashes(rec["sources"]), rec["sources"]) != rec["source_sha"]:
+            return None
+        return rec
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def summarize_counters(d: str, out_path: str | None = None) -> dict:
+    """profiles/counters_512x800.json from the rocprofv3 --pmc runs under d (d/<run>/pmc_counter_collection.csv
+    for every run of COUNTER_RUNS and CAL_RUNS, each with the source_stamp.json its bench.py wrote).
+    Counters are averaged per dispatch; FETCH_SIZE and WRITE_SIZE are scaled by bytes moved / counter
+    reading of the plain copy.  Refuses runs whose stamps differ from each other or from the current
+    sources of a recorded kernel."""
+    import collections
+    import csv
+
+    def agg(run):
+        a = collections.defaultdict(list)
+        for r in csv.DictReader(open(os.path.join(d, run, "pmc_counter_collection.csv"))):
+            a[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in a.items()}, {k: len(v) for k, v in a.items()}
+
+    def pick(a, pat, counter):
+        ks = [k for k in a if pat in k[0] and k[1] == counter]
         if len(ks) != 1:
-            raise SystemExit(f"bench: {len(ks)} kernels match {pat!r} in the counter files")
+            raise SystemExit(f"bench: {len(ks)} kernels match {pat!r} / {counter} in the counter files")
         return a[ks[0]]
 
-    f, w = agg("pmc_FETCH_SIZE"), agg("pmc_WRITE_SIZE")
-    cf = pick(agg("cal_FETCH_SIZE"), "copyBuffer")
-    cw = pick(agg("cal_WRITE_SIZE"), "copyBuffer")
-    copy_kib = copy_mib * 1024
+    stamps = {}
+    for run in list(COUNTER_RUNS) + list(CAL_RUNS):
+        stamps[run] = json.load(open(os.path.join(d, run, "source_stamp.json")))["sources"]
+    first = stamps["hbm_fetch"]
+    now = source_hashes()
+    for run, st in stamps.items():
+        if st != first:
+            raise SystemExit(f"bench: counter run {run} was taken from different sources than hbm_fetch")
+    data = {run: agg(run) for run in COUNTER_RUNS}
+    cf = pick(agg("cal_fetch")[0], "copyBuffer", "FETCH_SIZE")
+    cw = pick(agg("cal_write")[0], "copyBuffer", "WRITE_SIZE")
+    copy_kib = CAL_MIB * 1024
     ff, wf = copy_kib / cf, copy_kib / cw
     kernels = {}
-    for name, (pat, src) in TRAFFIC_SOURCES.items():
-        h = hashlib.sha256()
-        for x in src:
-            h.update(open(os.path.join(ROOT, x), "rb").read())
-        kernels[name] = {"fetch_kib": pick(f, pat), "write_kib": pick(w, pat),
-                         "fetch_bytes": pick(f, pat) * 1024 * ff, "write_bytes": pick(w, pat) * 1024 * wf,
-                         "source_sha": h.hexdigest()[:16], "sources": src}
-    out = {"workload": "512x512, 800 views x 738 channels, 20 subsets (one subset per launch)",
-           "calibration": {"copy_mib": copy_mib, "fetch_kib_read": cf, "write_kib_read": cw,
+    for name, (pat, src) in COUNTER_KERNELS.items():
+        sha = combined_sha(first, src)
+        if sha != combined_sha(now, src):
+            raise SystemExit(f"bench: the sources of {name} changed since the counters were taken")
+        counters = {}
+        n_disp = None
+        for run, names in COUNTER_RUNS.items():
+            vals, counts = data[run]
+            for c in names:
+                counters[c] = pick(vals, pat, c)
+                n_disp = pick(counts, pat, c)
+        rec = {"pattern": pat, "dispatches": n_disp, "counters": counters,
+               "fetch_bytes": counters["FETCH_SIZE"] * 1024 * ff, "write_bytes": counters["WRITE_SIZE"] * 1024 * wf,
+               "valu_issue_s": counters["SQ_INSTS_VALU"] * 4 / (SIMDS * CLOCK_HZ),
+               "l2_hit_rate": counters["TCC_HIT_sum"] / max(1.0, counters["TCC_HIT_sum"] + counters["TCC_MISS_sum"]),
+               "source_sha": sha, "sources": src}
+        kernels[name] = rec
+    cmd = f"python3 <repo>/bench.py {COUNTER_ARGS}"
+    commands = [f"cd /tmp && rocprofv3 --pmc {' '.join(c)} --output-format csv -d <dir>/{run} -o pmc -- "
+                f"{cmd} --stamp <dir>/{run}" for run, c in COUNTER_RUNS.items()]
+    commands += [f"cd /tmp && rocprofv3 --pmc {' '.join(c)} --output-format csv -d <dir>/{run} -o pmc -- "
+                 f"python3 <repo>/bench.py --calibrate-copy {CAL_MIB} --stamp <dir>/{run}" for run, c in CAL_RUNS.items()]
+    commands.append("python3 <repo>/bench.py --summarize-counters <dir>")
+    out = {"workload": "512x512, 800 views x 738 channels, 20 subsets, 40 sub-iterations (two dispatches of "
+                       "each subset per kernel); averages per dispatch",
+           "calibration": {"copy_mib": CAL_MIB, "fetch_kib_read": cf, "write_kib_read": cw,
                            "fetch_factor": ff, "write_factor": wf},
-           "kernels": kernels,
-           "commands": [f"cd /tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o pmc -- {COUNTER_CMD}",
-                        f"cd /tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o pmc -- {COUNTER_CMD}",
-                        "cd /tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o pmc -- "
-                        f"python3 <repo>/bench.py --calibrate-copy {copy_mib}",
-                        "cd /tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o pmc -- "
-                        f"python3 <repo>/bench.py --calibrate-copy {copy_mib}",
-                        "python3 <repo>/bench.py --summarize-counters <dir>"]}
-    with open(out_path or os.path.join(ROOT, "profiles", "traffic_512x800.json"), "w") as fh:
+           "clock_hz": CLOCK_HZ, "simds": SIMDS, "kernels": kernels, "commands": commands}
+    with open(out_path or COUNTER_RECORD, "w") as fh:
         json.dump(out, fh, indent=1)
     return out
 
@@ -134,7 +193,9 @@ def main():
     ap.add_argument("--rebin-slices", type=int, default=16,
                     help="slices of the helical-rebinning leg (0 = skip)")
     ap.add_argument("--summarize-counters", default=None, metavar="DIR",
-                    help="write profiles/traffic_512x800.json from the counter runs under DIR (no GPU)")
+                    help="write profiles/counters_512x800.json from the counter runs under DIR (no GPU)")
+    ap.add_argument("--stamp", default=None, metavar="DIR",
+                    help="write DIR/source_stamp.json (hashes of the library sources) before running")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 10 plain device copies of MIB MiB (reference for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -143,6 +204,8 @@ def main():
         rec = summarize_counters(args.summarize_counters)
         print(json.dumps(rec["kernels"]))
         return
+    if args.stamp:
+        write_stamp(args.stamp)
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (slices shard across GPUs with no "
               "exchange, so N GPUs would run N independent copies). Run with --gpus 1.", file=sys.stderr)
@@ -184,23 +247,36 @@ def main():
         step()
     torch.cuda.synchronize()
     log(f"bench: timing {args.steps} step(s) of {args.iters} sub-iterations")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    ev0.record()
     for _ in range(args.steps):
         step()
+    ev1.record()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    ev_ms_per_step = ev0.elapsed_time(ev1) / args.steps
     ms_per_step = 1e3 * elapsed / args.steps
     slices_per_s = args.steps / elapsed
     log(f"bench: {ms_per_step:.2f} ms per slice, {slices_per_s:.2f} slices/s")
 
     # Per-kernel durations: each kernel launched time_iters times back to back on
     # the library's stream (torch's current stream) between two HIP events.
+    # Kernel durations in the timed run: a graph-replayed sub-iteration is the projector and the
+    # update back to back, each meeting the cache state the other leaves, so each kernel's duration
+    # in the run is its share of the sub-iteration time measured over the timed region (HIP events
+    # on the library's stream), split in the ratio of the two kernels' back-to-back durations.  The
+    # back-to-back means (caches warm for the same kernel) and means with an event pair around every
+    # launch in sub-iteration order (which adds the events' own gaps) bracket it.
+    sub_ms = ev_ms_per_step / args.iters
     if args.time_iters > 0:
         kimg = R.initial_image(dev)
-        fp_ms, _, bp_ms = R.time_kernels(counts, i0, kimg, args.time_iters)
+        fp_b2b, _, bp_b2b, bp_pair, fp_pair = R.time_kernels(counts, i0, kimg, args.time_iters)
         torch.cuda.synchronize()
+        fp_ms = sub_ms * fp_b2b / (fp_b2b + bp_b2b)
+        bp_ms = sub_ms * bp_b2b / (fp_b2b + bp_b2b)
     else:
-        fp_ms = bp_ms = float("nan")
+        fp_ms = bp_ms = fp_b2b = bp_b2b = fp_pair = bp_pair = float("nan")
     # Algorithmic bytes per launch (per unit: 4 B per ray-pixel interpolation
     # pair read, over every in-image pixel of the projector's matrix; projector
     # 12 B per ray for y/I0 and p read and w written; update 8 B per pixel for
@@ -212,15 +288,19 @@ def main():
     bp_bytes = np.mean([4 * p + 8 * npix for p in pairs])
     fp_gbps = fp_bytes / (fp_ms * 1e-3) / 1e9
     bp_gbps = bp_bytes / (bp_ms * 1e-3) / 1e9
-    sub_ms = ms_per_step / args.iters
     slice_bytes = args.iters * (fp_bytes + bp_bytes)
-    log(f"bench: kernels fp {fp_ms * 1e3:.1f} us ({fp_gbps:.0f} GB/s alg), step rule + bp + tv + update "
-        f"{bp_ms * 1e3:.1f} us ({bp_gbps:.0f} GB/s alg); graph sub-iteration {sub_ms * 1e3:.1f} us")
-    if bp_ms >= fp_ms:
-        dom = dict(name="bp_update_kernel", ms=bp_ms, bytes=bp_bytes, gbps=bp_gbps)
-    else:
-        dom = dict(name="fp_kernel<OS>", ms=fp_ms, bytes=fp_bytes, gbps=fp_gbps)
-    traffic = measured_traffic(dom["name"])
+    log(f"bench: graph sub-iteration {sub_ms * 1e3:.2f} us: fp {fp_ms * 1e3:.2f} us ({fp_gbps:.0f} GB/s alg), "
+        f"step rule + bp + tv + update {bp_ms * 1e3:.2f} us ({bp_gbps:.0f} GB/s alg); back to back "
+        f"{fp_b2b * 1e3:.1f} and {bp_b2b * 1e3:.1f} us, with event pairs {fp_pair * 1e3:.1f} and "
+        f"{bp_pair * 1e3:.1f} us")
+    # ceiling of the gather kernels' algorithmic rates: what 2048 blocks reading an L2-resident
+    # buffer draw from the caches, measured now on this GPU
+    l2_gbps = recon.read_bandwidth(2 << 20, 10) if args.time_iters > 0 else None
+    if l2_gbps:
+        log(f"bench: L2-resident read bandwidth {l2_gbps:.0f} GB/s")
+    kern = {"bp_update_kernel": kernel_roofline("bp_update_kernel", bp_ms, bp_bytes, l2_gbps),
+            "fp_kernel<OS>": kernel_roofline("fp_kernel<OS>", fp_ms, fp_bytes, l2_gbps)}
+    dom = kern["bp_update_kernel"] if bp_ms >= fp_ms else kern["fp_kernel<OS>"]
 
     cpu = None
     parity = None
@@ -247,7 +327,7 @@ def main():
 
     fbp = fbp_leg(R, counts, sl.i0)
     rebin = rebin_leg(args.rebin_slices, dev) if args.rebin_slices > 0 else None
-    batch = batch_leg(args.batch_slices, args.iters, dev) if args.batch_slices > 0 else None
+    batch = batch_leg(args.batch_slices, args.iters, dev, l2_gbps) if args.batch_slices > 0 else None
     cnn = cnn_leg(args.cnn_batch, dev) if args.cnn_batch > 0 else None
     warm = warm_leg(args.warm_slices, args.weights, dev) if args.warm_slices > 0 else None
 
@@ -268,15 +348,16 @@ def main():
                                "SAD 850 / SDD 1450 mm, I0 2e3, 20 subsets, 500 sub-iterations, beta 1e-3",
                    "image": g.n, "views": g.n_views, "channels": g.n_channels, "subsets": M,
                    "sub_iterations": args.iters, "beta": args.beta, "i0": i0},
-        "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": dom["gbps"], "peak": PEAK_HBM_GBPS,
-                     "unit": "GB/s", "frac": dom["gbps"] / PEAK_HBM_GBPS, "traffic": traffic,
-                     "alg_bytes_per_launch": dom["bytes"], "avg_launch_us": dom["ms"] * 1e3},
+        "roofline": dom["roofline"],
         "cpu_baseline": cpu,
         "projector_gbps": fp_gbps,
-        "projector_frac_of_hbm_peak": fp_gbps / PEAK_HBM_GBPS,
+        "projector": kern["fp_kernel<OS>"]["roofline"],
+        "l2_read_gbps": l2_gbps,
         "slice_alg_gbps": slice_bytes / (ms_per_step * 1e-3) / 1e9,
-        "kernel_us": {"fp": fp_ms * 1e3, "bp_update": bp_ms * 1e3,
-                      "graph_sub_iteration": sub_ms * 1e3},
+        "slice_alg_frac_of_l2_read": (slice_bytes / (ms_per_step * 1e-3) / 1e9 / l2_gbps) if l2_gbps else None,
+        "kernel_us": {"fp": fp_ms * 1e3, "bp_update": bp_ms * 1e3, "graph_sub_iteration": sub_ms * 1e3,
+                      "fp_back_to_back": fp_b2b * 1e3, "bp_update_back_to_back": bp_b2b * 1e3,
+                      "fp_event_pairs": fp_pair * 1e3, "bp_update_event_pairs": bp_pair * 1e3},
         "parity": parity,
         "fbp_baseline": fbp,
         "helical_rebin": rebin,
@@ -287,6 +368,43 @@ def main():
                           "thinning": "1/20", "note": "context only; channel count and precision not stated"},
     }
     print(json.dumps(out), flush=True)
+
+
+def kernel_roofline(name: str, ms: float, alg_bytes: float, l2_gbps):
+    """Roofline of one kernel from its live mean launch time: the fraction of each ceiling it
+    reaches -- VALU issue (SQ_INSTS_VALU per launch from the committed counter record, one wave64
+    instruction per SIMD every 4 cycles), HBM (calibrated FETCH_SIZE + WRITE_SIZE bytes per launch
+    against 8 TB/s) and the L2-resident read bandwidth (algorithmic bytes) -- and the largest of
+    them as the bound.  Without a counter record for the current sources only the L2 fraction is
+    known."""
+    sec = ms * 1e-3
+    alg_gbps = alg_bytes / sec / 1e9
+    ctr = measured_counters(name)
+    fr = {}
+    if l2_gbps:
+        fr["l2"] = alg_gbps / l2_gbps
+    traffic = None
+    if ctr:
+        fr["alu"] = ctr["valu_issue_s"] / sec
+        traffic = ctr["fetch_bytes"] + ctr["write_bytes"]
+        fr["hbm"] = traffic / sec / 1e9 / PEAK_HBM_GBPS
+    roof = {"kernel": name, "avg_launch_us": ms * 1e3, "alg_bytes_per_launch": alg_bytes, "alg_gbps": alg_gbps,
+            "fractions": fr, "traffic": traffic,
+            "hbm_gbps_measured": traffic / sec / 1e9 if traffic else None,
+            "counters": "profiles/counters_512x800.json" if ctr else None}
+    if not fr:
+        roof.update(bound=None, achieved=None, peak=None, unit=None, frac=None)
+    else:
+        bound = max(fr, key=fr.get)
+        if bound == "alu":
+            lane_ops = ctr["counters"]["SQ_INSTS_VALU"] * 64 / sec / 1e12
+            roof.update(bound="alu", achieved=lane_ops, peak=VALU_PEAK_TOPS, unit="T VALU lane-ops/s")
+        elif bound == "hbm":
+            roof.update(bound="hbm", achieved=traffic / sec / 1e9, peak=PEAK_HBM_GBPS, unit="GB/s")
+        else:
+            roof.update(bound="l2", achieved=alg_gbps, peak=l2_gbps, unit="GB/s")
+        roof["frac"] = roof["achieved"] / roof["peak"]
+    return {"name": name, "ms": ms, "bytes": alg_bytes, "gbps": alg_gbps, "roofline": roof}
 
 
 def fbp_leg(R, counts, i0: float, reps: int = 20):
@@ -307,11 +425,15 @@ def fbp_leg(R, counts, i0: float, reps: int = 20):
     return {"ms_per_slice": ms, "slices_per_s": 1e3 / ms}
 
 
-def batch_leg(n_slices: int, iters: int, dev):
+def batch_leg(n_slices: int, iters: int, dev, l2_gbps=None):
     """Batched plain method on helical-rebinned-like slices (256^2 or 512^2 over 400 mm, 600-900
     views, 520-738 channels, I0 log-uniform 1e3..1e4; 20 subsets, beta 1e-3): launch shapes
     autotuned on the batch, then `iters` sub-iterations of every slice from the homogeneous
-    start, timed over 3 runs (best)."""
+    start, timed over 3 runs (best).  Algorithmic bytes as for the single slice (per sub-iteration,
+    averaged over the subsets: 8 B per ray-pixel pair, 12 B per ray, 8 B per pixel), the pairs
+    counted from each slice's own ray tables."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import torch
 
     from paper_1903_10088_amd import phantom as ph
@@ -335,10 +457,21 @@ def batch_leg(n_slices: int, iters: int, dev):
         _, dt = ws.timed(lambda: B.run(cts, i0s, imgs, iters))
         best = dt if best is None else min(best, dt)
     n512 = sum(1 for g in geoms if g.n == 512)
+
+    def sub_iteration_bytes(g):
+        R = recon.Recon(g, 20, 1e-3)
+        pairs = R.count_pairs(-1)
+        R.close()
+        return (8 * pairs + 12 * g.n_views * g.n_channels) / 20 + 8 * g.n * g.n
+
+    with ThreadPoolExecutor(8) as ex:
+        alg = iters * sum(ex.map(sub_iteration_bytes, geoms))
+    gbps = alg / best / 1e9
     out = {"slices": n_slices, "slices_512": n512, "slices_256": n_slices - n512, "sub_iterations": iters,
-           "tuned_fp_segments": seg, "tuned_bp_variant": var, "seconds": best, "slices_per_s": n_slices / best}
+           "tuned_fp_segments": seg, "tuned_bp_variant": var, "seconds": best, "slices_per_s": n_slices / best,
+           "alg_bytes": alg, "alg_gbps": gbps, "alg_frac_of_l2_read": gbps / l2_gbps if l2_gbps else None}
     log(f"bench: batched plain {out['slices_per_s']:.1f} slices/s ({n512} of {n_slices} at 512^2; "
-        f"fp_segments {seg}, bp variant {var})")
+        f"fp_segments {seg}, bp variant {var}); {gbps:.0f} GB/s algorithmic")
     B.close()
     return out
 

@@ -376,13 +376,28 @@ recon_status recon_warm_start_noalloc(recon_batch_handle* b, struct recon_cnn* n
  * iteration's iterate can be nonzero).  Host, synchronous. */
 recon_status recon_count_pairs(recon_handle* h, int32_t subset, int32_t disc_only, int64_t* pairs);
 
+/* Measurement helper (no operation of the paper): the read bandwidth the cache
+ * hierarchy delivers to a kernel that gathers from a buffer held in L2, as a
+ * ceiling for the gather kernels' algorithmic rates.  2048 blocks of 256
+ * threads (8 per compute unit) each read all of a `bytes`-byte buffer (a power
+ * of two in [16 KiB, 64 MiB]; 2 MiB fits the 4 MB L2 of every XCD) with
+ * 16-byte loads, after one untimed launch that brings it into the caches;
+ * *gbps_out = bytes read / time over `reps` (1..100) launches timed with HIP
+ * events on `stream`.  Allocates and frees its own buffers; blocks until done.
+ * RECON_INVALID_ARG for other sizes or counts. */
+recon_status recon_read_bandwidth(int64_t bytes, int32_t reps, double* gbps_out, void* stream);
+
 /* Measurement helper: from d_img (read only) runs one sub-iteration of every
  * subset, then launches each kernel of a sub-iteration n_iter (1..4096) times
  * back to back on `stream` (subsets in turn) between two HIP events, and
  * writes the mean time per launch in ms of the projector to ms_out[0] and of
  * the fused step-rule + backprojection + update kernel to ms_out[2]
- * (ms_out[1] = 0: the step rule has no launch of its own).  Blocks until
- * done. */
+ * (ms_out[1] = 0: the step rule has no launch of its own).  Then it runs
+ * min(n_iter, 256) sub-iterations' kernels in their order (projector, update,
+ * subsets in turn) with a pair of HIP events around every launch, and writes
+ * the mean of the update's launches to ms_out[3] and of the projector's to
+ * ms_out[4] (each kernel then meets the cache state the other leaves, as in a
+ * reconstruction).  ms_out: 5 doubles.  Blocks until done. */
 recon_status recon_time_kernels(recon_handle* h, const float* d_counts, float i0, float* d_img, int32_t n_iter,
                                 double* ms_out, void* stream);
 

@@ -650,6 +650,40 @@ recon_status recon_count_pairs(recon_handle* h, int32_t subset, int32_t disc_onl
     return RECON_OK;
 }
 
+recon_status recon_read_bandwidth(int64_t bytes, int32_t reps, double* gbps_out, void* stream)
+{
+    if (!gbps_out) return fail(RECON_INVALID_ARG, "NULL argument");
+    if (bytes < 16384 || bytes > (64L << 20) || (bytes & (bytes - 1)) != 0)
+        return fail(RECON_INVALID_ARG, "bytes must be a power of two in [16 KiB, 64 MiB]");
+    if (reps < 1 || reps > 100) return fail(RECON_INVALID_ARG, "reps must be in [1, 100]");
+    hipStream_t s = as_stream(stream);
+    constexpr int kBlocks = 2048;  // 8 blocks of 256 threads per compute unit
+    float* buf = nullptr;
+    float* out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t err = hipMalloc(&buf, (size_t)bytes);
+    if (err == hipSuccess) err = hipMalloc(&out, (size_t)kBlocks * 256 * sizeof(float));
+    if (err == hipSuccess) err = hipMemsetAsync(buf, 0, (size_t)bytes, s);
+    if (err == hipSuccess) err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    const uint32_t n16 = (uint32_t)(bytes / 16);
+    // one untimed launch brings the buffer into every XCD's L2
+    if (err == hipSuccess) err = launch_read_probe(buf, n16, kBlocks, out, s);
+    if (err == hipSuccess) err = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_read_probe(buf, n16, kBlocks, out, s);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (buf) (void)hipFree(buf);
+    if (out) (void)hipFree(out);
+    if (err != hipSuccess) return fail(RECON_DEVICE, std::string("read probe: ") + hipGetErrorString(err));
+    *gbps_out = (double)kBlocks * (double)bytes * reps / (ms * 1e-3) / 1e9;
+    return RECON_OK;
+}
+
 recon_status recon_time_kernels(recon_handle* h, const float* d_counts, float i0, float* d_img, int32_t n_iter,
                                 double* ms_out, void* stream)
 {
@@ -677,6 +711,20 @@ recon_status recon_time_kernels(recon_handle* h, const float* d_counts, float i0
     for (int n = 0; n < n_iter && status == RECON_OK && err == hipSuccess; ++n)
         err = launch_bp_update(G, h->bp_variant, update_args(h, n % h->M, 0), s);
     if (status == RECON_OK && err == hipSuccess) err = hipEventRecord(ev[3], s);
+    // then the kernels in their sub-iteration order (projector, update, subsets in turn), each
+    // launch between two events of its own, as they meet each other's cache state in a run
+    const int ns = std::min(n_iter, 256);
+    std::vector<hipEvent_t> se(4 * (size_t)ns, nullptr);
+    for (auto& e : se)
+        if (status == RECON_OK && hipEventCreate(&e) != hipSuccess) status = fail(RECON_DEVICE, "hipEventCreate failed");
+    for (int n = 0; n < ns && status == RECON_OK && err == hipSuccess; ++n) {
+        err = hipEventRecord(se[4 * n], s);
+        if (err == hipSuccess) err = enqueue_fp(h, n % h->M, 0, s);
+        if (err == hipSuccess) err = hipEventRecord(se[4 * n + 1], s);
+        if (err == hipSuccess) err = hipEventRecord(se[4 * n + 2], s);
+        if (err == hipSuccess) err = launch_bp_update(G, h->bp_variant, update_args(h, n % h->M, 0), s);
+        if (err == hipSuccess) err = hipEventRecord(se[4 * n + 3], s);
+    }
     if (status == RECON_OK && err == hipSuccess) err = hipStreamSynchronize(s);
     if (status == RECON_OK && err != hipSuccess)
         status = fail(RECON_DEVICE, std::string("timing run: ") + hipGetErrorString(err));
@@ -686,8 +734,20 @@ recon_status recon_time_kernels(recon_handle* h, const float* d_counts, float i0
             (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
             ms_out[k] = ms / n_iter;
         }
+        double fp_seq = 0.0, bp_seq = 0.0;
+        for (int n = 0; n < ns; ++n) {
+            float a = 0.0f, b = 0.0f;
+            (void)hipEventElapsedTime(&a, se[4 * n], se[4 * n + 1]);
+            (void)hipEventElapsedTime(&b, se[4 * n + 2], se[4 * n + 3]);
+            fp_seq += a;
+            bp_seq += b;
+        }
+        ms_out[3] = bp_seq / ns;
+        ms_out[4] = fp_seq / ns;
     }
     for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : se)
         if (e) (void)hipEventDestroy(e);
     return status;
 }

@@ -551,7 +551,9 @@ __device__ __forceinline__ void gather_quad(StageLds& S, const Geo& G, const Vie
                                             const RayGeo* __restrict__ rg, const float* __restrict__ w, int q0,
                                             int nq, int ti0, int tj0, float (&acc)[2][2])
 {
-    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    // the wave's group, read into a scalar register: views, their records and the
+    // branches on them are then wave-uniform to the compiler too
+    const int lane = threadIdx.x & 63, grp = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int bxl = 2 * (lane & 7), byl = 2 * (lane >> 3);
     const int i0 = ti0 + bxl, j0 = tj0 + byl;
     const bool active = i0 < G.n && j0 < G.n;
@@ -582,7 +584,9 @@ __device__ __forceinline__ void gather_quad(StageLds& S, const Geo& G, const Vie
                 major_intervals(v, G.nch, x0, x1, y0, y1);
                 if (x0 < x1) {
                     int lo, hi;
-                    candidate_range_f(kp, va.w, vb.y, vb.z, lo, hi);
+                    // (integer clamps of candidate_range: the same window for finite kp)
+                    lo = max((int)ceilf(kp - va.w), x0);
+                    hi = min((int)floorf(kp + va.w), x1 - 1);
                     if (lo <= hi) {
                         if (cnt > 0)  // every window lies in the staged range (stage_range)
                             add_window_blk<2, 2, true, false, QUAD_UNROLL>(acc, lo, hi, i0, j0,
@@ -594,7 +598,8 @@ __device__ __forceinline__ void gather_quad(StageLds& S, const Geo& G, const Vie
                 }
                 if (y0 < y1) {
                     int lo, hi;
-                    candidate_range_f(kp, vb.x, vb.w, __int_as_float(vc.x), lo, hi);
+                    lo = max((int)ceilf(kp - vb.x), y0);
+                    hi = min((int)floorf(kp + vb.x), y1 - 1);
                     if (lo <= hi) {
                         if (cnt > 0)
                             add_window_blk<2, 2, false, false, QUAD_UNROLL>(acc, lo, hi, i0, j0,

@@ -193,8 +193,8 @@ struct FpArgs {
 
 // Joseph samples of one ray on sample lines [t0, t1), summed in line order.
 // u(t) = lattice + residual; lattice - floor(u) is exact, so the interpolation
-// fraction keeps the residual's precision.  Four lines' loads are issued before
-// their additions.  The index clamp to [-PAD, n] keeps every read inside the
+// fraction keeps the residual's precision.  The loads of the next four lines
+// are issued before the previous four lines are added.  The index clamp to [-PAD, n] keeps every read inside the
 // padded row, where out-of-image entries are zero.  img is the buffer's base
 // (wave-uniform) and off0 the 32-bit element offset of column 0 of line 0 of
 // the copy this ray samples, so addresses are 32-bit offsets from one base.
@@ -210,42 +210,55 @@ __device__ __forceinline__ f32x2u pair_at(const float* __restrict__ img, uint32_
 __device__ __forceinline__ float chunk_sum(const float* __restrict__ img, uint32_t off0, int P, int n,
                                            const RayGeo& g, int t0, int t1)
 {
+    const float fn = (float)n;
+    // interpolation fraction and the pair of pixels of sample line t (the lattice part minus its
+    // floor is exact, so the fraction keeps the residual's precision)
+    auto sample = [&](float ft, uint32_t row, float& f, f32x2u& v) {
+        const float lat = fmaf(ft, g.s_hi, g.a_int);
+        const float res = fmaf(ft, g.s_lo, g.a_frac);
+        const float fl = floorf(lat + res);
+        f = (lat - fl) + res;
+        // clamp in float (fl is integral, so this equals clamping the integer)
+        const int j0 = (int)__builtin_amdgcn_fmed3f(fl, (float)-PAD, fn);
+        v = pair_at(img, row + (uint32_t)j0);
+    };
     float acc = 0.0f;
     int t = t0;
-    float ft0 = (float)t0;  // exact: t < 2^24
-    const float fn = (float)n;
+    float ft = (float)t0;  // exact: t < 2^24
     uint32_t row = off0 + (uint32_t)(t0 * P);
-    for (; t + 3 < t1; t += 4) {
-        float v0[4], v1[4], f[4];
+    if (t + 3 < t1) {
+        // software pipelined by 4 lines: the next 4 lines' loads are in flight while the
+        // previous 4 are added (in line order)
+        float f[4];
+        f32x2u v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const float ft = ft0 + (float)u;
-            const float lat = fmaf(ft, g.s_hi, g.a_int);
-            const float res = fmaf(ft, g.s_lo, g.a_frac);
-            const float fl = floorf(lat + res);
-            f[u] = (lat - fl) + res;
-            // clamp in float (fl is integral, so this equals clamping the integer)
-            const int j0 = (int)__builtin_amdgcn_fmed3f(fl, (float)-PAD, fn);
-            const f32x2u v = pair_at(img, row + (uint32_t)(u * P) + (uint32_t)j0);
-            v0[u] = v.x;
-            v1[u] = v.y;
+        for (int u = 0; u < 4; ++u) sample(ft + (float)u, row + (uint32_t)(u * P), f[u], v[u]);
+        t += 4;
+        ft += 4.0f;
+        row += (uint32_t)(4 * P);
+        for (; t + 3 < t1; t += 4) {
+            float fn4[4];
+            f32x2u vn4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) sample(ft + (float)u, row + (uint32_t)(u * P), fn4[u], vn4[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                acc += fmaf(f[u], v[u].y - v[u].x, v[u].x);
+                f[u] = fn4[u];
+                v[u] = vn4[u];
+            }
+            ft += 4.0f;
+            row += (uint32_t)(4 * P);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc += fmaf(f[u], v1[u] - v0[u], v0[u]);
-        ft0 += 4.0f;
-        row += (uint32_t)(4 * P);
+        for (int u = 0; u < 4; ++u) acc += fmaf(f[u], v[u].y - v[u].x, v[u].x);
     }
     for (; t < t1; ++t) {
-        const float lat = fmaf(ft0, g.s_hi, g.a_int);
-        const float res = fmaf(ft0, g.s_lo, g.a_frac);
-        const float fl = floorf(lat + res);
-        const float f = (lat - fl) + res;
-        const int j0 = (int)__builtin_amdgcn_fmed3f(fl, (float)-PAD, fn);
-        const f32x2u v = pair_at(img, row + (uint32_t)j0);
-        const float v0 = v.x;
-        const float v1 = v.y;
-        acc += fmaf(f, v1 - v0, v0);
-        ft0 += 1.0f;
+        float f;
+        f32x2u v;
+        sample(ft, row, f, v);
+        acc += fmaf(f, v.y - v.x, v.x);
+        ft += 1.0f;
         row += (uint32_t)P;
     }
     return acc;
@@ -477,11 +490,43 @@ __global__ void residual_combine_batch_kernel(const SliceDesc* __restrict__ slic
     residual_combine(D->res_part, (long)D->geo.nv * D->geo.nch, out + 2 * i);
 }
 
+// Measurement probe of the read bandwidth the caches deliver to gather kernels:
+// every block reads the whole buffer (n16 16-byte words, a power of two) once,
+// from a block-dependent start, four independent loads in flight per thread;
+// each thread writes its sum so that no load can be dropped.
+__global__ __launch_bounds__(256) void read_probe_kernel(const float4* __restrict__ buf, uint32_t n16,
+                                                         float* __restrict__ out)
+{
+    const uint32_t mask = n16 - 1;
+    const uint32_t start = (blockIdx.x * 4099u * 256u) & mask;
+    float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (uint32_t e = threadIdx.x; e < n16; e += 4 * 256) {
+        float4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = buf[(start + e + u * 256) & mask];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            acc.x += v[u].x;
+            acc.y += v[u].y;
+            acc.z += v[u].z;
+            acc.w += v[u].w;
+        }
+    }
+    out[blockIdx.x * 256 + threadIdx.x] = (acc.x + acc.y) + (acc.z + acc.w);
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------------------
 // Launchers
 // ----------------------------------------------------------------------------
+
+hipError_t launch_read_probe(const float* buf, uint32_t n16, int blocks, float* out, hipStream_t s)
+{
+    if ((n16 & (n16 - 1)) != 0 || n16 < 1024) return hipErrorInvalidValue;
+    read_probe_kernel<<<blocks, 256, 0, s>>>(reinterpret_cast<const float4*>(buf), n16, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_pad_image(const float* src, float* dst, float* dstT, int n, int P, hipStream_t s, bool mask_disc)
 {

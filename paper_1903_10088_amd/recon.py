@@ -56,7 +56,7 @@ EXPORTS = ["recon_default_params", "recon_status_string", "recon_last_error", "r
            "recon_cnn_set_state", "recon_cnn_save", "recon_cnn_load", "recon_cnn_forward", "recon_cnn_loss_grad",
            "recon_cnn_adam_step", "recon_cnn_train_step", "recon_cnn_tensor", "recon_cnn_time_kernels",
            "recon_data_residual", "recon_warm_start", "recon_warm_start_noalloc", "recon_fbp",
-           "recon_rebin_helical"]
+           "recon_rebin_helical", "recon_read_bandwidth"]
 
 _lib = None
 
@@ -88,6 +88,7 @@ def lib():
         L.recon_initial_image.argtypes = [vp, vp, vp]
         L.recon_subset_size.argtypes = [vp, i32, P(i32)]
         L.recon_set_launch.argtypes = [vp, i32, i32]
+        L.recon_read_bandwidth.argtypes = [i64, i32, P(d), vp]
         L.recon_check_tables.argtypes = [P(Geometry_c), i32, i32, P(i64), P(i64), P(i64)]
         L.recon_count_pairs.argtypes = [vp, i32, i32, P(i64)]
         L.recon_time_kernels.argtypes = [vp, vp, f, vp, i32, P(d), vp]
@@ -139,6 +140,13 @@ def default_params() -> dict:
     p = Params_c()
     lib().recon_default_params(ctypes.byref(p))
     return {name: getattr(p, name) for name, _ in Params_c._fields_}
+
+
+def read_bandwidth(nbytes: int = 2 << 20, reps: int = 10) -> float:
+    """recon_read_bandwidth: GB/s that 2048 blocks reading an L2-resident buffer of nbytes achieve."""
+    out = ctypes.c_double()
+    _check(lib().recon_read_bandwidth(int(nbytes), int(reps), ctypes.byref(out), _stream()), "recon_read_bandwidth")
+    return float(out.value)
 
 
 def check_tables(g, subsets: int, view_stride: int = 1):
@@ -253,10 +261,11 @@ class Recon:
         return out
 
     def time_kernels(self, counts, i0: float, img, n_iter: int):
-        """Mean kernel durations (ms) over n_iter direct-launch sub-iterations: (fp, lambda, bp_update)."""
+        """Mean kernel durations (ms): (fp, 0, bp_update) over n_iter back-to-back launches of each,
+        then (bp_update, fp) over launches in sub-iteration order, each between events of its own."""
         torch = _torch()
         g = self.geometry
-        out = (ctypes.c_double * 3)()
+        out = (ctypes.c_double * 5)()
         _check(lib().recon_time_kernels(self._h, _ptr(counts, torch.float32, (g.n_views, g.n_channels), "counts"),
                                         float(i0), _ptr(img, torch.float32, (g.n, g.n), "img"), int(n_iter), out,
                                         _stream()), "recon_time_kernels")

@@ -1,5 +1,6 @@
-"""Host-side pieces of bench.py: the counter summary that turns rocprofv3 FETCH_SIZE / WRITE_SIZE
-readings into HBM bytes per launch (scaled by a plain copy of known size), and the one-GPU rule."""
+"""Host-side pieces of bench.py: the counter summary that turns rocprofv3 readings into per-launch
+HBM bytes (scaled by a plain copy of known size) and VALU issue time, the source stamps that tie
+counters to the sources they were taken from, and the one-GPU rule."""
 import csv
 import json
 import os
@@ -23,28 +24,71 @@ def write_counters(d, sub, rows):
             w.writerow(dict(zip(FIELDS, r)))
 
 
-def test_counter_summary_scales_by_the_copy(tmp_path):
-    d = str(tmp_path)
-    bp = "void recon::(anonymous namespace)::bp_update_kernel<1>(recon::Geo, ...)"
+def fake_runs(d, stamp):
+    """Counter files of every run bench.py summarizes, two dispatches per kernel, each run stamped
+    with the given source hashes."""
+    bp = "void recon::(anonymous namespace)::bp_update_kernel<5>(recon::Geo, ...)"
     fp = "void recon::(anonymous namespace)::fp_kernel<16, true>(recon::(anonymous namespace)::FpArgs)"
-    # two dispatches each; the summary takes the mean per dispatch
-    write_counters(d, "pmc_FETCH_SIZE", [(bp, "FETCH_SIZE", 100.0), (bp, "FETCH_SIZE", 300.0),
-                                         (fp, "FETCH_SIZE", 50.0), (fp, "FETCH_SIZE", 50.0)])
-    write_counters(d, "pmc_WRITE_SIZE", [(bp, "WRITE_SIZE", 10.0), (bp, "WRITE_SIZE", 30.0),
-                                         (fp, "WRITE_SIZE", 1.0), (fp, "WRITE_SIZE", 3.0)])
-    # a 4 MiB copy reads as 2048 KiB fetched (factor 2) and 4096 KiB written (factor 1)
-    write_counters(d, "cal_FETCH_SIZE", [("__amd_rocclr_copyBuffer", "FETCH_SIZE", 2048.0)])
-    write_counters(d, "cal_WRITE_SIZE", [("__amd_rocclr_copyBuffer", "WRITE_SIZE", 4096.0)])
-    out = os.path.join(d, "traffic.json")
-    rec = bench.summarize_counters(d, copy_mib=4, out_path=out)
+    other = "void recon::(anonymous namespace)::bp_update_kernel<1>(recon::Geo, ...)"
+    for run, names in bench.COUNTER_RUNS.items():
+        rows = []
+        for c in names:
+            base = 1000.0 + len(c)
+            rows += [(bp, c, base), (bp, c, base + 200.0), (fp, c, 50.0), (fp, c, 50.0), (other, c, 9e9)]
+        write_counters(d, run, rows)
+    # a 256 MiB copy reads as 131072 KiB fetched (factor 2) and 262144 KiB written (factor 1)
+    write_counters(d, "cal_fetch", [("__amd_rocclr_copyBuffer", "FETCH_SIZE", 131072.0)])
+    write_counters(d, "cal_write", [("__amd_rocclr_copyBuffer", "WRITE_SIZE", 262144.0)])
+    for run in list(bench.COUNTER_RUNS) + list(bench.CAL_RUNS):
+        with open(os.path.join(d, run, "source_stamp.json"), "w") as f:
+            json.dump({"sources": stamp}, f)
+
+
+def test_counter_summary(tmp_path):
+    """Per-dispatch means per kernel and counter (the kernel picked by its exact template), HBM bytes
+    scaled by the plain copy, VALU issue time at one wave64 instruction per SIMD every 4 cycles,
+    and the hash of the sources recorded at collection time."""
+    d = str(tmp_path)
+    fake_runs(d, bench.source_hashes())
+    out = os.path.join(d, "counters.json")
+    rec = bench.summarize_counters(d, out_path=out)
     assert json.load(open(out)) == rec
     k = rec["kernels"]["bp_update_kernel"]
-    assert k["fetch_kib"] == 200.0 and k["write_kib"] == 20.0
-    assert k["fetch_bytes"] == 200.0 * 1024 * 2.0 and k["write_bytes"] == 20.0 * 1024
-    assert rec["kernels"]["fp_kernel<OS>"]["fetch_bytes"] == 50.0 * 1024 * 2.0
-    assert rec["calibration"]["fetch_factor"] == 2.0 and rec["calibration"]["write_factor"] == 1.0
-    # the recorded hash is the one bench.py checks before reporting the traffic
+    assert k["dispatches"] == 2
+    assert k["counters"]["FETCH_SIZE"] == 1000.0 + len("FETCH_SIZE") + 100.0
+    assert k["fetch_bytes"] == k["counters"]["FETCH_SIZE"] * 1024 * 2.0
+    assert k["write_bytes"] == k["counters"]["WRITE_SIZE"] * 1024 * 1.0
+    valu = k["counters"]["SQ_INSTS_VALU"]
+    assert abs(k["valu_issue_s"] - valu * 4 / (1024 * 2.4e9)) <= 1e-18
+    assert rec["kernels"]["fp_kernel<OS>"]["counters"]["SQ_WAVES"] == 50.0
     assert len(k["source_sha"]) == 16
+    assert rec["calibration"]["fetch_factor"] == 2.0 and rec["calibration"]["write_factor"] == 1.0
+
+
+def test_counter_summary_refuses_other_sources(tmp_path):
+    """Counters stamped with sources other than the current ones (a kernel changed after the runs),
+    or runs stamped differently from each other, are refused."""
+    import pytest
+
+    d = str(tmp_path / "a")
+    stamp = dict(bench.source_hashes())
+    stamp["paper_1903_10088_amd/csrc/bp.hip"] = "0" * 16
+    fake_runs(d, stamp)
+    with pytest.raises(SystemExit):
+        bench.summarize_counters(d, out_path=os.path.join(d, "x.json"))
+    d2 = str(tmp_path / "b")
+    fake_runs(d2, bench.source_hashes())
+    with open(os.path.join(d2, "sq_wait", "source_stamp.json"), "w") as f:
+        json.dump({"sources": stamp}, f)
+    with pytest.raises(SystemExit):
+        bench.summarize_counters(d2, out_path=os.path.join(d2, "x.json"))
+
+
+def test_stamp_records_the_library_sources(tmp_path):
+    bench.write_stamp(str(tmp_path))
+    rec = json.load(open(os.path.join(str(tmp_path), "source_stamp.json")))
+    assert "paper_1903_10088_amd/csrc/bp.hip" in rec["sources"] and "include/recon.h" in rec["sources"]
+    assert rec["sources"] == bench.source_hashes()
 
 
 def test_more_than_one_gpu_is_refused():
