@@ -318,6 +318,17 @@ recon_status recon_batch_tune(recon_batch_handle* b, const float* const* d_count
  * 512^2 slices. */
 recon_status recon_batch_set_launch(recon_batch_handle* b, int32_t fp_segments, int32_t bp_variant);
 
+/* Host-only check of the batched kernels' work tables (no GPU needed): builds,
+ * for the given slices, the XCD placement and the tables the batch would
+ * upload (the update's 16x16 tiles, the projector's blocks of 256 / fp_segments
+ * rays for every subset and for all views) and counts in *errors every tile or
+ * ray block that is missing, repeated, out of range or placed on an XCD other
+ * than its slice's (block p runs on XCD p mod 8); *blocks receives the total
+ * table length.  RECON_INVALID_ARG as recon_batch_create, or for an
+ * fp_segments outside {1, 2, 4, 8, 16}. */
+recon_status recon_batch_check_work(const recon_geometry* geoms, int32_t n_slices, int32_t subsets,
+                                    int32_t fp_segments, int64_t* errors, int64_t* blocks);
+
 /* One-shot form: create, run n_iter sub-iterations, wait, destroy. */
 recon_status recon_batch(const recon_geometry* geoms, int32_t n_slices, int32_t subsets, double beta,
                          const recon_params* params, const float* const* d_counts, const float* i0,

@@ -1,8 +1,10 @@
 """Convergence study of the plain method on 512 x 512 slices (sections 3.C.2, 3.D and 4.B-4.D):
 the squared difference between projection and reprojection over the whole sinogram against the
 sub-iteration count, for the step-rule readings, a constant step, the three homogeneous initial
-images, the thinning factors and half of the views (Fig. 3's quantities), the kept best-epoch
-iterate, and the time to reconstruct one slice at each thinning factor (Table I's quantity).
+images, the thinning factors and fewer projection data -- every other view, half a turn and a
+fan-beam short scan (section 4's reconstructions from half of the projection data) -- (Fig. 3's
+quantities), the kept best-epoch iterate, and the time to reconstruct one slice at each thinning
+factor (Table I's quantity).
 
 Orchestration only: every reconstruction step runs in the library (recon_os_iterate_ex,
 recon_data_residual); this module draws the seeded slices, schedules the calls and reduces the
@@ -16,6 +18,7 @@ from __future__ import annotations
 import argparse
 import dataclasses
 import json
+import math
 import sys
 import time
 
@@ -46,11 +49,18 @@ def checkpoints(n_total: int):
 class Case:
     """One seeded slice on the device: counts, truth and the reconstruction disc."""
 
-    def __init__(self, g, seed: int, i0: float, dev, view_stride: int = 1):
+    def __init__(self, g, seed: int, i0: float, dev, view_stride: int = 1, first_views: int = 0):
         torch = _torch()
         sl = ph.make_slice(g, seed, i0, low_contrast=True)
-        counts = sl.counts[::view_stride]  # every view_stride-th view: still equally spaced over the turn
-        self.g = dataclasses.replace(g, n_views=counts.shape[0])
+        if first_views:
+            # the first views of the turn, at the full turn's spacing: limited-angle data over an
+            # arc of 2 pi first_views / n_views (the same measured rows)
+            counts = sl.counts[:first_views]
+            self.g = dataclasses.replace(g, n_views=first_views,
+                                         scan_arc_rad=2 * math.pi * first_views / g.n_views)
+        else:
+            counts = sl.counts[::view_stride]  # every view_stride-th view: still equally spaced over the turn
+            self.g = dataclasses.replace(g, n_views=counts.shape[0])
         self.seed, self.i0 = seed, i0
         self.counts = torch.from_numpy(np.ascontiguousarray(counts)).to(dev)
         self.truth = torch.from_numpy(sl.truth).to(dev)
@@ -153,6 +163,10 @@ def run(seeds, beta: float = 1e-3, i0: float = 2e3, M: int = 20, n_long: int = 1
     log(f"study: {len(seeds)} slices ...")
     cases = [Case(g, s, i0, dev) for s in seeds]
     half = [Case(g, s, i0, dev, view_stride=2) for s in seeds]
+    # limited angle: half a turn (400 views) and a short scan, half a turn plus the fan
+    n_short = math.ceil(g.n_views * (math.pi + 2 * g.gamma_max) / (2 * math.pi))
+    half_turn = [Case(g, s, i0, dev, first_views=g.n_views // 2) for s in seeds]
+    short = [Case(g, s, i0, dev, first_views=n_short) for s in seeds]
     mu0 = lambda cm: dict(mu0_per_mm=cm * MU_PER_CM_TO_MM)  # noqa: E731
     const = dict(lambda_inc=0.0, lambda_dec=0.0)
 
@@ -167,6 +181,9 @@ def run(seeds, beta: float = 1e-3, i0: float = 2e3, M: int = 20, n_long: int = 1
         "constant_0.01_mu0_0": (cases, M, n_long, dict(const, **mu0(0.0))),
         # half of the views (every other one), subsets of the same 40 views
         "half_views_M10": (half, M // 2, n_std, {}),
+        # limited angle, subsets of about 40 views
+        "half_turn_M10": (half_turn, M // 2, n_std, {}),
+        f"short_scan_M{round(n_short / 40)}": (short, round(n_short / 40), n_std, {}),
     }
     for m in (1, 2, 5, 10, 40):  # thinning factors (M = 20 is "adaptive")
         variants[f"thinning_M{m}"] = (cases, m, 1000 if m == 40 else n_std, {})
@@ -194,9 +211,11 @@ def run(seeds, beta: float = 1e-3, i0: float = 2e3, M: int = 20, n_long: int = 1
     V = out["variants"]
     idx500 = V["adaptive"]["n"].index(n_std)
     target = V["adaptive"]["r_over_v"][idx500]
-    summ = {"target_r_over_v": target, "sub_iterations_to_target": {}}
+    summ = {"target_r_over_v": target, "sub_iterations_to_target": {}, "least_rmse_truth": {}}
     for name, v in V.items():
         summ["sub_iterations_to_target"][name] = first_reaching(v, target * 1.001)
+        k = int(np.argmin(v["rmse_truth"]))
+        summ["least_rmse_truth"][name] = {"rmse": v["rmse_truth"][k], "at": v["n"][k]}
     a = summ["sub_iterations_to_target"]
     if a.get("constant_0.01_mu0_0"):
         summ["adaptive_vs_constant_from_zero"] = a["constant_0.01_mu0_0"] / n_std
@@ -217,6 +236,67 @@ def compact(x, digits: int = 5):
     return x
 
 
+LABELS = {
+    "adaptive": "adaptive, literal comparison (default)",
+    "adaptive_same_subset": "adaptive, same-subset comparison",
+    "constant_0.01": "constant lambda 0.01",
+    "adaptive_mu0_0": "adaptive, mu0 = 0",
+    "adaptive_mu0_0.1": "adaptive, mu0 = 0.1 / cm",
+    "constant_0.01_mu0_0": "constant 0.01, mu0 = 0",
+    "half_views_M10": "every other view (400 views over the turn)",
+    "half_turn_M10": "half a turn (the first 400 views, arc pi)",
+}
+
+
+def markdown(res: dict, out_name: str) -> str:
+    """The record's tables as markdown: every variant at 100 and 500 sub-iterations, its least RMSE
+    to the phantom and its sub-iterations to the literal rule's data fit, then Table I's quantity."""
+    V = res["variants"]
+    S = res["summary"]
+
+    def at(v, key, n):
+        return v[key][v["n"].index(n)] if n in v["n"] else float("nan")
+
+    lines = [f"# Convergence study: {res['workload']}", "",
+             "Command (GPU, about half a minute):", "", "```",
+             f"python -m paper_1903_10088_amd.conv_study --out {out_name}", "```", "",
+             "`r/v`: full-data mean of (l - p)^2 over its Poisson noise level (`recon_data_residual`), on each "
+             "variant's own views; 1 = the image explains the data to the noise, below 1 it fits the noise. `RMSE`: "
+             "to the rasterised phantom over the disc, in units of mu_water. All runs from the homogeneous start; "
+             "means over the slices. \"to target\" = first checkpoint at which r/v is at or below the literal "
+             f"adaptive rule's value after 500 sub-iterations ({S['target_r_over_v']:.4f}; comparable only between "
+             "variants with the same views).", "",
+             "| variant | M | r/v @100 | r/v @500 | RMSE @100 | RMSE @500 | least RMSE (at) | lambda @500 | to target |",
+             "|---|---|---|---|---|---|---|---|---|"]
+    for name, v in V.items():
+        label = LABELS.get(name, name)
+        if name.startswith("short_scan"):
+            label = "short scan (half a turn plus the fan: the first views over pi + 2 gamma_max)"
+        elif name.startswith("thinning_M"):
+            m = int(name[len("thinning_M"):])
+            label = f"thinning 1/{m}" if m > 1 else "thinning 1"
+        least = S["least_rmse_truth"][name]
+        tgt = S["sub_iterations_to_target"][name]
+        lines.append(f"| {label} | {v['M']} | {at(v, 'r_over_v', 100):.4g} | {at(v, 'r_over_v', 500):.4g} | "
+                     f"{at(v, 'rmse_truth', 100):.4g} | {at(v, 'rmse_truth', 500):.4g} | "
+                     f"{least['rmse']:.4g} ({least['at']}) | {at(v, 'lambda', 500):.2g} | "
+                     f"{tgt if tgt is not None else 'never'} |")
+    kept = {name: v["kept"]["best_n"] for name, v in V.items() if "kept" in v}
+    if kept:
+        lines += ["", "Best-epoch iterate (keep_best): sub-iterations of the kept image per slice -- " +
+                  "; ".join(f"{LABELS.get(k, k)}: {b}" for k, b in kept.items()) +
+                  " (the last epoch whenever the epoch sums of f keep falling)."]
+    T = res["table1_s_per_slice_500"]
+    ms = sorted(T, key=lambda k: int(k))
+    lines += ["", "Time per slice, 500 sub-iterations, one slice per launch (Table I's quantity; the paper's "
+              "GTX 1080 Ti row for context only):", "",
+              "| thinning | " + " | ".join("1" if int(m) == 1 else f"1/{m}" for m in ms) + " |",
+              "|---|" + "---|" * len(ms),
+              "| MI355X, this library (s) | " + " | ".join(f"{T[m]['s_per_slice']:.3g}" for m in ms) + " |",
+              "| paper, GTX 1080 Ti (s) | " + " | ".join(f"{T[m]['paper_gtx1080ti_s']:.2f}" for m in ms) + " |", ""]
+    return "\n".join(lines)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--seeds", type=int, nargs="*", default=[100, 101, 102, 103])
@@ -225,7 +305,10 @@ def main(argv=None):
     a = ap.parse_args(argv)
     res = run(a.seeds, beta=a.beta)
     res = compact(res)
+    res["table1_s_per_slice_500"] = {str(k): v for k, v in res["table1_s_per_slice_500"].items()}
     if a.out:
+        with open(a.out.rsplit(".", 1)[0] + ".md", "w") as f:
+            f.write(markdown(res, a.out))
         with open(a.out, "w") as f:  # one line per variant
             f.write("{\n")
             items = [(k, v) for k, v in res.items() if k != "variants"]

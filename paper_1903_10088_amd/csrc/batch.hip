@@ -86,23 +86,38 @@ void free_batch(recon_batch_handle* b)
     delete b;
 }
 
-// Greedy placement of slices on XCDs by cost (pixels x views per subset).
-void assign_xcds(recon_batch_handle* b)
+// What the work tables need to know of a slice.
+struct SliceShape {
+    int n, nch, nv;
+    std::vector<int> subset_count;  // views per subset
+    int max_subset_views;
+};
+
+std::vector<SliceShape> shapes_of(const recon_batch_handle* b)
 {
-    const int n = (int)b->h.size();
-    std::vector<int> order(n);
+    std::vector<SliceShape> sh;
+    for (const recon_handle* h : b->h)
+        sh.push_back(SliceShape{h->geo.n, h->geo.nch, h->geo.nv, h->subset_count, h->max_subset_views});
+    return sh;
+}
+
+// Greedy placement of slices on XCDs by cost (pixels x views per subset).
+std::vector<int> assign_xcds(const std::vector<SliceShape>& sh)
+{
+    const int n = (int)sh.size();
+    std::vector<int> order(n), xcd(n, 0);
     std::vector<double> cost(n), load(NXCD, 0.0);
     for (int i = 0; i < n; ++i) {
         order[i] = i;
-        cost[i] = (double)b->h[i]->geo.n * b->h[i]->geo.n * b->h[i]->max_subset_views;
+        cost[i] = (double)sh[i].n * sh[i].n * sh[i].max_subset_views;
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
-    b->xcd.assign(n, 0);
     for (int i : order) {
         const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        b->xcd[i] = x;
+        xcd[i] = x;
         load[x] += cost[i];
     }
+    return xcd;
 }
 
 // Interleaves per-XCD lists so that block p runs on XCD p mod 8.
@@ -117,18 +132,34 @@ std::vector<W> interleave(const std::vector<std::vector<W>>& lists, const W& idl
     return out;
 }
 
+// Update work: every 16x16 tile of every slice, slice by slice within an XCD.
+std::vector<BpWork> bp_work_table(const std::vector<SliceShape>& sh, const std::vector<int>& xcd)
+{
+    std::vector<std::vector<BpWork>> bl(NXCD);
+    for (size_t i = 0; i < sh.size(); ++i) {
+        const int T = (sh[i].n + 15) / 16;
+        for (int ty = 0; ty < T; ++ty)
+            for (int tx = 0; tx < T; ++tx) bl[xcd[i]].push_back(BpWork{(int)i, tx * 16, ty * 16, 0});
+    }
+    return interleave(bl, BpWork{-1, 0, 0, 0});
+}
+
+// Projector work of subset s (-1: every view) in blocks of rpb rays.
+std::vector<FpWork> fp_work_table(const std::vector<SliceShape>& sh, const std::vector<int>& xcd, int s, int rpb)
+{
+    std::vector<std::vector<FpWork>> fl(NXCD);
+    for (size_t i = 0; i < sh.size(); ++i) {
+        const int nrays = (s < 0 ? sh[i].nv : sh[i].subset_count[s]) * sh[i].nch;
+        for (int r0 = 0; r0 < nrays; r0 += rpb) fl[xcd[i]].push_back(FpWork{(int)i, r0});
+    }
+    return interleave(fl, FpWork{-1, 0});
+}
+
 recon_status upload_work(recon_batch_handle* b)
 {
     drop_graphs(b);
-    const int n = (int)b->h.size();
-    // update: every tile of every slice, slice by slice within an XCD
-    std::vector<std::vector<BpWork>> bl(NXCD);
-    for (int i = 0; i < n; ++i) {
-        const int N = b->h[i]->geo.n, T = (N + 15) / 16;
-        for (int ty = 0; ty < T; ++ty)
-            for (int tx = 0; tx < T; ++tx) bl[b->xcd[i]].push_back(BpWork{i, tx * 16, ty * 16, 0});
-    }
-    const std::vector<BpWork> bp = interleave(bl, BpWork{-1, 0, 0, 0});
+    const std::vector<SliceShape> sh = shapes_of(b);
+    const std::vector<BpWork> bp = bp_work_table(sh, b->xcd);
     if (b->d_bp) (void)hipFree(b->d_bp);
     b->d_bp = nullptr;
     RECON_HIP_TRY(hipMalloc(&b->d_bp, std::max<size_t>(1, bp.size()) * sizeof(BpWork)));
@@ -141,23 +172,13 @@ recon_status upload_work(recon_batch_handle* b)
     b->d_fp.assign(b->M, nullptr);
     b->n_fp.assign(b->M, 0);
     for (int s = 0; s < b->M; ++s) {
-        std::vector<std::vector<FpWork>> fl(NXCD);
-        for (int i = 0; i < n; ++i) {
-            const int nrays = b->h[i]->subset_count[s] * b->h[i]->geo.nch;
-            for (int r0 = 0; r0 < nrays; r0 += rpb) fl[b->xcd[i]].push_back(FpWork{i, r0});
-        }
-        const std::vector<FpWork> fp = interleave(fl, FpWork{-1, 0});
+        const std::vector<FpWork> fp = fp_work_table(sh, b->xcd, s, rpb);
         RECON_HIP_TRY(hipMalloc(&b->d_fp[s], std::max<size_t>(1, fp.size()) * sizeof(FpWork)));
         RECON_HIP_TRY(hipMemcpy(b->d_fp[s], fp.data(), fp.size() * sizeof(FpWork), hipMemcpyHostToDevice));
         b->n_fp[s] = (int)fp.size();
     }
     {
-        std::vector<std::vector<FpWork>> fl(NXCD);
-        for (int i = 0; i < n; ++i) {
-            const int nrays = b->h[i]->geo.nv * b->h[i]->geo.nch;
-            for (int r0 = 0; r0 < nrays; r0 += rpb) fl[b->xcd[i]].push_back(FpWork{i, r0});
-        }
-        const std::vector<FpWork> fp = interleave(fl, FpWork{-1, 0});
+        const std::vector<FpWork> fp = fp_work_table(sh, b->xcd, -1, rpb);
         if (b->d_fp_all) (void)hipFree(b->d_fp_all);
         b->d_fp_all = nullptr;
         RECON_HIP_TRY(hipMalloc(&b->d_fp_all, std::max<size_t>(1, fp.size()) * sizeof(FpWork)));
@@ -173,7 +194,7 @@ recon_status setup_batch(recon_batch_handle* b, int fp_segments)
 {
     const int n_slices = (int)b->h.size(), subsets = b->M;
     b->fp_segments = fp_segments > 0 ? fp_segments : BATCH_FP_SEGMENTS;
-    assign_xcds(b);
+    b->xcd = assign_xcds(shapes_of(b));
     std::vector<int2> subs((size_t)n_slices * subsets);
     for (int i = 0; i < n_slices; ++i)
         for (int s = 0; s < subsets; ++s)
@@ -319,6 +340,70 @@ recon_status batch_run(recon_batch_handle* b, const float* const* d_counts, cons
 }  // namespace
 
 extern "C" {
+
+recon_status recon_batch_check_work(const recon_geometry* geoms, int32_t n_slices, int32_t subsets,
+                                    int32_t fp_segments, int64_t* errors, int64_t* blocks)
+{
+    if (!geoms || !errors || !blocks) return fail(RECON_INVALID_ARG, "NULL argument");
+    if (n_slices < 1) return fail(RECON_INVALID_ARG, "n_slices must be >= 1");
+    if (fp_segments != 1 && fp_segments != 2 && fp_segments != 4 && fp_segments != 8 && fp_segments != 16)
+        return fail(RECON_INVALID_ARG, "fp_segments must be 1, 2, 4, 8 or 16");
+    std::vector<SliceShape> sh;
+    for (int i = 0; i < n_slices; ++i) {
+        recon_status st = validate_create(&geoms[i], subsets, 0.0, nullptr);
+        if (st != RECON_OK) return fail(st, "slice " + std::to_string(i) + ": " + recon_last_error());
+        const recon_geometry& g = geoms[i];
+        SliceShape s{g.n, g.n_channels, g.n_views, std::vector<int>(subsets, 0), 0};
+        for (int v = 0; v < g.n_views; ++v) ++s.subset_count[v % subsets];  // V_s = {v : v mod M = s}
+        s.max_subset_views = *std::max_element(s.subset_count.begin(), s.subset_count.end());
+        sh.push_back(s);
+    }
+    const std::vector<int> xcd = assign_xcds(sh);
+    int64_t bad = 0, nblk = 0;
+    // every tile of every slice exactly once, each on its slice's XCD
+    const std::vector<BpWork> bp = bp_work_table(sh, xcd);
+    std::vector<std::vector<int>> seen(n_slices);
+    for (int i = 0; i < n_slices; ++i) seen[i].assign((size_t)((sh[i].n + 15) / 16) * ((sh[i].n + 15) / 16), 0);
+    for (size_t p = 0; p < bp.size(); ++p) {
+        const BpWork& w = bp[p];
+        if (w.slice < 0) continue;
+        const int T = (sh[w.slice].n + 15) / 16;
+        if (w.slice >= n_slices || w.ti0 % 16 || w.tj0 % 16 || w.ti0 / 16 >= T || w.tj0 / 16 >= T ||
+            xcd[w.slice] != (int)(p % NXCD)) {
+            ++bad;
+            continue;
+        }
+        ++seen[w.slice][(size_t)(w.tj0 / 16) * T + w.ti0 / 16];
+    }
+    for (const auto& v : seen)
+        for (int c : v) bad += c != 1;
+    nblk += (int64_t)bp.size();
+    // every ray block of every subset (and of all views) exactly once, on its slice's XCD
+    const int rpb = fp_rays_per_block(fp_segments);
+    for (int s = -1; s < subsets; ++s) {
+        const std::vector<FpWork> fp = fp_work_table(sh, xcd, s, rpb);
+        for (int i = 0; i < n_slices; ++i) {
+            const int nrays = (s < 0 ? sh[i].nv : sh[i].subset_count[s]) * sh[i].nch;
+            seen[i].assign((size_t)((nrays + rpb - 1) / rpb), 0);
+        }
+        for (size_t p = 0; p < fp.size(); ++p) {
+            const FpWork& w = fp[p];
+            if (w.slice < 0) continue;
+            const int nrays = (s < 0 ? sh[w.slice].nv : sh[w.slice].subset_count[s]) * sh[w.slice].nch;
+            if (w.slice >= n_slices || w.r0 % rpb || w.r0 >= nrays || xcd[w.slice] != (int)(p % NXCD)) {
+                ++bad;
+                continue;
+            }
+            ++seen[w.slice][w.r0 / rpb];
+        }
+        for (const auto& v : seen)
+            for (int c : v) bad += c != 1;
+        nblk += (int64_t)fp.size();
+    }
+    *errors = bad;
+    *blocks = nblk;
+    return RECON_OK;
+}
 
 recon_status recon_batch_create(const recon_geometry* geoms, int32_t n_slices, int32_t subsets, double beta,
                                 const recon_params* params, recon_batch_handle** out)

@@ -56,7 +56,7 @@ EXPORTS = ["recon_default_params", "recon_status_string", "recon_last_error", "r
            "recon_cnn_set_state", "recon_cnn_save", "recon_cnn_load", "recon_cnn_forward", "recon_cnn_loss_grad",
            "recon_cnn_adam_step", "recon_cnn_train_step", "recon_cnn_tensor", "recon_cnn_time_kernels",
            "recon_data_residual", "recon_warm_start", "recon_warm_start_noalloc", "recon_fbp",
-           "recon_rebin_helical", "recon_read_bandwidth"]
+           "recon_rebin_helical", "recon_read_bandwidth", "recon_batch_check_work"]
 
 _lib = None
 
@@ -89,6 +89,7 @@ def lib():
         L.recon_subset_size.argtypes = [vp, i32, P(i32)]
         L.recon_set_launch.argtypes = [vp, i32, i32]
         L.recon_read_bandwidth.argtypes = [i64, i32, P(d), vp]
+        L.recon_batch_check_work.argtypes = [P(Geometry_c), i32, i32, i32, P(i64), P(i64)]
         L.recon_check_tables.argtypes = [P(Geometry_c), i32, i32, P(i64), P(i64), P(i64)]
         L.recon_count_pairs.argtypes = [vp, i32, i32, P(i64)]
         L.recon_time_kernels.argtypes = [vp, vp, f, vp, i32, P(d), vp]
@@ -140,6 +141,16 @@ def default_params() -> dict:
     p = Params_c()
     lib().recon_default_params(ctypes.byref(p))
     return {name: getattr(p, name) for name, _ in Params_c._fields_}
+
+
+def batch_check_work(geometries, subsets: int, fp_segments: int = 4):
+    """Host-only check of a batch's work tables: (errors, blocks)."""
+    n = len(geometries)
+    garr = (Geometry_c * max(1, n))(*[geometry_c(g) for g in geometries])
+    e, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().recon_batch_check_work(garr, n, subsets, fp_segments, ctypes.byref(e), ctypes.byref(b)),
+           "recon_batch_check_work")
+    return int(e.value), int(b.value)
 
 
 def read_bandwidth(nbytes: int = 2 << 20, reps: int = 10) -> float:

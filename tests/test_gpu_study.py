@@ -42,3 +42,26 @@ def test_constant_step_and_timer(case):
     s = cs.time_slice(case, 5, 1e-3, 20, reps=2)
     assert 0 < s < 1.0
     assert cs.first_reaching(t, t["r_over_v"][-1]) <= 30
+
+
+def test_limited_angle_case_takes_the_first_views():
+    """The study's limited-angle case: the first views of the turn's own data at the turn's spacing,
+    and tracking it equals an uninterrupted run on that arc."""
+    import math
+
+    from paper_1903_10088_amd import conv_study as cs
+    from paper_1903_10088_amd import recon
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dev = torch.device("cuda:0")
+    g = ph.config0_geometry()
+    full = cs.Case(g, 3, 1e4, dev)
+    part = cs.Case(g, 3, 1e4, dev, first_views=100)
+    assert part.g.n_views == 100 and part.g.scan_arc_rad == 2 * math.pi * 100 / 180
+    assert torch.equal(part.counts, full.counts[:100])
+    print("study: limited-angle case, 20 sub-iterations", flush=True)
+    t = cs.track(part, 5, 1e-3, 20)
+    R = recon.Recon(part.g, 5, 1e-3)
+    img, _ = R.os_iterate(part.counts, part.i0, None, 20)
+    res = R.data_residual(part.counts, part.i0, img).cpu().numpy()
+    assert t["r_over_v"][-1] == float(res[0] / res[1])

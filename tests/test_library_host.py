@@ -206,3 +206,22 @@ def test_partial_arc_tables_hold_every_ray():
                     scan_arc_rad=math.pi + 2 * g0.gamma_max)
     missed, cand, pairs = recon.check_tables(g, 4)
     assert missed == 0 and pairs > 0 and cand >= pairs
+
+
+def test_batch_work_tables_cover_every_tile_and_ray_block():
+    """The batched kernels' work tables (host-only check): for the 64-slice mixed batch of the bench
+    and a batch of limited-angle and odd slices, every update tile and every projector ray block of
+    every subset (and of all views) appears exactly once, on its slice's XCD, for every projector
+    shape."""
+    mixed = [ph.random_batch_geometry(1000 + i)[0] for i in range(64)]
+    odd = [ph.Geometry(n=37, pixel_mm=10.0, n_views=33, n_channels=51, start_angle_rad=0.3),
+           ph.Geometry(n=64, pixel_mm=6.25, n_views=40, n_channels=97, scan_arc_rad=2.5),
+           ph.config0_geometry()]
+    for geoms, M in ((mixed, 20), (odd, 5), (odd[:1], 33)):
+        for seg in (1, 4, 16):
+            errors, blocks = recon.batch_check_work(geoms, M, seg)
+            assert errors == 0 and blocks > 0, (len(geoms), M, seg)
+    with pytest.raises(recon.ReconError):
+        recon.batch_check_work(odd, 5, 3)
+    with pytest.raises(recon.ReconError):
+        recon.batch_check_work(odd, 34)  # more subsets than the 33-view slice has views
