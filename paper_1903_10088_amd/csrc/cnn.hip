@@ -114,17 +114,34 @@ __device__ __forceinline__ Tile tile_plain(int t, int tiles_x, int tiles_per_img
 __device__ __forceinline__ size_t pix(int b, int i, int j, int n) { return ((size_t)b * n + i) * n + j; }
 
 // Stages the (T+2)^2 halo tile of a channels-last bf16 tensor into LDS (zeros
-// outside the image).
+// outside the image); called by all 256 threads of a block.  Every load of a
+// thread is issued before its first LDS store, so their latencies overlap
+// (pixels outside the image load the tensor's first element and store zero).
 __device__ __forceinline__ void load_halo(uint16_t (*s)[HALO][LDS_PIX], const uint16_t* __restrict__ act, Tile t,
                                           int n)
 {
-    for (int e = threadIdx.x; e < HALO * HALO * 4; e += blockDim.x) {
+    constexpr int NCH = HALO * HALO * 4;       // 16-byte chunks of the halo tile
+    constexpr int PER = (NCH + 255) / 256;     // chunks per thread
+    u32x4 v[PER];
+    bool in[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = (int)threadIdx.x + 256 * k;
         const int p = e >> 2, q = e & 3;
         const int ly = p / HALO, lx = p - ly * HALO;
         const int gi = t.i0 + ly - 1, gj = t.j0 + lx - 1;
-        u32x4 v = {0u, 0u, 0u, 0u};
-        if (gi >= 0 && gi < n && gj >= 0 && gj < n) v = *(const u32x4*)(act + pix(t.b, gi, gj, n) * C + q * 8);
-        *(u32x4*)(&s[ly][lx][q * 8]) = v;
+        in[k] = e < NCH && gi >= 0 && gi < n && gj >= 0 && gj < n;
+        const size_t off = in[k] ? pix(t.b, gi, gj, n) * C + q * 8 : 0;
+        v[k] = *(const u32x4*)(act + off);
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = (int)threadIdx.x + 256 * k;
+        if (e < NCH) {
+            const int p = e >> 2, q = e & 3;
+            const int ly = p / HALO, lx = p - ly * HALO;
+            *(u32x4*)(&s[ly][lx][q * 8]) = in[k] ? v[k] : u32x4{0u, 0u, 0u, 0u};
+        }
     }
 }
 
@@ -197,53 +214,66 @@ __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ 
     for (int q = 0; q < 4; ++q) dst[q] = u32x4{pk[4 * q], pk[4 * q + 1], pk[4 * q + 2], pk[4 * q + 3]};
 }
 
-// One 16x16 output tile of the 32 -> 32 convolution (stages its halo, then the MFMAs).
+// One 16x16 output tile of the 32 -> 32 convolution (stages its halo, then the
+// MFMAs).  Wave w computes output channels hh*16 .. hh*16+15 (hh = w mod 2) of
+// the 8 output rows r0 .. r0+7 (r0 = 8 (w / 2)), reading staged rows r0 ..
+// r0+9; each staged fragment feeds up to 3 output rows.  Every output sums its
+// taps in the order (ky, kx) = (0,0), (0,1), ..., (2,2).
 template <int MODE>
-__device__ __forceinline__ void conv32_tile(uint16_t (*s)[HALO][LDS_PIX], const bf16x8 (&A)[9][2],
+__device__ __forceinline__ void conv32_tile(uint16_t (*s)[HALO][LDS_PIX], const bf16x8 (&A)[9],
                                             const uint16_t* __restrict__ in, const float* __restrict__ bias,
                                             const uint16_t* __restrict__ mask, uint16_t* __restrict__ out, int n,
                                             Tile tl, int wave, int m, int g)
 {
+    // (bias: the block's LDS copy, written before the first tile)
     load_halo(s, in, tl, n);
     __syncthreads();
-    f32x4 acc[4][2];
+    const int hh = wave & 1, r0 = (wave >> 1) * 8;
+    f32x4 acc[8];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r][0] = acc[r][1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    const int r0 = wave * 4;  // this wave's output rows (tile-local); it reads staged rows r0 .. r0 + 5
+    for (int r = 0; r < 8; ++r) acc[r] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int R = 0; R < 6; ++R)
+    for (int R = 0; R < 10; ++R)
 #pragma unroll
         for (int kx = 0; kx < 3; ++kx) {
             // B operand: lane (m, g) holds channels 8g .. 8g+7 of staged pixel (r0 + R, m + kx)
             const bf16x8 Bf = as_bf8(*(const u32x4*)(&s[r0 + R][m + kx][g * 8]));
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
+            for (int rr = 0; rr < 8; ++rr) {
                 const int ky = R - rr;
-                if (ky >= 0 && ky < 3) {
-                    acc[rr][0] = mfma(A[ky * 3 + kx][0], Bf, acc[rr][0]);
-                    acc[rr][1] = mfma(A[ky * 3 + kx][1], Bf, acc[rr][1]);
-                }
+                if (ky >= 0 && ky < 3) acc[rr] = mfma(A[ky * 3 + kx], Bf, acc[rr]);
             }
         }
-    // D[4g + i][m]: output channels h*16 + 4g + i of pixel column m
+    // D[4g + i][m]: output channels hh*16 + 4g + i of pixel column m
+    const int o0 = hh * 16 + g * 4;
+    // rows in two halves of 4; in dgrad the 4 mask loads of a half go first, so their latencies overlap
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-        const int gi = tl.i0 + r0 + rr, gj = tl.j0 + m;
-        if (gi >= n || gj >= n) continue;
-        const size_t base = pix(tl.b, gi, gj, n) * C;
+    for (int half = 0; half < 2; ++half) {
+        u32x2 mks[4];
+        if constexpr (MODE == 1) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int o0 = h * 16 + g * 4;
+            for (int k = 0; k < 4; ++k) {
+                const int gi = tl.i0 + r0 + 4 * half + k, gj = tl.j0 + m;
+                const size_t base = (gi < n && gj < n) ? pix(tl.b, gi, gj, n) * C : 0;
+                mks[k] = *(const u32x2*)(mask + base + o0);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int rr = 4 * half + k;
+            const int gi = tl.i0 + r0 + rr, gj = tl.j0 + m;
+            if (gi >= n || gj >= n) continue;
+            const size_t base = pix(tl.b, gi, gj, n) * C;
             float v[4];
             if constexpr (MODE == 0) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[rr][h][i] + bias[o0 + i], 0.0f);
+                for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[rr][i] + bias[o0 + i], 0.0f);
             } else {
-                const u32x2 mk = *(const u32x2*)(mask + base + o0);
-                v[0] = bf_lo(mk.x) > 0.0f ? acc[rr][h][0] : 0.0f;
-                v[1] = bf_hi(mk.x) > 0.0f ? acc[rr][h][1] : 0.0f;
-                v[2] = bf_lo(mk.y) > 0.0f ? acc[rr][h][2] : 0.0f;
-                v[3] = bf_hi(mk.y) > 0.0f ? acc[rr][h][3] : 0.0f;
+                const u32x2 mk = mks[k];
+                v[0] = bf_lo(mk.x) > 0.0f ? acc[rr][0] : 0.0f;
+                v[1] = bf_hi(mk.x) > 0.0f ? acc[rr][1] : 0.0f;
+                v[2] = bf_lo(mk.y) > 0.0f ? acc[rr][2] : 0.0f;
+                v[3] = bf_hi(mk.y) > 0.0f ? acc[rr][3] : 0.0f;
             }
             *(u32x2*)(out + base + o0) = u32x2{f2bf(v[0]) | (f2bf(v[1]) << 16), f2bf(v[2]) | (f2bf(v[3]) << 16)};
         }
@@ -253,10 +283,10 @@ __device__ __forceinline__ void conv32_tile(uint16_t (*s)[HALO][LDS_PIX], const 
 // 32 -> 32 convolution on the matrix cores.  MODE 0 (forward): out =
 // bf(relu(conv(in, W) + bias)).  MODE 1 (dgrad): out = bf(conv(in, Wt) *
 // [mask > 0]) with Wt the flipped, transposed taps.  wts: [9][32 out][32 in]
-// bfloat16.  Persistent: the weights are loaded into registers once per
-// block, which then takes tiles blockIdx.x, blockIdx.x + gridDim.x, ... of the
-// XCD-aware order (gridDim.x a multiple of 8 or equal to the tile count, so a
-// block's tiles stay on its own XCD).
+// bfloat16.  Persistent: each wave loads the weights of its output-channel half
+// into registers once, then the block takes tiles blockIdx.x, blockIdx.x +
+// gridDim.x, ... of the XCD-aware order (gridDim.x a multiple of 8 or equal to
+// the tile count, so a block's tiles stay on its own XCD).
 template <int MODE>
 __device__ __forceinline__ void conv32_body(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wts,
                                             const float* __restrict__ bias, const uint16_t* __restrict__ mask,
@@ -264,23 +294,23 @@ __device__ __forceinline__ void conv32_body(const uint16_t* __restrict__ in, con
                                             int nblocks)
 {
     __shared__ __attribute__((aligned(16))) uint16_t s[HALO][HALO][LDS_PIX];
+    __shared__ __attribute__((aligned(16))) float sbias[C];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 15, g = lane >> 4;
-    // A operands: lane (m, g) holds W_tap[h*16 + m][8g .. 8g+7]
-    bf16x8 A[9][2];
+    const int hh = wave & 1;
+    if (MODE == 0 && threadIdx.x < C) sbias[threadIdx.x] = bias[threadIdx.x];  // read after conv32_tile's barrier
+    // A operands: lane (m, g) holds W_tap[hh*16 + m][8g .. 8g+7]
+    bf16x8 A[9];
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) A[tap][h] = as_bf8(*(const u32x4*)(wts + ((tap * C) + h * 16 + m) * C + g * 8));
+    for (int tap = 0; tap < 9; ++tap) A[tap] = as_bf8(*(const u32x4*)(wts + ((tap * C) + hh * 16 + m) * C + g * 8));
     for (int v = blockIdx.x; v < nblocks; v += gridDim.x) {
         if (v != (int)blockIdx.x) __syncthreads();  // the previous tile's reads of s are done
-        conv32_tile<MODE>(s, A, in, bias, mask, out, n, tile_of(v, nblocks, tiles_x, tiles_per_img), wave, m, g);
+        conv32_tile<MODE>(s, A, in, sbias, mask, out, n, tile_of(v, nblocks, tiles_x, tiles_per_img), wave, m, g);
     }
 }
 
-// Held to 4 waves per SIMD: with the weights in registers for the whole
-// persistent loop the compiler would otherwise settle on 3, and a whole
-// forward pass measured faster at 4 despite a few spilled registers.
+// Held to 4 waves per SIMD (each wave keeps only its output-channel half of
+// the weights, 36 registers, so this fits without spills).
 template <int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void conv32_kernel(
     const uint16_t* __restrict__ in, const uint16_t* __restrict__ wts, const float* __restrict__ bias,
