@@ -572,6 +572,7 @@ def warm_leg(n_slices: int, weights: str, dev):
     rec = _json.load(open(meta)) if os.path.exists(meta) else {}
     ratio = rec.get("residual_ratio_limit", 1.05)
     n_pre, n_refine, n_cold = rec.get("n_pre", 10), rec.get("n_refine", 5), rec.get("n_cold", 500)
+    stride = rec.get("check_stride", 1)
     items = ws.config4_items(range(30000, 30000 + n_slices))
     log(f"bench: warm-start leg: {n_slices} slices ...")
     counts = ws.make_counts(items, workers=8)
@@ -586,15 +587,16 @@ def warm_leg(n_slices: int, weights: str, dev):
     cts = [torch.from_numpy(c).to(dev) for c in counts]
     i0s = [i0 for _, _, i0 in items]
     imgs = [torch.empty((512, 512), dtype=torch.float32, device=dev) for _ in items]
-    B.warm_start(net, cts, i0s, imgs, n_pre, n_refine, n_cold, ratio)
-    (_, res, flo, fb), t_warm = ws.timed(lambda: B.warm_start(net, cts, i0s, imgs, n_pre, n_refine, n_cold, ratio))
+    B.warm_start(net, cts, i0s, imgs, n_pre, n_refine, n_cold, ratio, check_stride=stride)
+    (_, res, flo, fb), t_warm = ws.timed(lambda: B.warm_start(net, cts, i0s, imgs, n_pre, n_refine, n_cold, ratio,
+                                                              check_stride=stride))
     rmse_w = float(np.mean(ws.disc_rmse(torch.stack(imgs), conv, 512)) / ph.MU_WATER_PER_MM)
     n_eq = ws.equal_rmse_count(curve, rmse_w)
     pimgs = B.initial_images(dev)
     B.run(cts, i0s, pimgs, n_eq)
     pimgs = B.initial_images(dev)
     _, t_plain = ws.timed(lambda: B.run(cts, i0s, pimgs, n_eq))
-    out = {"slices": n_slices, "n_pre": n_pre, "n_refine": n_refine, "n_cold": n_cold,
+    out = {"slices": n_slices, "n_pre": n_pre, "n_refine": n_refine, "n_cold": n_cold, "check_stride": stride,
            "warm_slices_per_s": n_slices / t_warm,
            "warm_rmse_to_converged_over_muw": rmse_w, "fallbacks": int(fb.sum()), "residual_ratio_limit": ratio,
            "plain_sub_iterations_at_equal_rmse": n_eq, "plain_rmse_to_converged_over_muw": curve[n_eq],

@@ -243,17 +243,20 @@ recon_status recon_rebin_helical(const recon_geometry* g, int32_t n_helical_view
                                  const float* d_counts, float i0, const double* z_slices, int32_t n_slices,
                                  float* d_out, void* stream);
 
-/* Data consistency of an image against the counts of all views:
- *   d_out[0] = mean over every ray of (l_i - p_i)^2, l = A mu (d_img, 1/mm),
+/* Data consistency of an image against the counts of the views of every
+ * subset_stride-th subset (subsets 0, K, 2K, ... with K = subset_stride; K = 1:
+ * every view; for K dividing the subset count, every K-th view of the turn):
+ *   d_out[0] = mean over those rays of (l_i - p_i)^2, l = A mu (d_img, 1/mm),
  *              p = ln(I0 / max(y, 1))  (the squared difference of section
- *              3.C.2 taken over the whole sinogram instead of one subset);
- *   d_out[1] = mean over every ray of 1 / max(y, 1), the variance of p under
- *              Poisson noise to first order: the level d_out[0] settles near
- *              once the image explains the data.
- * d_out: device double[2].  Uses the handle's workspace: do not overlap with
- * other calls on the same handle. */
-recon_status recon_data_residual(recon_handle* h, const float* d_counts, float i0, const float* d_img, double* d_out,
-                                 void* stream);
+ *              3.C.2 taken over those views instead of one subset);
+ *   d_out[1] = mean over the same rays of 1 / max(y, 1), the variance of p
+ *              under Poisson noise to first order: the level d_out[0] settles
+ *              near once the image explains the data.
+ * 1 <= subset_stride <= subsets and, for subset_stride > 1, at most 64
+ * subsets chosen, else RECON_INVALID_ARG.  d_out: device double[2].  Uses the handle's workspace:
+ * do not overlap with other calls on the same handle. */
+recon_status recon_data_residual(recon_handle* h, const float* d_counts, float i0, const float* d_img,
+                                 int32_t subset_stride, double* d_out, void* stream);
 
 /* Geometry queries (host, synchronous). */
 recon_status recon_subset_size(recon_handle* h, int32_t subset, int32_t* n_views_out);
@@ -341,12 +344,13 @@ recon_status recon_batch(const recon_geometry* geoms, int32_t n_slices, int32_t 
  *      non-negative); its max_n must cover every slice;
  *   3. n_refine sub-iterations refine that image with a fresh step-rule state
  *      (lambda_0, subsets from 0);
- *   4. the full-data residual r and noise level v of each result are taken as
- *      in recon_data_residual (one projection of every view);
+ *   4. the residual r and noise level v of each result are taken as in
+ *      recon_data_residual over the views of every check_stride-th subset
+ *      (1: every view; same limits as its subset_stride);
  *   5. every slice with r > residual_ratio * v (the level the plain iteration
- *      reaches, calibrated on its own converged images) is reconstructed again
- *      from the homogeneous start with n_cold sub-iterations (alone, or as a
- *      batch when there are many).
+ *      reaches, calibrated on its own images with the same check_stride) is
+ *      reconstructed again from the homogeneous start with n_cold
+ *      sub-iterations (alone, or as a batch when there are many).
  * d_counts, d_imgs: host arrays of device pointers as in recon_batch_run
  * (d_imgs receive the results); i0: host array.  h_residual, h_floor (host
  * double[n_slices]) and h_fallback (host int32[n_slices], 1 = cold start used)
@@ -355,8 +359,8 @@ recon_status recon_batch(const recon_geometry* geoms, int32_t n_slices, int32_t 
 struct recon_cnn;
 recon_status recon_warm_start(recon_batch_handle* b, struct recon_cnn* net, const float* const* d_counts,
                               const float* i0, float* const* d_imgs, int32_t n_pre, int32_t n_refine, int32_t n_cold,
-                              double residual_ratio, double* h_residual, double* h_floor, int32_t* h_fallback,
-                              void* stream);
+                              double residual_ratio, int32_t check_stride, double* h_residual, double* h_floor,
+                              int32_t* h_fallback, void* stream);
 
 /* recon_warm_start for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
@@ -377,8 +381,8 @@ recon_status recon_warm_start(recon_batch_handle* b, struct recon_cnn* net, cons
  * recon_warm_start. */
 recon_status recon_warm_start_noalloc(recon_batch_handle* b, struct recon_cnn* net, const float* const* d_counts,
                                       const float* i0, float* const* d_imgs, int32_t n_pre, int32_t n_refine,
-                                      int32_t n_cold, double residual_ratio, double* h_residual, double* h_floor,
-                                      int32_t* h_fallback, void* stream);
+                                      int32_t n_cold, double residual_ratio, int32_t check_stride, double* h_residual,
+                                      double* h_floor, int32_t* h_fallback, void* stream);
 
 /* Number of (ray, in-image pixel) interpolation pairs of `subset` (-1 = all
  * views): the pixel reads of the projector and the sinogram reads of the

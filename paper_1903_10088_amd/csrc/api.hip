@@ -612,21 +612,39 @@ recon_status os_iterate_run(recon_handle* h, const float* d_counts, float i0, fl
 
 extern "C" {
 
-recon_status recon_data_residual(recon_handle* h, const float* d_counts, float i0, const float* d_img, double* d_out,
-                                 void* stream)
+recon_status recon_data_residual(recon_handle* h, const float* d_counts, float i0, const float* d_img,
+                                 int32_t subset_stride, double* d_out, void* stream)
 {
     if (!h || !d_counts || !d_img || !d_out) return fail(RECON_INVALID_ARG, "NULL argument");
     if (!(i0 > 0) || !std::isfinite(i0)) return fail(RECON_INVALID_ARG, "i0 must be finite and > 0");
+    if (subset_stride < 1 || subset_stride > h->M ||
+        (subset_stride > 1 && (h->M + subset_stride - 1) / subset_stride > RES_BLOCKS))
+        return fail(RECON_INVALID_ARG, "subset_stride must be in [1, subsets], choosing at most 64 subsets if > 1");
     hipStream_t s = as_stream(stream);
     const Geo& G = h->geo;
     const long nrays = (long)G.nv * G.nch;
     HIP_TRY(launch_prep_counts(d_counts, h->d_views, G.nv, G.nch, i0, h->d_yt, h->d_p, s));
     HIP_TRY(launch_pad_image(d_img, h->d_img[0], h->d_imgT[0], G.n, G.P, s));
-    // all views are one contiguous ray range in subset order
-    HIP_TRY(launch_fp_os(G, h->fp_segments, h->d_img[0], h->d_imgT[0], h->d_raygeo, h->d_raymeta, 0, (int)nrays,
-                         h->d_yt, h->d_p, h->d_w, h->d_part_all, s));
-    HIP_TRY(launch_residual_final(h->d_part_all, (int)((nrays + SQ_GROUP - 1) / SQ_GROUP), d_counts, nrays,
-                                  h->d_res_part, d_out, s));
+    if (subset_stride == 1) {
+        // all views are one contiguous ray range in subset order
+        HIP_TRY(launch_fp_os(G, h->fp_segments, h->d_img[0], h->d_imgT[0], h->d_raygeo, h->d_raymeta, 0, (int)nrays,
+                             h->d_yt, h->d_p, h->d_w, h->d_part_all, s));
+        HIP_TRY(launch_residual_final(h->d_part_all, (int)((nrays + SQ_GROUP - 1) / SQ_GROUP), d_counts, nrays,
+                                      h->d_res_part, d_out, s));
+        return RECON_OK;
+    }
+    // every subset_stride-th subset, one projection each
+    long nchosen_rays = 0;
+    int j = 0;
+    for (int sub = 0; sub < h->M; sub += subset_stride, ++j) {
+        const int ray0 = h->subset_start[sub] * G.nch, nr = h->subset_count[sub] * G.nch;
+        HIP_TRY(launch_fp_os(G, h->fp_segments, h->d_img[0], h->d_imgT[0], h->d_raygeo, h->d_raymeta, ray0, nr,
+                             h->d_yt, h->d_p, h->d_w, h->d_part, s));
+        HIP_TRY(launch_residual_subset(h->d_part, (nr + SQ_GROUP - 1) / SQ_GROUP, h->d_res_part, j, s));
+        nchosen_rays += nr;
+    }
+    HIP_TRY(launch_residual_strided_final(d_counts, G.nv, G.nch, h->M, subset_stride, j, nchosen_rays, h->d_res_part,
+                                          d_out, s));
     return RECON_OK;
 }
 

@@ -638,8 +638,8 @@ constexpr size_t NOALLOC_BYTES = NOALLOC_CPTR_OFFSET + sizeof(float*) * NOALLOC_
 
 recon_status warm_start_impl(recon_batch_handle* b, recon_cnn* net, const float* const* d_counts, const float* i0,
                              float* const* d_imgs, int n_pre, int n_refine, int n_cold, double residual_ratio,
-                             double* h_residual, double* h_floor, int32_t* h_fallback, hipStream_t s,
-                             unsigned char* ws)
+                             int check_stride, double* h_residual, double* h_floor, int32_t* h_fallback,
+                             hipStream_t s, unsigned char* ws)
 {
     const bool noalloc = ws != nullptr;
     const int n = (int)b->h.size();
@@ -695,12 +695,22 @@ recon_status warm_start_impl(recon_batch_handle* b, recon_cnn* net, const float*
     }
     // 3. refinement by the plain iteration, fresh step-rule state
     if (e == hipSuccess && st == RECON_OK) st = batch_run(b, d_counts, i0, d_imgs, n_refine, nullptr, s, !noalloc);
-    // 4. full-data residual and its noise level, every slice at once from the final iterate
-    //    (one projection of every view; the last refining epoch's own squared differences lag
-    //    the still-moving iterate and would not be comparable with converged images)
-    if (e == hipSuccess && st == RECON_OK)
-        e = launch_fp_batch(b->fp_segments, b->d_slices, b->d_fp_all, b->n_fp_all, -1, b->last_in, s);
-    if (e == hipSuccess && st == RECON_OK) e = launch_residual_final_batch(b->d_slices, d_cptr, n, d_res, s);
+    // 4. residual and its noise level, every slice at once from the final iterate, over every
+    //    view or every check_stride-th subset (fresh projections: the refining sub-iterations'
+    //    own squared differences lag the still-moving iterate and would not be comparable with
+    //    the plain method's images)
+    if (check_stride == 1) {
+        if (e == hipSuccess && st == RECON_OK)
+            e = launch_fp_batch(b->fp_segments, b->d_slices, b->d_fp_all, b->n_fp_all, -1, b->last_in, s);
+        if (e == hipSuccess && st == RECON_OK) e = launch_residual_final_batch(b->d_slices, d_cptr, n, d_res, s);
+    } else {
+        for (int sub = 0, j = 0; sub < b->M && e == hipSuccess && st == RECON_OK; sub += check_stride, ++j) {
+            e = launch_fp_batch(b->fp_segments, b->d_slices, b->d_fp[sub], b->n_fp[sub], sub, b->last_in, s);
+            if (e == hipSuccess) e = launch_residual_subset_batch(b->d_slices, n, sub, j, s);
+        }
+        if (e == hipSuccess && st == RECON_OK)
+            e = launch_residual_strided_final_batch(b->d_slices, d_cptr, n, b->M, check_stride, d_res, s);
+    }
     std::vector<double> res(2 * (size_t)n);
     if (e == hipSuccess && st == RECON_OK)
         e = hipMemcpyAsync(res.data(), d_res, 2 * sizeof(double) * n, hipMemcpyDeviceToHost, s);
@@ -757,11 +767,15 @@ recon_status warm_start_impl(recon_batch_handle* b, recon_cnn* net, const float*
 }
 
 recon_status check_warm_args(recon_batch_handle* b, recon_cnn* net, const float* const* d_counts, const float* i0,
-                             float* const* d_imgs, int n_pre, int n_refine, int n_cold, double residual_ratio)
+                             float* const* d_imgs, int n_pre, int n_refine, int n_cold, double residual_ratio,
+                             int check_stride)
 {
     if (!b || !net || !d_counts || !i0 || !d_imgs) return fail(RECON_INVALID_ARG, "NULL argument");
     if (n_pre < 0 || n_refine < 0 || n_cold < 0) return fail(RECON_INVALID_ARG, "iteration counts must be >= 0");
     if (!(residual_ratio > 0)) return fail(RECON_INVALID_ARG, "residual_ratio must be > 0");
+    if (check_stride < 1 || check_stride > b->M ||
+        (check_stride > 1 && (b->M + check_stride - 1) / check_stride > RES_BLOCKS))
+        return fail(RECON_INVALID_ARG, "check_stride must be in [1, subsets], choosing at most 64 subsets if > 1");
     return RECON_OK;
 }
 
@@ -803,21 +817,23 @@ extern "C" {
 
 recon_status recon_warm_start(recon_batch_handle* b, recon_cnn* net, const float* const* d_counts, const float* i0,
                               float* const* d_imgs, int32_t n_pre, int32_t n_refine, int32_t n_cold,
-                              double residual_ratio, double* h_residual, double* h_floor, int32_t* h_fallback,
-                              void* stream)
+                              double residual_ratio, int32_t check_stride, double* h_residual, double* h_floor,
+                              int32_t* h_fallback, void* stream)
 {
-    recon_status st = check_warm_args(b, net, d_counts, i0, d_imgs, n_pre, n_refine, n_cold, residual_ratio);
+    recon_status st =
+        check_warm_args(b, net, d_counts, i0, d_imgs, n_pre, n_refine, n_cold, residual_ratio, check_stride);
     if (st != RECON_OK) return st;
-    return warm_start_impl(b, net, d_counts, i0, d_imgs, n_pre, n_refine, n_cold, residual_ratio, h_residual,
-                           h_floor, h_fallback, as_stream(stream), nullptr);
+    return warm_start_impl(b, net, d_counts, i0, d_imgs, n_pre, n_refine, n_cold, residual_ratio, check_stride,
+                           h_residual, h_floor, h_fallback, as_stream(stream), nullptr);
 }
 
 recon_status recon_warm_start_noalloc(recon_batch_handle* b, recon_cnn* net, const float* const* d_counts,
                                       const float* i0, float* const* d_imgs, int32_t n_pre, int32_t n_refine,
-                                      int32_t n_cold, double residual_ratio, double* h_residual, double* h_floor,
-                                      int32_t* h_fallback, void* stream)
+                                      int32_t n_cold, double residual_ratio, int32_t check_stride, double* h_residual,
+                                      double* h_floor, int32_t* h_fallback, void* stream)
 {
-    recon_status st = check_warm_args(b, net, d_counts, i0, d_imgs, n_pre, n_refine, n_cold, residual_ratio);
+    recon_status st =
+        check_warm_args(b, net, d_counts, i0, d_imgs, n_pre, n_refine, n_cold, residual_ratio, check_stride);
     if (st != RECON_OK) return st;
     if ((int)b->h.size() > NOALLOC_MAX_SLICES)
         return fail(RECON_INVALID_ARG, "recon_warm_start_noalloc takes at most 4096 slices per call");
@@ -831,8 +847,8 @@ recon_status recon_warm_start_noalloc(recon_batch_handle* b, recon_cnn* net, con
     unsigned char* sp = nullptr;
     st = scratch_of_current_device(&sp);
     if (st != RECON_OK) return st;
-    return warm_start_impl(b, net, d_counts, i0, d_imgs, n_pre, n_refine, n_cold, residual_ratio, h_residual,
-                           h_floor, h_fallback, as_stream(stream), sp);
+    return warm_start_impl(b, net, d_counts, i0, d_imgs, n_pre, n_refine, n_cold, residual_ratio, check_stride,
+                           h_residual, h_floor, h_fallback, as_stream(stream), sp);
 }
 
 }  // extern "C"

@@ -328,5 +328,15 @@ hipError_t launch_residual_final(const double* part, int ngroups, const float* c
 // kernels.hip: the same for every slice of a batch (block i -> out[2i], out[2i + 1]).
 hipError_t launch_residual_final_batch(const SliceDesc* slices, const float* const* counts, int n_slices,
                                        double* out, hipStream_t s);
+// kernels.hip, residual over every stride-th subset: res_part[2 j] = sum of part[0..ngroups) (the
+// subset of rank j among the chosen ones), then the noise level over the chosen views' rows into
+// res_part[2 b + 1] and out = (sum_j res_part[2 j], sum_b res_part[2 b + 1]) / nrays (chosen rays).
+hipError_t launch_residual_subset(const double* part, int ngroups, double* res_part, int j, hipStream_t s);
+hipError_t launch_residual_strided_final(const float* counts, int nv, int nch, int M, int stride, int nchosen,
+                                         long nrays, double* res_part, double* out, hipStream_t s);
+// Batched forms (each slice's subset buffer and res_part; subset counts from the slice table).
+hipError_t launch_residual_subset_batch(const SliceDesc* slices, int n_slices, int sub, int j, hipStream_t s);
+hipError_t launch_residual_strided_final_batch(const SliceDesc* slices, const float* const* counts, int n_slices,
+                                               int M, int stride, double* out, hipStream_t s);
 
 }  // namespace recon

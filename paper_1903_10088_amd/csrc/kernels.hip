@@ -490,6 +490,105 @@ __global__ void residual_combine_batch_kernel(const SliceDesc* __restrict__ slic
     residual_combine(D->res_part, (long)D->geo.nv * D->geo.nch, out + 2 * i);
 }
 
+// Residual over every stride-th subset (subsets 0, stride, 2 stride, ...): the
+// projector leaves each chosen subset's squared-difference group sums in the
+// slice's subset buffer, one block adds them (thread-strided, then a fixed tree)
+// into res_part[2 j] (j = the subset's rank among the chosen ones); the noise
+// level sums 1 / max(y, 1) over the chosen views' rows of the counts in
+// RES_BLOCKS row ranges into res_part[2 b + 1]; the combine adds both in index
+// order.  Alone and in a batch the same functions run in the same order, so a
+// slice gets the same bits either way.
+__device__ __forceinline__ double block_tree_sum(double s, double* red)
+{
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+__device__ __forceinline__ void residual_subset_sum(const double* __restrict__ part, int ngroups, double* dst)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < ngroups; k += 256) s += part[k];
+    const double t = block_tree_sum(s, red);
+    if (threadIdx.x == 0) *dst = t;
+}
+
+__device__ __forceinline__ void residual_noise_rows(const float* __restrict__ y, int nv, int nch, int M, int stride,
+                                                    int b, double* dst)
+{
+    __shared__ double red[256];
+    const int v0 = (int)((long)nv * b / RES_BLOCKS), v1 = (int)((long)nv * (b + 1) / RES_BLOCKS);
+    double s = 0.0;
+    for (int v = v0; v < v1; ++v) {
+        if ((v % M) % stride != 0) continue;
+        for (int k = threadIdx.x; k < nch; k += 256) s += 1.0 / (double)fmaxf(y[(size_t)v * nch + k], 1.0f);
+    }
+    const double t = block_tree_sum(s, red);
+    if (threadIdx.x == 0) *dst = t;
+}
+
+__device__ __forceinline__ void residual_strided_combine(const double* __restrict__ res_part, int nchosen, long nrays,
+                                                         double* __restrict__ out)
+{
+    double s0 = 0.0, s1 = 0.0;
+    for (int j = 0; j < nchosen; ++j) s0 += res_part[2 * j];
+    for (int b = 0; b < RES_BLOCKS; ++b) s1 += res_part[2 * b + 1];
+    out[0] = s0 / (double)nrays;
+    out[1] = s1 / (double)nrays;
+}
+
+__global__ __launch_bounds__(256) void residual_subset_kernel(const double* __restrict__ part, int ngroups,
+                                                              double* __restrict__ dst)
+{
+    residual_subset_sum(part, ngroups, dst);
+}
+
+__global__ __launch_bounds__(256) void residual_noise_kernel(const float* __restrict__ y, int nv, int nch, int M,
+                                                             int stride, double* __restrict__ res_part)
+{
+    residual_noise_rows(y, nv, nch, M, stride, blockIdx.x, res_part + 2 * blockIdx.x + 1);
+}
+
+__global__ void residual_strided_combine_kernel(const double* __restrict__ res_part, int nchosen, long nrays,
+                                                double* __restrict__ out)
+{
+    if (threadIdx.x == 0) residual_strided_combine(res_part, nchosen, nrays, out);
+}
+
+// Batched forms: block i -> slice i (subset s, rank j); block (b, i) -> row range b of slice i.
+__global__ __launch_bounds__(256) void residual_subset_batch_kernel(const SliceDesc* __restrict__ slices, int s, int j)
+{
+    const SliceDesc* __restrict__ D = slices + blockIdx.x;
+    const int nrays = D->subs[s].y * D->geo.nch;
+    residual_subset_sum(D->part, (nrays + SQ_GROUP - 1) / SQ_GROUP, D->res_part + 2 * j);
+}
+
+__global__ __launch_bounds__(256) void residual_noise_batch_kernel(const SliceDesc* __restrict__ slices,
+                                                                   const float* const* __restrict__ counts, int M,
+                                                                   int stride)
+{
+    const SliceDesc* __restrict__ D = slices + blockIdx.y;
+    residual_noise_rows(counts[blockIdx.y], D->geo.nv, D->geo.nch, M, stride, blockIdx.x,
+                        D->res_part + 2 * blockIdx.x + 1);
+}
+
+__global__ void residual_strided_combine_batch_kernel(const SliceDesc* __restrict__ slices, int n_slices, int M,
+                                                      int stride, double* __restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_slices) return;
+    const SliceDesc* __restrict__ D = slices + i;
+    long nrays = 0;
+    int nchosen = 0;
+    for (int s = 0; s < M; s += stride, ++nchosen) nrays += (long)D->subs[s].y * D->geo.nch;
+    residual_strided_combine(D->res_part, nchosen, nrays, out + 2 * i);
+}
+
 // Measurement probe of the read bandwidth the caches deliver to gather kernels:
 // every block reads the whole buffer (n16 16-byte words, a power of two) once,
 // from a block-dependent start, four independent loads in flight per thread;
@@ -675,6 +774,34 @@ hipError_t launch_residual_final(const double* part, int ngroups, const float* c
 {
     residual_range_kernel<<<RES_BLOCKS, 256, 0, s>>>(part, ngroups, counts, nrays, res_part);
     residual_combine_kernel<<<1, 64, 0, s>>>(res_part, nrays, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_subset(const double* part, int ngroups, double* res_part, int j, hipStream_t s)
+{
+    residual_subset_kernel<<<1, 256, 0, s>>>(part, ngroups, res_part + 2 * j);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_strided_final(const float* counts, int nv, int nch, int M, int stride, int nchosen,
+                                         long nrays, double* res_part, double* out, hipStream_t s)
+{
+    residual_noise_kernel<<<RES_BLOCKS, 256, 0, s>>>(counts, nv, nch, M, stride, res_part);
+    residual_strided_combine_kernel<<<1, 64, 0, s>>>(res_part, nchosen, nrays, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_subset_batch(const SliceDesc* slices, int n_slices, int sub, int j, hipStream_t s)
+{
+    residual_subset_batch_kernel<<<n_slices, 256, 0, s>>>(slices, sub, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_strided_final_batch(const SliceDesc* slices, const float* const* counts, int n_slices,
+                                               int M, int stride, double* out, hipStream_t s)
+{
+    residual_noise_batch_kernel<<<dim3(RES_BLOCKS, n_slices), 256, 0, s>>>(slices, counts, M, stride);
+    residual_strided_combine_batch_kernel<<<cdiv(n_slices, 64), 64, 0, s>>>(slices, n_slices, M, stride, out);
     return hipGetLastError();
 }
 

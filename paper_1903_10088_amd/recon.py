@@ -101,9 +101,9 @@ def lib():
         L.recon_batch_tune.argtypes = [vp, PP, P(f), PP, i32, P(i32), P(i32), vp]
         L.recon_batch_set_launch.argtypes = [vp, i32, i32]
         L.recon_batch.argtypes = [P(Geometry_c), i32, i32, d, P(Params_c), PP, P(f), PP, i32, vp]
-        L.recon_data_residual.argtypes = [vp, vp, f, vp, vp, vp]
-        L.recon_warm_start.argtypes = [vp, vp, PP, P(f), PP, i32, i32, i32, d, P(d), P(d), P(i32), vp]
-        L.recon_warm_start_noalloc.argtypes = [vp, vp, PP, P(f), PP, i32, i32, i32, d, P(d), P(d), P(i32), vp]
+        L.recon_data_residual.argtypes = [vp, vp, f, vp, i32, vp, vp]
+        L.recon_warm_start.argtypes = [vp, vp, PP, P(f), PP, i32, i32, i32, d, i32, P(d), P(d), P(i32), vp]
+        L.recon_warm_start_noalloc.argtypes = [vp, vp, PP, P(f), PP, i32, i32, i32, d, i32, P(d), P(d), P(i32), vp]
         L.recon_cnn_param_count.argtypes = []
         L.recon_cnn_param_count.restype = i64
         L.recon_cnn_create.argtypes = [P(f), i32, i32, f, P(vp)]
@@ -251,13 +251,14 @@ class Recon:
                "recon_count_pairs")
         return int(out.value)
 
-    def data_residual(self, counts, i0: float, img):
-        """(mean (l - p)^2 over all rays, mean 1 / max(y, 1)) as a float64 CUDA tensor [2]."""
+    def data_residual(self, counts, i0: float, img, subset_stride: int = 1):
+        """(mean (l - p)^2, mean 1 / max(y, 1)) over the rays of every subset_stride-th subset (1: all
+        rays) as a float64 CUDA tensor [2]."""
         torch = _torch()
         g = self.geometry
         out = torch.empty(2, dtype=torch.float64, device=img.device)
         _check(lib().recon_data_residual(self._h, _ptr(counts, torch.float32, (g.n_views, g.n_channels), "counts"),
-                                         float(i0), _ptr(img, torch.float32, (g.n, g.n), "img"),
+                                         float(i0), _ptr(img, torch.float32, (g.n, g.n), "img"), int(subset_stride),
                                          _ptr(out, torch.float64, (2,), "out"), _stream()), "recon_data_residual")
         return out
 
@@ -470,7 +471,7 @@ class Batch:
         _check(lib().recon_batch_set_launch(self._h, fp_segments, bp_variant), "recon_batch_set_launch")
 
     def warm_start(self, net, counts, i0s, imgs=None, n_pre: int = 10, n_refine: int = 40, n_cold: int = 500,
-                   residual_ratio: float = 1.0, noalloc: bool = False):
+                   residual_ratio: float = 1.0, noalloc: bool = False, check_stride: int = 1):
         """recon_warm_start (noalloc: recon_warm_start_noalloc, the entry point that allocates no device
         memory): returns (imgs, residual, floor, fallback) with numpy per-slice arrays."""
         torch = _torch()
@@ -483,7 +484,7 @@ class Batch:
         name = "recon_warm_start_noalloc" if noalloc else "recon_warm_start"
         _check(getattr(lib(), name)(self._h, net._h, _ptr_array(counts, torch.float32, self._count_shapes(), "counts"),
                                     i0, _ptr_array(imgs, torch.float32, self._img_shapes(), "img"), int(n_pre),
-                                    int(n_refine), int(n_cold), float(residual_ratio),
+                                    int(n_refine), int(n_cold), float(residual_ratio), int(check_stride),
                                     res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                     flo.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                     fb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _stream()), name)

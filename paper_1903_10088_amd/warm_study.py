@@ -82,7 +82,7 @@ def cmd_train(args):
     # calibration slices drawn like the workload
     citems = ws.calibration_items(args.calibrate)
     calib = ws.calibrate_equal_rmse(citems, ws.make_counts(citems, workers=args.workers), net, args.n_pre,
-                                    args.n_refine, n_final=args.n_final, device=dev)
+                                    args.n_refine, n_final=args.n_final, device=dev, check_stride=args.check_stride)
     # held-out RMSE to the converged image: network alone, and after refinement
     out = torch.empty_like(xva)
     net.forward(xva, out, project=True)
@@ -91,7 +91,7 @@ def cmd_train(args):
     rec = dict(slices=len(items), held_out=n_hold, n_pre=args.n_pre, n_final=args.n_final, epochs=epochs,
                batch=args.batch, lr=args.lr, step_ms=step_s * 1e3, train_s=t_train, plain_pairs_s=t_plain,
                loss_identity_val=base_val, history=hist, n_refine=args.n_refine, n_cold=calib["n_cold"],
-               residual_ratio_limit=calib["limit"], calibration=calib,
+               residual_ratio_limit=calib["limit"], check_stride=args.check_stride, calibration=calib,
                val_rmse_over_muw=dict(input=float(np.mean(r_in)), network=float(np.mean(r_net))),
                weights=os.path.basename(wpath))
     json.dump(rec, open(os.path.join(args.out, "train.json"), "w"), indent=1)
@@ -110,12 +110,13 @@ def cmd_calibrate(args):
     net = recon.Cnn(None, max_batch=8, max_n=512, mu_scale=MU_W)
     net.load(args.weights or os.path.join(os.path.dirname(os.path.abspath(args.train_json)), rec["weights"]))
     calib = ws.calibrate_equal_rmse(items, counts, net, rec["n_pre"], args.n_refine, n_final=rec["n_final"],
-                                    device=dev)
+                                    device=dev, check_stride=args.check_stride)
     for k in ("residual_ratios", "residual_statistic"):
         rec.pop(k, None)
     rec["n_refine"] = args.n_refine
     rec["n_cold"] = calib["n_cold"]
     rec["residual_ratio_limit"] = calib["limit"]
+    rec["check_stride"] = args.check_stride
     rec["calibration"] = calib
     os.makedirs(args.out, exist_ok=True)
     json.dump(rec, open(os.path.join(args.out, "train.json"), "w"), indent=1)
@@ -134,6 +135,7 @@ def cmd_eval(args):
     if args.n_refine is None:
         args.n_refine = rec.get("n_refine", 5)
     n_cold = rec.get("n_cold", args.n_final)
+    stride = rec.get("check_stride", 1)
     # converged images and the plain method's RMSE curve
     iters = sorted(set(args.curve + [args.n_final]))
     runs = ws.plain_runs(items, counts, iters, chunk=args.chunk, device=dev)
@@ -144,7 +146,7 @@ def cmd_eval(args):
     net = recon.Cnn(None, max_batch=8, max_n=512, mu_scale=MU_W)
     net.load(args.weights)
     res = dict(slices=len(items), n_pre=args.n_pre, n_refine=args.n_refine, n_cold=n_cold, residual_ratio_limit=lim,
-               plain_curve=curve, batches=[])
+               check_stride=stride, plain_curve=curve, batches=[])
     warm_imgs = torch.empty_like(conv)
     lat, fb_all, r_all = [], [], []
     t_total = 0.0
@@ -154,11 +156,12 @@ def cmd_eval(args):
         cts = [torch.from_numpy(c).to(dev) for c in counts[c0:c0 + args.chunk]]
         i0s = [i0 for _, _, i0 in sub]
         imgs = [warm_imgs[c0 + i] for i in range(len(sub))]
-        B.warm_start(net, cts, i0s, imgs, args.n_pre, args.n_refine, n_cold, lim)  # warm-up
+        B.warm_start(net, cts, i0s, imgs, args.n_pre, args.n_refine, n_cold, lim, check_stride=stride)  # warm-up
         # the batch up to its data-consistency check (no slice falls back), then the pipeline
-        _, dt_check = ws.timed(lambda: B.warm_start(net, cts, i0s, imgs, args.n_pre, args.n_refine, n_cold, 1e30))
+        _, dt_check = ws.timed(lambda: B.warm_start(net, cts, i0s, imgs, args.n_pre, args.n_refine, n_cold, 1e30,
+                                                    check_stride=stride))
         (_, rr, fl, fb), dt = ws.timed(lambda: B.warm_start(net, cts, i0s, imgs, args.n_pre, args.n_refine,
-                                                            n_cold, lim))
+                                                            n_cold, lim, check_stride=stride))
         t_total += dt
         lat += [dt if f else min(dt, dt_check) for f in fb]
         fb_all += list(map(int, fb))
@@ -234,6 +237,7 @@ def main():
     t.add_argument("--max-epochs", type=int, default=60)
     t.add_argument("--calibrate", type=int, default=128)
     t.add_argument("--n-refine", type=int, default=5, help="refining sub-iterations the limit is calibrated for")
+    t.add_argument("--check-stride", type=int, default=4, help="the check uses every k-th subset's rays")
     t.add_argument("--chunk", type=int, default=64)
     t.add_argument("--workers", type=int, default=12)
     t.add_argument("--seed", type=int, default=0)
@@ -242,6 +246,7 @@ def main():
     c.add_argument("--train-json", required=True)
     c.add_argument("--calibrate", type=int, default=128)
     c.add_argument("--n-refine", type=int, default=5)
+    c.add_argument("--check-stride", type=int, default=4, help="the check uses every k-th subset's rays")
     c.add_argument("--weights", default=None, help="default: the record's weights file beside it")
     c.add_argument("--workers", type=int, default=12)
     e = sp.add_parser("eval")

@@ -181,12 +181,13 @@ def evaluate_loss(net, inputs, targets, batch: int = 8):
 EQUAL_RMSE_GRID = list(range(10, 200, 5)) + [200, 250, 300, 400, 500]
 
 
-def residual_ratios(items, counts, imgs, subsets: int = 20, beta: float = 1e-3):
-    """Full-data residual over its noise level (recon_data_residual) of each slice's image."""
+def residual_ratios(items, counts, imgs, subsets: int = 20, beta: float = 1e-3, check_stride: int = 1):
+    """Residual over its noise level (recon_data_residual) of each slice's image, over the rays of
+    every check_stride-th subset."""
     out = []
     for (g, _, i0), c, img in zip(items, counts, imgs):
         R = recon.Recon(g, subsets, beta)
-        r = R.data_residual(c, i0, img.contiguous()).cpu().numpy()
+        r = R.data_residual(c, i0, img.contiguous(), check_stride).cpu().numpy()
         out.append(r[0] / r[1])
         R.close()
     return np.asarray(out)
@@ -198,10 +199,11 @@ def equal_rmse_count(curve: dict, rmse: float, n_final: int = 500) -> int:
 
 
 def calibrate_equal_rmse(items, counts, net, n_pre: int, n_refine: int, n_final: int = 500, subsets: int = 20,
-                         beta: float = 1e-3, margin: float = 0.02, grid=None, device="cuda"):
+                         beta: float = 1e-3, margin: float = 0.02, grid=None, device="cuda", check_stride: int = 1):
     """Fallback limit for the pipeline (n_pre, network, n_refine): the plain method's largest
-    residual ratio at the sub-iteration count where its mean RMSE to the converged image first
-    reaches the pipeline's (no fallback while measuring), times (1 + margin).  Returns a record."""
+    residual ratio (over the rays of every check_stride-th subset, as the pipeline's check takes
+    it) at the sub-iteration count where its mean RMSE to the converged image first reaches the
+    pipeline's (no fallback while measuring), times (1 + margin).  Returns a record."""
     torch = _torch()
     grid = sorted(set((grid or EQUAL_RMSE_GRID) + [n_final]))
     cts = [torch.from_numpy(c).to(device) for c in counts]
@@ -212,13 +214,14 @@ def calibrate_equal_rmse(items, counts, net, n_pre: int, n_refine: int, n_final:
     curve = {k: float(np.mean(disc_rmse(runs[k], conv, n))) / ph.MU_WATER_PER_MM for k in grid}
     B = recon.Batch([g for g, _, _ in items], subsets, beta)
     imgs = [torch.empty((n, n), dtype=torch.float32, device=device) for _ in items]
-    _, rr, fl, _ = B.warm_start(net, cts, i0s, imgs, n_pre, n_refine, n_final, 1e30)
+    _, rr, fl, _ = B.warm_start(net, cts, i0s, imgs, n_pre, n_refine, n_final, 1e30, check_stride=check_stride)
     B.close()
     warm_rmse = float(np.mean(disc_rmse(torch.stack(imgs), conv, n))) / ph.MU_WATER_PER_MM
     n_eq = equal_rmse_count(curve, warm_rmse, n_final)
-    plain_r = residual_ratios(items, cts, [runs[n_eq][i] for i in range(len(items))], subsets, beta)
+    plain_r = residual_ratios(items, cts, [runs[n_eq][i] for i in range(len(items))], subsets, beta, check_stride)
     warm_r = rr / fl
     return dict(limit=float(plain_r.max() * (1 + margin)), n_pre=n_pre, n_refine=n_refine, n_cold=n_final,
+                check_stride=check_stride,
                 warm_rmse_over_muw=warm_rmse, plain_sub_iterations_at_equal_rmse=n_eq,
                 plain_ratio=dict(min=float(plain_r.min()), median=float(np.median(plain_r)),
                                  max=float(plain_r.max())),

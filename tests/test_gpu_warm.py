@@ -48,6 +48,50 @@ def test_data_residual_matches_oracle(dev, k):
     assert abs(out[1] - floor) <= 1e-12 * floor
 
 
+@pytest.mark.parametrize("k,stride", [(0, 2), (1, 3), (2, 5), (0, 4)])
+def test_strided_residual_matches_oracle(dev, k, stride):
+    """Residual over the views of every stride-th subset (subset s holds the views v with
+    v mod M = s), against the oracle's projection of those views alone."""
+    from paper_1903_10088_amd import recon
+    geoms, slices = small_batch()
+    g, sl, M = geoms[k], slices[k], 5
+    R = recon.Recon(g, M, 1e-3)
+    counts = torch.from_numpy(sl.counts).to(dev)
+    img, _ = R.os_iterate(counts, sl.i0, None, 7)
+    out = R.data_residual(counts, sl.i0, img, stride).cpu().numpy()
+    views = np.concatenate([oracle.subset_views(g.n_views, M, s) for s in range(0, M, stride)])
+    ell = oracle.project(g, img.cpu().numpy().astype(np.float64), views)
+    y = np.maximum(sl.counts[views].astype(np.float64), 1.0)
+    ref = np.mean((ell - np.log(sl.i0 / y)) ** 2)
+    floor = np.mean(1.0 / y)
+    print(f"slice {k} stride {stride}: {len(views)} views, residual {out[0]:.6e} (oracle {ref:.6e}), "
+          f"floor {out[1]:.6e}", flush=True)
+    assert abs(out[0] - ref) <= 1e-5 * ref
+    assert abs(out[1] - floor) <= 1e-12 * floor
+
+
+def test_strided_residual_limits(dev):
+    """Strides outside [1, M], or choosing more than 64 subsets, are refused; stride 1 has no
+    subset limit."""
+    from paper_1903_10088_amd import recon
+    g = ph.Geometry(n=32, pixel_mm=12.5, n_views=130, n_channels=49)
+    sl = ph.make_slice(g, 3, 1e4, supersample=1)
+    counts = torch.from_numpy(sl.counts).to(dev)
+    R = recon.Recon(g, 65, 1e-3)
+    img = R.initial_image(dev)
+    for bad in (0, 66):
+        with pytest.raises(recon.ReconError) as ei:
+            R.data_residual(counts, sl.i0, img, bad)
+        assert ei.value.status == recon.RECON_INVALID_ARG
+    R.data_residual(counts, sl.i0, img, 2)
+    R.data_residual(counts, sl.i0, img, 1)
+    R130 = recon.Recon(g, 130, 1e-3)
+    with pytest.raises(recon.ReconError) as ei:
+        R130.data_residual(counts, sl.i0, img, 2)
+    assert ei.value.status == recon.RECON_INVALID_ARG
+    R130.data_residual(counts, sl.i0, img, 3)
+
+
 def test_pipeline_equals_its_steps(dev):
     """Identity network: pipeline = n_pre plain sub-iterations, then n_refine from that image with a
     fresh state; no fallback when the limit is generous."""
@@ -69,6 +113,16 @@ def test_pipeline_equals_its_steps(dev):
         R = recon.Recon(g, M, beta)
         r = R.data_residual(counts[k], sl.i0, imgs[k]).cpu().numpy()
         assert r[0] == res[k] and r[1] == flo[k]
+    # the check over every second subset: same images, residuals of the single-slice call, bit for bit
+    imgs2, res2, flo2, fb2 = B.warm_start(net, counts, i0s, None, n_pre, n_ref, 20, 1e6, check_stride=2)
+    assert not fb2.any()
+    for k, (g, sl) in enumerate(zip(geoms, slices)):
+        assert torch.equal(imgs2[k], imgs[k])
+        R = recon.Recon(g, M, beta)
+        r = R.data_residual(counts[k], sl.i0, imgs2[k], 2).cpu().numpy()
+        assert r[0] == res2[k] and r[1] == flo2[k]
+    with pytest.raises(recon.ReconError):
+        B.warm_start(net, counts, i0s, None, n_pre, n_ref, 20, 1e6, check_stride=M + 1)
 
 
 def test_pipeline_falls_back_to_a_cold_start(dev):

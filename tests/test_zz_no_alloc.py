@@ -37,7 +37,7 @@ def case(kind):
     return geoms, slices
 
 
-def compare(dev, kind, net):
+def compare(dev, kind, net, stride=1):
     from paper_1903_10088_amd import recon
     geoms, slices = case(kind)
     M, beta, n_pre, n_ref, n_cold = 4, 1e-3, 6, 5, 9
@@ -45,20 +45,21 @@ def compare(dev, kind, net):
     i0s = [s.i0 for s in slices]
     # the residual limit at the median ratio, so some slices fall back and some do not
     probe = recon.Batch(geoms, M, beta)
-    _, res, flo, _ = probe.warm_start(net, counts, i0s, None, n_pre, n_ref, n_cold, 1e6)
+    _, res, flo, _ = probe.warm_start(net, counts, i0s, None, n_pre, n_ref, n_cold, 1e6, check_stride=stride)
     r = np.sort(res / flo)
     k = len(geoms) // 2
     limit = float(0.5 * (r[k - 1] + r[k]))
     ref_b = recon.Batch(geoms, M, beta)
-    ref = ref_b.warm_start(net, counts, i0s, None, n_pre, n_ref, n_cold, limit)
+    ref = ref_b.warm_start(net, counts, i0s, None, n_pre, n_ref, n_cold, limit, check_stride=stride)
     torch.cuda.synchronize()
     ref_imgs = [r.clone() for r in ref[0]]
     # a fresh batch (no epoch graphs yet: every sub-iteration launched directly) and the reference
     # batch again (its graphs replayed)
     for label, B in (("fresh batch", recon.Batch(geoms, M, beta)), ("same batch", ref_b)):
-        out = B.warm_start(net, counts, i0s, None, n_pre, n_ref, n_cold, limit, noalloc=True)
+        out = B.warm_start(net, counts, i0s, None, n_pre, n_ref, n_cold, limit, noalloc=True, check_stride=stride)
         torch.cuda.synchronize()
-        print(f"{kind}, {label}: {len(geoms)} slices, fallbacks {out[3].tolist()}", flush=True)
+        print(f"{kind}, {label}, check stride {stride}: {len(geoms)} slices, fallbacks {out[3].tolist()}",
+              flush=True)
         assert 0 < out[3].sum() < len(geoms)
         for k in range(len(geoms)):
             assert torch.equal(out[0][k], ref_imgs[k]), (kind, label, k)
@@ -73,7 +74,7 @@ def test_noalloc_warm_start_equals_warm_start(dev):
     compare(dev, "chunked", big)
     small = recon.Cnn(theta, max_batch=2, max_n=128, mu_scale=ph.MU_WATER_PER_MM)
     compare(dev, "mixed", small)
-    compare(dev, "smaller", small)
+    compare(dev, "smaller", small, stride=2)
 
 
 def test_noalloc_rejects_images_beyond_the_scratch(dev):
