@@ -535,9 +535,12 @@ def cnn_leg(batch: int, dev):
     ms = net.time_kernels(mu, tgt, reps=20)
     torch.cuda.synchronize()
     flops = 2.0 * 9 * 32 * 32 * batch * n * n           # one 32 -> 32 layer
-    hbm = 2.0 * batch * n * n * 32 * 2                     # bf16 activations in and out
+    act = float(batch * n * n * 32 * 2)                    # one bf16 activation tensor
+    # compulsory tensors: forward reads a_{l-1}, writes a_l; dgrad reads the incoming gradient and
+    # the activation its ReLU mask comes from, writes the outgoing gradient; wgrad reads a_{l-1}
+    # and the gradient (its 18 KB of weights written are negligible)
     out = {"batch": batch, "n": n}
-    for name, t in zip(("conv32_forward", "conv32_dgrad", "wgrad32"), ms[:3]):
+    for name, t, hbm in zip(("conv32_forward", "conv32_dgrad", "wgrad32"), ms[:3], (2 * act, 3 * act, 2 * act)):
         out[name] = {"us": t * 1e3, "tflops": flops / (t * 1e-3) / 1e12,
                      "frac_of_bf16_peak": flops / (t * 1e-3) / 1e12 / PEAK_BF16_TFLOPS,
                      "gbps_compulsory": hbm / (t * 1e-3) / 1e9,
