@@ -43,6 +43,8 @@ using namespace recon;
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
@@ -81,6 +83,24 @@ __device__ __forceinline__ float bf_lo(uint32_t w) { return __uint_as_float(w <<
 __device__ __forceinline__ float bf_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
 __device__ __forceinline__ bf16x8 as_bf8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+__device__ __forceinline__ bf16x2 as_bf2(uint32_t v) { return __builtin_bit_cast(bf16x2, v); }
+// a.lo * b.lo + a.hi * b.hi + c on bf16 pairs (one dot-product instruction)
+__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c)
+{
+    return __builtin_amdgcn_fdot2_f32_bf16(as_bf2(a), as_bf2(b), c, false);
+}
+// two floats -> packed bf16 pair (lo, hi), rounded to nearest even by the conversion instruction
+__device__ __forceinline__ uint32_t pack_bf2(float lo, float hi)
+{
+    const bf16x2 v = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(uint32_t, v);
+}
+// max(x, 0) of both halves of a bf16 pair: a bf16 is negative exactly when it is negative as an
+// int16, so one packed integer max does it (negative values and -0 become +0)
+__device__ __forceinline__ uint32_t relu_bf2(uint32_t v)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, v), s16x2{0, 0}));
+}
 
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
 {
@@ -114,34 +134,67 @@ __device__ __forceinline__ Tile tile_plain(int t, int tiles_x, int tiles_per_img
 __device__ __forceinline__ size_t pix(int b, int i, int j, int n) { return ((size_t)b * n + i) * n + j; }
 
 // Stages the (T+2)^2 halo tile of a channels-last bf16 tensor into LDS (zeros
-// outside the image); called by all 256 threads of a block.  Every load of a
-// thread is issued before its first LDS store, so their latencies overlap
-// (pixels outside the image load the tensor's first element and store zero).
-__device__ __forceinline__ void load_halo(uint16_t (*s)[HALO][LDS_PIX], const uint16_t* __restrict__ act, Tile t,
-                                          int n)
-{
-    constexpr int NCH = HALO * HALO * 4;       // 16-byte chunks of the halo tile
-    constexpr int PER = (NCH + 255) / 256;     // chunks per thread
+// outside the image); called by all NT threads of a block.  halo_issue starts
+// a thread's loads (pixels outside the image load the tensor's first element
+// and keep a cleared bit in `in`), halo_store waits for them and writes LDS,
+// so a caller can keep the loads in flight while it works on another tile.
+constexpr int HALO_CHUNKS = HALO * HALO * 4;  // 16-byte chunks of the halo tile
+template <int NT>
+struct HaloRegs {
+    static constexpr int PER = (HALO_CHUNKS + NT - 1) / NT;  // chunks per thread
     u32x4 v[PER];
-    bool in[PER];
+    uint32_t in;  // bit k: chunk k lies in the image
+};
+template <int NT>
+__device__ __forceinline__ void halo_issue(HaloRegs<NT>& h, const uint16_t* __restrict__ act, Tile t, int n)
+{
+    // the chunk coordinates are recomputed on every call (an empty asm hides that the thread
+    // index is loop-invariant): kept live across a persistent kernel's tile loop they would
+    // take a dozen registers
+    int tid = (int)threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    h.in = 0u;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int e = (int)threadIdx.x + 256 * k;
+    for (int k = 0; k < HaloRegs<NT>::PER; ++k) {
+        const int e = tid + NT * k;
         const int p = e >> 2, q = e & 3;
         const int ly = p / HALO, lx = p - ly * HALO;
         const int gi = t.i0 + ly - 1, gj = t.j0 + lx - 1;
-        in[k] = e < NCH && gi >= 0 && gi < n && gj >= 0 && gj < n;
-        const size_t off = in[k] ? pix(t.b, gi, gj, n) * C + q * 8 : 0;
-        v[k] = *(const u32x4*)(act + off);
+        const bool in = e < HALO_CHUNKS && gi >= 0 && gi < n && gj >= 0 && gj < n;
+        h.in |= in ? 1u << k : 0u;
+        const size_t off = in ? pix(t.b, gi, gj, n) * C + q * 8 : 0;
+        h.v[k] = *(const u32x4*)(act + off);
     }
+}
+template <int NT>
+__device__ __forceinline__ void halo_store(uint16_t (*s)[HALO][LDS_PIX], const HaloRegs<NT>& h)
+{
+    // chunk e = threadIdx.x + NT k is 16-byte part e mod 4 of staged pixel e / 4 (row-major)
+    uint16_t* base = &s[0][0][0] + (threadIdx.x >> 2) * LDS_PIX + (threadIdx.x & 3) * 8;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int e = (int)threadIdx.x + 256 * k;
-        if (e < NCH) {
-            const int p = e >> 2, q = e & 3;
-            const int ly = p / HALO, lx = p - ly * HALO;
-            *(u32x4*)(&s[ly][lx][q * 8]) = in[k] ? v[k] : u32x4{0u, 0u, 0u, 0u};
-        }
+    for (int k = 0; k < HaloRegs<NT>::PER; ++k) {
+        if ((int)threadIdx.x + NT * k < HALO_CHUNKS)
+            *(u32x4*)(base + (NT / 4) * k * LDS_PIX) = (h.in >> k) & 1u ? h.v[k] : u32x4{0u, 0u, 0u, 0u};
+    }
+}
+
+// Writes the 64-byte channel rows of the block's 256 consecutive pixels (pixel
+// first + threadIdx.x holds words w) so that every store instruction of a wave
+// covers 1 KB of contiguous memory: the rows pass through LDS (80-byte stride,
+// no bank conflicts) and wave v then writes 16-byte words v*256 + q*64 + lane.
+// Called by all 256 threads; pixels at or beyond `total` are not written.
+constexpr int ROW_STAGE_WORDS = 256 * 5;
+__device__ __forceinline__ void store_pixel_rows(u32x4* __restrict__ stage, const u32x4 (&w)[4],
+                                                 uint16_t* __restrict__ dst, long first, long total)
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) stage[threadIdx.x * 5 + q] = w[q];
+    __syncthreads();
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int word = wv * 256 + q * 64 + l;
+        if (first + (word >> 2) < total) ((u32x4*)dst)[first * 4 + word] = stage[(word >> 2) * 5 + (word & 3)];
     }
 }
 
@@ -150,25 +203,35 @@ __device__ __forceinline__ void load_halo(uint16_t (*s)[HALO][LDS_PIX], const ui
 // ----------------------------------------------------------------------------
 
 // wf[l][tap][o][c] = bf(W[o][c][tap]); wt[l][tap][c][o] = bf(W[o][c][8 - tap])
-// (the dgrad convolution); w1r[o][tap], w8r[c][tap] = bf(W) as float.
+// (the dgrad convolution); w8r[c][tap] = bf(W8) as float;
+// w1p[o][k] = bf16 pair (W1[o][2k], W1[o][2k+1]) (k = 4: (W1[o][8], 0));
+// w8p[tap][k] = bf16 pair (W8[2k][tap], W8[2k+1][tap]).
+constexpr int PREP_W8R = NHID * W32, PREP_W1P = PREP_W8R + 288, PREP_W8P = PREP_W1P + C * 5,
+              PREP_END = PREP_W8P + 9 * (C / 2);
 __global__ __launch_bounds__(256) void prep_weights_kernel(const float* __restrict__ th, uint16_t* __restrict__ wf,
-                                                           uint16_t* __restrict__ wt, float* __restrict__ w1r,
-                                                           float* __restrict__ w8r)
+                                                           uint16_t* __restrict__ wt, float* __restrict__ w8r,
+                                                           uint32_t* __restrict__ w1p, uint32_t* __restrict__ w8p)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < NHID * W32) {
+    if (k < PREP_W8R) {
         const int l = k / W32, r = k - l * W32;
         const int tap = r / (C * C), oc = r - tap * C * C;
         const int a = oc / C, bq = oc - a * C;  // wf: a = o, bq = c; wt: a = c, bq = o
         const float* W = th + OFF_HID + l * P32;
         wf[k] = (uint16_t)f2bf(W[(a * C + bq) * 9 + tap]);
         wt[k] = (uint16_t)f2bf(W[(bq * C + a) * 9 + (8 - tap)]);
-    } else if (k < NHID * W32 + 288) {
-        const int r = k - NHID * W32;  // o * 9 + tap
-        w1r[r] = bfround(th[OFF_W1 + r]);
-    } else if (k < NHID * W32 + 576) {
-        const int r = k - NHID * W32 - 288;  // c * 9 + tap
+    } else if (k < PREP_W1P) {
+        const int r = k - PREP_W8R;  // c * 9 + tap
         w8r[r] = bfround(th[OFF_W8 + r]);
+    } else if (k < PREP_W8P) {
+        const int r = k - PREP_W1P;  // o * 5 + pair
+        const int o = r / 5, q = r - o * 5;
+        const float* w = th + OFF_W1 + o * 9;
+        w1p[r] = f2bf(w[2 * q]) | (q < 4 ? f2bf(w[2 * q + 1]) << 16 : 0u);
+    } else if (k < PREP_END) {
+        const int r = k - PREP_W8P;  // tap * 16 + pair
+        const int tap = r / (C / 2), q = r - tap * (C / 2);
+        w8p[r] = f2bf(th[OFF_W8 + 2 * q * 9 + tap]) | (f2bf(th[OFF_W8 + (2 * q + 1) * 9 + tap]) << 16);
     }
 }
 
@@ -176,60 +239,64 @@ __global__ __launch_bounds__(256) void prep_weights_kernel(const float* __restri
 // Forward
 // ----------------------------------------------------------------------------
 
-// Layer 1 (1 -> 32): a0 = bf(mu / scale), a1 = bf(relu(b1 + sum_tap w1 a0)).
+// Layer 1 (1 -> 32): a0 = bf(mu / scale), a1 = bf(relu(b1 + sum_tap w1 a0)),
+// the nine taps summed as the bf16 pairs (0,1), (2,3), (4,5), (6,7), (8) with
+// one dot-product instruction each (products exact in FP32).  w1p: packed
+// pairs from prep_weights_kernel.
 __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ mu, float inv_scale,
-                                                      const float* __restrict__ w1r, const float* __restrict__ b1,
+                                                      const uint32_t* __restrict__ w1p, const float* __restrict__ b1,
                                                       uint16_t* __restrict__ a0, uint16_t* __restrict__ a1, int n,
                                                       long total)
 {
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= total) return;
-    const int j = (int)(idx % n);
-    const long bi = idx / n;
-    const int i = (int)(bi % n);
-    const int b = (int)(bi / n);
-    float xn[9];
+    __shared__ u32x4 stage[ROW_STAGE_WORDS];
+    const long first = (long)blockIdx.x * blockDim.x;
+    const long idx = first + threadIdx.x;
+    u32x4 rows[4] = {};
+    if (idx < total) {
+        const int j = (int)(idx % n);
+        const long bi = idx / n;
+        const int i = (int)(bi % n);
+        const int b = (int)(bi / n);
+        uint32_t xb[10];
 #pragma unroll
-    for (int ky = 0; ky < 3; ++ky)
+        for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
-        for (int kx = 0; kx < 3; ++kx) {
-            const int gi = i + ky - 1, gj = j + kx - 1;
-            xn[ky * 3 + kx] =
-                (gi >= 0 && gi < n && gj >= 0 && gj < n) ? bfround(mu[pix(b, gi, gj, n)] * inv_scale) : 0.0f;
+            for (int kx = 0; kx < 3; ++kx) {
+                const int gi = i + ky - 1, gj = j + kx - 1;
+                xb[ky * 3 + kx] =
+                    (gi >= 0 && gi < n && gj >= 0 && gj < n) ? f2bf(mu[pix(b, gi, gj, n)] * inv_scale) : 0u;
+            }
+        xb[9] = 0u;
+        a0[idx] = (uint16_t)xb[4];  // the centre tap is this pixel
+        uint32_t xp[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) xp[q] = xb[2 * q] | (xb[2 * q + 1] << 16);
+        uint32_t pk[16];
+#pragma unroll
+        for (int o = 0; o < C; o += 2) {
+            float z0 = b1[o], z1 = b1[o + 1];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                z0 = dot2(w1p[o * 5 + q], xp[q], z0);
+                z1 = dot2(w1p[(o + 1) * 5 + q], xp[q], z1);
+            }
+            pk[o >> 1] = relu_bf2(pack_bf2(z0, z1));
         }
-    a0[idx] = (uint16_t)f2bf(mu[idx] * inv_scale);
-    uint32_t pk[16];
 #pragma unroll
-    for (int o = 0; o < C; o += 2) {
-        float z0 = b1[o], z1 = b1[o + 1];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            z0 = fmaf(w1r[o * 9 + t], xn[t], z0);
-            z1 = fmaf(w1r[(o + 1) * 9 + t], xn[t], z1);
-        }
-        pk[o >> 1] = f2bf(fmaxf(z0, 0.0f)) | (f2bf(fmaxf(z1, 0.0f)) << 16);
+        for (int q = 0; q < 4; ++q) rows[q] = u32x4{pk[4 * q], pk[4 * q + 1], pk[4 * q + 2], pk[4 * q + 3]};
     }
-    u32x4* dst = (u32x4*)(a1 + (size_t)idx * C);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) dst[q] = u32x4{pk[4 * q], pk[4 * q + 1], pk[4 * q + 2], pk[4 * q + 3]};
+    store_pixel_rows(stage, rows, a1, first, total);
 }
 
-// One 16x16 output tile of the 32 -> 32 convolution (stages its halo, then the
-// MFMAs).  Wave w computes output channels hh*16 .. hh*16+15 (hh = w mod 2) of
-// the 8 output rows r0 .. r0+7 (r0 = 8 (w / 2)), reading staged rows r0 ..
-// r0+9; each staged fragment feeds up to 3 output rows.  Every output sums its
-// taps in the order (ky, kx) = (0,0), (0,1), ..., (2,2).
-template <int MODE>
-__device__ __forceinline__ void conv32_tile(uint16_t (*s)[HALO][LDS_PIX], const bf16x8 (&A)[9],
-                                            const uint16_t* __restrict__ in, const float* __restrict__ bias,
-                                            const uint16_t* __restrict__ mask, uint16_t* __restrict__ out, int n,
-                                            Tile tl, int wave, int m, int g)
+// Matrix products of one 16x16 output tile of the 32 -> 32 convolution from its
+// halo staged in LDS.  Wave w computes output channels hh*16 .. hh*16+15 (hh =
+// w mod 2) of the 8 output rows r0 .. r0+7 (r0 = 8 (w / 2)), reading staged rows
+// r0 .. r0+9; each staged fragment feeds up to 3 output rows.  Every output sums
+// its taps in the order (ky, kx) = (0,0), (0,1), ..., (2,2).
+__device__ __forceinline__ void conv32_mma(const uint16_t (*s)[HALO][LDS_PIX], const bf16x8 (&A)[9],
+                                           f32x4 (&acc)[8], int wave, int m, int g)
 {
-    // (bias: the block's LDS copy, written before the first tile)
-    load_halo(s, in, tl, n);
-    __syncthreads();
-    const int hh = wave & 1, r0 = (wave >> 1) * 8;
-    f32x4 acc[8];
+    const int r0 = (wave >> 1) * 8;
 #pragma unroll
     for (int r = 0; r < 8; ++r) acc[r] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -244,39 +311,66 @@ __device__ __forceinline__ void conv32_tile(uint16_t (*s)[HALO][LDS_PIX], const 
                 if (ky >= 0 && ky < 3) acc[rr] = mfma(A[ky * 3 + kx], Bf, acc[rr]);
             }
         }
-    // D[4g + i][m]: output channels hh*16 + 4g + i of pixel column m
+}
+
+// The tile's outputs as bf16 into the LDS tile o (pixel (r, c) at (r T + c)
+// LDS_PIX): the forward adds the bias and applies the ReLU, dgrad stores the
+// unmasked sums (its mask is applied on the way out).  D[4g + i][m] of row rr
+// is output channel hh*16 + 4g + i of pixel column m.
+template <int MODE>
+__device__ __forceinline__ void conv32_stage(uint16_t* __restrict__ o, const f32x4 (&acc)[8],
+                                             const float* __restrict__ bias, int wave, int m, int g)
+{
+    const int hh = wave & 1, r0 = (wave >> 1) * 8;
     const int o0 = hh * 16 + g * 4;
-    // rows in two halves of 4; in dgrad the 4 mask loads of a half go first, so their latencies overlap
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        u32x2 mks[4];
-        if constexpr (MODE == 1) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int gi = tl.i0 + r0 + 4 * half + k, gj = tl.j0 + m;
-                const size_t base = (gi < n && gj < n) ? pix(tl.b, gi, gj, n) * C : 0;
-                mks[k] = *(const u32x2*)(mask + base + o0);
-            }
+    for (int rr = 0; rr < 8; ++rr) {
+        u32x2 w;
+        if constexpr (MODE == 0) {
+            w = u32x2{relu_bf2(pack_bf2(acc[rr][0] + bias[o0], acc[rr][1] + bias[o0 + 1])),
+                      relu_bf2(pack_bf2(acc[rr][2] + bias[o0 + 2], acc[rr][3] + bias[o0 + 3]))};
+        } else {
+            w = u32x2{pack_bf2(acc[rr][0], acc[rr][1]), pack_bf2(acc[rr][2], acc[rr][3])};
         }
+        *(u32x2*)(o + ((r0 + rr) * T + m) * LDS_PIX + o0) = w;
+    }
+}
+
+// Keeps each bf16 half of v where the same half of mk is positive (a bf16 is
+// positive exactly when it is positive as an int16), zero elsewhere.
+__device__ __forceinline__ uint32_t mask_bf2(uint32_t v, uint32_t mk)
+{
+    const uint32_t keep = ((int16_t)(mk & 0xffffu) > 0 ? 0x0000ffffu : 0u) | ((int16_t)(mk >> 16) > 0 ? 0xffff0000u : 0u);
+    return v & keep;
+}
+
+// Copies the staged tile to the output: wave w writes rows 4w .. 4w+3, one
+// contiguous 1 KB row (16 pixels x 64 bytes) per instruction; dgrad zeroes the
+// channels whose forward activation (mask) is not positive, reading the mask
+// the same way.
+template <int MODE>
+__device__ __forceinline__ void conv32_copy_out(const uint16_t* __restrict__ o, const uint16_t* __restrict__ mask,
+                                                uint16_t* __restrict__ out, int n, Tile tl, int wave, int lane)
+{
+    const int px = lane >> 2, c4 = lane & 3;
+    const int gj = tl.j0 + px;
+    u32x4 mk[4];
+    if constexpr (MODE == 1) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int rr = 4 * half + k;
-            const int gi = tl.i0 + r0 + rr, gj = tl.j0 + m;
-            if (gi >= n || gj >= n) continue;
-            const size_t base = pix(tl.b, gi, gj, n) * C;
-            float v[4];
-            if constexpr (MODE == 0) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[rr][i] + bias[o0 + i], 0.0f);
-            } else {
-                const u32x2 mk = mks[k];
-                v[0] = bf_lo(mk.x) > 0.0f ? acc[rr][0] : 0.0f;
-                v[1] = bf_hi(mk.x) > 0.0f ? acc[rr][1] : 0.0f;
-                v[2] = bf_lo(mk.y) > 0.0f ? acc[rr][2] : 0.0f;
-                v[3] = bf_hi(mk.y) > 0.0f ? acc[rr][3] : 0.0f;
-            }
-            *(u32x2*)(out + base + o0) = u32x2{f2bf(v[0]) | (f2bf(v[1]) << 16), f2bf(v[2]) | (f2bf(v[3]) << 16)};
+            const int gi = tl.i0 + wave * 4 + k;
+            const size_t off = (gi < n && gj < n) ? pix(tl.b, gi, gj, n) * C + c4 * 8 : 0;
+            mk[k] = *(const u32x4*)(mask + off);
         }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int r = wave * 4 + k, gi = tl.i0 + r;
+        if (gi >= n || gj >= n) continue;
+        u32x4 v = *(const u32x4*)(o + (r * T + px) * LDS_PIX + c4 * 8);
+        if constexpr (MODE == 1)
+            v = u32x4{mask_bf2(v.x, mk[k].x), mask_bf2(v.y, mk[k].y), mask_bf2(v.z, mk[k].z), mask_bf2(v.w, mk[k].w)};
+        *(u32x4*)(out + pix(tl.b, gi, gj, n) * C + c4 * 8) = v;
     }
 }
 
@@ -286,7 +380,10 @@ __device__ __forceinline__ void conv32_tile(uint16_t (*s)[HALO][LDS_PIX], const 
 // bfloat16.  Persistent: each wave loads the weights of its output-channel half
 // into registers once, then the block takes tiles blockIdx.x, blockIdx.x +
 // gridDim.x, ... of the XCD-aware order (gridDim.x a multiple of 8 or equal to
-// the tile count, so a block's tiles stay on its own XCD).
+// the tile count, so a block's tiles stay on its own XCD).  Per tile: the halo
+// goes from registers into LDS, the next tile's halo loads are issued (they stay
+// in flight through this tile's work), the matrix products read the halo, the
+// outputs are staged in the same LDS and written out row by row.
 template <int MODE>
 __device__ __forceinline__ void conv32_body(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wts,
                                             const float* __restrict__ bias, const uint16_t* __restrict__ mask,
@@ -295,17 +392,30 @@ __device__ __forceinline__ void conv32_body(const uint16_t* __restrict__ in, con
 {
     __shared__ __attribute__((aligned(16))) uint16_t s[HALO][HALO][LDS_PIX];
     __shared__ __attribute__((aligned(16))) float sbias[C];
+    static_assert(T * T <= HALO * HALO, "the output tile fits the halo buffer");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 15, g = lane >> 4;
     const int hh = wave & 1;
-    if (MODE == 0 && threadIdx.x < C) sbias[threadIdx.x] = bias[threadIdx.x];  // read after conv32_tile's barrier
+    if (MODE == 0 && threadIdx.x < C) sbias[threadIdx.x] = bias[threadIdx.x];  // read after the first barrier
     // A operands: lane (m, g) holds W_tap[hh*16 + m][8g .. 8g+7]
     bf16x8 A[9];
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) A[tap] = as_bf8(*(const u32x4*)(wts + ((tap * C) + hh * 16 + m) * C + g * 8));
+    HaloRegs<256> h;
+    if ((int)blockIdx.x < nblocks) halo_issue<256>(h, in, tile_of(blockIdx.x, nblocks, tiles_x, tiles_per_img), n);
     for (int v = blockIdx.x; v < nblocks; v += gridDim.x) {
+        const Tile tl = tile_of(v, nblocks, tiles_x, tiles_per_img);
         if (v != (int)blockIdx.x) __syncthreads();  // the previous tile's reads of s are done
-        conv32_tile<MODE>(s, A, in, sbias, mask, out, n, tile_of(v, nblocks, tiles_x, tiles_per_img), wave, m, g);
+        halo_store<256>(s, h);
+        __syncthreads();
+        if (v + (int)gridDim.x < nblocks)
+            halo_issue<256>(h, in, tile_of(v + gridDim.x, nblocks, tiles_x, tiles_per_img), n);
+        f32x4 acc[8];
+        conv32_mma(s, A, acc, wave, m, g);
+        __syncthreads();  // every wave's reads of the halo are done
+        conv32_stage<MODE>(&s[0][0][0], acc, sbias, wave, m, g);
+        __syncthreads();
+        conv32_copy_out<MODE>(&s[0][0][0], mask, out, n, tl, wave, lane);
     }
 }
 
@@ -321,52 +431,74 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
 
 // Layer 8 (32 -> 1): z = b8 + sum_tap sum_c w8 a7, y = x + z with x = mu / scale
 // (float32).  mu_out (optional) = mu + scale * z, projected onto the
-// constraints when asked.
-__global__ __launch_bounds__(256) void conv_out_kernel(const uint16_t* __restrict__ a7, const float* __restrict__ w8r,
-                                                       const float* __restrict__ b8, const float* __restrict__ mu,
-                                                       float inv_scale, float scale, float* __restrict__ y,
-                                                       float* __restrict__ mu_out, int project, int n, int tiles_x,
-                                                       int tiles_per_img, int nblocks)
+// constraints when asked.  Taps in order (0,0), (0,1), ..., (2,2), channels as
+// the bf16 pairs (0,1), ..., (30,31) with one dot-product instruction each
+// (w8p: packed pairs from prep_weights_kernel, read as uniform loads, so they
+// come through the scalar cache into scalar registers).  128 threads per 16x16
+// tile, each two vertically adjacent pixels, which share two of their three
+// rows of staged inputs.
+constexpr int OUT_THREADS = 128;
+constexpr int OUT_GRID = 256 * 6;  // blocks resident at once (6 per CU by LDS), a multiple of 8
+__global__ __launch_bounds__(OUT_THREADS) void conv_out_kernel(const uint16_t* __restrict__ a7,
+                                                               const uint32_t* __restrict__ w8p,
+                                                               const float* __restrict__ b8,
+                                                               const float* __restrict__ mu, float inv_scale,
+                                                               float scale, float* __restrict__ y,
+                                                               float* __restrict__ mu_out, int project, int n,
+                                                               int tiles_x, int tiles_per_img, int nblocks)
 {
     __shared__ __attribute__((aligned(16))) uint16_t s[HALO][HALO][LDS_PIX];
-    __shared__ __attribute__((aligned(16))) float wt[9][C];  // tap-major: 8 channels per two 16-byte reads
-    const Tile tl = tile_of(blockIdx.x, nblocks, tiles_x, tiles_per_img);
-    load_halo(s, a7, tl, n);
-    for (int e = threadIdx.x; e < 9 * C; e += blockDim.x) {
-        const int c = e / 9, tap = e - c * 9;
-        wt[tap][c] = w8r[e];
-    }
-    __syncthreads();
-    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-    const int i = tl.i0 + ty, j = tl.j0 + tx;
-    if (i >= n || j >= n) return;
-    float z = b8[0];
+    // persistent: tiles blockIdx.x, blockIdx.x + gridDim.x, ... of the XCD-aware order, the next
+    // tile's halo loads in flight while the current tile is computed
+    HaloRegs<OUT_THREADS> h;
+    if ((int)blockIdx.x < nblocks)
+        halo_issue<OUT_THREADS>(h, a7, tile_of(blockIdx.x, nblocks, tiles_x, tiles_per_img), n);
+    const int ty = (threadIdx.x >> 4) * 2, tx = threadIdx.x & 15;
+    for (int v = blockIdx.x; v < nblocks; v += gridDim.x) {
+        const Tile tl = tile_of(v, nblocks, tiles_x, tiles_per_img);
+        if (v != (int)blockIdx.x) __syncthreads();  // the previous tile's reads of s are done
+        halo_store<OUT_THREADS>(s, h);
+        __syncthreads();
+        if (v + (int)gridDim.x < nblocks)
+            halo_issue<OUT_THREADS>(h, a7, tile_of(v + gridDim.x, nblocks, tiles_x, tiles_per_img), n);
+        float z[2] = {b8[0], b8[0]};
+        // staged row ty + R serves pixel 0 with ky = R (R <= 2) and pixel 1 with ky = R - 1 (R >= 1)
+#pragma unroll 1
+        for (int R = 0; R < 4; ++R)
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-        const int ky = tap / 3, kx = tap - ky * 3;
-        const u32x4* src = (const u32x4*)(&s[ty + ky][tx + kx][0]);
-        const float4* wv = (const float4*)(&wt[tap][0]);
+            for (int kx = 0; kx < 3; ++kx) {
+                const u32x4* src = (const u32x4*)(&s[ty + R][tx + kx][0]);
+                u32x4 a[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const u32x4 v = src[q];
-            const float4 w0 = wv[2 * q], w1 = wv[2 * q + 1];
-            z = fmaf(w0.x, bf_lo(v.x), z);
-            z = fmaf(w0.y, bf_hi(v.x), z);
-            z = fmaf(w0.z, bf_lo(v.y), z);
-            z = fmaf(w0.w, bf_hi(v.y), z);
-            z = fmaf(w1.x, bf_lo(v.z), z);
-            z = fmaf(w1.y, bf_hi(v.z), z);
-            z = fmaf(w1.z, bf_lo(v.w), z);
-            z = fmaf(w1.w, bf_hi(v.w), z);
+                for (int q = 0; q < 4; ++q) a[q] = src[q];
+#pragma unroll
+                for (int px = 0; px < 2; ++px) {
+                    const int ky = R - px;
+                    if (ky < 0 || ky > 2) continue;
+                    const u32x4* wv = (const u32x4*)(w8p + (ky * 3 + kx) * (C / 2));
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const u32x4 w = wv[q];
+                        z[px] = dot2(w.x, a[q].x, z[px]);
+                        z[px] = dot2(w.y, a[q].y, z[px]);
+                        z[px] = dot2(w.z, a[q].z, z[px]);
+                        z[px] = dot2(w.w, a[q].w, z[px]);
+                    }
+                }
+            }
+#pragma unroll
+        for (int px = 0; px < 2; ++px) {
+            const int i = tl.i0 + ty + px, j = tl.j0 + tx;
+            if (i >= n || j >= n) continue;
+            const size_t p = pix(tl.b, i, j, n);
+            const float xin = mu[p];
+            if (y) y[p] = fmaf(xin, inv_scale, z[px]);
+            if (mu_out) {
+                // mu + scale * z = scale * y, formed so that z = 0 returns mu exactly
+                const float m = fmaf(scale, z[px], xin);
+                mu_out[p] = project ? (in_disc(j, i, n) ? fmaxf(m, 0.0f) : 0.0f) : m;
+            }
         }
-    }
-    const size_t p = pix(tl.b, i, j, n);
-    const float xin = mu[p];
-    if (y) y[p] = fmaf(xin, inv_scale, z);
-    if (mu_out) {
-        // mu + scale * z = scale * y, formed so that z = 0 returns mu exactly
-        const float m = fmaf(scale, z, xin);
-        mu_out[p] = project ? (in_disc(j, i, n) ? fmaxf(m, 0.0f) : 0.0f) : m;
     }
 }
 
@@ -420,42 +552,46 @@ __global__ __launch_bounds__(256) void dgrad_out_kernel(const float* __restrict_
                                                         const uint16_t* __restrict__ a7, uint16_t* __restrict__ g7,
                                                         int n, long total)
 {
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= total) return;
-    const int j = (int)(idx % n);
-    const long bi = idx / n;
-    const int i = (int)(bi % n);
-    const int b = (int)(bi / n);
-    float gn[9];  // g8 at (i - dy, j - dx) for tap (dy + 1, dx + 1)
+    __shared__ u32x4 stage[ROW_STAGE_WORDS];
+    const long first = (long)blockIdx.x * blockDim.x;
+    const long idx = first + threadIdx.x;
+    u32x4 rows[4] = {};
+    if (idx < total) {
+        const int j = (int)(idx % n);
+        const long bi = idx / n;
+        const int i = (int)(bi % n);
+        const int b = (int)(bi / n);
+        float gn[9];  // g8 at (i - dy, j - dx) for tap (dy + 1, dx + 1)
 #pragma unroll
-    for (int ky = 0; ky < 3; ++ky)
+        for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
-        for (int kx = 0; kx < 3; ++kx) {
-            const int gi = i - (ky - 1), gj = j - (kx - 1);
-            gn[ky * 3 + kx] = (gi >= 0 && gi < n && gj >= 0 && gj < n) ? g8[pix(b, gi, gj, n)] : 0.0f;
-        }
-    const u32x4* msk = (const u32x4*)(a7 + (size_t)idx * C);
-    u32x4* dst = (u32x4*)(g7 + (size_t)idx * C);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const u32x4 mv = msk[q];
-        const uint32_t mw[4] = {mv.x, mv.y, mv.z, mv.w};
-        uint32_t pk[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int c = q * 8 + e * 2;
-            float d0 = 0.0f, d1 = 0.0f;
-#pragma unroll
-            for (int t = 0; t < 9; ++t) {
-                d0 = fmaf(w8r[c * 9 + t], gn[t], d0);
-                d1 = fmaf(w8r[(c + 1) * 9 + t], gn[t], d1);
+            for (int kx = 0; kx < 3; ++kx) {
+                const int gi = i - (ky - 1), gj = j - (kx - 1);
+                gn[ky * 3 + kx] = (gi >= 0 && gi < n && gj >= 0 && gj < n) ? g8[pix(b, gi, gj, n)] : 0.0f;
             }
-            d0 = bf_lo(mw[e]) > 0.0f ? d0 : 0.0f;
-            d1 = bf_hi(mw[e]) > 0.0f ? d1 : 0.0f;
-            pk[e] = f2bf(d0) | (f2bf(d1) << 16);
+        const u32x4* msk = (const u32x4*)(a7 + (size_t)idx * C);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const u32x4 mv = msk[q];
+            const uint32_t mw[4] = {mv.x, mv.y, mv.z, mv.w};
+            uint32_t pk[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int c = q * 8 + e * 2;
+                float d0 = 0.0f, d1 = 0.0f;
+#pragma unroll
+                for (int t = 0; t < 9; ++t) {
+                    d0 = fmaf(w8r[c * 9 + t], gn[t], d0);
+                    d1 = fmaf(w8r[(c + 1) * 9 + t], gn[t], d1);
+                }
+                d0 = bf_lo(mw[e]) > 0.0f ? d0 : 0.0f;
+                d1 = bf_hi(mw[e]) > 0.0f ? d1 : 0.0f;
+                pk[e] = f2bf(d0) | (f2bf(d1) << 16);
+            }
+            rows[q] = u32x4{pk[0], pk[1], pk[2], pk[3]};
         }
-        dst[q] = u32x4{pk[0], pk[1], pk[2], pk[3]};
     }
+    store_pixel_rows(stage, rows, g7, first, total);
 }
 
 // Weight gradient of a 32 -> 32 layer on the matrix cores:
@@ -598,7 +734,31 @@ __global__ __launch_bounds__(256) void wgrad32_kernel(const uint16_t* __restrict
 // Thread t owns a channel pair cp = t mod 16 and a tile row r = t / 16: for
 // each pixel of its row it loads the pair once and each of the 9 neighbours
 // once and adds into 9 x 2 register accumulators.  At the end the 16 rows'
-// sums are added in row order through LDS.
+// sums are added in row order through LDS.  The loads of a block's next tile
+// are issued before the current tile's sums, so they are in flight meanwhile.
+struct WgradInRegs {
+    uint32_t g[T];   // the thread's channel pair of g1 at the 16 pixels of its tile row
+    uint16_t a[2];   // a0 at halo pixels tid and tid + 256
+};
+__device__ __forceinline__ void wgrad_in_issue(WgradInRegs& q, const uint16_t* __restrict__ g1,
+                                               const uint16_t* __restrict__ a0, Tile tl, int n, int r, int cp)
+{
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int e = (int)threadIdx.x + 256 * k;
+        const int ly = e / HALO, lx = e - ly * HALO;
+        const int gi = tl.i0 + ly - 1, gj = tl.j0 + lx - 1;
+        const bool in = e < HALO * HALO && gi >= 0 && gi < n && gj >= 0 && gj < n;
+        q.a[k] = in ? a0[pix(tl.b, gi, gj, n)] : (uint16_t)0;
+    }
+    const int gi = tl.i0 + r;
+#pragma unroll
+    for (int x = 0; x < T; ++x) {
+        const int gj = tl.j0 + x;
+        q.g[x] = (gi < n && gj < n) ? *(const uint32_t*)(g1 + pix(tl.b, gi, gj, n) * C + 2 * cp) : 0u;
+    }
+}
+
 __global__ __launch_bounds__(256) void wgrad_in_kernel(const uint16_t* __restrict__ g1, const uint16_t* __restrict__ a0,
                                                        float* __restrict__ part, int n, int tiles_x,
                                                        int tiles_per_img, int ntiles)
@@ -609,22 +769,29 @@ __global__ __launch_bounds__(256) void wgrad_in_kernel(const uint16_t* __restric
     float acc[9][2], bacc[2] = {0.0f, 0.0f};
 #pragma unroll
     for (int t = 0; t < 9; ++t) acc[t][0] = acc[t][1] = 0.0f;
+    WgradInRegs q;
+    if ((int)blockIdx.x < ntiles) wgrad_in_issue(q, g1, a0, tile_plain(blockIdx.x, tiles_x, tiles_per_img), n, r, cp);
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const Tile tl = tile_plain(t, tiles_x, tiles_per_img);
         __syncthreads();
-        for (int e = tid; e < HALO * HALO; e += 256) {
-            const int ly = e / HALO, lx = e - ly * HALO;
-            const int gi = tl.i0 + ly - 1, gj = tl.j0 + lx - 1;
-            as[ly][lx] = (gi >= 0 && gi < n && gj >= 0 && gj < n) ? bf2f(a0[pix(tl.b, gi, gj, n)]) : 0.0f;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int e = tid + 256 * k;
+            if (e < HALO * HALO) as[e / HALO][e % HALO] = bf2f(q.a[k]);
         }
+        uint32_t gw[T];
+#pragma unroll
+        for (int x = 0; x < T; ++x) gw[x] = q.g[x];
         __syncthreads();
+        if (t + (int)gridDim.x < ntiles)
+            wgrad_in_issue(q, g1, a0, tile_plain(t + gridDim.x, tiles_x, tiles_per_img), n, r, cp);
         const int gi = tl.i0 + r;
         if (gi < n) {
+#pragma unroll
             for (int x = 0; x < T; ++x) {
                 const int gj = tl.j0 + x;
                 if (gj >= n) break;
-                const uint32_t gw = *(const uint32_t*)(g1 + pix(tl.b, gi, gj, n) * C + 2 * cp);
-                const float g0 = bf_lo(gw), gq = bf_hi(gw);
+                const float g0 = bf_lo(gw[x]), gq = bf_hi(gw[x]);
                 bacc[0] += g0;
                 bacc[1] += gq;
 #pragma unroll
@@ -675,15 +842,20 @@ __global__ __launch_bounds__(256) void wgrad_out_kernel(const float* __restrict_
     float acc[9][2], bacc = 0.0f;
 #pragma unroll
     for (int t = 0; t < 9; ++t) acc[t][0] = acc[t][1] = 0.0f;
+    HaloRegs<256> h;
+    float gnext = 0.0f;  // g8 at pixel (r, cp) of the next tile
+    auto issue = [&](Tile tl) {
+        halo_issue<256>(h, a7, tl, n);
+        const int gi = tl.i0 + r, gj = tl.j0 + cp;
+        gnext = (gi < n && gj < n) ? g8[pix(tl.b, gi, gj, n)] : 0.0f;
+    };
+    if ((int)blockIdx.x < ntiles) issue(tile_plain(blockIdx.x, tiles_x, tiles_per_img));
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const Tile tl = tile_plain(t, tiles_x, tiles_per_img);
         __syncthreads();
-        load_halo(s, a7, tl, n);
-        {
-            const int gi = tl.i0 + r, gj = tl.j0 + cp;
-            gs[r][cp] = (gi < n && gj < n) ? g8[pix(tl.b, gi, gj, n)] : 0.0f;
-        }
+        halo_store<256>(s, h);
+        gs[r][cp] = gnext;
         __syncthreads();
+        if (t + (int)gridDim.x < ntiles) issue(tile_plain(t + gridDim.x, tiles_x, tiles_per_img));
         for (int x = 0; x < T; ++x) {
             const float g = gs[r][x];
             bacc += g;
@@ -773,8 +945,9 @@ struct recon_cnn {
     float* d_grad = nullptr;
     uint16_t* d_wf = nullptr;  // [6][9][32][32]
     uint16_t* d_wt = nullptr;  // [6][9][32][32]
-    float* d_w1r = nullptr;    // [32][9]
-    float* d_w8r = nullptr;    // [32][9]
+    uint32_t* d_w1p = nullptr;  // [32][5] bf16 pairs of taps
+    float* d_w8r = nullptr;     // [32][9]
+    uint32_t* d_w8p = nullptr;  // [9][16] bf16 pairs of channels
     uint16_t* d_a0 = nullptr;  // [B][n][n]
     uint16_t* d_act[8] = {};   // 1..7: [B][n][n][32]
     uint16_t* d_g[8] = {};     // 1..7: [B][n][n][32]
@@ -807,7 +980,7 @@ Shape shape_of(int batch, int n)
 void free_cnn(recon_cnn* c)
 {
     if (!c) return;
-    void* ptrs[] = {c->d_theta, c->d_m, c->d_v, c->d_grad, c->d_wf, c->d_wt, c->d_w1r, c->d_w8r,
+    void* ptrs[] = {c->d_theta, c->d_m, c->d_v, c->d_grad, c->d_wf, c->d_wt, c->d_w1p, c->d_w8r, c->d_w8p,
                     c->d_a0, c->d_y, c->d_g8, c->d_part, c->d_part2, c->d_loss_part};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -820,8 +993,8 @@ void free_cnn(recon_cnn* c)
 
 hipError_t launch_prep(recon_cnn* c, hipStream_t s)
 {
-    prep_weights_kernel<<<cdiv(NHID * W32 + 576, 256), 256, 0, s>>>(c->d_theta, c->d_wf, c->d_wt, c->d_w1r,
-                                                                     c->d_w8r);
+    prep_weights_kernel<<<cdiv(PREP_END, 256), 256, 0, s>>>(c->d_theta, c->d_wf, c->d_wt, c->d_w8r, c->d_w1p,
+                                                           c->d_w8p);
     return hipGetLastError();
 }
 
@@ -844,15 +1017,16 @@ hipError_t launch_conv32(int mode, const uint16_t* in, const uint16_t* w, const 
 hipError_t enqueue_forward(recon_cnn* c, const float* mu, float* mu_out, int project, const Shape& S, hipStream_t s)
 {
     const float inv = 1.0f / c->mu_scale;
-    conv_in_kernel<<<cdiv(S.pixels, 256), 256, 0, s>>>(mu, inv, c->d_w1r, c->d_theta + OFF_B1, c->d_a0, c->d_act[1],
+    conv_in_kernel<<<cdiv(S.pixels, 256), 256, 0, s>>>(mu, inv, c->d_w1p, c->d_theta + OFF_B1, c->d_a0, c->d_act[1],
                                                         S.n, S.pixels);
     hipError_t e = hipGetLastError();
     for (int l = 2; l <= 7 && e == hipSuccess; ++l)
         e = launch_conv32(0, c->d_act[l - 1], c->d_wf + (size_t)(l - 2) * W32,
                           c->d_theta + OFF_HID + (l - 2) * P32 + W32, nullptr, c->d_act[l], S, s);
     if (e != hipSuccess) return e;
-    conv_out_kernel<<<S.ntiles, 256, 0, s>>>(c->d_act[7], c->d_w8r, c->d_theta + OFF_B8, mu, inv, c->mu_scale, c->d_y,
-                                             mu_out, project, S.n, S.tiles_x, S.tiles_per_img, S.ntiles);
+    conv_out_kernel<<<std::min(S.ntiles, OUT_GRID), OUT_THREADS, 0, s>>>(
+        c->d_act[7], c->d_w8p, c->d_theta + OFF_B8, mu, inv, c->mu_scale, c->d_y, mu_out, project, S.n, S.tiles_x,
+        S.tiles_per_img, S.ntiles);
     return hipGetLastError();
 }
 
@@ -963,8 +1137,9 @@ recon_status recon_cnn_create(const float* h_params, int32_t max_batch, int32_t 
     C_TRY(hipMalloc(&c->d_grad, NPARAM * sizeof(float)));
     C_TRY(hipMalloc(&c->d_wf, NHID * W32 * sizeof(uint16_t)));
     C_TRY(hipMalloc(&c->d_wt, NHID * W32 * sizeof(uint16_t)));
-    C_TRY(hipMalloc(&c->d_w1r, 288 * sizeof(float)));
+    C_TRY(hipMalloc(&c->d_w1p, C * 5 * sizeof(uint32_t)));
     C_TRY(hipMalloc(&c->d_w8r, 288 * sizeof(float)));
+    C_TRY(hipMalloc(&c->d_w8p, 9 * (C / 2) * sizeof(uint32_t)));
     C_TRY(hipMalloc(&c->d_a0, px * sizeof(uint16_t)));
     for (int l = 1; l <= 7; ++l) {
         C_TRY(hipMalloc(&c->d_act[l], px * C * sizeof(uint16_t)));
