@@ -56,7 +56,11 @@ COUNTER_ARGS = ("--steps 1 --warmup 0 --iters 40 --cpu-iters 0 --time-iters 0 --
 CAL_MIB = 256
 SIMDS = 1024              # 256 compute units x 4 SIMDs
 CLOCK_HZ = 2.4e9          # peak engine clock
-VALU_PEAK_TOPS = SIMDS * 16 * CLOCK_HZ / 1e12  # non-packed wave64 issue: 16 lanes per SIMD per cycle
+# the published FP32 vector rate, 157.3 TFLOP/s, counts an FMA as two operations: 32 lanes per SIMD per
+# cycle, i.e. one wave64 VALU instruction every 2 cycles (what plain FP32 and integer adds reach;
+# conversions, 32-bit integer multiplies and the bf16 dot product issue every 4, recon_valu_rate)
+VALU_CYCLES = 2
+VALU_PEAK_TOPS = SIMDS * 64 / VALU_CYCLES * CLOCK_HZ / 1e12
 
 
 def source_hashes(paths=None) -> dict:
@@ -148,7 +152,7 @@ def summarize_counters(d: str, out_path: str | None = None) -> dict:
                 n_disp = pick(counts, pat, c)
         rec = {"pattern": pat, "dispatches": n_disp, "counters": counters,
                "fetch_bytes": counters["FETCH_SIZE"] * 1024 * ff, "write_bytes": counters["WRITE_SIZE"] * 1024 * wf,
-               "valu_issue_s": counters["SQ_INSTS_VALU"] * 4 / (SIMDS * CLOCK_HZ),
+               "valu_issue_s": counters["SQ_INSTS_VALU"] * VALU_CYCLES / (SIMDS * CLOCK_HZ),
                "l2_hit_rate": counters["TCC_HIT_sum"] / max(1.0, counters["TCC_HIT_sum"] + counters["TCC_MISS_sum"]),
                "source_sha": sha, "sources": src}
         kernels[name] = rec
@@ -298,6 +302,11 @@ def main():
     l2_gbps = recon.read_bandwidth(2 << 20, 10) if args.time_iters > 0 else None
     if l2_gbps:
         log(f"bench: L2-resident read bandwidth {l2_gbps:.0f} GB/s")
+    # the vector ALU's issue rate for a few instruction kinds, measured now (T lane-ops/s)
+    valu_rates = {name: recon.valu_rate(k, 5) / 1e12 for k, name in enumerate(recon.VALU_OPS)} \
+        if args.time_iters > 0 else None
+    if valu_rates:
+        log("bench: VALU issue (T lane-ops/s): " + ", ".join(f"{k} {v:.1f}" for k, v in valu_rates.items()))
     kern = {"bp_update_kernel": kernel_roofline("bp_update_kernel", bp_ms, bp_bytes, l2_gbps),
             "fp_kernel<OS>": kernel_roofline("fp_kernel<OS>", fp_ms, fp_bytes, l2_gbps)}
     dom = kern["bp_update_kernel"] if bp_ms >= fp_ms else kern["fp_kernel<OS>"]
@@ -353,6 +362,7 @@ def main():
         "projector_gbps": fp_gbps,
         "projector": kern["fp_kernel<OS>"]["roofline"],
         "l2_read_gbps": l2_gbps,
+        "valu_rates_tops": valu_rates,
         "slice_alg_gbps": slice_bytes / (ms_per_step * 1e-3) / 1e9,
         "slice_alg_frac_of_l2_read": (slice_bytes / (ms_per_step * 1e-3) / 1e9 / l2_gbps) if l2_gbps else None,
         "kernel_us": {"fp": fp_ms * 1e3, "bp_update": bp_ms * 1e3, "graph_sub_iteration": sub_ms * 1e3,
@@ -373,7 +383,7 @@ def main():
 def kernel_roofline(name: str, ms: float, alg_bytes: float, l2_gbps):
     """Roofline of one kernel from its live mean launch time: the fraction of each ceiling it
     reaches -- VALU issue (SQ_INSTS_VALU per launch from the committed counter record, one wave64
-    instruction per SIMD every 4 cycles), HBM (calibrated FETCH_SIZE + WRITE_SIZE bytes per launch
+    instruction per SIMD every 2 cycles), HBM (calibrated FETCH_SIZE + WRITE_SIZE bytes per launch
     against 8 TB/s) and the L2-resident read bandwidth (algorithmic bytes) -- and the largest of
     them as the bound.  Without a counter record for the current sources only the L2 fraction is
     known."""

@@ -402,6 +402,18 @@ recon_status recon_count_pairs(recon_handle* h, int32_t subset, int32_t disc_onl
  * RECON_INVALID_ARG for other sizes or counts. */
 recon_status recon_read_bandwidth(int64_t bytes, int32_t reps, double* gbps_out, void* stream);
 
+/* Measurement helper (no operation of the paper): the vector ALU's issue rate
+ * for one instruction, as a check of the ALU ceiling the gather kernels are
+ * measured against.  2048 blocks of 256 threads (8 waves per SIMD) each run 16
+ * independent chains of 1024 instances of the instruction `op`: 0 v_fmac_f32
+ * (sources in two different registers), 1 v_add_f32, 2 v_add_u32,
+ * 3 v_cvt_f32_i32, 4 v_lshl_add_u64, 5 v_dot2c_f32_bf16.  *lane_ops_out = lane
+ * operations per second (wave64 instructions x 64) over `reps` (1..100)
+ * launches timed with HIP events on `stream`, after one untimed launch.
+ * Allocates and frees its own buffers; blocks until done.  RECON_INVALID_ARG
+ * for other ops or counts. */
+recon_status recon_valu_rate(int32_t op, int32_t reps, double* lane_ops_out, void* stream);
+
 /* Measurement helper: from d_img (read only) runs one sub-iteration of every
  * subset, then launches each kernel of a sub-iteration n_iter (1..4096) times
  * back to back on `stream` (subsets in turn) between two HIP events, and

@@ -702,6 +702,38 @@ recon_status recon_read_bandwidth(int64_t bytes, int32_t reps, double* gbps_out,
     return RECON_OK;
 }
 
+recon_status recon_valu_rate(int32_t op, int32_t reps, double* lane_ops_out, void* stream)
+{
+    if (!lane_ops_out) return fail(RECON_INVALID_ARG, "NULL argument");
+    if (op < 0 || op > 5) return fail(RECON_INVALID_ARG, "op must be in [0, 5]");
+    if (reps < 1 || reps > 100) return fail(RECON_INVALID_ARG, "reps must be in [1, 100]");
+    hipStream_t s = as_stream(stream);
+    constexpr int kBlocks = 2048;  // 8 blocks of 4 waves per compute unit: 8 waves per SIMD
+    uint32_t* seed = nullptr;
+    float* out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    long inst = 0;
+    hipError_t err = hipMalloc(&seed, 256 * sizeof(uint32_t));
+    if (err == hipSuccess) err = hipMalloc(&out, (size_t)kBlocks * 256 * sizeof(float));
+    if (err == hipSuccess) err = hipMemsetAsync(seed, 0x5b, 256 * sizeof(uint32_t), s);
+    if (err == hipSuccess) err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    if (err == hipSuccess) err = launch_valu_probe(op, seed, kBlocks, out, &inst, s);  // untimed
+    if (err == hipSuccess) err = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_valu_probe(op, seed, kBlocks, out, &inst, s);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (seed) (void)hipFree(seed);
+    if (out) (void)hipFree(out);
+    if (err != hipSuccess) return fail(RECON_DEVICE, std::string("VALU probe: ") + hipGetErrorString(err));
+    *lane_ops_out = (double)inst * 64.0 * reps / (ms * 1e-3);
+    return RECON_OK;
+}
+
 recon_status recon_time_kernels(recon_handle* h, const float* d_counts, float i0, float* d_img, int32_t n_iter,
                                 double* ms_out, void* stream)
 {

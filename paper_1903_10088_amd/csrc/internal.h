@@ -316,6 +316,7 @@ hipError_t launch_tv_grad(const float* img, float* grad, int n, float eps, hipSt
 // Read-bandwidth probe: `blocks` blocks of 256 threads each read the n16 16-byte
 // words at buf (n16 a power of two >= 1024) once; out: blocks * 256 floats.
 hipError_t launch_read_probe(const float* buf, uint32_t n16, int blocks, float* out, hipStream_t s);
+hipError_t launch_valu_probe(int op, const uint32_t* seed, int blocks, float* out, long* instructions, hipStream_t s);
 // fbp.hip: the filtered-backprojection tables of a geometry (host, double
 // precision, stored as float): D cos(gamma_k) in pixel units for every channel,
 // then dgamma h(m) for m = -(n_ch - 1) ... n_ch - 1.

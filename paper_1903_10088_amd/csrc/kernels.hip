@@ -614,11 +614,65 @@ __global__ __launch_bounds__(256) void read_probe_kernel(const float4* __restric
     out[blockIdx.x * 256 + threadIdx.x] = (acc.x + acc.y) + (acc.z + acc.w);
 }
 
+// Measurement probe of the vector ALU's issue rate for one instruction: every
+// thread runs VALU_CHAINS independent chains of VALU_ITERS instructions, each
+// written as inline assembly so that the compiler can neither fold nor replace
+// it; one value per thread is written so that nothing is dropped.
+constexpr int VALU_ITERS = 1024, VALU_CHAINS = 16;
+typedef __bf16 probe_bf16x2 __attribute__((ext_vector_type(2)));
+template <int OP>
+__global__ __launch_bounds__(256) void valu_probe_kernel(const uint32_t* __restrict__ seed, float* __restrict__ out)
+{
+    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t b = seed[t & 255], c = seed[(t + 97) & 255];
+    const float bf = __uint_as_float((b & 0x007fffffu) | 0x3f000000u), cf = __uint_as_float((c & 0x007fffffu) | 0x3f000000u);
+    const uint64_t b64 = ((uint64_t)b << 32) | c;
+    float f[VALU_CHAINS];
+    uint32_t u[VALU_CHAINS];
+    uint64_t w[VALU_CHAINS];
+#pragma unroll
+    for (int k = 0; k < VALU_CHAINS; ++k) {
+        f[k] = (float)k;
+        u[k] = t + k;
+        w[k] = (uint64_t)(t + k);
+    }
+    for (int it = 0; it < VALU_ITERS; ++it) {
+#pragma unroll
+        for (int k = 0; k < VALU_CHAINS; ++k) {
+            if constexpr (OP == 0) asm volatile("v_fmac_f32 %0, %1, %2" : "+v"(f[k]) : "v"(bf), "v"(cf));
+            if constexpr (OP == 1) asm volatile("v_add_f32 %0, %0, %1" : "+v"(f[k]) : "v"(bf));
+            if constexpr (OP == 2) asm volatile("v_add_u32 %0, %0, %1" : "+v"(u[k]) : "v"(b));
+            if constexpr (OP == 3) asm volatile("v_cvt_f32_i32 %0, %0" : "+v"(f[k]));
+            if constexpr (OP == 4) asm volatile("v_lshl_add_u64 %0, %0, 1, %1" : "+v"(w[k]) : "v"(b64));
+            if constexpr (OP == 5) asm volatile("v_dot2c_f32_bf16 %0, %1, %2" : "+v"(f[k]) : "v"(b), "v"(c));
+        }
+    }
+    float r = 0.0f;
+#pragma unroll
+    for (int k = 0; k < VALU_CHAINS; ++k) r += f[k] + (float)u[k] + (float)(uint32_t)w[k];
+    out[t] = r;
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------------------
 // Launchers
 // ----------------------------------------------------------------------------
+
+hipError_t launch_valu_probe(int op, const uint32_t* seed, int blocks, float* out, long* instructions, hipStream_t s)
+{
+    switch (op) {
+    case 0: valu_probe_kernel<0><<<blocks, 256, 0, s>>>(seed, out); break;
+    case 1: valu_probe_kernel<1><<<blocks, 256, 0, s>>>(seed, out); break;
+    case 2: valu_probe_kernel<2><<<blocks, 256, 0, s>>>(seed, out); break;
+    case 3: valu_probe_kernel<3><<<blocks, 256, 0, s>>>(seed, out); break;
+    case 4: valu_probe_kernel<4><<<blocks, 256, 0, s>>>(seed, out); break;
+    case 5: valu_probe_kernel<5><<<blocks, 256, 0, s>>>(seed, out); break;
+    default: return hipErrorInvalidValue;
+    }
+    *instructions = (long)blocks * 4 * VALU_ITERS * VALU_CHAINS;  // wave64 instructions of the probed kind
+    return hipGetLastError();
+}
 
 hipError_t launch_read_probe(const float* buf, uint32_t n16, int blocks, float* out, hipStream_t s)
 {

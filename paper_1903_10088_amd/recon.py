@@ -56,7 +56,7 @@ EXPORTS = ["recon_default_params", "recon_status_string", "recon_last_error", "r
            "recon_cnn_set_state", "recon_cnn_save", "recon_cnn_load", "recon_cnn_forward", "recon_cnn_loss_grad",
            "recon_cnn_adam_step", "recon_cnn_train_step", "recon_cnn_tensor", "recon_cnn_time_kernels",
            "recon_data_residual", "recon_warm_start", "recon_warm_start_noalloc", "recon_fbp",
-           "recon_rebin_helical", "recon_read_bandwidth", "recon_batch_check_work"]
+           "recon_rebin_helical", "recon_read_bandwidth", "recon_valu_rate", "recon_batch_check_work"]
 
 _lib = None
 
@@ -89,6 +89,7 @@ def lib():
         L.recon_subset_size.argtypes = [vp, i32, P(i32)]
         L.recon_set_launch.argtypes = [vp, i32, i32]
         L.recon_read_bandwidth.argtypes = [i64, i32, P(d), vp]
+        L.recon_valu_rate.argtypes = [i32, i32, P(d), vp]
         L.recon_batch_check_work.argtypes = [P(Geometry_c), i32, i32, i32, P(i64), P(i64)]
         L.recon_check_tables.argtypes = [P(Geometry_c), i32, i32, P(i64), P(i64), P(i64)]
         L.recon_count_pairs.argtypes = [vp, i32, i32, P(i64)]
@@ -157,6 +158,16 @@ def read_bandwidth(nbytes: int = 2 << 20, reps: int = 10) -> float:
     """recon_read_bandwidth: GB/s that 2048 blocks reading an L2-resident buffer of nbytes achieve."""
     out = ctypes.c_double()
     _check(lib().recon_read_bandwidth(int(nbytes), int(reps), ctypes.byref(out), _stream()), "recon_read_bandwidth")
+    return float(out.value)
+
+
+VALU_OPS = ("v_fmac_f32", "v_add_f32", "v_add_u32", "v_cvt_f32_i32", "v_lshl_add_u64", "v_dot2c_f32_bf16")
+
+
+def valu_rate(op: int, reps: int = 5) -> float:
+    """recon_valu_rate: lane operations per second of one VALU instruction (VALU_OPS[op])."""
+    out = ctypes.c_double()
+    _check(lib().recon_valu_rate(int(op), int(reps), ctypes.byref(out), _stream()), "recon_valu_rate")
     return float(out.value)
 
 

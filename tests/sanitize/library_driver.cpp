@@ -92,6 +92,8 @@ int main()
     expect(recon_batch_create(two, 2, 4, 1e-3, nullptr, &b) == RECON_INVALID_ARG && b == nullptr, "batch create");
     double gbps = 0.0;
     expect(recon_read_bandwidth(3000, 5, &gbps, nullptr) == RECON_INVALID_ARG, "read probe size");
+    expect(recon_valu_rate(6, 5, &gbps, nullptr) == RECON_INVALID_ARG, "VALU probe op");
+    expect(recon_valu_rate(0, 0, &gbps, nullptr) == RECON_INVALID_ARG, "VALU probe reps");
     expect(recon_warm_start_noalloc(nullptr, nullptr, nullptr, nullptr, nullptr, 1, 1, 1, 1.0, 1, nullptr, nullptr,
                                     nullptr, nullptr) == RECON_INVALID_ARG,
            "warm start NULL");

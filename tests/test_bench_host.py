@@ -46,8 +46,8 @@ def fake_runs(d, stamp):
 
 def test_counter_summary(tmp_path):
     """Per-dispatch means per kernel and counter (the kernel picked by its exact template), HBM bytes
-    scaled by the plain copy, VALU issue time at one wave64 instruction per SIMD every 4 cycles,
-    and the hash of the sources recorded at collection time."""
+    scaled by the plain copy, VALU issue time at one wave64 instruction per SIMD every 2 cycles, and
+    the hash of the sources recorded at collection time."""
     d = str(tmp_path)
     fake_runs(d, bench.source_hashes())
     out = os.path.join(d, "counters.json")
@@ -59,7 +59,7 @@ def test_counter_summary(tmp_path):
     assert k["fetch_bytes"] == k["counters"]["FETCH_SIZE"] * 1024 * 2.0
     assert k["write_bytes"] == k["counters"]["WRITE_SIZE"] * 1024 * 1.0
     valu = k["counters"]["SQ_INSTS_VALU"]
-    assert abs(k["valu_issue_s"] - valu * 4 / (1024 * 2.4e9)) <= 1e-18
+    assert abs(k["valu_issue_s"] - valu * 2 / (1024 * 2.4e9)) <= 1e-18
     assert rec["kernels"]["fp_kernel<OS>"]["counters"]["SQ_WAVES"] == 50.0
     assert len(k["source_sha"]) == 16
     assert rec["calibration"]["fetch_factor"] == 2.0 and rec["calibration"]["write_factor"] == 1.0
