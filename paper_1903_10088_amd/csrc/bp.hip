@@ -245,6 +245,73 @@ __device__ __forceinline__ void stage_store(StageLds& S, int b, int t0, int cv, 
     }
 }
 
+// Per-wave staging for a reader that is one wave per view group: wave g reads
+// only views cq = g and g + VIEW_GROUPS of a chunk, so it stages exactly those
+// rows itself (lane l holds slot l of each: STAGE_SLOTS = 64) and no other wave
+// touches them.  Between its store and its reads the wave needs no block
+// barrier: LDS operations of one wave are performed in order, and wave_sync
+// keeps the compiler from moving the reads above the stores.
+static_assert(STAGE_SLOTS == 64 && STAGE_VIEWS == 2 * VIEW_GROUPS, "per-wave staging: one slot per lane, two views");
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void stage_load_wave(const StageLds& S, const RayGeo* __restrict__ rg,
+                                                const float* __restrict__ w, int t0, int cv, int grp,
+                                                StagePrefetch& P)
+{
+    const int e = threadIdx.x & 63;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int cq = grp + VIEW_GROUPS * r;
+        P.slot[r] = -1;
+        if (cq < cv) {
+            const int t = t0 + cq;
+            if (e < S.cnt[t]) {
+                const int k = S.k0[t] + e;
+                const RayGeo g = rg[S.ray0[t] + k];
+                P.g[r] = make_float4(g.a_int, g.a_frac, g.s_hi, g.s_lo);
+                P.w[r] = w[S.ray0[t] + k];
+                P.slot[r] = cq * STAGE_ROW + (k < S.ks[t] ? e : k - S.kb[t]);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void stage_store_wave(StageLds& S, int b, int t0, int cv, int grp, const StagePrefetch& P)
+{
+    float4* geo = &S.geo[b][0][0];
+    float* wr = &S.w[b][0][0];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+        if (P.slot[r] >= 0) {
+            geo[P.slot[r]] = P.g[r];
+            wr[P.slot[r]] = P.w[r];
+        }
+    const int lane = threadIdx.x & 63;
+    if (lane < 2 * 2 * STAGE_GAP) {
+        const int cq = grp + VIEW_GROUPS * (lane / (2 * STAGE_GAP)), m = lane % (2 * STAGE_GAP);
+        if (cq < cv) {
+            const int t = t0 + cq;
+            const int k0 = S.k0[t], kb = S.kb[t], cnt = S.cnt[t];
+            int pos = -1;
+            if (cnt > 0) {
+                if (m < STAGE_GAP)
+                    pos = cnt + (k0 - kb) + m;
+                else if (kb != k0)
+                    pos = S.ks[t] - k0 + (m - STAGE_GAP);
+            }
+            if (pos >= 0) {
+                S.geo[b][cq][pos] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                S.w[b][cq][pos] = 0.0f;
+            }
+        }
+    }
+}
+
 // Table of views [s0, s0 + sn) for the tile centred at (Xc, Yc), one view per
 // thread: each view's linear channel model over the tile, the channel range
 // that holds every pixel's window, and the window half-widths, widened by the
@@ -565,13 +632,14 @@ __device__ __forceinline__ void gather_quad(StageLds& S, const Geo& G, const Vie
         stage_table(S, G, V, s0, sn, Xc, Yc, 2, 2);
         __syncthreads();
         StagePrefetch P;
-        stage_load(S, rg, w, 0, min(STAGE_VIEWS, sn), P);
+        stage_load_wave(S, rg, w, 0, min(STAGE_VIEWS, sn), grp, P);
         for (int t0 = 0, b = 0; t0 < sn; t0 += STAGE_VIEWS, b ^= 1) {
             const int cv = min(STAGE_VIEWS, sn - t0);
-            // buffer b was last read by chunk t0 - 2, before the previous barrier
-            stage_store(S, b, t0, cv, P);
-            __syncthreads();
-            if (t0 + STAGE_VIEWS < sn) stage_load(S, rg, w, t0 + STAGE_VIEWS, min(STAGE_VIEWS, sn - t0 - STAGE_VIEWS), P);
+            // this wave's rows of buffer b were last read by its own chunk t0 - 2
+            stage_store_wave(S, b, t0, cv, grp, P);
+            wave_sync();
+            if (t0 + STAGE_VIEWS < sn)
+                stage_load_wave(S, rg, w, t0 + STAGE_VIEWS, min(STAGE_VIEWS, sn - t0 - STAGE_VIEWS), grp, P);
             // view cq of the chunk (wave-uniform)
             auto view = [&](int cq) {
                 const int t = t0 + cq;
