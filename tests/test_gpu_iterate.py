@@ -1,10 +1,10 @@
 """GPU parity of the full ordered-subset iteration against the FP64 oracle.
 
 Bar: image RMSE over the reconstruction disc <= 1e-4 * mu_water (4.9e-7 / mm)
-after the full iteration count, the GPU taking its own step-rule decisions; the
-lambda traces must be equal (a differing decision is tolerated only at a
-near-tie of the oracle's own comparison, and then judged on a replay of the
-oracle's schedule).
+after the full iteration count, the GPU taking its own step-rule decisions, and
+the lambda traces equal to the oracle's, decision for decision (a differing
+decision fails the test and names the first differing sub-iteration and the
+oracle's margin there).
 """
 import numpy as np
 import pytest
@@ -45,12 +45,10 @@ def disc_rmse(g, a, b):
 
 
 def check_parity(dev, g, M, beta, sl, n_iter, label):
-    """GPU run (own step-rule decisions) against the oracle.  The lambda traces must be equal; a
-    differing decision is accepted only where the oracle's own comparison was a near-tie, i.e.
-    its relative margin |f_n - f_ref| / f_n at the first differing sub-iteration is below the
-    GPU-vs-oracle agreement of f (FP32 line integrals), and the run is then judged on a replay of
-    the oracle's schedule, as the tolerances allow.  Anything else fails and names the first
-    differing sub-iteration."""
+    """GPU run (own step-rule decisions) against the oracle: the lambda traces must be equal, and
+    a differing decision fails with the first differing sub-iteration, the oracle's relative
+    margin |f_n - f_ref| / f_n there and the GPU-vs-oracle agreement of f up to it (a near-tie
+    shows as a margin below that agreement)."""
     print(f"os_iterate parity {label}: n={g.n} views={g.n_views} M={M} beta={beta} iters={n_iter}", flush=True)
     img, tr, ref, rtr = run_both(dev, g, M, beta, sl, n_iter)
     same = np.array_equal(tr[:, 1], rtr[:, 1])
@@ -58,10 +56,8 @@ def check_parity(dev, g, M, beta, sl, n_iter, label):
         first = int(np.argmax(tr[:, 1] != rtr[:, 1]))
         margin = abs(rtr[first, 0] - rtr[first - 1, 0]) / rtr[first, 0] if first > 0 else np.inf
         fdiff = np.max(np.abs(tr[:first + 1, 0] - rtr[:first + 1, 0]) / rtr[:first + 1, 0])
-        print(f"  lambda decision differs first at sub-iteration {first}: oracle margin {margin:.2e}, "
-              f"f agreement up to there {fdiff:.2e}", flush=True)
-        assert margin <= max(10 * fdiff, 1e-6), f"lambda schedule diverges at sub-iteration {first}"
-        img, tr, ref, rtr = run_both(dev, g, M, beta, sl, n_iter, schedule=rtr[:, 1].copy())
+        raise AssertionError(f"lambda decision differs first at sub-iteration {first}: oracle margin {margin:.2e}, "
+                             f"f agreement up to there {fdiff:.2e}")
     rmse = disc_rmse(g, img, ref)
     frel = np.max(np.abs(tr[:, 0] - rtr[:, 0]) / rtr[:, 0])
     print(f"  rmse {rmse:.3e} (tol {RMSE_TOL:.2e}), max rel f diff {frel:.2e}, same lambda: {same}", flush=True)
@@ -73,7 +69,7 @@ def check_parity(dev, g, M, beta, sl, n_iter, label):
 def test_config0_full(dev):
     g = ph.config0_geometry()
     sl = ph.make_slice(g, 0, 1e4)
-    assert check_parity(dev, g, 10, 1e-3, sl, 20, "config0")
+    check_parity(dev, g, 10, 1e-3, sl, 20, "config0")
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
