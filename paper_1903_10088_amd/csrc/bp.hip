@@ -172,9 +172,10 @@ constexpr int STAGE_LOADS = STAGE_VIEWS * STAGE_SLOTS / 256;  // staged slots pe
 // va = (kpc, gx, gy, hwx), vb = (hwy, x-part first and last channel, y-part
 // first channel), vc = (y-part last channel, staged count, x-part and y-part
 // slot bases); channels as floats for the window clamps.
-struct StageLds {
-    float4 geo[2][STAGE_VIEWS][STAGE_ROW];
-    float w[2][STAGE_VIEWS][STAGE_ROW];
+template <int NB>
+struct StageLdsT {
+    float4 geo[NB][STAGE_VIEWS][STAGE_ROW];
+    float w[NB][STAGE_VIEWS][STAGE_ROW];
     float4 va[STAGE_TABLE];
     float4 vb[STAGE_TABLE];
     int4 vc[STAGE_TABLE];
@@ -184,6 +185,8 @@ struct StageLds {
     int ray0[STAGE_TABLE];
     int ks[STAGE_TABLE];
 };
+typedef StageLdsT<2> StageLds;   // double-buffered rows (block-wide staging)
+typedef StageLdsT<1> StageLdsQ;  // single-buffered rows (per-wave staging)
 
 // One thread's share of a chunk's staged rays, held in registers between the
 // load and the LDS store.
@@ -259,7 +262,8 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ void stage_load_wave(const StageLds& S, const RayGeo* __restrict__ rg,
+template <class SL>
+__device__ __forceinline__ void stage_load_wave(const SL& S, const RayGeo* __restrict__ rg,
                                                 const float* __restrict__ w, int t0, int cv, int grp,
                                                 StagePrefetch& P)
 {
@@ -281,7 +285,8 @@ __device__ __forceinline__ void stage_load_wave(const StageLds& S, const RayGeo*
     }
 }
 
-__device__ __forceinline__ void stage_store_wave(StageLds& S, int b, int t0, int cv, int grp, const StagePrefetch& P)
+template <class SL>
+__device__ __forceinline__ void stage_store_wave(SL& S, int b, int t0, int cv, int grp, const StagePrefetch& P)
 {
     float4* geo = &S.geo[b][0][0];
     float* wr = &S.w[b][0][0];
@@ -317,7 +322,8 @@ __device__ __forceinline__ void stage_store_wave(StageLds& S, int b, int t0, int
 // that holds every pixel's window, and the window half-widths, widened by the
 // model's spread over a PX x PY block of pixels when a thread owns such a
 // block.  The slot bases put the part from k_split on behind the gap.
-__device__ __forceinline__ void stage_table(StageLds& S, const Geo& G, const ViewRec* __restrict__ V, int s0, int sn,
+template <class SL>
+__device__ __forceinline__ void stage_table(SL& S, const Geo& G, const ViewRec* __restrict__ V, int s0, int sn,
                                             float Xc, float Yc, int PX, int PY)
 {
     const int tid = threadIdx.x;
@@ -614,7 +620,10 @@ __device__ __forceinline__ void gather_block(StageLdsBlk& S, const Geo& G, const
 // sampling line of the block: a quarter of the window set-ups and half of the
 // crossing arithmetic of one pixel per thread, with as many waves per tile.
 // acc[b][a] receives group g's sum for pixel (2 (l mod 8) + a, 2 (l / 8) + b).
-__device__ __forceinline__ void gather_quad(StageLds& S, const Geo& G, const ViewRec* __restrict__ V,
+// Each wave stages its own rows in one buffer: a chunk's rows are overwritten
+// only after the wave has read them (its LDS operations are performed in order).
+// Returns after a block barrier, so S is free for other use afterwards.
+__device__ __forceinline__ void gather_quad(StageLdsQ& S, const Geo& G, const ViewRec* __restrict__ V,
                                             const RayGeo* __restrict__ rg, const float* __restrict__ w, int q0,
                                             int nq, int ti0, int tj0, float (&acc)[2][2])
 {
@@ -633,9 +642,10 @@ __device__ __forceinline__ void gather_quad(StageLds& S, const Geo& G, const Vie
         __syncthreads();
         StagePrefetch P;
         stage_load_wave(S, rg, w, 0, min(STAGE_VIEWS, sn), grp, P);
-        for (int t0 = 0, b = 0; t0 < sn; t0 += STAGE_VIEWS, b ^= 1) {
+        for (int t0 = 0; t0 < sn; t0 += STAGE_VIEWS) {
             const int cv = min(STAGE_VIEWS, sn - t0);
-            // this wave's rows of buffer b were last read by its own chunk t0 - 2
+            constexpr int b = 0;
+            // this wave's rows were last read by its own previous chunk
             stage_store_wave(S, b, t0, cv, grp, P);
             wave_sync();
             if (t0 + STAGE_VIEWS < sn)
@@ -682,6 +692,7 @@ __device__ __forceinline__ void gather_quad(StageLds& S, const Geo& G, const Vie
                 if (grp < cv) view(grp);
                 if (grp + VIEW_GROUPS < cv) view(grp + VIEW_GROUPS);
             }
+            wave_sync();  // this chunk's reads of the rows come before the next chunk's stores
         }
         __syncthreads();  // the table and both buffers are rewritten by the next group of views
     }
@@ -997,8 +1008,13 @@ __device__ __forceinline__ void bp_update_tile_quad(Geo G, const ViewRec* __rest
     __shared__ float s[TILE + 2][TILE + 3];
     __shared__ float t[TILE][TILE + 1];
     __shared__ double red[4];
-    __shared__ StageLds S;
-    __shared__ float gsum[VIEW_GROUPS][TILE * TILE];
+    // the staging area, and after the gather (which ends at a block barrier) the four groups' sums
+    constexpr size_t STAGE_BYTES = sizeof(StageLdsQ) > sizeof(float) * VIEW_GROUPS * TILE * TILE
+                                       ? sizeof(StageLdsQ)
+                                       : sizeof(float) * VIEW_GROUPS * TILE * TILE;
+    __shared__ __attribute__((aligned(16))) unsigned char stage_raw[STAGE_BYTES];
+    StageLdsQ& S = *reinterpret_cast<StageLdsQ*>(stage_raw);
+    float (*gsum)[TILE * TILE] = reinterpret_cast<float (*)[TILE * TILE]>(stage_raw);
     const int tid = threadIdx.x;
     for (int e = tid; e < (TILE + 2) * (TILE + 2); e += 256) {
         const int ly = e / (TILE + 2), lx = e - ly * (TILE + 2);
@@ -1096,10 +1112,12 @@ __global__ __launch_bounds__(256) void step_batch_kernel(const SliceDesc* __rest
 // A batch of slices: block b updates tile work[b] of slice work[b].slice with
 // that slice's subset s and the step size step_batch_kernel left in state
 // 1 - in, reading image buffer `in` and writing 1 - in.
+// the 2x2 view-group variant (18 KB of LDS) is held to 6 waves per SIMD (80 VGPRs) for batches
+constexpr int bp_batch_waves(int var) { return var == 5 ? 6 : 1; }
 template <int VAR>
-__global__ __launch_bounds__(bp_threads(VAR)) void bp_update_batch_kernel(const SliceDesc* __restrict__ slices,
-                                                                          const BpWork* __restrict__ work, int s,
-                                                                          int in, StepRule rule)
+__global__ __launch_bounds__(bp_threads(VAR)) __attribute__((amdgpu_waves_per_eu(bp_batch_waves(VAR))))
+void bp_update_batch_kernel(const SliceDesc* __restrict__ slices, const BpWork* __restrict__ work, int s, int in,
+                            StepRule rule)
 {
     const BpWork wk = work[blockIdx.x];
     if (wk.slice < 0) return;
