@@ -83,11 +83,13 @@ __device__ __forceinline__ float bf_lo(uint32_t w) { return __uint_as_float(w <<
 __device__ __forceinline__ float bf_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
 __device__ __forceinline__ bf16x8 as_bf8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
-__device__ __forceinline__ bf16x2 as_bf2(uint32_t v) { return __builtin_bit_cast(bf16x2, v); }
-// a.lo * b.lo + a.hi * b.hi + c on bf16 pairs (one dot-product instruction)
-__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c)
+// Makes the compiler wait here for the load that produced v: an empty asm that reads it.  Called
+// on a persistent kernel's weights before its tile loop, so that no wait for them is left inside
+// the loop (where the in-order load/store counter would also wait for the tile prefetches).
+template <class V>
+__device__ __forceinline__ void settle(const V& v)
 {
-    return __builtin_amdgcn_fdot2_f32_bf16(as_bf2(a), as_bf2(b), c, false);
+    asm volatile("" ::"v"(v));
 }
 // two floats -> packed bf16 pair (lo, hi), rounded to nearest even by the conversion instruction
 __device__ __forceinline__ uint32_t pack_bf2(float lo, float hi)
@@ -169,14 +171,18 @@ __device__ __forceinline__ void halo_issue(HaloRegs<NT>& h, const uint16_t* __re
 template <int NT>
 __device__ __forceinline__ void halo_store(uint16_t (*s)[HALO][LDS_PIX], const HaloRegs<NT>& h)
 {
-    // chunk e = threadIdx.x + NT k is 16-byte part e mod 4 of staged pixel e / 4 (row-major)
+    // chunk e = threadIdx.x + NT k is 16-byte part e mod 4 of staged pixel e / 4 (row-major); lanes
+    // past the last chunk store into the unused padding of pixel (0, 0) instead of branching, which
+    // lets the compiler wait for each prefetched chunk exactly
     uint16_t* base = &s[0][0][0] + (threadIdx.x >> 2) * LDS_PIX + (threadIdx.x & 3) * 8;
 #pragma unroll
     for (int k = 0; k < HaloRegs<NT>::PER; ++k) {
-        if ((int)threadIdx.x + NT * k < HALO_CHUNKS)
-            *(u32x4*)(base + (NT / 4) * k * LDS_PIX) = (h.in >> k) & 1u ? h.v[k] : u32x4{0u, 0u, 0u, 0u};
+        const bool real = NT * (k + 1) <= HALO_CHUNKS || (int)threadIdx.x + NT * k < HALO_CHUNKS;
+        uint16_t* dst = real ? base + (NT / 4) * k * LDS_PIX : &s[0][0][C];
+        *(u32x4*)dst = (h.in >> k) & 1u ? h.v[k] : u32x4{0u, 0u, 0u, 0u};
     }
 }
+static_assert(LDS_PIX >= C + 8, "the halo store's spare slot lies in a staged pixel's padding");
 
 // Writes the 64-byte channel rows of the block's 256 consecutive pixels (pixel
 // first + threadIdx.x holds words w) so that every store instruction of a wave
@@ -204,13 +210,15 @@ __device__ __forceinline__ void store_pixel_rows(u32x4* __restrict__ stage, cons
 
 // wf[l][tap][o][c] = bf(W[o][c][tap]); wt[l][tap][c][o] = bf(W[o][c][8 - tap])
 // (the dgrad convolution); w8r[c][tap] = bf(W8) as float;
-// w1p[o][k] = bf16 pair (W1[o][2k], W1[o][2k+1]) (k = 4: (W1[o][8], 0));
-// w8p[tap][k] = bf16 pair (W8[2k][tap], W8[2k+1][tap]).
-constexpr int PREP_W8R = NHID * W32, PREP_W1P = PREP_W8R + 288, PREP_W8P = PREP_W1P + C * 5,
-              PREP_END = PREP_W8P + 9 * (C / 2);
+// w1a[o][k] = bf(W1[o][tap k]) for k < 9, 0 for k = 9..31 (the first layer's
+// matrix-core operand: K = the 9 taps, padded);
+// w8a[m][c] = bf(W8[c][tap m]) for m < 9, 0 for m = 9..15 (the last layer's
+// matrix-core operand: 16 rows, 9 of them taps).
+constexpr int PREP_W8R = NHID * W32, PREP_W1A = PREP_W8R + 288, PREP_W8A = PREP_W1A + C * C,
+              PREP_END = PREP_W8A + 16 * C;
 __global__ __launch_bounds__(256) void prep_weights_kernel(const float* __restrict__ th, uint16_t* __restrict__ wf,
                                                            uint16_t* __restrict__ wt, float* __restrict__ w8r,
-                                                           uint32_t* __restrict__ w1p, uint32_t* __restrict__ w8p)
+                                                           uint16_t* __restrict__ w1a, uint16_t* __restrict__ w8a)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < PREP_W8R) {
@@ -220,18 +228,17 @@ __global__ __launch_bounds__(256) void prep_weights_kernel(const float* __restri
         const float* W = th + OFF_HID + l * P32;
         wf[k] = (uint16_t)f2bf(W[(a * C + bq) * 9 + tap]);
         wt[k] = (uint16_t)f2bf(W[(bq * C + a) * 9 + (8 - tap)]);
-    } else if (k < PREP_W1P) {
+    } else if (k < PREP_W1A) {
         const int r = k - PREP_W8R;  // c * 9 + tap
         w8r[r] = bfround(th[OFF_W8 + r]);
-    } else if (k < PREP_W8P) {
-        const int r = k - PREP_W1P;  // o * 5 + pair
-        const int o = r / 5, q = r - o * 5;
-        const float* w = th + OFF_W1 + o * 9;
-        w1p[r] = f2bf(w[2 * q]) | (q < 4 ? f2bf(w[2 * q + 1]) << 16 : 0u);
+    } else if (k < PREP_W8A) {
+        const int r = k - PREP_W1A;  // o * 32 + k
+        const int o = r / C, q = r - o * C;
+        w1a[r] = q < 9 ? (uint16_t)f2bf(th[OFF_W1 + o * 9 + q]) : (uint16_t)0;
     } else if (k < PREP_END) {
-        const int r = k - PREP_W8P;  // tap * 16 + pair
-        const int tap = r / (C / 2), q = r - tap * (C / 2);
-        w8p[r] = f2bf(th[OFF_W8 + 2 * q * 9 + tap]) | (f2bf(th[OFF_W8 + (2 * q + 1) * 9 + tap]) << 16);
+        const int r = k - PREP_W8A;  // m * 32 + c
+        const int m = r / C, c = r - m * C;
+        w8a[r] = m < 9 ? (uint16_t)f2bf(th[OFF_W8 + c * 9 + m]) : (uint16_t)0;
     }
 }
 
@@ -239,53 +246,109 @@ __global__ __launch_bounds__(256) void prep_weights_kernel(const float* __restri
 // Forward
 // ----------------------------------------------------------------------------
 
-// Layer 1 (1 -> 32): a0 = bf(mu / scale), a1 = bf(relu(b1 + sum_tap w1 a0)),
-// the nine taps summed as the bf16 pairs (0,1), (2,3), (4,5), (6,7), (8) with
-// one dot-product instruction each (products exact in FP32).  w1p: packed
-// pairs from prep_weights_kernel.
-__global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ mu, float inv_scale,
-                                                      const uint32_t* __restrict__ w1p, const float* __restrict__ b1,
-                                                      uint16_t* __restrict__ a0, uint16_t* __restrict__ a1, int n,
-                                                      long total)
+// Layer 1 (1 -> 32): a0 = bf(mu / scale), a1 = bf(relu(b1 + sum_tap w1 a0)) on
+// the matrix cores: per 16 pixels of a tile row and 16 output channels, one
+// 16 x 16 x 32 product with K = the 9 taps (padded with zeros), A = the weights
+// (w1a), B = lane (m, g) holding taps 8g .. 8g+7 of pixel m, formed from the
+// tile's a0 halo staged in LDS; accumulators start at the bias.  The outputs
+// are staged in LDS and written one contiguous 1 KB row per store instruction.
+// Persistent over the XCD-aware tile order; the next tile's mu halo is loaded
+// while the current tile is computed.
+constexpr int IN_GRID = 256 * 4;  // blocks resident at once, a multiple of 8
+struct InHalo {
+    float v[2];   // mu at halo pixels threadIdx.x and threadIdx.x + 256
+    uint32_t in;  // bit k: halo pixel k lies in the image (else it counts as 0)
+};
+__device__ __forceinline__ void in_issue(InHalo& h, const float* __restrict__ mu, Tile t, int n)
 {
-    __shared__ u32x4 stage[ROW_STAGE_WORDS];
-    const long first = (long)blockIdx.x * blockDim.x;
-    const long idx = first + threadIdx.x;
-    u32x4 rows[4] = {};
-    if (idx < total) {
-        const int j = (int)(idx % n);
-        const long bi = idx / n;
-        const int i = (int)(bi % n);
-        const int b = (int)(bi / n);
-        uint32_t xb[10];
+    h.in = 0u;
 #pragma unroll
-        for (int ky = 0; ky < 3; ++ky)
-#pragma unroll
-            for (int kx = 0; kx < 3; ++kx) {
-                const int gi = i + ky - 1, gj = j + kx - 1;
-                xb[ky * 3 + kx] =
-                    (gi >= 0 && gi < n && gj >= 0 && gj < n) ? f2bf(mu[pix(b, gi, gj, n)] * inv_scale) : 0u;
-            }
-        xb[9] = 0u;
-        a0[idx] = (uint16_t)xb[4];  // the centre tap is this pixel
-        uint32_t xp[5];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) xp[q] = xb[2 * q] | (xb[2 * q + 1] << 16);
-        uint32_t pk[16];
-#pragma unroll
-        for (int o = 0; o < C; o += 2) {
-            float z0 = b1[o], z1 = b1[o + 1];
-#pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                z0 = dot2(w1p[o * 5 + q], xp[q], z0);
-                z1 = dot2(w1p[(o + 1) * 5 + q], xp[q], z1);
-            }
-            pk[o >> 1] = relu_bf2(pack_bf2(z0, z1));
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) rows[q] = u32x4{pk[4 * q], pk[4 * q + 1], pk[4 * q + 2], pk[4 * q + 3]};
+    for (int k = 0; k < 2; ++k) {
+        const int e = (int)threadIdx.x + 256 * k;
+        const int ly = e / HALO, lx = e - ly * HALO;
+        const int gi = t.i0 + ly - 1, gj = t.j0 + lx - 1;
+        const bool in = e < HALO * HALO && gi >= 0 && gi < n && gj >= 0 && gj < n;
+        h.in |= in ? 1u << k : 0u;
+        h.v[k] = mu[in ? pix(t.b, gi, gj, n) : 0];  // (masked where it is stored, so the load stays in flight)
     }
-    store_pixel_rows(stage, rows, a1, first, total);
+}
+__global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ mu, float inv_scale,
+                                                      const uint16_t* __restrict__ w1a, const float* __restrict__ b1,
+                                                      uint16_t* __restrict__ a0, uint16_t* __restrict__ a1, int n,
+                                                      int tiles_x, int tiles_per_img, int nblocks)
+{
+    __shared__ float xs[HALO][HALO + 1];                                 // bf(mu / scale) as float
+    __shared__ __attribute__((aligned(16))) uint16_t o[T * T * LDS_PIX];  // staged outputs, 80-byte pixel stride
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    // A operands: lane (m, g) holds W1[hh*16 + m][taps 8g .. 8g+7]
+    bf16x8 A[2];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) A[hh] = as_bf8(*(const u32x4*)(w1a + (hh * 16 + m) * C + g * 8));
+    f32x4 bias[2];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bias[hh][i] = b1[hh * 16 + 4 * g + i];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+        settle(A[hh]);
+        settle(bias[hh]);
+    }
+    InHalo h;
+    if ((int)blockIdx.x < nblocks) in_issue(h, mu, tile_of(blockIdx.x, nblocks, tiles_x, tiles_per_img), n);
+    for (int v = blockIdx.x; v < nblocks; v += gridDim.x) {
+        const Tile tl = tile_of(v, nblocks, tiles_x, tiles_per_img);
+        if (v != (int)blockIdx.x) __syncthreads();  // the previous tile's reads of xs and o are done
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int e = (int)threadIdx.x + 256 * k;
+            // lanes past the halo store into the spare column of row 0 instead of branching
+            float* dst = e < HALO * HALO ? &xs[e / HALO][e % HALO] : &xs[0][HALO];
+            *dst = (h.in >> k) & 1u ? bfround(h.v[k] * inv_scale) : 0.0f;
+        }
+        __syncthreads();
+        if (v + (int)gridDim.x < nblocks) in_issue(h, mu, tile_of(v + gridDim.x, nblocks, tiles_x, tiles_per_img), n);
+        {
+            // a0: this thread's pixel of the tile (the halo centre)
+            const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+            const int i = tl.i0 + ty, j = tl.j0 + tx;
+            if (i < n && j < n) a0[pix(tl.b, i, j, n)] = (uint16_t)f2bf(xs[ty + 1][tx + 1]);
+        }
+        // tile rows r = wave, wave + 4, ...: B operand of pixel (r, m)
+#pragma unroll
+        for (int k = 0; k < T / 4; ++k) {
+            const int r = wave + 4 * k;
+            uint32_t bw[4] = {0u, 0u, 0u, 0u};
+            if (g == 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int t0 = 2 * q, t1 = 2 * q + 1;
+                    bw[q] = pack_bf2(xs[r + t0 / 3][m + t0 % 3], xs[r + t1 / 3][m + t1 % 3]);
+                }
+            } else if (g == 1) {
+                bw[0] = pack_bf2(xs[r + 2][m + 2], 0.0f);
+            }
+            const bf16x8 B = as_bf8(u32x4{bw[0], bw[1], bw[2], bw[3]});
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const f32x4 d = mfma(A[hh], B, bias[hh]);
+                // D[4g + i][m]: channel hh*16 + 4g + i of pixel (r, m)
+                *(u32x2*)(o + (r * T + m) * LDS_PIX + hh * 16 + 4 * g) =
+                    u32x2{relu_bf2(pack_bf2(d[0], d[1])), relu_bf2(pack_bf2(d[2], d[3]))};
+            }
+        }
+        __syncthreads();
+        // out: wave w writes rows 4w .. 4w+3, one contiguous 1 KB row per instruction
+        const int px = lane >> 2, c4 = lane & 3;
+        const int gj = tl.j0 + px;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int r = wave * 4 + k, gi = tl.i0 + r;
+            if (gi < n && gj < n)
+                *(u32x4*)(a1 + pix(tl.b, gi, gj, n) * C + c4 * 8) = *(const u32x4*)(o + (r * T + px) * LDS_PIX + c4 * 8);
+        }
+    }
 }
 
 // Matrix products of one 16x16 output tile of the 32 -> 32 convolution from its
@@ -401,6 +464,8 @@ __device__ __forceinline__ void conv32_body(const uint16_t* __restrict__ in, con
     bf16x8 A[9];
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) A[tap] = as_bf8(*(const u32x4*)(wts + ((tap * C) + hh * 16 + m) * C + g * 8));
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) settle(A[tap]);
     HaloRegs<256> h;
     if ((int)blockIdx.x < nblocks) halo_issue<256>(h, in, tile_of(blockIdx.x, nblocks, tiles_x, tiles_per_img), n);
     for (int v = blockIdx.x; v < nblocks; v += gridDim.x) {
@@ -431,72 +496,80 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
 
 // Layer 8 (32 -> 1): z = b8 + sum_tap sum_c w8 a7, y = x + z with x = mu / scale
 // (float32).  mu_out (optional) = mu + scale * z, projected onto the
-// constraints when asked.  Taps in order (0,0), (0,1), ..., (2,2), channels as
-// the bf16 pairs (0,1), ..., (30,31) with one dot-product instruction each
-// (w8p: packed pairs from prep_weights_kernel, read as uniform loads, so they
-// come through the scalar cache into scalar registers).  128 threads per 16x16
-// tile, each two vertically adjacent pixels, which share two of their three
-// rows of staged inputs.
-constexpr int OUT_THREADS = 128;
-constexpr int OUT_GRID = 256 * 6;  // blocks resident at once (6 per CU by LDS), a multiple of 8
+// constraints when asked.  On the matrix cores: for every pixel p of a tile's
+// 18x18 halo, D[tap][p] = sum_c W8[c][tap] a7[p][c] (a 16 x 16 x 32 product per
+// 16 halo pixels, rows = the 9 taps and 7 zero rows, operands straight from
+// memory: lane (m, g) loads channels 8g .. 8g+7 of halo pixel m), the 9 x 324
+// tap sums go to LDS, and each output pixel adds its 9 neighbours' sums in tap
+// order (0,0), (0,1), ..., (2,2).  Persistent over the XCD-aware tile order, the
+// next tile's operand loads in flight while the current tile is finished.
+constexpr int OUT_THREADS = 256;
+constexpr int OUT_GRID = 256 * 4;                             // blocks resident at once, a multiple of 8
+constexpr int OUT_GROUPS = (HALO * HALO + 15) / 16;           // 16-pixel groups of the halo (21)
+constexpr int OUT_PER_WAVE = (OUT_GROUPS + 3) / 4;            // groups per wave (6)
+__device__ __forceinline__ void out_issue(u32x4 (&b)[OUT_PER_WAVE], const uint16_t* __restrict__ a7, Tile t, int n,
+                                          int wave, int m, int g)
+{
+#pragma unroll
+    for (int k = 0; k < OUT_PER_WAVE; ++k) {
+        const int p = 16 * (wave + 4 * k) + m;  // halo pixel of this lane in group wave + 4k
+        const int ly = p / HALO, lx = p - ly * HALO;
+        const int gi = t.i0 + ly - 1, gj = t.j0 + lx - 1;
+        const bool in = p < HALO * HALO && gi >= 0 && gi < n && gj >= 0 && gj < n;
+        const u32x4 v = *(const u32x4*)(a7 + (in ? pix(t.b, gi, gj, n) * C + g * 8 : 0));
+        b[k] = in ? v : u32x4{0u, 0u, 0u, 0u};
+    }
+}
 __global__ __launch_bounds__(OUT_THREADS) void conv_out_kernel(const uint16_t* __restrict__ a7,
-                                                               const uint32_t* __restrict__ w8p,
+                                                               const uint16_t* __restrict__ w8a,
                                                                const float* __restrict__ b8,
                                                                const float* __restrict__ mu, float inv_scale,
                                                                float scale, float* __restrict__ y,
                                                                float* __restrict__ mu_out, int project, int n,
                                                                int tiles_x, int tiles_per_img, int nblocks)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t s[HALO][HALO][LDS_PIX];
-    // persistent: tiles blockIdx.x, blockIdx.x + gridDim.x, ... of the XCD-aware order, the next
-    // tile's halo loads in flight while the current tile is computed
-    HaloRegs<OUT_THREADS> h;
-    if ((int)blockIdx.x < nblocks)
-        halo_issue<OUT_THREADS>(h, a7, tile_of(blockIdx.x, nblocks, tiles_x, tiles_per_img), n);
-    const int ty = (threadIdx.x >> 4) * 2, tx = threadIdx.x & 15;
+    __shared__ float dt[HALO * HALO][9];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    // A operand: lane (m, g) holds W8[8g .. 8g+7][tap m] (zero rows past tap 8)
+    const bf16x8 A = as_bf8(*(const u32x4*)(w8a + m * C + g * 8));
+    const float bias = b8[0];
+    settle(A);
+    settle(bias);
+    u32x4 bq[OUT_PER_WAVE];
+    if ((int)blockIdx.x < nblocks) out_issue(bq, a7, tile_of(blockIdx.x, nblocks, tiles_x, tiles_per_img), n, wave, m, g);
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     for (int v = blockIdx.x; v < nblocks; v += gridDim.x) {
         const Tile tl = tile_of(v, nblocks, tiles_x, tiles_per_img);
-        if (v != (int)blockIdx.x) __syncthreads();  // the previous tile's reads of s are done
-        halo_store<OUT_THREADS>(s, h);
+        f32x4 d[OUT_PER_WAVE];
+#pragma unroll
+        for (int k = 0; k < OUT_PER_WAVE; ++k) d[k] = mfma(A, as_bf8(bq[k]), f32x4{0.0f, 0.0f, 0.0f, 0.0f});
+        if (v != (int)blockIdx.x) __syncthreads();  // the previous tile's reads of dt are done
+        // D[4g + i][m]: tap 4g + i of halo pixel 16 (wave + 4k) + m
+#pragma unroll
+        for (int k = 0; k < OUT_PER_WAVE; ++k) {
+            const int p = 16 * (wave + 4 * k) + m;
+            if (p < HALO * HALO && g < 3) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (4 * g + i < 9) dt[p][4 * g + i] = d[k][i];
+            }
+        }
         __syncthreads();
         if (v + (int)gridDim.x < nblocks)
-            halo_issue<OUT_THREADS>(h, a7, tile_of(v + gridDim.x, nblocks, tiles_x, tiles_per_img), n);
-        float z[2] = {b8[0], b8[0]};
-        // staged row ty + R serves pixel 0 with ky = R (R <= 2) and pixel 1 with ky = R - 1 (R >= 1)
-#pragma unroll 1
-        for (int R = 0; R < 4; ++R)
+            out_issue(bq, a7, tile_of(v + gridDim.x, nblocks, tiles_x, tiles_per_img), n, wave, m, g);
+        const int i = tl.i0 + ty, j = tl.j0 + tx;
+        if (i < n && j < n) {
+            float z = bias;
 #pragma unroll
-            for (int kx = 0; kx < 3; ++kx) {
-                const u32x4* src = (const u32x4*)(&s[ty + R][tx + kx][0]);
-                u32x4 a[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) a[q] = src[q];
-#pragma unroll
-                for (int px = 0; px < 2; ++px) {
-                    const int ky = R - px;
-                    if (ky < 0 || ky > 2) continue;
-                    const u32x4* wv = (const u32x4*)(w8p + (ky * 3 + kx) * (C / 2));
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const u32x4 w = wv[q];
-                        z[px] = dot2(w.x, a[q].x, z[px]);
-                        z[px] = dot2(w.y, a[q].y, z[px]);
-                        z[px] = dot2(w.z, a[q].z, z[px]);
-                        z[px] = dot2(w.w, a[q].w, z[px]);
-                    }
-                }
-            }
-#pragma unroll
-        for (int px = 0; px < 2; ++px) {
-            const int i = tl.i0 + ty + px, j = tl.j0 + tx;
-            if (i >= n || j >= n) continue;
+            for (int tap = 0; tap < 9; ++tap) z += dt[(ty + tap / 3) * HALO + tx + tap % 3][tap];
             const size_t p = pix(tl.b, i, j, n);
             const float xin = mu[p];
-            if (y) y[p] = fmaf(xin, inv_scale, z[px]);
+            if (y) y[p] = fmaf(xin, inv_scale, z);
             if (mu_out) {
                 // mu + scale * z = scale * y, formed so that z = 0 returns mu exactly
-                const float m = fmaf(scale, z[px], xin);
-                mu_out[p] = project ? (in_disc(j, i, n) ? fmaxf(m, 0.0f) : 0.0f) : m;
+                const float mo = fmaf(scale, z, xin);
+                mu_out[p] = project ? (in_disc(j, i, n) ? fmaxf(mo, 0.0f) : 0.0f) : mo;
             }
         }
     }
@@ -945,9 +1018,9 @@ struct recon_cnn {
     float* d_grad = nullptr;
     uint16_t* d_wf = nullptr;  // [6][9][32][32]
     uint16_t* d_wt = nullptr;  // [6][9][32][32]
-    uint32_t* d_w1p = nullptr;  // [32][5] bf16 pairs of taps
+    uint16_t* d_w1a = nullptr;  // [32][32] bf16: the first layer's matrix-core operand
     float* d_w8r = nullptr;     // [32][9]
-    uint32_t* d_w8p = nullptr;  // [9][16] bf16 pairs of channels
+    uint16_t* d_w8a = nullptr;  // [16][32] bf16: the last layer's matrix-core operand
     uint16_t* d_a0 = nullptr;  // [B][n][n]
     uint16_t* d_act[8] = {};   // 1..7: [B][n][n][32]
     uint16_t* d_g[8] = {};     // 1..7: [B][n][n][32]
@@ -980,7 +1053,7 @@ Shape shape_of(int batch, int n)
 void free_cnn(recon_cnn* c)
 {
     if (!c) return;
-    void* ptrs[] = {c->d_theta, c->d_m, c->d_v, c->d_grad, c->d_wf, c->d_wt, c->d_w1p, c->d_w8r, c->d_w8p,
+    void* ptrs[] = {c->d_theta, c->d_m, c->d_v, c->d_grad, c->d_wf, c->d_wt, c->d_w1a, c->d_w8r, c->d_w8a,
                     c->d_a0, c->d_y, c->d_g8, c->d_part, c->d_part2, c->d_loss_part};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -993,8 +1066,8 @@ void free_cnn(recon_cnn* c)
 
 hipError_t launch_prep(recon_cnn* c, hipStream_t s)
 {
-    prep_weights_kernel<<<cdiv(PREP_END, 256), 256, 0, s>>>(c->d_theta, c->d_wf, c->d_wt, c->d_w8r, c->d_w1p,
-                                                           c->d_w8p);
+    prep_weights_kernel<<<cdiv(PREP_END, 256), 256, 0, s>>>(c->d_theta, c->d_wf, c->d_wt, c->d_w8r, c->d_w1a,
+                                                           c->d_w8a);
     return hipGetLastError();
 }
 
@@ -1017,15 +1090,15 @@ hipError_t launch_conv32(int mode, const uint16_t* in, const uint16_t* w, const 
 hipError_t enqueue_forward(recon_cnn* c, const float* mu, float* mu_out, int project, const Shape& S, hipStream_t s)
 {
     const float inv = 1.0f / c->mu_scale;
-    conv_in_kernel<<<cdiv(S.pixels, 256), 256, 0, s>>>(mu, inv, c->d_w1p, c->d_theta + OFF_B1, c->d_a0, c->d_act[1],
-                                                        S.n, S.pixels);
+    conv_in_kernel<<<std::min(S.ntiles, IN_GRID), 256, 0, s>>>(mu, inv, c->d_w1a, c->d_theta + OFF_B1, c->d_a0,
+                                                               c->d_act[1], S.n, S.tiles_x, S.tiles_per_img, S.ntiles);
     hipError_t e = hipGetLastError();
     for (int l = 2; l <= 7 && e == hipSuccess; ++l)
         e = launch_conv32(0, c->d_act[l - 1], c->d_wf + (size_t)(l - 2) * W32,
                           c->d_theta + OFF_HID + (l - 2) * P32 + W32, nullptr, c->d_act[l], S, s);
     if (e != hipSuccess) return e;
     conv_out_kernel<<<std::min(S.ntiles, OUT_GRID), OUT_THREADS, 0, s>>>(
-        c->d_act[7], c->d_w8p, c->d_theta + OFF_B8, mu, inv, c->mu_scale, c->d_y, mu_out, project, S.n, S.tiles_x,
+        c->d_act[7], c->d_w8a, c->d_theta + OFF_B8, mu, inv, c->mu_scale, c->d_y, mu_out, project, S.n, S.tiles_x,
         S.tiles_per_img, S.ntiles);
     return hipGetLastError();
 }
@@ -1137,9 +1210,9 @@ recon_status recon_cnn_create(const float* h_params, int32_t max_batch, int32_t 
     C_TRY(hipMalloc(&c->d_grad, NPARAM * sizeof(float)));
     C_TRY(hipMalloc(&c->d_wf, NHID * W32 * sizeof(uint16_t)));
     C_TRY(hipMalloc(&c->d_wt, NHID * W32 * sizeof(uint16_t)));
-    C_TRY(hipMalloc(&c->d_w1p, C * 5 * sizeof(uint32_t)));
+    C_TRY(hipMalloc(&c->d_w1a, C * C * sizeof(uint16_t)));
     C_TRY(hipMalloc(&c->d_w8r, 288 * sizeof(float)));
-    C_TRY(hipMalloc(&c->d_w8p, 9 * (C / 2) * sizeof(uint32_t)));
+    C_TRY(hipMalloc(&c->d_w8a, 16 * C * sizeof(uint16_t)));
     C_TRY(hipMalloc(&c->d_a0, px * sizeof(uint16_t)));
     for (int l = 1; l <= 7; ++l) {
         C_TRY(hipMalloc(&c->d_act[l], px * C * sizeof(uint16_t)));
