@@ -594,7 +594,7 @@ def warm_leg(n_slices: int, weights: str, dev):
     conv = runs[500]
     curve = {k: float(np.mean(ws.disc_rmse(runs[k], conv, 512)) / ph.MU_WATER_PER_MM) for k in iters}
     del runs
-    net = recon.Cnn(None, max_batch=8, max_n=512, mu_scale=ph.MU_WATER_PER_MM)
+    net = recon.Cnn(None, max_batch=n_slices, max_n=512, mu_scale=ph.MU_WATER_PER_MM)  # one pass per batch
     net.load(weights)
     B = recon.Batch([g for g, _, _ in items], 20, 1e-3)
     cts = [torch.from_numpy(c).to(dev) for c in counts]

@@ -290,7 +290,7 @@ recon_status for_groups(const recon_batch_handle* b, F&& f)
 // Start of a run of every slice: counts, start image, fresh step-rule state
 // (one launch per group of slices).
 recon_status prepare(recon_batch_handle* b, const float* const* d_counts, const float* i0, float* const* d_imgs,
-                     double* const* d_traces, hipStream_t s)
+                     double* const* d_traces, hipStream_t s, bool counts_ready = false)
 {
     for (size_t i = 0; i < b->h.size(); ++i)
         if (!d_counts[i] || !d_imgs[i] || !(i0[i] > 0) || !std::isfinite(i0[i]))
@@ -303,7 +303,7 @@ recon_status prepare(recon_batch_handle* b, const float* const* d_counts, const 
             a.trace[k] = d_traces ? d_traces[a.first + k] : nullptr;
             a.i0[k] = i0[a.first + k];
         }
-        RECON_HIP_TRY(launch_prepare_batch(b->d_slices, a, fresh, s));
+        RECON_HIP_TRY(launch_prepare_batch(b->d_slices, a, fresh, !counts_ready, s));
         return RECON_OK;
     });
 }
@@ -334,8 +334,9 @@ recon_status stage_copy(const recon_batch_handle* b, float* const* d_imgs, float
     return RECON_OK;
 }
 
+// counts_ready: the slices' y/I0 and p were prepared from these same counts by the previous run.
 recon_status batch_run(recon_batch_handle* b, const float* const* d_counts, const float* i0, float* const* d_imgs,
-                       int n_iter, double* const* d_traces, hipStream_t s, bool new_graphs);
+                       int n_iter, double* const* d_traces, hipStream_t s, bool new_graphs, bool counts_ready = false);
 
 }  // namespace
 
@@ -492,11 +493,11 @@ namespace {
 // graphs the batch has already instantiated and launches the rest directly
 // (same kernels, same bits).
 recon_status batch_run(recon_batch_handle* b, const float* const* d_counts, const float* i0, float* const* d_imgs,
-                       int n_iter, double* const* d_traces, hipStream_t s, bool new_graphs)
+                       int n_iter, double* const* d_traces, hipStream_t s, bool new_graphs, bool counts_ready)
 {
     if (!b || !d_counts || !i0 || !d_imgs) return fail(RECON_INVALID_ARG, "NULL argument");
     if (n_iter < 0) return fail(RECON_INVALID_ARG, "n_iter must be >= 0");
-    recon_status st = prepare(b, d_counts, i0, d_imgs, d_traces, s);
+    recon_status st = prepare(b, d_counts, i0, d_imgs, d_traces, s, counts_ready);
     if (st != RECON_OK) return st;
     int in = 0, n = 0;
     while (n < n_iter) {
@@ -694,7 +695,9 @@ recon_status warm_start_impl(recon_batch_handle* b, recon_cnn* net, const float*
         }
     }
     // 3. refinement by the plain iteration, fresh step-rule state
-    if (e == hipSuccess && st == RECON_OK) st = batch_run(b, d_counts, i0, d_imgs, n_refine, nullptr, s, !noalloc);
+    // (the same counts as step 1: their y/I0 and p are still in place)
+    if (e == hipSuccess && st == RECON_OK)
+        st = batch_run(b, d_counts, i0, d_imgs, n_refine, nullptr, s, !noalloc, /*counts_ready=*/true);
     // 4. residual and its noise level, every slice at once from the final iterate, over every
     //    view or every check_stride-th subset (fresh projections: the refining sub-iterations'
     //    own squared differences lag the still-moving iterate and would not be comparable with

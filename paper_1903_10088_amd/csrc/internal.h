@@ -258,7 +258,8 @@ static_assert(sizeof(BatchRunArgs) + sizeof(DevState) + 64 <= 4096, "batched lay
 static_assert(sizeof(BatchCopyArgs) + 64 <= 4096, "batched copy arguments too large");
 // Start of a batched run: counts -> yt, p; start image -> padded copies
 // (masked to the disc); state[0] = fresh with the slice's trace and it = 0.
-hipError_t launch_prepare_batch(const SliceDesc* slices, const BatchRunArgs& a, const DevState& fresh, hipStream_t s);
+hipError_t launch_prepare_batch(const SliceDesc* slices, const BatchRunArgs& a, const DevState& fresh, bool counts,
+                                hipStream_t s);
 // img[k] = the unpadded image buffer `in` of slice first + k.
 hipError_t launch_unpad_batch(const SliceDesc* slices, const BatchRunArgs& a, int in, hipStream_t s);
 // img[k] = the homogeneous start image (mu0[k] in the disc, 0 outside).

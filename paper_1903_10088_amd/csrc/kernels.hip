@@ -112,8 +112,10 @@ __global__ __launch_bounds__(256) void prep_counts_kernel(const float* __restric
 // Start of a run of every slice in the group: blocks [0, count_blocks) prepare
 // the counts (block 0 also writes the fresh step-rule state), the rest pad the
 // start image (masked to the disc) in 32x32 tiles.
+// count_blocks = 1 with counts = false: the slices' y/I0 and p are already
+// prepared from these counts (only the state and the images are reset).
 __global__ __launch_bounds__(256) void prepare_batch_kernel(const SliceDesc* __restrict__ slices, BatchRunArgs a,
-                                                            DevState fresh, int count_blocks)
+                                                            DevState fresh, int count_blocks, int counts)
 {
     __shared__ float tile[32][33];
     const int y = blockIdx.y;
@@ -121,7 +123,7 @@ __global__ __launch_bounds__(256) void prepare_batch_kernel(const SliceDesc* __r
     const Geo G = D->geo;
     if ((int)blockIdx.x < count_blocks) {
         const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;
-        if (r < (long)G.nv * G.nch) prep_count(a.counts[y], D->views, G.nch, a.i0[y], D->yt, D->p, r);
+        if (counts && r < (long)G.nv * G.nch) prep_count(a.counts[y], D->views, G.nch, a.i0[y], D->yt, D->p, r);
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             fresh.trace = a.trace[y];
             fresh.it = 0;
@@ -707,12 +709,13 @@ hipError_t launch_prep_counts(const float* counts, const ViewRec* views, int nv,
     return hipGetLastError();
 }
 
-hipError_t launch_prepare_batch(const SliceDesc* slices, const BatchRunArgs& a, const DevState& fresh, hipStream_t s)
+hipError_t launch_prepare_batch(const SliceDesc* slices, const BatchRunArgs& a, const DevState& fresh, bool counts,
+                                hipStream_t s)
 {
     if (a.count < 1 || a.count > BATCH_ARGS) return hipErrorInvalidValue;
-    const unsigned count_blocks = cdiv(a.max_rays, 256), tiles = cdiv(a.max_n, 32);
+    const unsigned count_blocks = counts ? cdiv(a.max_rays, 256) : 1, tiles = cdiv(a.max_n, 32);
     prepare_batch_kernel<<<dim3(count_blocks + tiles * tiles, a.count), 256, 0, s>>>(slices, a, fresh,
-                                                                                     (int)count_blocks);
+                                                                                     (int)count_blocks, counts ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -143,7 +143,8 @@ def cmd_eval(args):
     curve = {k: float(np.mean(ws.disc_rmse(runs[k], conv, 512)) / MU_W) for k in iters}
     ws.log(f"eval: plain RMSE-to-converged curve {curve}")
     del runs
-    net = recon.Cnn(None, max_batch=8, max_n=512, mu_scale=MU_W)
+    # inference only: one network pass covers a whole batch of the study
+    net = recon.Cnn(None, max_batch=args.chunk, max_n=512, mu_scale=MU_W)
     net.load(args.weights)
     res = dict(slices=len(items), n_pre=args.n_pre, n_refine=args.n_refine, n_cold=n_cold, residual_ratio_limit=lim,
                check_stride=stride, plain_curve=curve, batches=[])
@@ -237,7 +238,7 @@ def main():
     t.add_argument("--max-epochs", type=int, default=60)
     t.add_argument("--calibrate", type=int, default=128)
     t.add_argument("--n-refine", type=int, default=5, help="refining sub-iterations the limit is calibrated for")
-    t.add_argument("--check-stride", type=int, default=4, help="the check uses every k-th subset's rays")
+    t.add_argument("--check-stride", type=int, default=10, help="the check uses every k-th subset's rays")
     t.add_argument("--chunk", type=int, default=64)
     t.add_argument("--workers", type=int, default=12)
     t.add_argument("--seed", type=int, default=0)
@@ -246,7 +247,7 @@ def main():
     c.add_argument("--train-json", required=True)
     c.add_argument("--calibrate", type=int, default=128)
     c.add_argument("--n-refine", type=int, default=5)
-    c.add_argument("--check-stride", type=int, default=4, help="the check uses every k-th subset's rays")
+    c.add_argument("--check-stride", type=int, default=10, help="the check uses every k-th subset's rays")
     c.add_argument("--weights", default=None, help="default: the record's weights file beside it")
     c.add_argument("--workers", type=int, default=12)
     e = sp.add_parser("eval")
