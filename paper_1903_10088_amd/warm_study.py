@@ -14,11 +14,13 @@ eval: 256 full-study slices (512^2, views U{600..900}, 738 channels, I0
 log-uniform in [1e3, 1e4]; seeds 20000+): each slice's converged image (500
 sub-iterations), the plain method's RMSE to it after n sub-iterations, and the
 warm-start pipeline (10 + network + the record's refining sub-iterations, cold
-fallback) timed in batches, with per-slice latency: a slice that passes the
-data-consistency check is done when its batch's check is (the same pipeline with
-no fallback, timed), a fallback slice when its batch's cold starts are.  The
-network's own evaluation setting, 40 refining sub-iterations, is timed the same
-way against the plain method at its equal-RMSE count.  Writes DIR/eval.json.
+fallback) timed as a stream of batches of 32 run back to back, with per-slice
+latency: a slice that passes the data-consistency check is done when its
+batch's check is (the same pipeline with no fallback, timed), a fallback slice
+when its batch's cold starts are.  The plain method at the equal-RMSE count is
+timed as the same stream.  The network's own evaluation setting, 40 refining
+sub-iterations, is timed the same way against the plain method at its
+equal-RMSE count.  Writes DIR/eval.json.
 """
 from __future__ import annotations
 
@@ -149,69 +151,62 @@ def cmd_eval(args):
     res = dict(slices=len(items), n_pre=args.n_pre, n_refine=args.n_refine, n_cold=n_cold, residual_ratio_limit=lim,
                check_stride=stride, plain_curve=curve, batches=[])
     warm_imgs = torch.empty_like(conv)
-    lat, fb_all, r_all = [], [], []
-    t_total = 0.0
+    # every batch is set up before any timing, so that the timed passes run the batches back to back
+    # as a stream (ws.stream_times): both methods are timed under the same sustained load
+    batches = []
     for c0 in range(0, len(items), args.chunk):
         sub = items[c0:c0 + args.chunk]
         B = recon.Batch([g for g, _, _ in sub], 20, 1e-3)
         cts = [torch.from_numpy(c).to(dev) for c in counts[c0:c0 + args.chunk]]
         i0s = [i0 for _, _, i0 in sub]
         imgs = [warm_imgs[c0 + i] for i in range(len(sub))]
-        B.warm_start(net, cts, i0s, imgs, args.n_pre, args.n_refine, n_cold, lim, check_stride=stride)  # warm-up
-        # the batch up to its data-consistency check (no slice falls back), then the pipeline
-        _, dt_check = ws.timed(lambda: B.warm_start(net, cts, i0s, imgs, args.n_pre, args.n_refine, n_cold, 1e30,
-                                                    check_stride=stride))
-        (_, rr, fl, fb), dt = ws.timed(lambda: B.warm_start(net, cts, i0s, imgs, args.n_pre, args.n_refine,
-                                                            n_cold, lim, check_stride=stride))
-        t_total += dt
+        batches.append((c0, B, cts, i0s, imgs))
+
+    def pipelines(n_refine, limit, n_cold_run, check_stride):
+        return [lambda b=b: b[1].warm_start(net, b[2], b[3], b[4], args.n_pre, n_refine, n_cold_run, limit,
+                                            check_stride=check_stride) for b in batches]
+
+    # the batches up to their data-consistency check (no slice falls back), then the pipeline
+    _, dts_check = ws.stream_times(pipelines(args.n_refine, 1e30, n_cold, stride))
+    outs, dts = ws.stream_times(pipelines(args.n_refine, lim, n_cold, stride))
+    lat, fb_all, r_all = [], [], []
+    t_total = float(sum(dts))
+    for (c0, _, cts, _, _), (_, rr, fl, fb), dt, dt_check in zip(batches, outs, dts, dts_check):
         lat += [dt if f else min(dt, dt_check) for f in fb]
         fb_all += list(map(int, fb))
         r_all += list((rr / fl).tolist())
-        res["batches"].append(dict(first=c0, slices=len(sub), seconds=dt, seconds_to_check=dt_check,
+        res["batches"].append(dict(first=c0, slices=len(cts), seconds=dt, seconds_to_check=dt_check,
                                    fallbacks=int(fb.sum())))
-        B.close()
-        ws.log(f"eval: warm batch {c0}: {dt:.3f} s ({dt_check:.3f} s to the check), {int(fb.sum())} fallbacks")
+        ws.log(f"eval: warm batch {c0}: {dt:.4f} s ({dt_check:.4f} s to the check), {int(fb.sum())} fallbacks")
     r_warm = ws.disc_rmse(warm_imgs, conv, 512) / MU_W
     rmse_w = float(np.mean(r_warm))
     # the network's evaluation setting (40 refining sub-iterations, no fallback): RMSE to converged
-    # and data residual against the plain method, every slice
-    r40, t40 = [], 0.0
-    for c0 in range(0, len(items), args.chunk):
-        sub = items[c0:c0 + args.chunk]
-        B = recon.Batch([g for g, _, _ in sub], 20, 1e-3)
-        cts = [torch.from_numpy(c).to(dev) for c in counts[c0:c0 + args.chunk]]
-        i0s = [i0 for _, _, i0 in sub]
-        imgs = [warm_imgs[c0 + i] for i in range(len(sub))]
-        B.warm_start(net, cts, i0s, imgs, args.n_pre, 40, args.n_final, 1e30)  # warm-up
-        (_, rr, fl, _), dt = ws.timed(lambda: B.warm_start(net, cts, i0s, imgs, args.n_pre, 40, args.n_final, 1e30))
-        t40 += dt
-        r40 += list((rr / fl).tolist())
-        B.close()
+    # and data residual (over every view) against the plain method, every slice
+    outs40, dts40 = ws.stream_times(pipelines(40, 1e30, args.n_final, 1))
+    t40 = float(sum(dts40))
+    r40 = [x for (_, rr, fl, _) in outs40 for x in (rr / fl).tolist()]
     rmse40 = float(np.mean(ws.disc_rmse(warm_imgs, conv, 512) / MU_W))
     n_eq40 = ws.equal_rmse_count(curve, rmse40, args.n_final)
     res_refine40 = dict(n_refine=40, rmse_to_converged_over_muw=rmse40, plain_sub_iterations_at_equal_rmse=n_eq40,
                         slices_per_s=len(items) / t40,
                         residual_ratio=dict(median=float(np.median(r40)), max=float(np.max(r40))))
     n_eq = ws.equal_rmse_count(curve, rmse_w, args.n_final)
-    # plain batched throughput at n_eq sub-iterations (same batches, same timing)
+    # plain batched throughput at n_eq sub-iterations (same batches, same stream timing; each call
+    # starts from the homogeneous image)
+    plain_imgs = [b[1].initial_images(dev) for b in batches]
+
     def plain_time(n_iter):
-        t = 0.0
-        for c0 in range(0, len(items), args.chunk):
-            sub = items[c0:c0 + args.chunk]
-            B = recon.Batch([g for g, _, _ in sub], 20, 1e-3)
-            cts = [torch.from_numpy(c).to(dev) for c in counts[c0:c0 + args.chunk]]
-            i0s = [i0 for _, _, i0 in sub]
-            imgs = B.initial_images(dev)
-            B.run(cts, i0s, imgs, n_iter)
-            imgs = B.initial_images(dev)
-            _, dt = ws.timed(lambda: B.run(cts, i0s, imgs, n_iter))
-            t += dt
-            B.close()
-        return t
+        def run(b, imgs):
+            b[1].initial_images_into(imgs)
+            b[1].run(b[2], b[3], imgs, n_iter)
+        _, dts_p = ws.stream_times([lambda b=b, im=im: run(b, im) for b, im in zip(batches, plain_imgs)])
+        return float(sum(dts_p))
 
     t_plain = plain_time(n_eq)
     t_plain40 = plain_time(n_eq40)
     res_refine40.update(plain_slices_per_s_at_equal_rmse=len(items) / t_plain40, speedup=t_plain40 / t40)
+    for b in batches:
+        b[1].close()
     res.update(warm=dict(rmse_to_converged_over_muw=rmse_w, slices_per_s=len(items) / t_total,
                          latency_p50_s=float(np.percentile(lat, 50)), latency_p99_s=float(np.percentile(lat, 99)),
                          fallbacks=int(sum(fb_all)), residual_ratio=dict(median=float(np.median(r_all)),

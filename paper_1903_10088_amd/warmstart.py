@@ -250,3 +250,53 @@ def timed(fn):
     r = fn()
     torch.cuda.synchronize()
     return r, time.perf_counter() - t
+
+
+# The GPU runs a batch's first sub-iterations after an idle gap up to a quarter slower than under
+# sustained load (its clocks settle after some 40 ms of continuous work), so a short pipeline timed
+# after a gap pays a cost that a longer plain run mostly hides.  Throughput is timed as a stream: the
+# calls run back to back, after an untimed pass of at least STEADY_S seconds of the same calls.
+STEADY_S = 0.1
+
+
+def stream_times(fns, min_s: float = STEADY_S):
+    """Run the callables `fns` (one per batch) back to back as a stream and time each call.  An
+    untimed warm-up repeats the whole stream until it has lasted `min_s` seconds; the timed pass
+    follows without a gap.  Returns (results, seconds per call)."""
+    torch = _torch()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    while True:
+        for f in fns:
+            f()
+        torch.cuda.synchronize()
+        if time.perf_counter() - t >= min_s:
+            break
+    res, dts = [], []
+    for f in fns:
+        t = time.perf_counter()
+        res.append(f())
+        torch.cuda.synchronize()
+        dts.append(time.perf_counter() - t)
+    return res, dts
+
+
+def timed_steady(fn, min_s: float = STEADY_S):
+    """Seconds per call of `fn` under sustained load: `fn` is repeated until `min_s` seconds have
+    passed, then the same number of back-to-back calls is timed.  Returns (last result, seconds per
+    call)."""
+    torch = _torch()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    n = 0
+    while True:
+        fn()
+        n += 1
+        torch.cuda.synchronize()
+        if time.perf_counter() - t >= min_s:
+            break
+    t = time.perf_counter()
+    for _ in range(n):
+        r = fn()
+    torch.cuda.synchronize()
+    return r, (time.perf_counter() - t) / n
