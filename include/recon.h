@@ -281,9 +281,12 @@ recon_status recon_set_launch(recon_handle* h, int32_t fp_segments, int32_t bp_v
  * count M, beta and params.  One sub-iteration of every slice runs as one
  * projector launch, one step-rule launch (a block per slice) and one update
  * launch over work tables that cover all slices; each subset epoch is
- * replayed from a captured HIP graph.  Every
- * slice's result is bitwise equal to recon_os_iterate on that slice alone
- * (fresh state).
+ * replayed from a captured HIP graph.  The tables place each slice on one of
+ * the 8 XCDs (its image and tables then stay in one L2), balanced by cost;
+ * when whole slices cannot be balanced within 3 % (fewer slices than XCDs, a
+ * few large ones), the largest are cut into 2, 4 or 8 parts placed the same
+ * way.  Every slice's result is bitwise equal to recon_os_iterate on that
+ * slice alone (fresh state), whatever the placement.
  * ------------------------------------------------------------------------ */
 typedef struct recon_batch_handle recon_batch_handle;
 
@@ -316,9 +319,11 @@ recon_status recon_batch_tune(recon_batch_handle* b, const float* const* d_count
                               int32_t reps, int32_t* fp_segments_out, int32_t* bp_variant_out, void* stream);
 
 /* Pins the batch's launch shapes (as recon_set_launch; 0 keeps).  A new batch
- * starts with 4 threads per projector ray and bp_variant 6 (2x2 pixels per
- * thread, views split over a tile's waves), the tuner's choice for batches of
- * 512^2 slices. */
+ * starts with bp_variant 6 (2x2 pixels per thread, views split over a tile's
+ * waves) and 4 threads per projector ray, the tuner's choice for batches of
+ * 512^2 slices, doubled up to 16 while a subset's rays over the whole batch
+ * would give the GPU fewer than 2048 threads per compute unit (a batch of one
+ * or two 512^2 slices starts at 16). */
 recon_status recon_batch_set_launch(recon_batch_handle* b, int32_t fp_segments, int32_t bp_variant);
 
 /* Host-only check of the batched kernels' work tables (no GPU needed): builds,
@@ -326,8 +331,9 @@ recon_status recon_batch_set_launch(recon_batch_handle* b, int32_t fp_segments, 
  * upload (the update's 16x16 tiles, the projector's blocks of 256 / fp_segments
  * rays for every subset and for all views) and counts in *errors every tile or
  * ray block that is missing, repeated, out of range or placed on an XCD other
- * than its slice's (block p runs on XCD p mod 8); *blocks receives the total
- * table length.  RECON_INVALID_ARG as recon_batch_create, or for an
+ * than the one its slice, or its part of the slice, is placed on (block p runs
+ * on XCD p mod 8), and every slice cut into a number of parts other than 1, 2,
+ * 4 or 8; *blocks receives the total table length, idle entries included.  RECON_INVALID_ARG as recon_batch_create, or for an
  * fp_segments outside {1, 2, 4, 8, 16}. */
 recon_status recon_batch_check_work(const recon_geometry* geoms, int32_t n_slices, int32_t subsets,
                                     int32_t fp_segments, int64_t* errors, int64_t* blocks);
@@ -350,7 +356,7 @@ recon_status recon_batch(const recon_geometry* geoms, int32_t n_slices, int32_t 
  *   5. every slice with r > residual_ratio * v (the level the plain iteration
  *      reaches, calibrated on its own images with the same check_stride) is
  *      reconstructed again from the homogeneous start with n_cold
- *      sub-iterations (alone, or as a batch when there are many).
+ *      sub-iterations (alone when one slice falls back, else as a batch).
  * d_counts, d_imgs: host arrays of device pointers as in recon_batch_run
  * (d_imgs receive the results); i0: host array.  h_residual, h_floor (host
  * double[n_slices]) and h_fallback (host int32[n_slices], 1 = cold start used)

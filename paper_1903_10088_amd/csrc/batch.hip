@@ -7,7 +7,10 @@
 // (slice, 16x16 tile) for the update.  Slices are placed on XCDs (the
 // dispatcher hands block b to XCD b mod 8), so a slice's image, residuals and
 // ray tables stay in one XCD's L2; the per-XCD lists are balanced by cost and
-// interleaved, with idle blocks padding the shorter lists.
+// interleaved, with idle blocks padding the shorter lists.  When whole slices
+// cannot be balanced (fewer slices than XCDs, or a few large ones), the
+// largest are cut into 2, 4 or 8 parts (contiguous ranges of their tiles and
+// ray blocks), each part placed like a slice.
 //
 // Every slice's arithmetic is exactly that of recon_os_iterate on its own
 // handle (same device functions, same summation orders), so a batched slice
@@ -41,7 +44,7 @@ struct recon_batch_handle {
     // identical for every choice
     int fp_segments = BATCH_FP_SEGMENTS;
     int bp_variant = 5;
-    std::vector<int> xcd;  // XCD of each slice
+    std::vector<std::vector<int>> xcd;  // XCD of each part of each slice (1, 2, 4 or 8 parts)
 
     SliceDesc* d_slices = nullptr;
     int2* d_subs = nullptr;
@@ -101,23 +104,62 @@ std::vector<SliceShape> shapes_of(const recon_batch_handle* b)
     return sh;
 }
 
-// Greedy placement of slices on XCDs by cost (pixels x views per subset).
-std::vector<int> assign_xcds(const std::vector<SliceShape>& sh)
+// Placement of slices on XCDs.  A slice costs pixels x views per subset; it is
+// cut into k in {1, 2, 4, 8} equal parts, and the parts are placed greedily,
+// largest first, each on the least loaded XCD.  Starting from whole slices,
+// the slice with the largest part is cut in twice as many parts while the
+// busiest XCD carries more than SPLIT_TOLERANCE times the mean load (a batch
+// of one slice ends in 8 parts; batches of many similar slices stay whole).
+// Which block computes a tile or a ray block does not change its arithmetic,
+// so the placement never changes a result.
+constexpr double SPLIT_TOLERANCE = 1.03;
+
+std::vector<std::vector<int>> assign_xcds(const std::vector<SliceShape>& sh)
 {
     const int n = (int)sh.size();
-    std::vector<int> order(n), xcd(n, 0);
-    std::vector<double> cost(n), load(NXCD, 0.0);
+    std::vector<double> cost(n);
+    double total = 0.0;
     for (int i = 0; i < n; ++i) {
-        order[i] = i;
         cost[i] = (double)sh[i].n * sh[i].n * sh[i].max_subset_views;
+        total += cost[i];
     }
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
-    for (int i : order) {
-        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        xcd[i] = x;
-        load[x] += cost[i];
+    std::vector<int> k(n, 1);
+    std::vector<std::vector<int>> xcd(n);
+    for (;;) {
+        struct Part {
+            double c;
+            int slice, p;
+        };
+        std::vector<Part> parts;
+        for (int i = 0; i < n; ++i) {
+            xcd[i].assign(k[i], 0);
+            for (int p = 0; p < k[i]; ++p) parts.push_back(Part{cost[i] / k[i], i, p});
+        }
+        std::stable_sort(parts.begin(), parts.end(), [](const Part& a, const Part& c) { return a.c > c.c; });
+        std::vector<double> load(NXCD, 0.0);
+        for (const Part& q : parts) {
+            const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            xcd[q.slice][q.p] = x;
+            load[x] += q.c;
+        }
+        if (*std::max_element(load.begin(), load.end()) <= SPLIT_TOLERANCE * total / NXCD) break;
+        int j = -1;
+        for (int i = 0; i < n; ++i)
+            if (k[i] < NXCD && (j < 0 || cost[i] / k[i] > cost[j] / k[j])) j = i;
+        if (j < 0) break;
+        k[j] *= 2;
     }
     return xcd;
+}
+
+// Part of item t of a slice whose `count` items are cut into `parts` equal
+// contiguous ranges: the p with floor(p count / parts) <= t < floor((p+1) count / parts).
+int part_of(long t, long count, int parts)
+{
+    int p = (int)((t * parts) / count);
+    while (p + 1 < parts && (long)(p + 1) * count / parts <= t) ++p;
+    while (p > 0 && (long)p * count / parts > t) --p;
+    return p;
 }
 
 // Interleaves per-XCD lists so that block p runs on XCD p mod 8.
@@ -132,25 +174,32 @@ std::vector<W> interleave(const std::vector<std::vector<W>>& lists, const W& idl
     return out;
 }
 
-// Update work: every 16x16 tile of every slice, slice by slice within an XCD.
-std::vector<BpWork> bp_work_table(const std::vector<SliceShape>& sh, const std::vector<int>& xcd)
+// Update work: every 16x16 tile of every slice (row-major, each part's range
+// of tiles on that part's XCD), slice by slice within an XCD.
+std::vector<BpWork> bp_work_table(const std::vector<SliceShape>& sh, const std::vector<std::vector<int>>& xcd)
 {
     std::vector<std::vector<BpWork>> bl(NXCD);
     for (size_t i = 0; i < sh.size(); ++i) {
-        const int T = (sh[i].n + 15) / 16;
-        for (int ty = 0; ty < T; ++ty)
-            for (int tx = 0; tx < T; ++tx) bl[xcd[i]].push_back(BpWork{(int)i, tx * 16, ty * 16, 0});
+        const int T = (sh[i].n + 15) / 16, parts = (int)xcd[i].size();
+        const long nt = (long)T * T;
+        for (long t = 0; t < nt; ++t) {
+            const int ty = (int)(t / T), tx = (int)(t % T);
+            bl[xcd[i][part_of(t, nt, parts)]].push_back(BpWork{(int)i, tx * 16, ty * 16, 0});
+        }
     }
     return interleave(bl, BpWork{-1, 0, 0, 0});
 }
 
-// Projector work of subset s (-1: every view) in blocks of rpb rays.
-std::vector<FpWork> fp_work_table(const std::vector<SliceShape>& sh, const std::vector<int>& xcd, int s, int rpb)
+// Projector work of subset s (-1: every view) in blocks of rpb rays, each
+// part's range of ray blocks on that part's XCD.
+std::vector<FpWork> fp_work_table(const std::vector<SliceShape>& sh, const std::vector<std::vector<int>>& xcd, int s,
+                                  int rpb)
 {
     std::vector<std::vector<FpWork>> fl(NXCD);
     for (size_t i = 0; i < sh.size(); ++i) {
-        const int nrays = (s < 0 ? sh[i].nv : sh[i].subset_count[s]) * sh[i].nch;
-        for (int r0 = 0; r0 < nrays; r0 += rpb) fl[xcd[i]].push_back(FpWork{(int)i, r0});
+        const int nrays = (s < 0 ? sh[i].nv : sh[i].subset_count[s]) * sh[i].nch, parts = (int)xcd[i].size();
+        const long nb = (nrays + rpb - 1) / rpb;
+        for (long b = 0; b < nb; ++b) fl[xcd[i][part_of(b, nb, parts)]].push_back(FpWork{(int)i, (int)(b * rpb)});
     }
     return interleave(fl, FpWork{-1, 0});
 }
@@ -188,12 +237,25 @@ recon_status upload_work(recon_batch_handle* b)
     return RECON_OK;
 }
 
+// Default threads per projector ray: BATCH_FP_SEGMENTS, doubled (up to 16)
+// while a subset's rays over the whole batch, at that many threads each, would
+// not give every compute unit 2048 threads (a batch of one or two 512^2
+// slices gets 16, as a single slice does).
+int default_fp_segments(const recon_batch_handle* b)
+{
+    double rays = 0.0;  // rays of an average subset, all slices
+    for (const recon_handle* h : b->h) rays += (double)h->geo.nv * h->geo.nch / b->M;
+    int seg = BATCH_FP_SEGMENTS;
+    while (seg < 16 && rays * seg < 256.0 * 2048.0) seg *= 2;
+    return seg;
+}
+
 // Slice descriptors, subset tables, XCD placement and work tables of a batch
 // whose handles are in b->h; fp_segments 0 takes the batch default.
 recon_status setup_batch(recon_batch_handle* b, int fp_segments)
 {
     const int n_slices = (int)b->h.size(), subsets = b->M;
-    b->fp_segments = fp_segments > 0 ? fp_segments : BATCH_FP_SEGMENTS;
+    b->fp_segments = fp_segments > 0 ? fp_segments : default_fp_segments(b);
     b->xcd = assign_xcds(shapes_of(b));
     std::vector<int2> subs((size_t)n_slices * subsets);
     for (int i = 0; i < n_slices; ++i)
@@ -359,18 +421,31 @@ recon_status recon_batch_check_work(const recon_geometry* geoms, int32_t n_slice
         s.max_subset_views = *std::max_element(s.subset_count.begin(), s.subset_count.end());
         sh.push_back(s);
     }
-    const std::vector<int> xcd = assign_xcds(sh);
+    const std::vector<std::vector<int>> xcd = assign_xcds(sh);
     int64_t bad = 0, nblk = 0;
-    // every tile of every slice exactly once, each on its slice's XCD
+    for (int i = 0; i < n_slices; ++i) {
+        const size_t k = xcd[i].size();
+        if (k != 1 && k != 2 && k != 4 && k != 8) ++bad;
+        for (int x : xcd[i]) bad += x < 0 || x >= NXCD;
+    }
+    // every tile of every slice exactly once, each on the XCD of its part of the slice
     const std::vector<BpWork> bp = bp_work_table(sh, xcd);
     std::vector<std::vector<int>> seen(n_slices);
     for (int i = 0; i < n_slices; ++i) seen[i].assign((size_t)((sh[i].n + 15) / 16) * ((sh[i].n + 15) / 16), 0);
     for (size_t p = 0; p < bp.size(); ++p) {
         const BpWork& w = bp[p];
         if (w.slice < 0) continue;
+        if (w.slice >= n_slices) {
+            ++bad;
+            continue;
+        }
         const int T = (sh[w.slice].n + 15) / 16;
-        if (w.slice >= n_slices || w.ti0 % 16 || w.tj0 % 16 || w.ti0 / 16 >= T || w.tj0 / 16 >= T ||
-            xcd[w.slice] != (int)(p % NXCD)) {
+        if (w.ti0 % 16 || w.tj0 % 16 || w.ti0 / 16 >= T || w.tj0 / 16 >= T) {
+            ++bad;
+            continue;
+        }
+        const long t = (long)(w.tj0 / 16) * T + w.ti0 / 16;
+        if (xcd[w.slice][part_of(t, (long)T * T, (int)xcd[w.slice].size())] != (int)(p % NXCD)) {
             ++bad;
             continue;
         }
@@ -379,7 +454,7 @@ recon_status recon_batch_check_work(const recon_geometry* geoms, int32_t n_slice
     for (const auto& v : seen)
         for (int c : v) bad += c != 1;
     nblk += (int64_t)bp.size();
-    // every ray block of every subset (and of all views) exactly once, on its slice's XCD
+    // every ray block of every subset (and of all views) exactly once, on the XCD of its part of the slice
     const int rpb = fp_rays_per_block(fp_segments);
     for (int s = -1; s < subsets; ++s) {
         const std::vector<FpWork> fp = fp_work_table(sh, xcd, s, rpb);
@@ -390,8 +465,14 @@ recon_status recon_batch_check_work(const recon_geometry* geoms, int32_t n_slice
         for (size_t p = 0; p < fp.size(); ++p) {
             const FpWork& w = fp[p];
             if (w.slice < 0) continue;
+            if (w.slice >= n_slices) {
+                ++bad;
+                continue;
+            }
             const int nrays = (s < 0 ? sh[w.slice].nv : sh[w.slice].subset_count[s]) * sh[w.slice].nch;
-            if (w.slice >= n_slices || w.r0 % rpb || w.r0 >= nrays || xcd[w.slice] != (int)(p % NXCD)) {
+            const long nb = (nrays + rpb - 1) / rpb;
+            if (w.r0 % rpb || w.r0 >= nrays ||
+                xcd[w.slice][part_of(w.r0 / rpb, nb, (int)xcd[w.slice].size())] != (int)(p % NXCD)) {
                 ++bad;
                 continue;
             }
@@ -733,7 +814,7 @@ recon_status warm_start_impl(recon_batch_handle* b, recon_cnn* net, const float*
     if (fb.empty()) return RECON_OK;
     // A few slices (or any number, without allocation) run alone on their own
     // handles; many go through a batch over their handles.  Both give the same bits.
-    constexpr size_t kSubBatchMin = 8;
+    constexpr size_t kSubBatchMin = 2;  // one slice runs faster on its own handle; two or more as a batch
     if (noalloc || fb.size() < kSubBatchMin) {
         for (int i : fb) {
             st = recon_initial_image(b->h[i], d_imgs[i], s);
@@ -759,7 +840,7 @@ recon_status warm_start_impl(recon_batch_handle* b, recon_cnn* net, const float*
         i0_sub.push_back(i0[i]);
         img_sub.push_back(d_imgs[i]);
     }
-    st = setup_batch(sub, b->fp_segments);
+    st = setup_batch(sub, 0);
     if (st == RECON_OK) st = recon_batch_initial_images(sub, img_sub.data(), s);
     if (st == RECON_OK) st = recon_batch_run(sub, c_sub.data(), i0_sub.data(), img_sub.data(), n_cold, nullptr, s);
     hipError_t se = hipStreamSynchronize(s);

@@ -172,6 +172,21 @@ def test_bad_network_falls_back_through_the_check(dev, kind):
         assert torch.equal(imgs[k], cold)
 
 
+def test_one_fallback_runs_on_its_own_handle(dev):
+    """A batch of one slice sent to the cold start (a single fallback slice runs on its own handle,
+    not as a batch of one): the result is its plain cold reconstruction."""
+    from paper_1903_10088_amd import recon
+    geoms, slices = small_batch()
+    M, beta = 5, 1e-3
+    B = recon.Batch(geoms[1:2], M, beta)
+    net = recon.Cnn(None, max_batch=1, max_n=128, mu_scale=ph.MU_WATER_PER_MM)
+    counts = [torch.from_numpy(slices[1].counts).to(dev)]
+    imgs, _, _, fb = B.warm_start(net, counts, [slices[1].i0], None, 4, 6, 13, 1e-9)
+    assert fb.all()
+    cold, _ = recon.Recon(geoms[1], M, beta).os_iterate(counts[0], slices[1].i0, None, 13)
+    assert torch.equal(imgs[0], cold)
+
+
 def test_many_fallbacks_go_through_a_batch(dev):
     """Nine slices, all sent to the cold start (the batched cold-start path): each equals its own
     single-slice cold reconstruction."""

@@ -211,8 +211,8 @@ def test_partial_arc_tables_hold_every_ray():
 def test_batch_work_tables_cover_every_tile_and_ray_block():
     """The batched kernels' work tables (host-only check): for the 64-slice mixed batch of the bench
     and a batch of limited-angle and odd slices, every update tile and every projector ray block of
-    every subset (and of all views) appears exactly once, on its slice's XCD, for every projector
-    shape."""
+    every subset (and of all views) appears exactly once, on the XCD its slice (or its part of the
+    slice) is placed on, for every projector shape."""
     mixed = [ph.random_batch_geometry(1000 + i)[0] for i in range(64)]
     odd = [ph.Geometry(n=37, pixel_mm=10.0, n_views=33, n_channels=51, start_angle_rad=0.3),
            ph.Geometry(n=64, pixel_mm=6.25, n_views=40, n_channels=97, scan_arc_rad=2.5),
@@ -225,3 +225,35 @@ def test_batch_work_tables_cover_every_tile_and_ray_block():
         recon.batch_check_work(odd, 5, 3)
     with pytest.raises(recon.ReconError):
         recon.batch_check_work(odd, 34)  # more subsets than the 33-view slice has views
+
+
+def _work_items(geoms, M, seg):
+    """Tiles plus projector ray blocks (every subset and all views) of a batch: the table entries
+    that are not idle padding."""
+    rpb = 256 // seg
+    total = 0
+    for g in geoms:
+        total += ((g.n + 15) // 16) ** 2
+        cnt = [0] * M
+        for v in range(g.n_views):
+            cnt[v % M] += 1
+        total += sum(-(-c * g.n_channels // rpb) for c in cnt) + -(-g.n_views * g.n_channels // rpb)
+    return total
+
+
+def test_batch_work_tables_split_slices_over_xcds():
+    """Batches that whole slices cannot balance over the 8 XCDs (one slice, three, nine equal ones,
+    one large slice among small ones) have their largest slices cut into parts: the tables still
+    hold every tile and ray block once, each on its part's XCD, and the idle padding stays small
+    (a one-slice batch on one XCD would pad its tables to 8 times their work)."""
+    one = [ph.config1_geometry()]
+    three = [ph.config1_geometry(), ph.Geometry(n=256, pixel_mm=1.5625, n_views=700, n_channels=600),
+             ph.Geometry(n=384, pixel_mm=1.0, n_views=650, n_channels=700)]
+    nine = [ph.config1_geometry()] * 9
+    lopsided = [ph.config1_geometry()] + [ph.Geometry(n=128, pixel_mm=3.125, n_views=180, n_channels=192)] * 20
+    for geoms, M in ((one, 20), (three, 20), (nine, 20), (lopsided, 10)):
+        for seg in (1, 4, 16):
+            errors, blocks = recon.batch_check_work(geoms, M, seg)
+            items = _work_items(geoms, M, seg)
+            assert errors == 0, (len(geoms), M, seg)
+            assert items <= blocks <= 1.2 * items + 8 * (M + 2), (len(geoms), M, seg, blocks, items)
