@@ -140,13 +140,26 @@ __device__ __forceinline__ size_t pix(int b, int i, int j, int n) { return ((siz
 // a thread's loads (pixels outside the image load the tensor's first element
 // and keep a cleared bit in `in`), halo_store waits for them and writes LDS,
 // so a caller can keep the loads in flight while it works on another tile.
-constexpr int HALO_CHUNKS = HALO * HALO * 4;  // 16-byte chunks of the halo tile
+//
+// Chunk slot e (thread e mod NT, step e / NT) holds 16-byte part (e / 16) mod 4
+// of staged pixel 16 (e / 64) + e mod 16: the 16 lanes of a quarter-wave take
+// one part of 16 consecutive pixels, the pattern of the matrix-operand reads
+// (fewer LDS bank conflicts at the 80-byte pixel stride than four parts of four
+// pixels), while each wave instruction still covers 16 whole pixels of global
+// memory.
+constexpr int HALO_GROUPS = (HALO * HALO + 15) / 16;  // 16-pixel groups of the halo tile
 template <int NT>
 struct HaloRegs {
-    static constexpr int PER = (HALO_CHUNKS + NT - 1) / NT;  // chunks per thread
+    static constexpr int PER = (HALO_GROUPS * 64 + NT - 1) / NT;  // chunks per thread
     u32x4 v[PER];
     uint32_t in;  // bit k: chunk k lies in the image
 };
+template <int NT>
+__device__ __forceinline__ int halo_pixel(int tid, int k)
+{
+    const int e = tid + NT * k;
+    return 16 * (e >> 6) + (e & 15);
+}
 template <int NT>
 __device__ __forceinline__ void halo_issue(HaloRegs<NT>& h, const uint16_t* __restrict__ act, Tile t, int n)
 {
@@ -158,11 +171,10 @@ __device__ __forceinline__ void halo_issue(HaloRegs<NT>& h, const uint16_t* __re
     h.in = 0u;
 #pragma unroll
     for (int k = 0; k < HaloRegs<NT>::PER; ++k) {
-        const int e = tid + NT * k;
-        const int p = e >> 2, q = e & 3;
+        const int p = halo_pixel<NT>(tid, k), q = (tid >> 4) & 3;
         const int ly = p / HALO, lx = p - ly * HALO;
         const int gi = t.i0 + ly - 1, gj = t.j0 + lx - 1;
-        const bool in = e < HALO_CHUNKS && gi >= 0 && gi < n && gj >= 0 && gj < n;
+        const bool in = p < HALO * HALO && gi >= 0 && gi < n && gj >= 0 && gj < n;
         h.in |= in ? 1u << k : 0u;
         const size_t off = in ? pix(t.b, gi, gj, n) * C + q * 8 : 0;
         h.v[k] = *(const u32x4*)(act + off);
@@ -171,14 +183,15 @@ __device__ __forceinline__ void halo_issue(HaloRegs<NT>& h, const uint16_t* __re
 template <int NT>
 __device__ __forceinline__ void halo_store(uint16_t (*s)[HALO][LDS_PIX], const HaloRegs<NT>& h)
 {
-    // chunk e = threadIdx.x + NT k is 16-byte part e mod 4 of staged pixel e / 4 (row-major); lanes
-    // past the last chunk store into the unused padding of pixel (0, 0) instead of branching, which
-    // lets the compiler wait for each prefetched chunk exactly
-    uint16_t* base = &s[0][0][0] + (threadIdx.x >> 2) * LDS_PIX + (threadIdx.x & 3) * 8;
+    // slots past the last pixel store into the unused padding of pixel (0, 0) instead of branching,
+    // which lets the compiler wait for each prefetched chunk exactly
+    const int tid = (int)threadIdx.x;
+    uint16_t* base = &s[0][0][0] + halo_pixel<NT>(tid, 0) * LDS_PIX + ((tid >> 4) & 3) * 8;
 #pragma unroll
     for (int k = 0; k < HaloRegs<NT>::PER; ++k) {
-        const bool real = NT * (k + 1) <= HALO_CHUNKS || (int)threadIdx.x + NT * k < HALO_CHUNKS;
-        uint16_t* dst = real ? base + (NT / 4) * k * LDS_PIX : &s[0][0][C];
+        // every slot of step k is a real pixel when the step's last group ends inside the tile
+        const bool real = 16 * ((NT * (k + 1) - 1) >> 6) + 15 < HALO * HALO || halo_pixel<NT>(tid, k) < HALO * HALO;
+        uint16_t* dst = real ? base + 16 * (NT / 64) * k * LDS_PIX : &s[0][0][C];
         *(u32x4*)dst = (h.in >> k) & 1u ? h.v[k] : u32x4{0u, 0u, 0u, 0u};
     }
 }
@@ -186,8 +199,9 @@ static_assert(LDS_PIX >= C + 8, "the halo store's spare slot lies in a staged pi
 
 // Writes the 64-byte channel rows of the block's 256 consecutive pixels (pixel
 // first + threadIdx.x holds words w) so that every store instruction of a wave
-// covers 1 KB of contiguous memory: the rows pass through LDS (80-byte stride,
-// no bank conflicts) and wave v then writes 16-byte words v*256 + q*64 + lane.
+// covers 1 KB of contiguous memory: the rows pass through LDS (80-byte stride)
+// and wave v then writes pixels v*64 + q*16 .. +15, lane l taking 16-byte part
+// l / 16 of pixel l mod 16 (the halo tile's lane pattern).
 // Called by all 256 threads; pixels at or beyond `total` are not written.
 constexpr int ROW_STAGE_WORDS = 256 * 5;
 __device__ __forceinline__ void store_pixel_rows(u32x4* __restrict__ stage, const u32x4 (&w)[4],
@@ -199,8 +213,8 @@ __device__ __forceinline__ void store_pixel_rows(u32x4* __restrict__ stage, cons
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int word = wv * 256 + q * 64 + l;
-        if (first + (word >> 2) < total) ((u32x4*)dst)[first * 4 + word] = stage[(word >> 2) * 5 + (word & 3)];
+        const int px = wv * 64 + q * 16 + (l & 15), part = l >> 4;
+        if (first + px < total) ((u32x4*)dst)[(first + px) * 4 + part] = stage[px * 5 + part];
     }
 }
 
@@ -340,7 +354,7 @@ __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ 
         }
         __syncthreads();
         // out: wave w writes rows 4w .. 4w+3, one contiguous 1 KB row per instruction
-        const int px = lane >> 2, c4 = lane & 3;
+        const int px = lane & 15, c4 = lane >> 4;  // the halo tile's lane pattern
         const int gj = tl.j0 + px;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -415,7 +429,7 @@ template <int MODE>
 __device__ __forceinline__ void conv32_copy_out(const uint16_t* __restrict__ o, const uint16_t* __restrict__ mask,
                                                 uint16_t* __restrict__ out, int n, Tile tl, int wave, int lane)
 {
-    const int px = lane >> 2, c4 = lane & 3;
+    const int px = lane & 15, c4 = lane >> 4;  // the halo tile's lane pattern
     const int gj = tl.j0 + px;
     u32x4 mk[4];
     if constexpr (MODE == 1) {

@@ -119,6 +119,31 @@ def test_realistic_batch_equals_single(dev):
         assert torch.equal(imgs[k], ref), k
 
 
+@pytest.mark.parametrize("k", [1, 3])
+def test_batch_cut_over_xcds_equals_single(dev, k):
+    """Batches that whole slices cannot balance over the 8 XCDs (one clinical slice; three
+    helical-rebinned-like ones) are cut into parts placed on several XCDs: every slice still equals
+    its single-slice run bit for bit, one epoch of 20 subsets, at every projector shape."""
+    from paper_1903_10088_amd import recon
+    if k == 1:
+        g = ph.config1_geometry()
+        geoms, slices = [g], [ph.make_slice(g, 100, 2e3, low_contrast=True, supersample=1)]
+    else:
+        geoms, slices = realistic_batch(3)
+    errors, blocks = recon.batch_check_work(geoms, 20, 4)
+    assert errors == 0
+    M, beta, n_iter = 20, 1e-3, 20
+    B = recon.Batch(geoms, M, beta)
+    counts = [torch.from_numpy(s.counts).to(dev) for s in slices]
+    refs = [run_single(dev, g, sl, M, beta, n_iter)[0] for g, sl in zip(geoms, slices)]
+    for seg in (16, 4, 1):
+        B.set_launch(fp_segments=seg)
+        imgs, _ = B.run(counts, [s.i0 for s in slices], None, n_iter)
+        torch.cuda.synchronize()
+        for j in range(len(geoms)):
+            assert torch.equal(imgs[j], refs[j]), (seg, j)
+
+
 def test_one_shot_batch_call(dev):
     import ctypes
     from paper_1903_10088_amd import recon
