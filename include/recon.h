@@ -361,7 +361,10 @@ recon_status recon_batch(const recon_geometry* geoms, int32_t n_slices, int32_t 
  * (d_imgs receive the results); i0: host array.  h_residual, h_floor (host
  * double[n_slices]) and h_fallback (host int32[n_slices], 1 = cold start used)
  * may be NULL.  Blocks until done (the fallback decision is taken on the
- * host). */
+ * host).  Its device staging (the images of one size for the network, the
+ * residuals, the count pointers) is allocated by the first call on a batch
+ * and kept with the batch for later calls (freed by recon_batch_destroy);
+ * calls on one batch must not overlap. */
 struct recon_cnn;
 recon_status recon_warm_start(recon_batch_handle* b, struct recon_cnn* net, const float* const* d_counts,
                               const float* i0, float* const* d_imgs, int32_t n_pre, int32_t n_refine, int32_t n_cold,

@@ -58,6 +58,12 @@ struct recon_batch_handle {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     bool graph_bad = false;
+
+    // recon_warm_start's staging, allocated by its first call and kept for the next ones
+    float* ws_stage = nullptr;
+    size_t ws_stage_floats = 0;
+    double* ws_res = nullptr;        // 2 per slice
+    const float** ws_cptr = nullptr;  // one per slice
 };
 
 namespace {
@@ -84,6 +90,9 @@ void free_batch(recon_batch_handle* b)
     if (b->d_subs) (void)hipFree(b->d_subs);
     if (b->d_slices) (void)hipFree(b->d_slices);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->ws_stage) (void)hipFree(b->ws_stage);
+    if (b->ws_res) (void)hipFree(b->ws_res);
+    if (b->ws_cptr) (void)hipFree(b->ws_cptr);
     if (b->owns)
         for (recon_handle* h : b->h) recon_destroy(h);
     delete b;
@@ -750,19 +759,24 @@ recon_status warm_start_impl(recon_batch_handle* b, recon_cnn* net, const float*
         d_res = reinterpret_cast<double*>(ws + NOALLOC_RES_OFFSET);
         d_cptr = reinterpret_cast<const float**>(ws + NOALLOC_CPTR_OFFSET);
     } else {
+        // kept with the batch: a stream of calls on one batch allocates once (a free here would
+        // wait for the whole device between one call's check and the next call's first kernel)
         size_t stage_floats = 0;
         for (size_t k = 0; k < sizes.size(); ++k)
             stage_floats = std::max(stage_floats, (size_t)per_size[k] * sizes[k] * sizes[k]);
-        e = hipMalloc(&d_stage, stage_floats * sizeof(float));
-        if (e == hipSuccess) e = hipMalloc(&d_res, 2 * sizeof(double) * n);
-        if (e == hipSuccess) e = hipMalloc((void**)&d_cptr, sizeof(float*) * n);
+        if (b->ws_stage_floats < stage_floats) {
+            if (b->ws_stage) (void)hipFree(b->ws_stage);
+            b->ws_stage = nullptr;
+            b->ws_stage_floats = 0;
+            e = hipMalloc(&b->ws_stage, stage_floats * sizeof(float));
+            if (e == hipSuccess) b->ws_stage_floats = stage_floats;
+        }
+        if (e == hipSuccess && !b->ws_res) e = hipMalloc(&b->ws_res, 2 * sizeof(double) * n);
+        if (e == hipSuccess && !b->ws_cptr) e = hipMalloc((void**)&b->ws_cptr, sizeof(float*) * n);
+        d_stage = b->ws_stage;
+        d_res = b->ws_res;
+        d_cptr = b->ws_cptr;
     }
-    auto cleanup = [&]() {
-        if (noalloc) return;
-        if (d_stage) (void)hipFree(d_stage);
-        if (d_res) (void)hipFree(d_res);
-        if (d_cptr) (void)hipFree(d_cptr);
-    };
     if (e == hipSuccess) e = hipMemcpyAsync(d_cptr, d_counts, sizeof(float*) * n, hipMemcpyHostToDevice, s);
     for (size_t k = 0; k < sizes.size() && e == hipSuccess && st == RECON_OK; ++k) {
         const int sz = sizes[k];
@@ -799,7 +813,6 @@ recon_status warm_start_impl(recon_batch_handle* b, recon_cnn* net, const float*
     if (e == hipSuccess && st == RECON_OK)
         e = hipMemcpyAsync(res.data(), d_res, 2 * sizeof(double) * n, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && st == RECON_OK) e = hipStreamSynchronize(s);
-    cleanup();
     if (st != RECON_OK) return st;
     if (e != hipSuccess) return fail(RECON_DEVICE, std::string("warm start: ") + hipGetErrorString(e));
     // 5. cold start for every slice whose data residual exceeds the limit
