@@ -54,6 +54,15 @@ CAL_RUNS = {"cal_fetch": ["FETCH_SIZE"], "cal_write": ["WRITE_SIZE"]}
 COUNTER_ARGS = ("--steps 1 --warmup 0 --iters 40 --cpu-iters 0 --time-iters 0 --cnn-batch 0 --warm-slices 0 "
                 "--batch-slices 0 --rebin-slices 0")
 CAL_MIB = 256
+# the batched leg's VALU instructions per sub-iteration: one rocprofv3 --pmc SQ_INSTS_VALU run of
+# BATCH_COUNTER_ARGS (64 mixed slices, tuned, 3 runs of 20 sub-iterations), averaged over each
+# kernel's last 20 dispatches (the last run: one dispatch per subset)
+BATCH_COUNTER_RECORD = os.path.join(ROOT, "profiles", "counters_batched_64mixed.json")
+BATCH_COUNTER_SOURCES = ["paper_1903_10088_amd/csrc/batch.hip", "paper_1903_10088_amd/csrc/bp.hip",
+                         "paper_1903_10088_amd/csrc/kernels.hip", "paper_1903_10088_amd/csrc/gather.h",
+                         "paper_1903_10088_amd/csrc/internal.h"]
+BATCH_COUNTER_ARGS = ("--steps 1 --warmup 0 --iters 20 --cpu-iters 0 --time-iters 0 --cnn-batch 0 --warm-slices 0 "
+                      "--rebin-slices 0 --batch-slices 64")
 SIMDS = 1024              # 256 compute units x 4 SIMDs
 CLOCK_HZ = 2.4e9          # peak engine clock
 # the published FP32 vector rate, 157.3 TFLOP/s, counts an FMA as two operations: 32 lanes per SIMD per
@@ -172,6 +181,56 @@ def summarize_counters(d: str, out_path: str | None = None) -> dict:
     return out
 
 
+def summarize_batch_counters(d: str, out_path: str | None = None) -> dict:
+    """profiles/counters_batched_64mixed.json from one rocprofv3 --pmc SQ_INSTS_VALU run of
+    BATCH_COUNTER_ARGS under d (d/pmc_counter_collection.csv and the source_stamp.json its bench.py
+    wrote): SQ_INSTS_VALU per dispatch of every batched kernel, averaged over its last 20 dispatches.
+    Refuses a run taken from sources other than the current ones."""
+    import collections
+    import csv
+    import re
+
+    stamp = json.load(open(os.path.join(d, "source_stamp.json")))["sources"]
+    now = source_hashes()
+    sha = combined_sha(stamp, BATCH_COUNTER_SOURCES)
+    if sha != combined_sha(now, BATCH_COUNTER_SOURCES):
+        raise SystemExit("bench: the batched kernels' sources changed since the counters were taken")
+    per = collections.defaultdict(list)
+    for r in csv.DictReader(open(os.path.join(d, "pmc_counter_collection.csv"))):
+        if r["Counter_Name"] != "SQ_INSTS_VALU":
+            continue
+        m = re.search(r"([A-Za-z_0-9]+(<[^>]*>)?)\(", r["Kernel_Name"])
+        name = m.group(1) if m else r["Kernel_Name"]
+        if "batch_kernel" in name:
+            per[name].append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+    kernels = {}
+    for name, v in per.items():
+        last = [x for _, x in sorted(v)[-20:]]
+        kernels[name] = {"valu_instructions": sum(last) / len(last), "dispatches_averaged": len(last)}
+    out = {"workload": "64 mixed slices (38 at 512x512, 26 at 256x256; 600-900 views, 520-738 channels), seeds "
+                       "1000+, 20 subsets; SQ_INSTS_VALU (wave64 instructions) per dispatch, mean over each "
+                       "kernel's last 20 dispatches",
+           "source_sha": sha, "sources": BATCH_COUNTER_SOURCES, "kernels": kernels,
+           "commands": [f"cd /tmp && rocprofv3 --pmc SQ_INSTS_VALU --output-format csv -d <dir> -o pmc -- "
+                        f"python3 <repo>/bench.py {BATCH_COUNTER_ARGS} --stamp <dir>",
+                        "python3 <repo>/bench.py --summarize-batch-counters <dir>"]}
+    with open(out_path or BATCH_COUNTER_RECORD, "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
+
+
+def batch_counters():
+    """The committed VALU record of the batched kernels, or None when missing or when their sources
+    differ from those it was taken from."""
+    try:
+        rec = json.load(open(BATCH_COUNTER_RECORD))
+        if combined_sha(source_hashes(rec["sources"]), rec["sources"]) != rec["source_sha"]:
+            return None
+        return rec["kernels"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +257,9 @@ def main():
                     help="slices of the helical-rebinning leg (0 = skip)")
     ap.add_argument("--summarize-counters", default=None, metavar="DIR",
                     help="write profiles/counters_512x800.json from the counter runs under DIR (no GPU)")
+    ap.add_argument("--summarize-batch-counters", default=None, metavar="DIR",
+                    help="write profiles/counters_batched_64mixed.json from the batched counter run under DIR "
+                         "(no GPU)")
     ap.add_argument("--stamp", default=None, metavar="DIR",
                     help="write DIR/source_stamp.json (hashes of the library sources) before running")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -206,6 +268,10 @@ def main():
 
     if args.summarize_counters:
         rec = summarize_counters(args.summarize_counters)
+        print(json.dumps(rec["kernels"]))
+        return
+    if args.summarize_batch_counters:
+        rec = summarize_batch_counters(args.summarize_batch_counters)
         print(json.dumps(rec["kernels"]))
         return
     if args.stamp:
@@ -479,9 +545,23 @@ def batch_leg(n_slices: int, iters: int, dev, l2_gbps=None):
     gbps = alg / best / 1e9
     out = {"slices": n_slices, "slices_512": n512, "slices_256": n_slices - n512, "sub_iterations": iters,
            "tuned_fp_segments": seg, "tuned_bp_variant": var, "seconds": best, "slices_per_s": n_slices / best,
-           "alg_bytes": alg, "alg_gbps": gbps, "alg_frac_of_l2_read": gbps / l2_gbps if l2_gbps else None}
+           "alg_bytes": alg, "alg_gbps": gbps, "alg_frac_of_l2_read": gbps / l2_gbps if l2_gbps else None,
+           "roofline": None}
+    # VALU issue of a whole batched sub-iteration (projector + step rule + update) from the committed
+    # instruction counts, against the sub-iteration's time in this run (the 64-slice workload only)
+    ctr = batch_counters() if n_slices == 64 else None
+    names = [f"fp_batch_kernel<{seg}>", "step_batch_kernel", f"bp_update_batch_kernel<{var - 1}>"]
+    if ctr and all(k in ctr for k in names):
+        instr = sum(ctr[k]["valu_instructions"] for k in names)
+        t_sub = best / iters
+        out["roofline"] = {"bound": "alu", "scope": "whole batched sub-iteration: " + " + ".join(names),
+                           "valu_instructions": instr, "sub_iteration_us": t_sub * 1e6,
+                           "achieved": instr * 64 / t_sub / 1e12, "peak": VALU_PEAK_TOPS,
+                           "unit": "T VALU lane-ops/s", "frac": instr * VALU_CYCLES / (SIMDS * CLOCK_HZ) / t_sub,
+                           "counters": "profiles/counters_batched_64mixed.json"}
+    alu = f", VALU issue {out['roofline']['frac']:.2f} of peak" if out["roofline"] else ""
     log(f"bench: batched plain {out['slices_per_s']:.1f} slices/s ({n512} of {n_slices} at 512^2; "
-        f"fp_segments {seg}, bp variant {var}); {gbps:.0f} GB/s algorithmic")
+        f"fp_segments {seg}, bp variant {var}); {gbps:.0f} GB/s algorithmic{alu}")
     B.close()
     return out
 

@@ -96,3 +96,44 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_batch_counter_summary(tmp_path):
+    """The batched kernels' VALU record: SQ_INSTS_VALU per dispatch averaged over each kernel's last 20
+    dispatches (the last run of one epoch), other counters and non-batched kernels ignored; a run
+    stamped with other sources of the batched kernels is refused."""
+    import pytest
+
+    d = str(tmp_path / "a")
+    os.makedirs(d)
+    bp = "void recon::(anonymous namespace)::bp_update_batch_kernel<5>(recon::SliceDesc const*, ...)"
+    fp = "void recon::(anonymous namespace)::fp_batch_kernel<4>(recon::SliceDesc const*, ...)"
+    single = "void recon::(anonymous namespace)::bp_update_kernel<5>(recon::Geo, ...)"
+    rows, disp = [], 0
+    for k in range(30):  # ten tuner dispatches (9e9), then the last run's 20 (k = 10..29)
+        disp += 1
+        rows.append((disp, bp, "SQ_INSTS_VALU", 9e9 if k < 10 else 1000.0 + k))
+        rows.append((disp, bp, "SQ_WAVES", 5.0))
+        disp += 1
+        rows.append((disp, fp, "SQ_INSTS_VALU", 40.0))
+        disp += 1
+        rows.append((disp, single, "SQ_INSTS_VALU", 7.0))
+    with open(os.path.join(d, "pmc_counter_collection.csv"), "w", newline="") as f:
+        w = csv.DictWriter(f, ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for r in rows:
+            w.writerow(dict(zip(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"], r)))
+    bench.write_stamp(d)
+    out = os.path.join(d, "rec.json")
+    rec = bench.summarize_batch_counters(d, out_path=out)
+    assert json.load(open(out)) == rec
+    k = rec["kernels"]
+    assert set(k) == {"bp_update_batch_kernel<5>", "fp_batch_kernel<4>"}
+    assert k["bp_update_batch_kernel<5>"]["valu_instructions"] == sum(1000.0 + i for i in range(10, 30)) / 20
+    assert k["fp_batch_kernel<4>"]["valu_instructions"] == 40.0
+    st = json.load(open(os.path.join(d, "source_stamp.json")))
+    st["sources"]["paper_1903_10088_amd/csrc/batch.hip"] = "0" * 16
+    with open(os.path.join(d, "source_stamp.json"), "w") as f:
+        json.dump(st, f)
+    with pytest.raises(SystemExit):
+        bench.summarize_batch_counters(d, out_path=out)
