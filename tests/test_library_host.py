@@ -257,3 +257,28 @@ def test_batch_work_tables_split_slices_over_xcds():
             items = _work_items(geoms, M, seg)
             assert errors == 0, (len(geoms), M, seg)
             assert items <= blocks <= 1.2 * items + 8 * (M + 2), (len(geoms), M, seg, blocks, items)
+
+
+def test_batch_work_tables_random_batches():
+    """Seeded random batches (1 to 24 slices, images 16 to 640 pixels, 8 to 900 views, any channel
+    count, 1 to 20 subsets): the work tables always hold every tile and ray block once, on the XCD
+    of the slice or of its part.  (Their idle padding is not bounded here: slices are placed by the
+    update's cost, pixels x views, so a small image with many rays can load one XCD's projector
+    table far more than the others.)"""
+    import random
+
+    rnd = random.Random(20261203)
+    for trial in range(40):
+        k = rnd.choice([1, 2, 3, 5, 7, 8, 9, 13, 24])
+        geoms = []
+        for _ in range(k):
+            n = rnd.choice([16, 37, 64, 128, 200, 256, 384, 512, 640])
+            views = rnd.randint(8, 900)
+            geoms.append(ph.Geometry(n=n, pixel_mm=400.0 / n, n_views=views, n_channels=rnd.randint(24, 738),
+                                     start_angle_rad=rnd.uniform(0.0, 6.28)))
+        M = rnd.randint(1, min(20, min(g.n_views for g in geoms)))
+        seg = rnd.choice([1, 4, 16])
+        errors, blocks = recon.batch_check_work(geoms, M, seg)
+        items = _work_items(geoms, M, seg)
+        assert errors == 0, (trial, k, M, seg)
+        assert blocks >= items, (trial, k, M, seg, blocks, items)
