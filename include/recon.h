@@ -282,7 +282,8 @@ recon_status recon_set_launch(recon_handle* h, int32_t fp_segments, int32_t bp_v
  * projector launch, one step-rule launch (a block per slice) and one update
  * launch over work tables that cover all slices; each subset epoch is
  * replayed from a captured HIP graph.  The tables place each slice on one of
- * the 8 XCDs (its image and tables then stay in one L2), balanced by cost;
+ * the 8 XCDs (its data for that kernel then stays in one L2), the update's by
+ * its cost (pixels x views) and the projector's by its own (ray samples);
  * when whole slices cannot be balanced within 3 % (fewer slices than XCDs, a
  * few large ones), the largest are cut into 2, 4 or 8 parts placed the same
  * way.  Every slice's result is bitwise equal to recon_os_iterate on that
@@ -331,9 +332,9 @@ recon_status recon_batch_set_launch(recon_batch_handle* b, int32_t fp_segments, 
  * upload (the update's 16x16 tiles, the projector's blocks of 256 / fp_segments
  * rays for every subset and for all views) and counts in *errors every tile or
  * ray block that is missing, repeated, out of range or placed on an XCD other
- * than the one its slice, or its part of the slice, is placed on (block p runs
- * on XCD p mod 8), and every slice cut into a number of parts other than 1, 2,
- * 4 or 8; *blocks receives the total table length, idle entries included.  RECON_INVALID_ARG as recon_batch_create, or for an
+ * than the one its slice, or its part of the slice, is placed on by that
+ * kernel's placement (block p runs on XCD p mod 8), and every slice cut into a
+ * number of parts other than 1, 2, 4 or 8; *blocks receives the total table length, idle entries included.  RECON_INVALID_ARG as recon_batch_create, or for an
  * fp_segments outside {1, 2, 4, 8, 16}. */
 recon_status recon_batch_check_work(const recon_geometry* geoms, int32_t n_slices, int32_t subsets,
                                     int32_t fp_segments, int64_t* errors, int64_t* blocks);

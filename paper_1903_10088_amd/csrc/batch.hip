@@ -5,11 +5,12 @@
 //
 // Work tables map thread blocks to (slice, ray block) for the projector and to
 // (slice, 16x16 tile) for the update.  Slices are placed on XCDs (the
-// dispatcher hands block b to XCD b mod 8), so a slice's image, residuals and
-// ray tables stay in one XCD's L2; the per-XCD lists are balanced by cost and
+// dispatcher hands block b to XCD b mod 8), so a slice's work in one kernel
+// stays in one XCD's L2; the per-XCD lists are balanced by each kernel's own
+// cost (the update's by pixels x views, the projector's by ray samples) and
 // interleaved, with idle blocks padding the shorter lists.  When whole slices
 // cannot be balanced (fewer slices than XCDs, or a few large ones), the
-// largest are cut into 2, 4 or 8 parts (contiguous ranges of their tiles and
+// largest are cut into 2, 4 or 8 parts (contiguous ranges of their tiles or
 // ray blocks), each part placed like a slice.
 //
 // Every slice's arithmetic is exactly that of recon_os_iterate on its own
@@ -44,7 +45,8 @@ struct recon_batch_handle {
     // identical for every choice
     int fp_segments = BATCH_FP_SEGMENTS;
     int bp_variant = 5;
-    std::vector<std::vector<int>> xcd;  // XCD of each part of each slice (1, 2, 4 or 8 parts)
+    std::vector<std::vector<int>> xcd;     // update: XCD of each part of each slice (1, 2, 4 or 8 parts)
+    std::vector<std::vector<int>> xcd_fp;  // projector: the same, placed by the projector's cost
 
     SliceDesc* d_slices = nullptr;
     int2* d_subs = nullptr;
@@ -113,9 +115,11 @@ std::vector<SliceShape> shapes_of(const recon_batch_handle* b)
     return sh;
 }
 
-// Placement of slices on XCDs.  A slice costs pixels x views per subset; it is
-// cut into k in {1, 2, 4, 8} equal parts, and the parts are placed greedily,
-// largest first, each on the least loaded XCD.  Starting from whole slices,
+// Placement of slices on XCDs.  A slice costs, in the update, pixels x views
+// per subset and, in the projector (`projector`), image edge x channels x
+// views per subset (its rays' samples); it is cut into k in {1, 2, 4, 8}
+// equal parts, and the parts are placed greedily, largest first, each on the
+// least loaded XCD.  Starting from whole slices,
 // the slice with the largest part is cut in twice as many parts while the
 // busiest XCD carries more than SPLIT_TOLERANCE times the mean load (a batch
 // of one slice ends in 8 parts; batches of many similar slices stay whole).
@@ -123,13 +127,13 @@ std::vector<SliceShape> shapes_of(const recon_batch_handle* b)
 // so the placement never changes a result.
 constexpr double SPLIT_TOLERANCE = 1.03;
 
-std::vector<std::vector<int>> assign_xcds(const std::vector<SliceShape>& sh)
+std::vector<std::vector<int>> assign_xcds(const std::vector<SliceShape>& sh, bool projector)
 {
     const int n = (int)sh.size();
     std::vector<double> cost(n);
     double total = 0.0;
     for (int i = 0; i < n; ++i) {
-        cost[i] = (double)sh[i].n * sh[i].n * sh[i].max_subset_views;
+        cost[i] = (double)sh[i].n * (projector ? sh[i].nch : sh[i].n) * sh[i].max_subset_views;
         total += cost[i];
     }
     std::vector<int> k(n, 1);
@@ -230,13 +234,13 @@ recon_status upload_work(recon_batch_handle* b)
     b->d_fp.assign(b->M, nullptr);
     b->n_fp.assign(b->M, 0);
     for (int s = 0; s < b->M; ++s) {
-        const std::vector<FpWork> fp = fp_work_table(sh, b->xcd, s, rpb);
+        const std::vector<FpWork> fp = fp_work_table(sh, b->xcd_fp, s, rpb);
         RECON_HIP_TRY(hipMalloc(&b->d_fp[s], std::max<size_t>(1, fp.size()) * sizeof(FpWork)));
         RECON_HIP_TRY(hipMemcpy(b->d_fp[s], fp.data(), fp.size() * sizeof(FpWork), hipMemcpyHostToDevice));
         b->n_fp[s] = (int)fp.size();
     }
     {
-        const std::vector<FpWork> fp = fp_work_table(sh, b->xcd, -1, rpb);
+        const std::vector<FpWork> fp = fp_work_table(sh, b->xcd_fp, -1, rpb);
         if (b->d_fp_all) (void)hipFree(b->d_fp_all);
         b->d_fp_all = nullptr;
         RECON_HIP_TRY(hipMalloc(&b->d_fp_all, std::max<size_t>(1, fp.size()) * sizeof(FpWork)));
@@ -265,7 +269,8 @@ recon_status setup_batch(recon_batch_handle* b, int fp_segments)
 {
     const int n_slices = (int)b->h.size(), subsets = b->M;
     b->fp_segments = fp_segments > 0 ? fp_segments : default_fp_segments(b);
-    b->xcd = assign_xcds(shapes_of(b));
+    b->xcd = assign_xcds(shapes_of(b), false);
+    b->xcd_fp = assign_xcds(shapes_of(b), true);
     std::vector<int2> subs((size_t)n_slices * subsets);
     for (int i = 0; i < n_slices; ++i)
         for (int s = 0; s < subsets; ++s)
@@ -430,13 +435,14 @@ recon_status recon_batch_check_work(const recon_geometry* geoms, int32_t n_slice
         s.max_subset_views = *std::max_element(s.subset_count.begin(), s.subset_count.end());
         sh.push_back(s);
     }
-    const std::vector<std::vector<int>> xcd = assign_xcds(sh);
+    const std::vector<std::vector<int>> xcd = assign_xcds(sh, false), xfp = assign_xcds(sh, true);
     int64_t bad = 0, nblk = 0;
-    for (int i = 0; i < n_slices; ++i) {
-        const size_t k = xcd[i].size();
-        if (k != 1 && k != 2 && k != 4 && k != 8) ++bad;
-        for (int x : xcd[i]) bad += x < 0 || x >= NXCD;
-    }
+    for (const auto* pl : {&xcd, &xfp})
+        for (int i = 0; i < n_slices; ++i) {
+            const size_t k = (*pl)[i].size();
+            if (k != 1 && k != 2 && k != 4 && k != 8) ++bad;
+            for (int x : (*pl)[i]) bad += x < 0 || x >= NXCD;
+        }
     // every tile of every slice exactly once, each on the XCD of its part of the slice
     const std::vector<BpWork> bp = bp_work_table(sh, xcd);
     std::vector<std::vector<int>> seen(n_slices);
@@ -466,7 +472,7 @@ recon_status recon_batch_check_work(const recon_geometry* geoms, int32_t n_slice
     // every ray block of every subset (and of all views) exactly once, on the XCD of its part of the slice
     const int rpb = fp_rays_per_block(fp_segments);
     for (int s = -1; s < subsets; ++s) {
-        const std::vector<FpWork> fp = fp_work_table(sh, xcd, s, rpb);
+        const std::vector<FpWork> fp = fp_work_table(sh, xfp, s, rpb);
         for (int i = 0; i < n_slices; ++i) {
             const int nrays = (s < 0 ? sh[i].nv : sh[i].subset_count[s]) * sh[i].nch;
             seen[i].assign((size_t)((nrays + rpb - 1) / rpb), 0);
@@ -481,7 +487,7 @@ recon_status recon_batch_check_work(const recon_geometry* geoms, int32_t n_slice
             const int nrays = (s < 0 ? sh[w.slice].nv : sh[w.slice].subset_count[s]) * sh[w.slice].nch;
             const long nb = (nrays + rpb - 1) / rpb;
             if (w.r0 % rpb || w.r0 >= nrays ||
-                xcd[w.slice][part_of(w.r0 / rpb, nb, (int)xcd[w.slice].size())] != (int)(p % NXCD)) {
+                xfp[w.slice][part_of(w.r0 / rpb, nb, (int)xfp[w.slice].size())] != (int)(p % NXCD)) {
                 ++bad;
                 continue;
             }

@@ -262,9 +262,8 @@ def test_batch_work_tables_split_slices_over_xcds():
 def test_batch_work_tables_random_batches():
     """Seeded random batches (1 to 24 slices, images 16 to 640 pixels, 8 to 900 views, any channel
     count, 1 to 20 subsets): the work tables always hold every tile and ray block once, on the XCD
-    of the slice or of its part.  (Their idle padding is not bounded here: slices are placed by the
-    update's cost, pixels x views, so a small image with many rays can load one XCD's projector
-    table far more than the others.)"""
+    of the slice or of its part.  (Their idle padding is not bounded here: each kernel's placement
+    balances that kernel's cost, which need not balance its table lengths.)"""
     import random
 
     rnd = random.Random(20261203)
