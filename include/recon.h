@@ -372,6 +372,27 @@ recon_status recon_warm_start(recon_batch_handle* b, struct recon_cnn* net, cons
                               double residual_ratio, int32_t check_stride, double* h_residual, double* h_floor,
                               int32_t* h_fallback, void* stream);
 
+/* recon_warm_start for a stream of batches (paper §3.C-§3.D pipeline, as
+ * recon_warm_start; a serving loop's form of it): the same arguments, the same
+ * results bit for bit and the same fallback decision, but the cold starts of
+ * the slices that fall back are enqueued on a stream the batch owns (created
+ * by the first such call, default priority), ordered after the check on
+ * `stream` by an event, and the call returns once they are enqueued, so that
+ * the caller's next batch on `stream` overlaps them.  h_residual, h_floor and
+ * h_fallback are filled before it returns; the images of fallback slices are
+ * final only once recon_batch_wait(b) has returned.  Every other call on the
+ * batch, and recon_batch_destroy, first waits for them.  Allocates like
+ * recon_warm_start, plus the stream and two events once per batch. */
+recon_status recon_warm_start_async(recon_batch_handle* b, struct recon_cnn* net, const float* const* d_counts,
+                                    const float* i0, float* const* d_imgs, int32_t n_pre, int32_t n_refine,
+                                    int32_t n_cold, double residual_ratio, int32_t check_stride, double* h_residual,
+                                    double* h_floor, int32_t* h_fallback, void* stream);
+
+/* Blocks until the cold starts that recon_warm_start_async left running on
+ * the batch are done (returns at once when there are none).
+ * RECON_INVALID_ARG for a NULL batch. */
+recon_status recon_batch_wait(recon_batch_handle* b);
+
 /* recon_warm_start for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same arguments and the same results, bit for bit, with no hipMalloc,

@@ -66,6 +66,12 @@ struct recon_batch_handle {
     size_t ws_stage_floats = 0;
     double* ws_res = nullptr;        // 2 per slice
     const float** ws_cptr = nullptr;  // one per slice
+
+    // recon_warm_start_async: cold starts left running on the batch's own stream
+    hipStream_t side = nullptr;
+    hipEvent_t side_ready = nullptr, side_done = nullptr;
+    bool pending = false;                       // side_done not yet waited for
+    recon_batch_handle* pending_sub = nullptr;  // the sub-batch they ran as, freed once they are done
 };
 
 namespace {
@@ -84,6 +90,11 @@ void drop_graphs(recon_batch_handle* b)
 void free_batch(recon_batch_handle* b)
 {
     if (!b) return;
+    if (b->pending) (void)hipEventSynchronize(b->side_done);
+    if (b->pending_sub) free_batch(b->pending_sub);
+    if (b->side_ready) (void)hipEventDestroy(b->side_ready);
+    if (b->side_done) (void)hipEventDestroy(b->side_done);
+    if (b->side) (void)hipStreamDestroy(b->side);
     drop_graphs(b);
     for (FpWork* p : b->d_fp)
         if (p) (void)hipFree(p);
@@ -98,6 +109,24 @@ void free_batch(recon_batch_handle* b)
     if (b->owns)
         for (recon_handle* h : b->h) recon_destroy(h);
     delete b;
+}
+
+// Waits for the cold starts a recon_warm_start_async call left running on the
+// batch's stream; their sub-batch is freed then unless free_sub is false (the
+// allocation-free entry point), in which case a later call frees it.
+recon_status wait_pending(recon_batch_handle* b, bool free_sub = true)
+{
+    hipError_t e = hipSuccess;
+    if (b->pending) {
+        e = hipEventSynchronize(b->side_done);
+        b->pending = false;
+    }
+    if (free_sub && b->pending_sub) {
+        free_batch(b->pending_sub);
+        b->pending_sub = nullptr;
+    }
+    if (e != hipSuccess) return fail(RECON_DEVICE, std::string("pending cold starts: ") + hipGetErrorString(e));
+    return RECON_OK;
 }
 
 // What the work tables need to know of a slice.
@@ -414,6 +443,21 @@ recon_status stage_copy(const recon_batch_handle* b, float* const* d_imgs, float
 recon_status batch_run(recon_batch_handle* b, const float* const* d_counts, const float* i0, float* const* d_imgs,
                        int n_iter, double* const* d_traces, hipStream_t s, bool new_graphs, bool counts_ready = false);
 
+// The homogeneous start image of every slice into d_imgs (host array of device pointers).
+recon_status initial_images(recon_batch_handle* b, float* const* d_imgs, hipStream_t s)
+{
+    for (size_t i = 0; i < b->h.size(); ++i)
+        if (!d_imgs[i]) return fail(RECON_INVALID_ARG, "slice " + std::to_string(i) + ": NULL image");
+    return for_groups(b, [&](BatchRunArgs& a) -> recon_status {
+        for (int k = 0; k < a.count; ++k) {
+            a.img[k] = d_imgs[a.first + k];
+            a.mu0[k] = (float)b->h[a.first + k]->p.mu0_per_mm;
+        }
+        RECON_HIP_TRY(launch_initial_batch(b->d_slices, a, s));
+        return RECON_OK;
+    });
+}
+
 }  // namespace
 
 extern "C" {
@@ -539,17 +583,9 @@ recon_status recon_batch_create(const recon_geometry* geoms, int32_t n_slices, i
 recon_status recon_batch_initial_images(recon_batch_handle* b, float* const* d_imgs, void* stream)
 {
     if (!b || !d_imgs) return fail(RECON_INVALID_ARG, "NULL argument");
-    for (size_t i = 0; i < b->h.size(); ++i)
-        if (!d_imgs[i]) return fail(RECON_INVALID_ARG, "slice " + std::to_string(i) + ": NULL image");
-    hipStream_t s = as_stream(stream);
-    return for_groups(b, [&](BatchRunArgs& a) -> recon_status {
-        for (int k = 0; k < a.count; ++k) {
-            a.img[k] = d_imgs[a.first + k];
-            a.mu0[k] = (float)b->h[a.first + k]->p.mu0_per_mm;
-        }
-        RECON_HIP_TRY(launch_initial_batch(b->d_slices, a, s));
-        return RECON_OK;
-    });
+    recon_status pst = wait_pending(b);
+    if (pst != RECON_OK) return pst;
+    return initial_images(b, d_imgs, as_stream(stream));
 }
 
 recon_status recon_batch_destroy(recon_batch_handle* b)
@@ -563,6 +599,8 @@ recon_status recon_batch_destroy(recon_batch_handle* b)
 recon_status recon_batch_set_launch(recon_batch_handle* b, int32_t fp_segments, int32_t bp_variant)
 {
     if (!b) return fail(RECON_INVALID_ARG, "NULL batch");
+    recon_status pst = wait_pending(b);
+    if (pst != RECON_OK) return pst;
     if (fp_segments != 0) {
         if (fp_segments != 1 && fp_segments != 2 && fp_segments != 4 && fp_segments != 8 && fp_segments != 16)
             return fail(RECON_INVALID_ARG, "fp_segments must be 1, 2, 4, 8 or 16");
@@ -578,6 +616,9 @@ recon_status recon_batch_set_launch(recon_batch_handle* b, int32_t fp_segments, 
 recon_status recon_batch_run(recon_batch_handle* b, const float* const* d_counts, const float* i0, float* const* d_imgs,
                              int32_t n_iter, double* const* d_traces, void* stream)
 {
+    if (!b) return fail(RECON_INVALID_ARG, "NULL argument");
+    recon_status pst = wait_pending(b);
+    if (pst != RECON_OK) return pst;
     return batch_run(b, d_counts, i0, d_imgs, n_iter, d_traces, as_stream(stream), true);
 }
 
@@ -631,6 +672,8 @@ recon_status recon_batch_tune(recon_batch_handle* b, const float* const* d_count
 {
     if (!b || !d_counts || !i0 || !d_imgs) return fail(RECON_INVALID_ARG, "NULL argument");
     if (reps < 1 || reps > 1000) return fail(RECON_INVALID_ARG, "reps must be in [1, 1000]");
+    recon_status pst = wait_pending(b);
+    if (pst != RECON_OK) return pst;
     hipStream_t s = as_stream(stream);
     recon_status st = prepare(b, d_counts, i0, d_imgs, nullptr, s);
     if (st != RECON_OK) return st;
@@ -736,12 +779,15 @@ constexpr size_t NOALLOC_BYTES = NOALLOC_CPTR_OFFSET + sizeof(float*) * NOALLOC_
 recon_status warm_start_impl(recon_batch_handle* b, recon_cnn* net, const float* const* d_counts, const float* i0,
                              float* const* d_imgs, int n_pre, int n_refine, int n_cold, double residual_ratio,
                              int check_stride, double* h_residual, double* h_floor, int32_t* h_fallback,
-                             hipStream_t s, unsigned char* ws)
+                             hipStream_t s, unsigned char* ws, bool async = false)
 {
     const bool noalloc = ws != nullptr;
     const int n = (int)b->h.size();
+    // the cold starts an earlier asynchronous call left running use this batch's handles
+    recon_status pst = wait_pending(b, !noalloc);
+    if (pst != RECON_OK) return pst;
     // 1. early iterate of every slice from the homogeneous start
-    recon_status st = recon_batch_initial_images(b, d_imgs, s);
+    recon_status st = initial_images(b, d_imgs, s);
     if (st == RECON_OK) st = batch_run(b, d_counts, i0, d_imgs, n_pre, nullptr, s, !noalloc);
     if (st != RECON_OK) return st;
     // 2. network estimate of the converged image, projected onto the constraints:
@@ -831,17 +877,44 @@ recon_status warm_start_impl(recon_batch_handle* b, recon_cnn* net, const float*
         if (bad) fb.push_back(i);
     }
     if (fb.empty()) return RECON_OK;
+    // The cold starts run on `s`, or (async) on the batch's own stream, after
+    // the check's reads of the images on `s`, and the call returns once they are
+    // enqueued.
+    hipStream_t fs = s;
+    if (async) {
+        if (!b->side) {
+            RECON_HIP_TRY(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+            RECON_HIP_TRY(hipEventCreateWithFlags(&b->side_ready, hipEventDisableTiming));
+            RECON_HIP_TRY(hipEventCreateWithFlags(&b->side_done, hipEventDisableTiming));
+        }
+        RECON_HIP_TRY(hipEventRecord(b->side_ready, s));
+        RECON_HIP_TRY(hipStreamWaitEvent(b->side, b->side_ready, 0));
+        fs = b->side;
+    }
+    auto leave_pending = [&]() -> recon_status {
+        const hipError_t re = hipEventRecord(b->side_done, fs);
+        if (re != hipSuccess) {
+            (void)hipStreamSynchronize(fs);
+            return fail(RECON_DEVICE, std::string("cold start: ") + hipGetErrorString(re));
+        }
+        b->pending = true;
+        return RECON_OK;
+    };
     // A few slices (or any number, without allocation) run alone on their own
     // handles; many go through a batch over their handles.  Both give the same bits.
     constexpr size_t kSubBatchMin = 2;  // one slice runs faster on its own handle; two or more as a batch
     if (noalloc || fb.size() < kSubBatchMin) {
         for (int i : fb) {
-            st = recon_initial_image(b->h[i], d_imgs[i], s);
+            st = recon_initial_image(b->h[i], d_imgs[i], fs);
             if (st == RECON_OK)
                 st = os_iterate_run(b->h[i], d_counts[i], i0[i], d_imgs[i], n_cold, nullptr, nullptr, nullptr, nullptr,
-                                    nullptr, s, !noalloc);
-            if (st != RECON_OK) return st;
+                                    nullptr, fs, !noalloc);
+            if (st != RECON_OK) {
+                if (async) (void)hipStreamSynchronize(fs);
+                return st;
+            }
         }
+        if (async) return leave_pending();
         RECON_HIP_TRY(hipStreamSynchronize(s));
         return RECON_OK;
     }
@@ -860,9 +933,16 @@ recon_status warm_start_impl(recon_batch_handle* b, recon_cnn* net, const float*
         img_sub.push_back(d_imgs[i]);
     }
     st = setup_batch(sub, 0);
-    if (st == RECON_OK) st = recon_batch_initial_images(sub, img_sub.data(), s);
-    if (st == RECON_OK) st = recon_batch_run(sub, c_sub.data(), i0_sub.data(), img_sub.data(), n_cold, nullptr, s);
-    hipError_t se = hipStreamSynchronize(s);
+    if (st == RECON_OK) st = recon_batch_initial_images(sub, img_sub.data(), fs);
+    if (st == RECON_OK) st = recon_batch_run(sub, c_sub.data(), i0_sub.data(), img_sub.data(), n_cold, nullptr, fs);
+    if (async && st == RECON_OK) {
+        st = leave_pending();
+        if (st == RECON_OK) {
+            b->pending_sub = sub;  // freed once the cold starts are done
+            return RECON_OK;
+        }
+    }
+    hipError_t se = hipStreamSynchronize(fs);
     free_batch(sub);
     if (st != RECON_OK) return st;
     if (se != hipSuccess) return fail(RECON_DEVICE, std::string("cold start: ") + hipGetErrorString(se));
@@ -928,6 +1008,24 @@ recon_status recon_warm_start(recon_batch_handle* b, recon_cnn* net, const float
     if (st != RECON_OK) return st;
     return warm_start_impl(b, net, d_counts, i0, d_imgs, n_pre, n_refine, n_cold, residual_ratio, check_stride,
                            h_residual, h_floor, h_fallback, as_stream(stream), nullptr);
+}
+
+recon_status recon_warm_start_async(recon_batch_handle* b, recon_cnn* net, const float* const* d_counts,
+                                    const float* i0, float* const* d_imgs, int32_t n_pre, int32_t n_refine,
+                                    int32_t n_cold, double residual_ratio, int32_t check_stride, double* h_residual,
+                                    double* h_floor, int32_t* h_fallback, void* stream)
+{
+    recon_status st =
+        check_warm_args(b, net, d_counts, i0, d_imgs, n_pre, n_refine, n_cold, residual_ratio, check_stride);
+    if (st != RECON_OK) return st;
+    return warm_start_impl(b, net, d_counts, i0, d_imgs, n_pre, n_refine, n_cold, residual_ratio, check_stride,
+                           h_residual, h_floor, h_fallback, as_stream(stream), nullptr, /*async=*/true);
+}
+
+recon_status recon_batch_wait(recon_batch_handle* b)
+{
+    if (!b) return fail(RECON_INVALID_ARG, "NULL batch");
+    return wait_pending(b);
 }
 
 recon_status recon_warm_start_noalloc(recon_batch_handle* b, recon_cnn* net, const float* const* d_counts,

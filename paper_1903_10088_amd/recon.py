@@ -55,7 +55,8 @@ EXPORTS = ["recon_default_params", "recon_status_string", "recon_last_error", "r
            "recon_cnn_param_count", "recon_cnn_create", "recon_cnn_destroy", "recon_cnn_get_state",
            "recon_cnn_set_state", "recon_cnn_save", "recon_cnn_load", "recon_cnn_forward", "recon_cnn_loss_grad",
            "recon_cnn_adam_step", "recon_cnn_train_step", "recon_cnn_tensor", "recon_cnn_time_kernels",
-           "recon_data_residual", "recon_warm_start", "recon_warm_start_noalloc", "recon_fbp",
+           "recon_data_residual", "recon_warm_start", "recon_warm_start_noalloc", "recon_warm_start_async",
+           "recon_batch_wait", "recon_fbp",
            "recon_rebin_helical", "recon_read_bandwidth", "recon_valu_rate", "recon_batch_check_work"]
 
 _lib = None
@@ -105,6 +106,8 @@ def lib():
         L.recon_data_residual.argtypes = [vp, vp, f, vp, i32, vp, vp]
         L.recon_warm_start.argtypes = [vp, vp, PP, P(f), PP, i32, i32, i32, d, i32, P(d), P(d), P(i32), vp]
         L.recon_warm_start_noalloc.argtypes = [vp, vp, PP, P(f), PP, i32, i32, i32, d, i32, P(d), P(d), P(i32), vp]
+        L.recon_warm_start_async.argtypes = [vp, vp, PP, P(f), PP, i32, i32, i32, d, i32, P(d), P(d), P(i32), vp]
+        L.recon_batch_wait.argtypes = [vp]
         L.recon_cnn_param_count.argtypes = []
         L.recon_cnn_param_count.restype = i64
         L.recon_cnn_create.argtypes = [P(f), i32, i32, f, P(vp)]
@@ -482,9 +485,13 @@ class Batch:
         _check(lib().recon_batch_set_launch(self._h, fp_segments, bp_variant), "recon_batch_set_launch")
 
     def warm_start(self, net, counts, i0s, imgs=None, n_pre: int = 10, n_refine: int = 40, n_cold: int = 500,
-                   residual_ratio: float = 1.0, noalloc: bool = False, check_stride: int = 1):
+                   residual_ratio: float = 1.0, noalloc: bool = False, check_stride: int = 1,
+                   async_fallback: bool = False):
         """recon_warm_start (noalloc: recon_warm_start_noalloc, the entry point that allocates no device
-        memory): returns (imgs, residual, floor, fallback) with numpy per-slice arrays."""
+        memory; async_fallback: recon_warm_start_async, whose fallback cold starts are final only after
+        wait()): returns (imgs, residual, floor, fallback) with numpy per-slice arrays."""
+        if noalloc and async_fallback:
+            raise ValueError("noalloc and async_fallback are separate entry points")
         torch = _torch()
         n = len(self.geometries)
         if imgs is None:
@@ -492,7 +499,8 @@ class Batch:
         i0 = (ctypes.c_float * n)(*[float(x) for x in i0s])
         res, flo = np.zeros(n), np.zeros(n)
         fb = np.zeros(n, dtype=np.int32)
-        name = "recon_warm_start_noalloc" if noalloc else "recon_warm_start"
+        name = ("recon_warm_start_noalloc" if noalloc else
+                "recon_warm_start_async" if async_fallback else "recon_warm_start")
         _check(getattr(lib(), name)(self._h, net._h, _ptr_array(counts, torch.float32, self._count_shapes(), "counts"),
                                     i0, _ptr_array(imgs, torch.float32, self._img_shapes(), "img"), int(n_pre),
                                     int(n_refine), int(n_cold), float(residual_ratio), int(check_stride),
@@ -500,6 +508,10 @@ class Batch:
                                     flo.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                     fb.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _stream()), name)
         return imgs, res, flo, fb
+
+    def wait(self):
+        """recon_batch_wait: blocks until the cold starts of warm_start(async_fallback=True) are done."""
+        _check(lib().recon_batch_wait(self._h), "recon_batch_wait")
 
 
 def _fptr(a):

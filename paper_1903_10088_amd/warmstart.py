@@ -281,6 +281,27 @@ def stream_times(fns, min_s: float = STEADY_S):
     return res, dts
 
 
+def stream_total(fns, finish, min_s: float = STEADY_S):
+    """Wall time of one pass of the callables `fns` run back to back followed by `finish()` (which waits
+    for work they left running, e.g. asynchronous cold starts), after untimed passes of the same that
+    last at least `min_s` seconds.  No synchronisation between the calls.  Returns (results, seconds)."""
+    torch = _torch()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    while True:
+        for f in fns:
+            f()
+        finish()
+        torch.cuda.synchronize()
+        if time.perf_counter() - t >= min_s:
+            break
+    t = time.perf_counter()
+    res = [f() for f in fns]
+    finish()
+    torch.cuda.synchronize()
+    return res, time.perf_counter() - t
+
+
 def timed_steady(fn, min_s: float = STEADY_S):
     """Seconds per call of `fn` under sustained load: `fn` is repeated until `min_s` seconds have
     passed, then the same number of back-to-back calls is timed.  Returns (last result, seconds per

@@ -97,6 +97,10 @@ int main()
     expect(recon_warm_start_noalloc(nullptr, nullptr, nullptr, nullptr, nullptr, 1, 1, 1, 1.0, 1, nullptr, nullptr,
                                     nullptr, nullptr) == RECON_INVALID_ARG,
            "warm start NULL");
+    expect(recon_warm_start_async(nullptr, nullptr, nullptr, nullptr, nullptr, 1, 1, 1, 1.0, 1, nullptr, nullptr,
+                                  nullptr, nullptr) == RECON_INVALID_ARG,
+           "async warm start NULL");
+    expect(recon_batch_wait(nullptr) == RECON_INVALID_ARG, "batch wait NULL");
     const double z[1] = {0.0};
     expect(recon_rebin_helical(&good, 72, 10.0, 0.0, nullptr, 1e4f, z, 0, nullptr, nullptr) == RECON_OK,
            "rebin zero slices");

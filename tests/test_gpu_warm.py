@@ -244,3 +244,47 @@ def test_trained_network_gains_over_the_plain_method(dev):
     assert np.all(r_net < 0.5 * r_in)
     assert np.all(r_warm < 0.5 * r_plain)
     assert not fb.any()
+
+
+def test_async_fallbacks_equal_sync(dev):
+    """recon_warm_start_async: with every slice sent to the cold start (three slices: the batched cold
+    start; one slice: its own handle) the results after wait() equal recon_warm_start's bit for bit,
+    also while another batch's pipeline runs on the caller's stream in between; a later call on the
+    batch (a plain run, an allocation-free warm start) first waits for the pending cold starts."""
+    from paper_1903_10088_amd import recon
+    geoms, slices = small_batch()
+    M, beta = 5, 1e-3
+    theta = ph.cnn_initial_params(3, zero_last=False, last_std=0.05)
+    net = recon.Cnn(theta, max_batch=3, max_n=128, mu_scale=ph.MU_WATER_PER_MM)
+    counts = [torch.from_numpy(s.counts).to(dev) for s in slices]
+    i0s = [s.i0 for s in slices]
+    ref3, res3, _, fb3 = recon.Batch(geoms, M, beta).warm_start(net, counts, i0s, None, 4, 6, 13, 1e-9)
+    ref1, _, _, _ = recon.Batch(geoms[1:2], M, beta).warm_start(net, counts[1:2], i0s[1:2], None, 4, 6, 13, 1e-9)
+    assert fb3.all()
+    A = recon.Batch(geoms, M, beta)
+    C = recon.Batch(geoms[1:2], M, beta)
+    imgs3, r3, _, f3 = A.warm_start(net, counts, i0s, None, 4, 6, 13, 1e-9, async_fallback=True)
+    imgs1, _, _, f1 = C.warm_start(net, counts[1:2], i0s[1:2], None, 4, 6, 13, 1e-9, async_fallback=True)
+    assert f3.all() and f1.all() and np.array_equal(r3, res3)
+    A.wait()
+    C.wait()
+    torch.cuda.synchronize()
+    for k in range(3):
+        assert torch.equal(imgs3[k], ref3[k]), k
+    assert torch.equal(imgs1[0], ref1[0])
+    # a later call on the batch waits for the pending cold starts first
+    A.warm_start(net, counts, i0s, imgs3, 4, 6, 13, 1e-9, async_fallback=True)
+    run, _ = A.run(counts, i0s, None, 7)
+    fresh, _ = recon.Batch(geoms, M, beta).run(counts, i0s, None, 7)
+    torch.cuda.synchronize()
+    for k in range(3):
+        assert torch.equal(imgs3[k], ref3[k]), k
+        assert torch.equal(run[k], fresh[k]), k
+    # an allocation-free call after an asynchronous one (it waits without freeing the sub-batch)
+    A.warm_start(net, counts, i0s, imgs3, 4, 6, 13, 1e-9, async_fallback=True)
+    out, _, _, _ = A.warm_start(net, counts, i0s, None, 4, 6, 13, 1e-9, noalloc=True)
+    A.close()
+    torch.cuda.synchronize()
+    for k in range(3):
+        assert torch.equal(out[k], ref3[k]), k
+        assert torch.equal(imgs3[k], ref3[k]), k

@@ -88,6 +88,9 @@ def test_null_handle_calls_are_rejected():
     assert L.recon_os_iterate_ex(None, None, 1.0, None, 1, None, None, None, None, None,
                                  None) == recon.RECON_INVALID_ARG
     assert L.recon_destroy(None) == recon.RECON_OK
+    assert L.recon_batch_wait(None) == recon.RECON_INVALID_ARG
+    assert L.recon_warm_start_async(None, None, None, None, None, 1, 1, 1, 1.0, 1, None, None, None,
+                                    None) == recon.RECON_INVALID_ARG
 
 
 @pytest.mark.parametrize("name,geom,M,stride", [
